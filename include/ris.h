@@ -1,0 +1,159 @@
+/*
+ * ris.h -- C ABI of the MI355X (gfx950) TDDFT-ris gradient / derivative-coupling
+ * hot path.
+ *
+ * Method (arXiv 2511.18233): the TDDFT-ris kernel replaces both two-electron
+ * integrals of the response matrices by a resolution of the identity over a
+ * minimal auxiliary basis, g^ris_{pq,sr} = sum_AB (pq|A)(M_J^-1)_AB (B|sr)
+ * - c_x sum_AB (pr|A)(M_K^-1)_AB (B|sq) with M_AB = (A|B), and drops f_xc
+ * (Sec. 2.2, eqs. ris and g_modified).  The ris term of the excited-state
+ * gradient and of the NAC numerator is <g^{ris,(xi)}; Gamma_IJ> with
+ * Gamma_IJ = {R^S_I, R^S_J} + {L^A_I, L^A_J} (Sec. 2.2, eqs. gI_xi_ris and
+ * gIJ_xi_ris; Appendix A.1), evaluated with the three-term derivative of the
+ * RI four-index object (last equation of Sec. 2.2).
+ *
+ * Conventions used by every call:
+ *   - FP64, row-major, atomic units (Bohr, Hartree).
+ *   - AO basis: uncontracted Cartesian Gaussians, one primitive per shell,
+ *     each Cartesian component normalised to one; l <= 2 with component order
+ *     x,y,z and xx,xy,xz,yy,yz,zz; AO index = shells in the caller's order.
+ *   - Auxiliary basis built by ris_aux_build: J (Coulomb) set = one s function
+ *     on every atom (atom order) followed, if requested, by one p shell
+ *     (x,y,z) on every atom with Z > 1 (atom order); K (exchange) set = the s
+ *     functions, i.e. the first natm J functions.  One exponent per atom,
+ *     theta / R_A^2 (Sec. 2.2: one Gaussian per angular momentum per atom;
+ *     Sec. 4: s+p for Coulomb, s for exchange).
+ *   - Amplitude arrays are [nstate][nvir][nocc] (index a*nocc + i).
+ *   - Large arrays (C, eps, V, out, X, Y, grad, nac, dbg) are DEVICE pointers
+ *     on the context's device; small tables (ris_mol, ris_aux_opts, sel,
+ *     pairs, omega) are HOST pointers.  The caller owns every buffer it
+ *     passes; the context owns all of its internal device state.
+ *   - All device work is enqueued on the stream given at ris_ctx_create;
+ *     calls return once the work is enqueued except where noted.
+ *   - Errors: a status code is returned and a message is kept for
+ *     ris_last_error; nothing is thrown across the ABI.  After an error the
+ *     outputs of that call are undefined.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef RIS_H
+#define RIS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ris_status {
+    RIS_OK = 0,
+    RIS_E_INVALID = 1,      /* bad argument, shape or pointer */
+    RIS_E_UNSUPPORTED = 2,  /* AO l > 2, or a precision mode not built */
+    RIS_E_NOMEM = 3,        /* request exceeds the context's HBM budget */
+    RIS_E_NOT_PD = 4,       /* auxiliary metric not positive definite */
+    RIS_E_DEGENERATE = 5,   /* |omega_J - omega_I| < 1e-12 (numerator still written) */
+    RIS_E_ORDER = 6,        /* calls out of order (aux_build -> int3c -> others) */
+    RIS_E_DEVICE = 7        /* HIP runtime error */
+};
+
+enum ris_precision { RIS_FP64 = 0 };
+
+/* Response operators of the Casida problem (Sec. 2.1, eqs. casida, A_matrix,
+ * B_matrix): A, B, A+B, A-B with the ris kernel. */
+enum ris_op { RIS_OP_A = 0, RIS_OP_B = 1, RIS_OP_APB = 2, RIS_OP_AMB = 3 };
+
+typedef struct ris_ctx ris_ctx;
+
+/* Molecule and AO basis (host pointers, copied during the call). */
+typedef struct {
+    int natm;
+    const int *Z;             /* [natm] nuclear charges (1..118) */
+    const double *xyz;        /* [natm][3] Bohr */
+    int nshell;
+    const int *shell_atom;    /* [nshell] atom of each AO shell */
+    const int *shell_l;       /* [nshell] 0..2 */
+    const double *shell_exp;  /* [nshell] Gaussian exponent > 0 */
+} ris_mol;
+
+/* Minimal auxiliary basis options (host pointers, copied). */
+typedef struct {
+    double theta;               /* exponent rule alpha_A = theta / R_A^2 */
+    const double *radius_bohr;  /* [119] radius R_A by Z, Bohr (> 0 for every Z used) */
+    int j_p_on_heavy;           /* 1: add a p shell on every Z > 1 atom to the J set */
+} ris_aux_opts;
+
+/* Orbitals and kernel parameters (C, eps are device pointers). */
+typedef struct {
+    int nao;            /* must equal the AO count of the molecule */
+    int nmo;            /* number of MOs (columns of C), nocc < nmo <= nao */
+    int nocc;           /* occupied orbitals are columns 0..nocc-1 */
+    const double *C;    /* [nao][nmo] device */
+    const double *eps;  /* [nmo] device, orbital energies */
+    double alpha_J;     /* Coulomb factor (closed-shell singlet: 2) */
+    double c_x;         /* exact-exchange fraction (Sec. 2.1, eq. g_integral) */
+    int precision;      /* enum ris_precision */
+} ris_mo;
+
+/* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`
+ * (a hipStream_t, NULL = the legacy default stream).  hbm_budget bounds the
+ * bytes the context may allocate (0 = 90% of the device's free memory).
+ * Returns RIS_E_DEVICE if HIP cannot be initialised. */
+int ris_ctx_create(ris_ctx **out, int device, void *hip_stream, size_t hbm_budget);
+
+/* Release every device buffer of the context (synchronises its stream). */
+void ris_ctx_destroy(ris_ctx *ctx);
+
+/* Message of the last failing call on this context ("" if none). */
+const char *ris_last_error(const ris_ctx *ctx);
+
+/* Bytes of device memory the context currently holds. */
+size_t ris_ctx_bytes(const ris_ctx *ctx);
+
+/* Minimal ris auxiliary basis and its Coulomb metric (Sec. 2.2).
+ * Builds the AO shell tables and the J and K auxiliary sets, evaluates
+ * M_PQ = (P|Q) on the device, factors M = L L^T (FP64 Cholesky) and forms
+ * M^-1 for both sets.  Writes the J and K function counts.  Synchronous
+ * (the Cholesky positivity check is read back).  RIS_E_NOT_PD if a metric
+ * is not positive definite (e.g. two atoms on the same spot); RIS_E_UNSUPPORTED
+ * for AO l > 2.  Invalidates previous ris_int3c state. */
+int ris_aux_build(ris_ctx *ctx, const ris_mol *mol, const ris_aux_opts *opts,
+                  int *nauxJ, int *nauxK);
+
+/* Three-centre integrals (mu nu|P) over the J set (Sec. 2.2, eq. g_modified)
+ * and their MO blocks (Sec. 3, reduced MO storage): (ai|P) for every J
+ * function, and (ij|P), (ab|P) for the K functions, plus the metric-applied
+ * blocks sum_Q (M_K^-1)_PQ (pq|Q).  mo->C and mo->eps are copied.  If
+ * dbg_int3c is not NULL it receives (mu nu|P) as [nauxJ][nao][nao] in the
+ * caller's AO order (device pointer).  RIS_E_ORDER before ris_aux_build,
+ * RIS_E_NOMEM if the tensors exceed the budget. */
+int ris_int3c(ris_ctx *ctx, const ris_mo *mo, double *dbg_int3c);
+
+/* ris response matrix-vector products (Sec. 2.1, eqs. A_matrix, B_matrix
+ * with K = g^ris): for each of nvec vectors V[v][o] (device, [nvec][nvir][nocc])
+ *   (A V)_ai = (e_a - e_i) V_ai + alpha_J sum_bj (ai|bj)_J V_bj - c_x sum_bj (ab|ij)_K V_bj
+ *   (B V)_ai =                     alpha_J sum_bj (ai|bj)_J V_bj - c_x sum_bj (aj|bi)_K V_bj
+ * op selects A, B, A+B or A-B; out has V's shape (device, may not alias V). */
+int ris_response_matvec(ris_ctx *ctx, int op, int nvec, const double *V, double *out);
+
+/* ris part of excited-state gradients (Sec. 2.2, eq. gI_xi_ris): for each
+ * selected state I = sel[k], grad[k][A][x] = d/dA_x <g^ris; Gamma_II> at fixed
+ * AO transition densities R^S_I, L^A_I built from R_I = X_I + Y_I and
+ * L_I = X_I - Y_I (Appendix A.1), including the (P|Q) metric derivative.
+ * X, Y: [nstate][nvir][nocc] device; Y = NULL means TDA (Y = 0, Sec. 3).
+ * grad: [nsel][natm][3] device, Ha/Bohr (dE/dR, not a force). */
+int ris_grad_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y,
+                      int nsel, const int *sel, double *grad);
+
+/* ris part of NACs between excited states (Sec. 2.2, eq. gIJ_xi_ris): for
+ * each pair (I, J) = (pairs[2k], pairs[2k+1]) writes the numerator
+ * d/dA_x <g^ris; Gamma_IJ> to nac[k][A][x] (device, Ha/Bohr); if omega
+ * (host, [nstate]) is given the result is divided by (omega_J - omega_I)
+ * (1/Bohr).  Returns RIS_E_DEGENERATE (after writing the numerator) if any
+ * gap is below 1e-12. */
+int ris_nac_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y,
+                     int npair, const int *pairs, const double *omega, double *nac);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIS_H */

@@ -1,0 +1,101 @@
+// Internal declarations shared by the gfx950 kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ris {
+
+constexpr int kMaxAOL = 2;   // AO shells up to d (Cartesian)
+constexpr int kMaxAuxL = 1;  // auxiliary shells up to p
+
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// Shell table in structure-of-arrays form (device pointers).
+struct ShellTab {
+    const double *x, *y, *z;  // centre
+    const double *exp;        // exponent
+    const double *nrm;        // radial normalisation (2a/pi)^{3/4} (4a)^{l/2}
+    const int *atom;          // atom index
+    const int *off;           // first function index of the shell
+};
+
+// --- Boys function table: F_m(T_k) on T_k = k / kBoysInvStep, k <= kBoysNGrid-1
+constexpr int kBoysMaxM = 7;       // highest order needed by any kernel
+constexpr int kBoysTaylor = 8;     // Taylor terms (orders kept: 0..kBoysTaylor-1)
+constexpr int kBoysCols = kBoysMaxM + kBoysTaylor;  // stored orders 0..kBoysCols-1
+constexpr double kBoysInvStep = 16.0;
+constexpr double kBoysTMax = 40.0;
+constexpr int kBoysNGrid = 641;    // 40 * 16 + 1
+
+// Host: fill tab[k * kBoysCols + m] = F_m(k / 16) (long-double series).
+void boys_table_host(double *tab);
+
+// --- kernels launched from the host library (ris_ints.hip / ris_linalg.hip)
+struct AuxGeom {
+    ShellTab sh;
+    int nshell;
+    int nfunc;
+};
+
+// (P|Q) metric over the auxiliary set, full square [n][n].
+hipError_t launch_int2c(const AuxGeom &aux, const double *boys, double *M, hipStream_t st);
+
+// (mu nu|P): X[P][mu][nu] (internal AO order), all J auxiliary shells.
+struct AOGeom {
+    ShellTab sh;
+    int nshell;
+    int nao;
+    int lbeg[kMaxAOL + 2];  // shells sorted by l: shells of l are [lbeg[l], lbeg[l+1])
+};
+hipError_t launch_int3c(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],
+                        const double *boys, double *X, hipStream_t st);
+
+// Fused three-centre derivative contraction (see ris_ints.hip).
+struct DerivJob {
+    int nout;                  // outputs in this launch (<= kMaxOutChunk)
+    const double *gammaK;      // [nout][nK][nao][nao] symmetric K weights, may be null
+    int nK;                    // K functions (first nK J functions)
+    const double *dens;        // [nstate][nao][nao] symmetric AO densities R^S
+    const double *cvec;        // [nstate][nJ] c_I = M_J^-1 t_I
+    int nJ;
+    int stI[8], stJ[8];        // state pair of each output
+    double alphaJ;
+    double *partial;           // [nshellAO][nshellAux][nout][6] (dA xyz, dC xyz)
+};
+constexpr int kMaxOutChunk = 4;
+hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],
+                              const double *boys, const DerivJob &job, hipStream_t st);
+
+// 2c metric derivative contraction: partial2[P shell][out][3] for d/dP.
+hipError_t launch_int2c_deriv(const AuxGeom &aux, const double *boys, int nout,
+                              const double *W /*[nout][n][n]*/, double *partial2, hipStream_t st);
+
+// Batched / batch-reduced FP64 GEMM on the matrix cores (ris_gemm.hip):
+// for b < batch: C_b = alpha * sum_{r < nred} op(A_{b,r}) op(B_{b,r}) + beta * C_b,
+// row-major; op(A) is M x K (A stored K x M when transA), op(B) is K x N.
+struct GemmArgs {
+    int M, N, K;
+    bool transA, transB;
+    double alpha, beta;
+    const double *A;
+    long lda, strideA, strideAr;
+    const double *B;
+    long ldb, strideB, strideBr;
+    double *C;
+    long ldc, strideC;
+    int batch, nred;
+};
+hipError_t dgemm(const GemmArgs &g, hipStream_t st);
+
+// Dense linear algebra on small matrices (ris_linalg.hip).
+// In-place Cholesky of the n x n SPD matrix (lower triangle written, upper
+// zeroed); *info (device int) = 0 or the 1-based failing column.  A pivot
+// below 1e-13 of Morig's diagonal (the unfactored matrix, may be null) fails.
+hipError_t cholesky(double *A, const double *Morig, int n, int *info, hipStream_t st);
+// Linv = L^-1 for lower-triangular L (n x n), full matrix written.
+hipError_t tri_inverse(const double *L, double *Linv, int n, hipStream_t st);
+
+}  // namespace ris

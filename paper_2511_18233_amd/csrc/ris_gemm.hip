@@ -1,0 +1,187 @@
+// FP64 GEMM on the CDNA4 matrix cores: v_mfma_f64_16x16x4f64.
+//
+// C_b = alpha * sum_{r < nred} op(A_{b,r}) op(B_{b,r}) + beta * C_b, row-major.
+// Block tile 128 x 128 x 16, 256 threads = 4 waves in a 2 x 2 arrangement,
+// each wave owning a 64 x 64 sub-tile = 4 x 4 MFMA tiles (16 accumulators of
+// four doubles).  Operand tiles are staged k-major in LDS so every MFMA
+// fragment read is 16 consecutive doubles; the next k-slab is prefetched into
+// registers while the current one is consumed.
+//
+// MFMA 16x16x4 f64 lane layout (wave64): A fragment lane l holds
+// A[l % 16][l / 16], B fragment lane l holds B[l / 16][l % 16], and the four
+// accumulator values of lane l are D[4 i + l / 16][l % 16], i = 0..3 (rows
+// interleaved across the four lane groups; checked by the layout probe test).
+#include "ris_common.hpp"
+
+namespace ris {
+typedef double v4d __attribute__((ext_vector_type(4)));
+namespace {
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int PAD = 2;  // LDS row padding (doubles) against bank conflicts on the transposing stores
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                               long lda, long sA, long sAr, const double *__restrict__ B, long ldb,
+                                               long sB, long sBr, double beta, double *__restrict__ C, long ldc,
+                                               long sC, int nred)
+{
+    __shared__ double As[BK][BM + PAD];
+    __shared__ double Bs[BK][BN + PAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const long bz = blockIdx.z;
+    A += bz * sA;
+    B += bz * sB;
+    C += bz * sC;
+
+    v4d acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    // global -> register staging: 8 doubles of A and 8 of B per thread
+    double ra[8], rb[8];
+    const int ktiles = (K + BK - 1) / BK;
+    const int total = ktiles * nred;
+
+    auto load = [&](int it) {
+        const int r = it / ktiles;
+        const int k0 = (it % ktiles) * BK;
+        const double *Ar = A + (long)r * sAr;
+        const double *Br = B + (long)r * sBr;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (!TA) {  // A is M x K: element (m, k) at Ar[m*lda + k]; 16 threads per row
+                const int k = tid & 15, m = (tid >> 4) + 16 * q;
+                const int gm = m0 + m, gk = k0 + k;
+                ra[q] = (gm < M && gk < K) ? Ar[(long)gm * lda + gk] : 0.0;
+            } else {    // A stored K x M: element (m, k) at Ar[k*lda + m]
+                const int m = tid & 127, k = (tid >> 7) + 2 * q;
+                const int gm = m0 + m, gk = k0 + k;
+                ra[q] = (gm < M && gk < K) ? Ar[(long)gk * lda + gm] : 0.0;
+            }
+            if (!TB) {  // B is K x N: element (k, n) at Br[k*ldb + n]
+                const int n = tid & 127, k = (tid >> 7) + 2 * q;
+                const int gn = n0 + n, gk = k0 + k;
+                rb[q] = (gn < N && gk < K) ? Br[(long)gk * ldb + gn] : 0.0;
+            } else {    // B stored N x K: element (k, n) at Br[n*ldb + k]
+                const int k = tid & 15, n = (tid >> 4) + 16 * q;
+                const int gn = n0 + n, gk = k0 + k;
+                rb[q] = (gn < N && gk < K) ? Br[(long)gn * ldb + gk] : 0.0;
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (!TA) As[tid & 15][(tid >> 4) + 16 * q] = ra[q];
+            else As[(tid >> 7) + 2 * q][tid & 127] = ra[q];
+            if (!TB) Bs[(tid >> 7) + 2 * q][tid & 127] = rb[q];
+            else Bs[tid & 15][(tid >> 4) + 16 * q] = rb[q];
+        }
+    };
+
+    if (total > 0) load(0);
+    for (int it = 0; it < total; ++it) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (it + 1 < total) load(it + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double fa[4], fb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fa[i] = As[kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fb[j] = Bs[kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + wm * 64 + i * 16 + 4 * e + (lane >> 4);
+                if (row < M && col < N) {
+                    double *cp = C + (long)row * ldc + col;
+                    const double v = alpha * acc[i][j][e];
+                    *cp = (beta == 0.0) ? v : v + beta * *cp;
+                }
+            }
+        }
+}
+
+}  // namespace
+
+hipError_t dgemm(const GemmArgs &g, hipStream_t st)
+{
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
+    const int nred = g.nred > 0 ? g.nred : 1;
+    if (!g.transA && !g.transB)
+        hipLaunchKernelGGL((k_dgemm<false, false>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,
+                           g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred);
+    else if (g.transA && !g.transB)
+        hipLaunchKernelGGL((k_dgemm<true, false>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,
+                           g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred);
+    else if (!g.transA && g.transB)
+        hipLaunchKernelGGL((k_dgemm<false, true>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,
+                           g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred);
+    else
+        hipLaunchKernelGGL((k_dgemm<true, true>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,
+                           g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred);
+    return hipGetLastError();
+}
+
+}  // namespace ris
+
+// ---------------------------------------------------------------- tests --
+namespace {
+__global__ __launch_bounds__(64) void k_mfma_probe(const double *a, const double *b, double *out)
+{
+    const int lane = threadIdx.x;
+    ris::v4d acc = ris::v4d{0.0, 0.0, 0.0, 0.0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lane], b[lane], acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[4 * lane + e] = acc[e];
+}
+}  // namespace
+
+extern "C" int ris_test_mfma_probe(const double *a, const double *b, double *out)
+{
+    if (!a || !b || !out) return 1;
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, 0, a, b, out);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return 7;
+    return 0;
+}
+
+extern "C" int ris_test_dgemm(int M, int N, int K, int transA, int transB, double alpha, const double *A, long lda,
+                              long sA, const double *B, long ldb, long sB, double beta, double *C, long ldc, long sC,
+                              int batch)
+{
+    if (M < 0 || N < 0 || K < 0 || batch < 0 || !A || !B || !C) return 1;
+    ris::GemmArgs g{};
+    g.M = M; g.N = N; g.K = K;
+    g.transA = transA != 0; g.transB = transB != 0;
+    g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.strideA = sA;
+    g.B = B; g.ldb = ldb; g.strideB = sB;
+    g.C = C; g.ldc = ldc; g.strideC = sC;
+    g.batch = batch; g.nred = 1;
+    if (ris::dgemm(g, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return 7;
+    return 0;
+}

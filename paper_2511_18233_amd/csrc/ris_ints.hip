@@ -1,0 +1,576 @@
+// Gaussian integrals of the ris auxiliary expansion on gfx950 (FP64 VALU).
+//
+// The RI kernel of TDDFT-ris needs the three-centre integrals (mu nu|P), the
+// metric (P|Q) (Sec. 2.2, eq. g_modified) and their nuclear derivatives (the
+// three-term RI derivative at the end of Sec. 2.2).  Every shell is a single
+// Cartesian primitive, so each integral is one McMurchie-Davidson expansion:
+//   (ab|c) = 2 pi^{5/2} / (p q sqrt(p+q)) exp(-mu |AB|^2)
+//            sum_T E^{ab}_T Lambda^c_T,
+//   Lambda^s_T = R_T,  Lambda^{p_k}_T = -R_{T+1_k} / (2q),
+// with Hermite coefficients E (recurrence over the Gaussian product) and
+// Hermite Coulomb integrals R_{tuv}(alpha, P-C) (recurrence over the Boys
+// function).  Derivatives used:
+//   d/dA_d (ab|c): E_x replaced by 2a E_{i+1} - i E_{i-1} in direction d,
+//   d/dC_d (ab|c) = -sum_T E^{ab}_T Lambda^c_{T+1_d}  (R depends on P-C only),
+//   d/dB = -d/dA - d/dC (translational invariance of the integral).
+// All angular loops are unrolled at compile time per (la, lb, lc) class so the
+// recurrence tables live in registers.
+#include <utility>
+
+#include "ris_boys.hpp"
+#include "ris_common.hpp"
+
+namespace ris {
+namespace {
+
+template <typename F, int... Is>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+// compile-time loop: f(integral_constant<int, 0..N-1>)
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// power of direction d in Cartesian component c of angular momentum l
+// (order x,y,z and xx,xy,xz,yy,yz,zz)
+__host__ __device__ constexpr int cpow(int l, int c, int d)
+{
+    return l == 0 ? 0
+         : l == 1 ? (c == d ? 1 : 0)
+         : d == 0 ? (c == 0 ? 2 : (c == 1 || c == 2) ? 1 : 0)
+         : d == 1 ? (c == 1 ? 1 : c == 3 ? 2 : c == 4 ? 1 : 0)
+                  : (c == 2 ? 1 : c == 4 ? 1 : c == 5 ? 2 : 0);
+}
+// 1/sqrt((2lx-1)!!(2ly-1)!!(2lz-1)!!) for the component
+__host__ __device__ constexpr double cnorm(int l, int c)
+{
+    return (l == 2 && (c == 0 || c == 3 || c == 5)) ? 0.57735026918962576451 : 1.0;
+}
+
+// packed index of R_{tuv}: level s = t+u+v, then (u+v), then v
+__host__ __device__ constexpr int ridx(int t, int u, int v)
+{
+    return (t + u + v) * (t + u + v + 1) * (t + u + v + 2) / 6 + (u + v) * (u + v + 1) / 2 + v;
+}
+__host__ __device__ constexpr int rsize(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
+
+// Hermite coefficients of one direction, E[i][j][t], i <= I, j <= J, without
+// the exp(-mu X_AB^2) factor (applied once per shell pair).
+template <int I, int J>
+struct Herm {
+    double e[I + 1][J + 1][I + J + 1];
+};
+
+template <int I, int J>
+__device__ __forceinline__ void herm_build(double xpa, double xpb, double inv2p, Herm<I, J> &H)
+{
+    sfor<I + 1>([&](auto ii) {
+        sfor<J + 1>([&](auto jj) {
+            sfor<I + J + 1>([&](auto tt) { H.e[ii][jj][tt] = 0.0; });
+        });
+    });
+    H.e[0][0][0] = 1.0;
+    sfor<I>([&](auto im) {  // i = im + 1, j = 0
+        constexpr int i = im + 1;
+        sfor<i + 1>([&](auto tt) {
+            constexpr int t = tt;
+            double v = 0.0;
+            if constexpr (t > 0) v += inv2p * H.e[i - 1][0][t - 1];
+            if constexpr (t <= i - 1) v += xpa * H.e[i - 1][0][t];
+            if constexpr (t + 1 <= i - 1) v += (t + 1) * H.e[i - 1][0][t + 1];
+            H.e[i][0][t] = v;
+        });
+    });
+    sfor<J>([&](auto jm) {
+        constexpr int j = jm + 1;
+        sfor<I + 1>([&](auto ii) {
+            constexpr int i = ii;
+            sfor<i + j + 1>([&](auto tt) {
+                constexpr int t = tt;
+                double v = 0.0;
+                if constexpr (t > 0) v += inv2p * H.e[i][j - 1][t - 1];
+                if constexpr (t <= i + j - 1) v += xpb * H.e[i][j - 1][t];
+                if constexpr (t + 1 <= i + j - 1) v += (t + 1) * H.e[i][j - 1][t + 1];
+                H.e[i][j][t] = v;
+            });
+        });
+    });
+}
+
+// R_{tuv} for t+u+v <= L into r[ridx], in place from level n = L down to 0.
+template <int L>
+__device__ __forceinline__ void hermite_r(double alpha, double X, double Y, double Z,
+                                          const double *__restrict__ boys, double (&r)[rsize(L)])
+{
+    double F[L + 1];
+    boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), boys, F);
+    const double m2a = -2.0 * alpha;
+    double pw[L + 1];
+    pw[0] = 1.0;
+    sfor<L>([&](auto n) { pw[n + 1] = pw[n] * m2a; });
+    r[0] = pw[L] * F[L];
+    sfor<L>([&](auto nn) {
+        constexpr int n = L - 1 - nn;  // level n, entries with sum <= L - n
+        sfor<L - n>([&](auto ss) {
+            constexpr int s = L - n - ss;  // descending s
+            sfor<s + 1>([&](auto tt) {
+                constexpr int t = s - tt;
+                sfor<s - t + 1>([&](auto uu) {
+                    constexpr int u = s - t - uu;
+                    constexpr int v = s - t - u;
+                    double val;
+                    if constexpr (t > 0) {
+                        val = X * r[ridx(t - 1, u, v)];
+                        if constexpr (t > 1) val += (t - 1) * r[ridx(t - 2, u, v)];
+                    } else if constexpr (u > 0) {
+                        val = Y * r[ridx(t, u - 1, v)];
+                        if constexpr (u > 1) val += (u - 1) * r[ridx(t, u - 2, v)];
+                    } else {
+                        val = Z * r[ridx(t, u, v - 1)];
+                        if constexpr (v > 1) val += (v - 1) * r[ridx(t, u, v - 2)];
+                    }
+                    r[ridx(t, u, v)] = val;
+                });
+            });
+        });
+        r[0] = pw[n] * F[n];
+    });
+}
+
+// sum_{t,u,v} ex[t] ey[u] ez[v] R[t+SX][u+SY][v+SZ] for compile-time extents
+template <int NX, int NY, int NZ, int SX, int SY, int SZ, int RS>
+__device__ __forceinline__ double hsum(const double *ex, const double *ey, const double *ez,
+                                       const double (&r)[RS])
+{
+    double acc = 0.0;
+    sfor<NX>([&](auto t) {
+        double ay = 0.0;
+        sfor<NY>([&](auto u) {
+            double az = 0.0;
+            sfor<NZ>([&](auto v) { az += ez[v] * r[ridx(t + SX, u + SY, v + SZ)]; });
+            ay += ey[u] * az;
+        });
+        acc += ex[t] * ay;
+    });
+    return acc;
+}
+
+struct PairGeo {
+    double a, b, p, xpa[3], xpb[3], P[3], kab;
+};
+
+__device__ __forceinline__ PairGeo pair_geo(const ShellTab &S, int sa, int sb)
+{
+    PairGeo g;
+    const double A[3] = {S.x[sa], S.y[sa], S.z[sa]};
+    const double B[3] = {S.x[sb], S.y[sb], S.z[sb]};
+    g.a = S.exp[sa];
+    g.b = S.exp[sb];
+    g.p = g.a + g.b;
+    const double ip = 1.0 / g.p;
+    double ab2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        g.P[d] = (g.a * A[d] + g.b * B[d]) * ip;
+        g.xpa[d] = g.P[d] - A[d];
+        g.xpb[d] = g.P[d] - B[d];
+        ab2 += (A[d] - B[d]) * (A[d] - B[d]);
+    }
+    g.kab = exp(-g.a * g.b * ip * ab2);
+    return g;
+}
+
+constexpr double kTwoPi52 = 34.98683665524972497;  // 2 pi^{5/2}
+
+// ------------------------------------------------------------------------
+// (mu nu|P): one thread per ordered shell triplet of the class.
+template <int LA, int LB, int LC>
+__global__ __launch_bounds__(128) void k_int3c(ShellTab ao, int nao, int a0, int na, int b0, int nb,
+                                               ShellTab aux, int c0, int nc,
+                                               const double *__restrict__ boys, double *__restrict__ X)
+{
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= (long)na * nb * nc) return;
+    const int sb = b0 + (int)(tid % nb);
+    const long r1 = tid / nb;
+    const int sa = a0 + (int)(r1 % na);
+    const int sc = c0 + (int)(r1 / na);
+
+    constexpr int L = LA + LB + LC;
+    const PairGeo g = pair_geo(ao, sa, sb);
+    const double c = aux.exp[sc];
+    const double PC[3] = {g.P[0] - aux.x[sc], g.P[1] - aux.y[sc], g.P[2] - aux.z[sc]};
+    const double alpha = g.p * c / (g.p + c);
+    double r[rsize(L)];
+    hermite_r<L>(alpha, PC[0], PC[1], PC[2], boys, r);
+    const double inv2p = 0.5 / g.p;
+    Herm<LA, LB> Ex, Ey, Ez;
+    herm_build<LA, LB>(g.xpa[0], g.xpb[0], inv2p, Ex);
+    herm_build<LA, LB>(g.xpa[1], g.xpb[1], inv2p, Ey);
+    herm_build<LA, LB>(g.xpa[2], g.xpb[2], inv2p, Ez);
+    const double pref = kTwoPi52 / (g.p * c * sqrt(g.p + c)) * g.kab * ao.nrm[sa] * ao.nrm[sb] * aux.nrm[sc];
+    const double cfac = (LC == 1) ? -0.5 / c : 1.0;
+    const int mu0 = ao.off[sa], nu0 = ao.off[sb], P0 = aux.off[sc];
+    sfor<ncart(LC)>([&](auto kc) {
+        constexpr int sx = cpow(LC, kc, 0), sy = cpow(LC, kc, 1), sz = cpow(LC, kc, 2);
+        sfor<ncart(LA)>([&](auto ka) {
+            constexpr int ix = cpow(LA, ka, 0), iy = cpow(LA, ka, 1), iz = cpow(LA, ka, 2);
+            double *row = X + ((size_t)(P0 + kc) * nao + (mu0 + ka)) * nao + nu0;
+            sfor<ncart(LB)>([&](auto kb) {
+                constexpr int jx = cpow(LB, kb, 0), jy = cpow(LB, kb, 1), jz = cpow(LB, kb, 2);
+                const double v = hsum<ix + jx + 1, iy + jy + 1, iz + jz + 1, sx, sy, sz>(
+                    Ex.e[ix][jx], Ey.e[iy][jy], Ez.e[iz][jz], r);
+                row[kb] = pref * cfac * cnorm(LA, ka) * cnorm(LB, kb) * v;
+            });
+        });
+    });
+}
+
+// ------------------------------------------------------------------------
+// Fused derivative contraction.  One wave per (A shell, C shell); lanes walk
+// the B shells of class LB.  For every ordered triplet and output o
+//   w_o = alphaJ (D_I[mu nu] c_J[P] + D_J[mu nu] c_I[P]) + GammaK_o[P][mu nu]
+//   accA_o[d] += 2 w_o d(mu nu|P)/dA_d,  accC_o[d] += w_o d(mu nu|P)/dC_d
+// (weights symmetric in mu nu, so the bra-2 derivative folds into the factor
+// 2 on bra 1 over ordered pairs).  The wave sum is written to
+// partial[sa][sc][LB][o][6] for a deterministic reduction afterwards.
+template <int LA, int LB, int LC, int NO>
+__global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0, int na, int b0, int nb,
+                                                    ShellTab aux, int c0, int nc, int nshAux,
+                                                    const double *__restrict__ boys, DerivJob job)
+{
+    const int wid = blockIdx.x;
+    if (wid >= na * nc) return;
+    const int sa = a0 + wid % na;
+    const int sc = c0 + wid / na;
+    const int lane = threadIdx.x;
+
+    constexpr int L = LA + LB + LC + 1;
+    const double Ax = ao.x[sa], Ay = ao.y[sa], Az = ao.z[sa];
+    const double c = aux.exp[sc];
+    const double Cx = aux.x[sc], Cy = aux.y[sc], Cz = aux.z[sc];
+    const int mu0 = ao.off[sa], P0 = aux.off[sc];
+    const bool inK = P0 < job.nK;  // K functions are the leading (s) J functions
+    const size_t nao2 = (size_t)nao * nao;
+
+    double acc[NO][6];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[o][k] = 0.0;
+
+    double cI[NO][ncart(LC)], cJ[NO][ncart(LC)];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int k = 0; k < ncart(LC); ++k) {
+            cI[o][k] = job.cvec[(size_t)job.stI[o] * job.nJ + P0 + k];
+            cJ[o][k] = job.cvec[(size_t)job.stJ[o] * job.nJ + P0 + k];
+        }
+
+    for (int ib = lane; ib < nb; ib += 64) {
+        const int sb = b0 + ib;
+        const double a = ao.exp[sa], b = ao.exp[sb];
+        const double p = a + b, ip = 1.0 / p;
+        const double Bx = ao.x[sb], By = ao.y[sb], Bz = ao.z[sb];
+        const double P[3] = {(a * Ax + b * Bx) * ip, (a * Ay + b * By) * ip, (a * Az + b * Bz) * ip};
+        const double ab2 = (Ax - Bx) * (Ax - Bx) + (Ay - By) * (Ay - By) + (Az - Bz) * (Az - Bz);
+        const double kab = exp(-a * b * ip * ab2);
+        const double alpha = p * c / (p + c);
+        double r[rsize(L)];
+        hermite_r<L>(alpha, P[0] - Cx, P[1] - Cy, P[2] - Cz, boys, r);
+        const double inv2p = 0.5 * ip;
+        Herm<LA + 1, LB> Ex, Ey, Ez;
+        herm_build<LA + 1, LB>(P[0] - Ax, P[0] - Bx, inv2p, Ex);
+        herm_build<LA + 1, LB>(P[1] - Ay, P[1] - By, inv2p, Ey);
+        herm_build<LA + 1, LB>(P[2] - Az, P[2] - Bz, inv2p, Ez);
+        const double pref = kTwoPi52 / (p * c * sqrt(p + c)) * kab * ao.nrm[sa] * ao.nrm[sb] * aux.nrm[sc];
+        const double cfac = (LC == 1) ? -0.5 / c : 1.0;
+        const int nu0 = ao.off[sb];
+        const double twoa = 2.0 * a;
+
+        sfor<ncart(LC)>([&](auto kc) {
+            constexpr int sx = cpow(LC, kc, 0), sy = cpow(LC, kc, 1), sz = cpow(LC, kc, 2);
+            sfor<ncart(LA)>([&](auto ka) {
+                constexpr int ix = cpow(LA, ka, 0), iy = cpow(LA, ka, 1), iz = cpow(LA, ka, 2);
+                sfor<ncart(LB)>([&](auto kb) {
+                    constexpr int jx = cpow(LB, kb, 0), jy = cpow(LB, kb, 1), jz = cpow(LB, kb, 2);
+                    const double *ex = Ex.e[ix][jx];
+                    const double *ey = Ey.e[iy][jy];
+                    const double *ez = Ez.e[iz][jz];
+                    // derivative coefficients 2a E_{i+1} - i E_{i-1} per direction
+                    double dx[ix + jx + 2], dy[iy + jy + 2], dz[iz + jz + 2];
+                    sfor<ix + jx + 2>([&](auto t) {
+                        double v = twoa * Ex.e[ix + 1][jx][t];
+                        if constexpr (ix > 0 && t <= ix - 1 + jx) v -= ix * Ex.e[ix - 1][jx][t];
+                        dx[t] = v;
+                    });
+                    sfor<iy + jy + 2>([&](auto t) {
+                        double v = twoa * Ey.e[iy + 1][jy][t];
+                        if constexpr (iy > 0 && t <= iy - 1 + jy) v -= iy * Ey.e[iy - 1][jy][t];
+                        dy[t] = v;
+                    });
+                    sfor<iz + jz + 2>([&](auto t) {
+                        double v = twoa * Ez.e[iz + 1][jz][t];
+                        if constexpr (iz > 0 && t <= iz - 1 + jz) v -= iz * Ez.e[iz - 1][jz][t];
+                        dz[t] = v;
+                    });
+                    constexpr int NX = ix + jx + 1, NY = iy + jy + 1, NZ = iz + jz + 1;
+                    const double f = pref * cfac * cnorm(LA, ka) * cnorm(LB, kb);
+                    double dA[3], dC[3];
+                    dA[0] = f * hsum<NX + 1, NY, NZ, sx, sy, sz>(dx, ey, ez, r);
+                    dA[1] = f * hsum<NX, NY + 1, NZ, sx, sy, sz>(ex, dy, ez, r);
+                    dA[2] = f * hsum<NX, NY, NZ + 1, sx, sy, sz>(ex, ey, dz, r);
+                    dC[0] = -f * hsum<NX, NY, NZ, sx + 1, sy, sz>(ex, ey, ez, r);
+                    dC[1] = -f * hsum<NX, NY, NZ, sx, sy + 1, sz>(ex, ey, ez, r);
+                    dC[2] = -f * hsum<NX, NY, NZ, sx, sy, sz + 1>(ex, ey, ez, r);
+                    const size_t mn = (size_t)(mu0 + ka) * nao + nu0 + kb;
+#pragma unroll
+                    for (int o = 0; o < NO; ++o) {
+                        if (o < job.nout) {
+                            double w = job.alphaJ * (job.dens[(size_t)job.stI[o] * nao2 + mn] * cJ[o][kc] +
+                                                     job.dens[(size_t)job.stJ[o] * nao2 + mn] * cI[o][kc]);
+                            if (inK && job.gammaK)
+                                w += job.gammaK[((size_t)o * job.nK + P0 + kc) * nao2 + mn];
+                            const double w2 = 2.0 * w;
+                            acc[o][0] += w2 * dA[0];
+                            acc[o][1] += w2 * dA[1];
+                            acc[o][2] += w2 * dA[2];
+                            acc[o][3] += w * dC[0];
+                            acc[o][4] += w * dC[1];
+                            acc[o][5] += w * dC[2];
+                        }
+                    }
+                });
+            });
+        });
+    }
+    // wave reduction (fixed order, deterministic)
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double v = acc[o][k];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            acc[o][k] = v;
+        }
+    if (lane == 0) {
+        double *dst = job.partial + (((size_t)sa * nshAux + sc) * (kMaxAOL + 1) + LB) * NO * 6;
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) dst[o * 6 + k] = acc[o][k];
+    }
+}
+
+// ------------------------------------------------------------------------
+// (P|Q) and its derivative for single-Gaussian auxiliary shells (l <= 1):
+//   (P|Q) = 2 pi^{5/2}/(a b sqrt(a+b)) sum E^P_T (-1)^{|T'|} E^Q_{T'} R_{T+T'}(ab/(a+b), P-Q),
+// E^s = 1, E^{p_k} = 1/(2e) at T = 1_k; d/dP_d shifts R by 1_d.
+template <int LP, int LQ, bool DERIV>
+__device__ __forceinline__ void aux_pair(const ShellTab &S, int sp, int sq, const double *boys,
+                                         double (&val)[ncart(LP)][ncart(LQ)][DERIV ? 3 : 1])
+{
+    constexpr int L = LP + LQ + (DERIV ? 1 : 0);
+    const double a = S.exp[sp], b = S.exp[sq];
+    const double X = S.x[sp] - S.x[sq], Y = S.y[sp] - S.y[sq], Z = S.z[sp] - S.z[sq];
+    double r[rsize(L)];
+    hermite_r<L>(a * b / (a + b), X, Y, Z, boys, r);
+    const double pref = kTwoPi52 / (a * b * sqrt(a + b)) * S.nrm[sp] * S.nrm[sq] *
+                        (LP == 1 ? 0.5 / a : 1.0) * (LQ == 1 ? -0.5 / b : 1.0);
+    sfor<ncart(LP)>([&](auto kp) {
+        sfor<ncart(LQ)>([&](auto kq) {
+            constexpr int tx = cpow(LP, kp, 0) + cpow(LQ, kq, 0);
+            constexpr int ty = cpow(LP, kp, 1) + cpow(LQ, kq, 1);
+            constexpr int tz = cpow(LP, kp, 2) + cpow(LQ, kq, 2);
+            if constexpr (DERIV) {
+                val[kp][kq][0] = pref * r[ridx(tx + 1, ty, tz)];
+                val[kp][kq][1] = pref * r[ridx(tx, ty + 1, tz)];
+                val[kp][kq][2] = pref * r[ridx(tx, ty, tz + 1)];
+            } else {
+                val[kp][kq][0] = pref * r[ridx(tx, ty, tz)];
+            }
+        });
+    });
+}
+
+template <int LP, int LQ>
+__global__ __launch_bounds__(128) void k_int2c(ShellTab S, int n, int p0, int np, int q0, int nq,
+                                               const double *__restrict__ boys, double *__restrict__ M)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= np * nq) return;
+    const int sq = q0 + tid % nq, sp = p0 + tid / nq;
+    double v[ncart(LP)][ncart(LQ)][1];
+    aux_pair<LP, LQ, false>(S, sp, sq, boys, v);
+#pragma unroll
+    for (int i = 0; i < ncart(LP); ++i)
+#pragma unroll
+        for (int j = 0; j < ncart(LQ); ++j) M[(size_t)(S.off[sp] + i) * n + S.off[sq] + j] = v[i][j][0];
+}
+
+// partial2[sp][LQ][o][3] = sum_{Q shells of class LQ} (W_PQ + W_QP) d(P|Q)/dP
+template <int LP, int LQ>
+__global__ __launch_bounds__(64) void k_int2c_deriv(ShellTab S, int n, int p0, int np, int q0, int nq,
+                                                    const double *__restrict__ boys, int nout,
+                                                    const double *__restrict__ W, double *__restrict__ part)
+{
+    const int sp = p0 + blockIdx.x;
+    if (blockIdx.x >= np) return;
+    const int lane = threadIdx.x;
+    const int o = blockIdx.y;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const double *Wo = W + (size_t)o * n * n;
+    for (int iq = lane; iq < nq; iq += 64) {
+        const int sq = q0 + iq;
+        double v[ncart(LP)][ncart(LQ)][3];
+        aux_pair<LP, LQ, true>(S, sp, sq, boys, v);
+#pragma unroll
+        for (int i = 0; i < ncart(LP); ++i)
+#pragma unroll
+            for (int j = 0; j < ncart(LQ); ++j) {
+                const int P = S.off[sp] + i, Q = S.off[sq] + j;
+                const double w = Wo[(size_t)P * n + Q] + Wo[(size_t)Q * n + P];
+                acc[0] += w * v[i][j][0];
+                acc[1] += w * v[i][j][1];
+                acc[2] += w * v[i][j][2];
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double v = acc[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[k] = v;
+    }
+    if (lane == 0) {
+        double *dst = part + (((size_t)sp * (kMaxAuxL + 1) + LQ) * nout + o) * 3;
+        dst[0] = acc[0];
+        dst[1] = acc[1];
+        dst[2] = acc[2];
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ hosts --
+hipError_t launch_int2c(const AuxGeom &aux, const double *boys, double *M, hipStream_t st)
+{
+    // auxiliary shells: s shells first, then p shells (contiguous classes)
+    int ns = 0;
+    // count s shells: offsets equal shell index for the leading s block
+    // (the host passes classes through AuxGeom.nshell and nfunc)
+    ns = 3 * aux.nshell - aux.nfunc;  // nfunc = ns + 3 (nshell - ns)
+    ns /= 2;
+    const int np = aux.nshell - ns;
+    const int n = aux.nfunc;
+    auto go = [&](auto kern, int p0, int npp, int q0, int nqq) {
+        if (npp == 0 || nqq == 0) return;
+        const int tot = npp * nqq;
+        hipLaunchKernelGGL(kern, dim3((tot + 127) / 128), dim3(128), 0, st, aux.sh, n, p0, npp, q0, nqq, boys, M);
+    };
+    go(k_int2c<0, 0>, 0, ns, 0, ns);
+    go(k_int2c<0, 1>, 0, ns, ns, np);
+    go(k_int2c<1, 0>, ns, np, 0, ns);
+    go(k_int2c<1, 1>, ns, np, ns, np);
+    return hipGetLastError();
+}
+
+hipError_t launch_int2c_deriv(const AuxGeom &aux, const double *boys, int nout, const double *W,
+                              double *part, hipStream_t st)
+{
+    const int ns = (3 * aux.nshell - aux.nfunc) / 2;
+    const int np = aux.nshell - ns;
+    const int n = aux.nfunc;
+    auto go = [&](auto kern, int p0, int npp, int q0, int nqq) {
+        if (npp == 0 || nqq == 0) return;
+        hipLaunchKernelGGL(kern, dim3(npp, nout), dim3(64), 0, st, aux.sh, n, p0, npp, q0, nqq, boys, nout, W, part);
+    };
+    go(k_int2c_deriv<0, 0>, 0, ns, 0, ns);
+    go(k_int2c_deriv<0, 1>, 0, ns, ns, np);
+    go(k_int2c_deriv<1, 0>, ns, np, 0, ns);
+    go(k_int2c_deriv<1, 1>, ns, np, ns, np);
+    return hipGetLastError();
+}
+
+namespace {
+template <int LA, int LB, int LC>
+void int3c_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, const double *boys, double *X,
+               hipStream_t st)
+{
+    const int a0 = ao.lbeg[LA], na = ao.lbeg[LA + 1] - a0;
+    const int b0 = ao.lbeg[LB], nb = ao.lbeg[LB + 1] - b0;
+    const int c0 = auxl_beg[LC], nc = auxl_beg[LC + 1] - c0;
+    const long tot = (long)na * nb * nc;
+    if (tot == 0) return;
+    hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, st, ao.sh,
+                       ao.nao, a0, na, b0, nb, aux.sh, c0, nc, boys, X);
+}
+
+template <int LA, int LB, int LC>
+void deriv_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, const double *boys,
+               const DerivJob &job, hipStream_t st)
+{
+    const int a0 = ao.lbeg[LA], na = ao.lbeg[LA + 1] - a0;
+    const int b0 = ao.lbeg[LB], nb = ao.lbeg[LB + 1] - b0;
+    const int c0 = auxl_beg[LC], nc = auxl_beg[LC + 1] - c0;
+    if (na == 0 || nb == 0 || nc == 0) return;
+    hipLaunchKernelGGL((k_int3c_deriv<LA, LB, LC, kMaxOutChunk>), dim3(na * nc), dim3(64), 0, st, ao.sh, ao.nao,
+                       a0, na, b0, nb, aux.sh, c0, nc, aux.nshell, boys, job);
+}
+}  // namespace
+
+hipError_t launch_int3c(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2], const double *boys,
+                        double *X, hipStream_t st)
+{
+    int3c_one<0, 0, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<0, 1, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<0, 2, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<1, 0, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<1, 1, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<1, 2, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<2, 0, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<2, 1, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<2, 2, 0>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<0, 0, 1>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<0, 1, 1>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<0, 2, 1>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<1, 0, 1>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<1, 1, 1>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<1, 2, 1>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<2, 0, 1>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<2, 1, 1>(ao, aux, auxl_beg, boys, X, st);
+    int3c_one<2, 2, 1>(ao, aux, auxl_beg, boys, X, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],
+                              const double *boys, const DerivJob &job, hipStream_t st)
+{
+    deriv_one<0, 0, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<0, 1, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<0, 2, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<1, 0, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<1, 1, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<1, 2, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<2, 0, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<2, 1, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<2, 2, 0>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<0, 0, 1>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<0, 1, 1>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<0, 2, 1>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<1, 0, 1>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<1, 1, 1>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<1, 2, 1>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<2, 0, 1>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<2, 1, 1>(ao, aux, auxl_beg, boys, job, st);
+    deriv_one<2, 2, 1>(ao, aux, auxl_beg, boys, job, st);
+    return hipGetLastError();
+}
+
+}  // namespace ris

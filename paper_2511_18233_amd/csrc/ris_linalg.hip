@@ -1,0 +1,370 @@
+// Small dense linear algebra and elementwise kernels for the ris path (FP64).
+//
+// The auxiliary metric M = (P|Q) is factored as M = L L^T (blocked
+// right-looking Cholesky: 64-wide diagonal blocks factored in LDS, panel
+// triangular solve, trailing update on the matrix-core GEMM), then
+// M^-1 = L^-T L^-1 is formed from the triangular inverse (Sec. 2.2 uses M^-1
+// in the RI kernel and -M^-1 M^x M^-1 in its derivative).
+#include "ris_common.hpp"
+#include "ris_linalg.hpp"
+
+namespace ris {
+namespace {
+
+constexpr int NB = 64;
+
+// Factor the NB x NB (or smaller) diagonal block at (k0, k0) in LDS.
+// A pivot below 1e-13 of the original diagonal entry (Morig) counts as a
+// failure: the metric is then numerically singular.
+__global__ __launch_bounds__(256) void k_potrf_diag(double *A, const double *Morig, int n, int k0, int b, int *info)
+{
+    __shared__ double T[NB][NB + 1];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < b * b; idx += blockDim.x) {
+        const int i = idx / b, j = idx % b;
+        T[i][j] = A[(size_t)(k0 + i) * n + k0 + j];
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int k = 0; k < b; ++k) {
+        if (tid == 0) {
+            const double d = T[k][k];
+            const double ref = Morig ? Morig[(size_t)(k0 + k) * n + k0 + k] : 0.0;
+            if (!(d > 1e-13 * ref) || !(d > 0.0)) {
+                bad = k0 + k + 1;
+            } else {
+                T[k][k] = sqrt(d);
+            }
+        }
+        __syncthreads();
+        if (bad) break;
+        const double dk = T[k][k];
+        for (int i = k + 1 + tid; i < b; i += blockDim.x) T[i][k] /= dk;
+        __syncthreads();
+        const int m = b - k - 1;
+        for (int idx = tid; idx < m * m; idx += blockDim.x) {
+            const int i = k + 1 + idx / m, j = k + 1 + idx % m;
+            if (j <= i) T[i][j] -= T[i][k] * T[j][k];
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (tid == 0 && *info == 0) *info = bad;
+        return;
+    }
+    for (int idx = tid; idx < b * b; idx += blockDim.x) {
+        const int i = idx / b, j = idx % b;
+        A[(size_t)(k0 + i) * n + k0 + j] = (j <= i) ? T[i][j] : 0.0;
+    }
+}
+
+// Panel: rows r >= k0+b of columns k0..k0+b-1 become A_r L_kk^{-T}
+// (forward substitution per row with the factored diagonal block in LDS).
+__global__ __launch_bounds__(64) void k_trsm_panel(double *A, int n, int k0, int b, const int *info)
+{
+    __shared__ double Lk[NB][NB + 1];
+    if (*info) return;
+    for (int idx = threadIdx.x; idx < b * b; idx += blockDim.x) {
+        const int i = idx / b, j = idx % b;
+        Lk[i][j] = A[(size_t)(k0 + i) * n + k0 + j];
+    }
+    __syncthreads();
+    const int r = k0 + b + blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double *row = A + (size_t)r * n + k0;
+    for (int j = 0; j < b; ++j) {
+        double s = row[j];
+        for (int l = 0; l < j; ++l) s -= row[l] * Lk[j][l];
+        row[j] = s / Lk[j][j];
+    }
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+__global__ void k_zero_upper(double *A, int n)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    if (j > i) A[idx] = 0.0;
+}
+
+// column j of L^-1 by forward substitution (one thread per column)
+__global__ void k_tri_inverse(const double *__restrict__ L, double *__restrict__ X, int n)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int i = 0; i < j; ++i) X[(size_t)i * n + j] = 0.0;
+    X[(size_t)j * n + j] = 1.0 / L[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+        double s = 0.0;
+        for (int k = j; k < i; ++k) s += L[(size_t)i * n + k] * X[(size_t)k * n + j];
+        X[(size_t)i * n + j] = -s / L[(size_t)i * n + i];
+    }
+}
+
+__global__ void k_fill(double *p, size_t n, double v)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// dst[i][:] = src[perm[i]][:]   (rows of length ncol)
+__global__ void k_gather_rows(const double *__restrict__ src, double *__restrict__ dst, const int *__restrict__ perm,
+                              int nrow, int ncol, int ld_src)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nrow * ncol) return;
+    const int i = (int)(idx / ncol), c = (int)(idx % ncol);
+    dst[idx] = src[(size_t)perm[i] * ld_src + c];
+}
+
+// out[b][perm[i]][perm[j]] = in[b][i][j]
+__global__ void k_scatter_sq(const double *__restrict__ in, double *__restrict__ out, const int *__restrict__ perm,
+                             int n, int nb)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long nn = (long)n * n;
+    if (idx >= nn * nb) return;
+    const long b = idx / nn, r = idx % nn;
+    const int i = (int)(r / n), j = (int)(r % n);
+    out[b * nn + (long)perm[i] * n + perm[j]] = in[idx];
+}
+
+// R = X + s Y, L = X - s Y  (s = 0 when Y is absent)
+__global__ void k_rl(const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ R,
+                     double *__restrict__ L, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = X[i], y = Y ? Y[i] : 0.0;
+    R[i] = x + y;
+    L[i] = x - y;
+}
+
+// in-place symmetrisation of nb square matrices: A = (A + A^T)/2
+__global__ void k_symmetrize(double *A, int n, int nb)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long nn = (long)n * n;
+    if (idx >= nn * nb) return;
+    const long b = idx / nn, r = idx % nn;
+    const int i = (int)(r / n), j = (int)(r % n);
+    if (j <= i) return;
+    double *M = A + b * nn;
+    const double v = 0.5 * (M[(size_t)i * n + j] + M[(size_t)j * n + i]);
+    M[(size_t)i * n + j] = v;
+    M[(size_t)j * n + i] = v;
+}
+
+// out[k][a][i] += s_de * (eps[nocc+a] - eps[i]) * V[k][a][i]
+__global__ void k_add_de(const double *__restrict__ eps, const double *__restrict__ V, double *__restrict__ out,
+                         int nvir, int nocc, int nvec, double s_de)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per = (long)nvir * nocc;
+    if (idx >= per * nvec) return;
+    const long r = idx % per;
+    const int a = (int)(r / nocc), i = (int)(r % nocc);
+    out[idx] += s_de * (eps[nocc + a] - eps[i]) * V[idx];
+}
+
+// dst = alpha * src (+ dst if accumulate)
+__global__ void k_axpby(const double *__restrict__ src, double *__restrict__ dst, size_t n, double alpha, double beta)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = alpha * src[i] + (beta == 0.0 ? 0.0 : beta * dst[i]);
+}
+
+// Exchange weight blocks of one output (3o x 3o per K function P):
+//   rows/cols ordered [U_R (o), U_L (o), C_O (o)];
+//   W[UR,UR] = H_OO/4   W[UR,O] =  HR_OU/4
+//   W[UL,UL] = H_OO/4   W[UL,O] = -HL_OU/4
+//   W[O,UR]  = HR_UO/4  W[O,UL] = -HL_UO/4   W[O,O] = (HR_UU + HL_UU)/4
+// (from D1 C^P D2^T with D = (U C_O^T + s C_O U^T)/2, s = +1 for R^S and -1
+// for L^A), scaled by `scale`.
+__global__ void k_assemble_w(const double *__restrict__ Hoo, const double *__restrict__ HRou,
+                             const double *__restrict__ HLou, const double *__restrict__ HRuo,
+                             const double *__restrict__ HLuo, const double *__restrict__ HRuu,
+                             const double *__restrict__ HLuu, double *__restrict__ W, int o, int nP, double scale)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long oo = (long)o * o;
+    const int n3 = 3 * o;
+    if (idx >= (long)n3 * n3 * nP) return;
+    const long P = idx / ((long)n3 * n3);
+    const long r = idx % ((long)n3 * n3);
+    const int row = (int)(r / n3), col = (int)(r % n3);
+    const int bi = row / o, bj = col / o, i = row % o, j = col % o;
+    const long e = P * oo + (long)i * o + j;
+    double v = 0.0;
+    if (bi == 0 && bj == 0) v = Hoo[e];
+    else if (bi == 1 && bj == 1) v = Hoo[e];
+    else if (bi == 0 && bj == 2) v = HRou[e];
+    else if (bi == 1 && bj == 2) v = -HLou[e];
+    else if (bi == 2 && bj == 0) v = HRuo[e];
+    else if (bi == 2 && bj == 1) v = -HLuo[e];
+    else if (bi == 2 && bj == 2) v = HRuu[e] + HLuu[e];
+    W[idx] = 0.25 * scale * v;
+}
+
+// Reduce the triplet partials into per-shell sums (fixed order).
+// p3: [nshAO][nshAux][3][NO][6]; shA[sa][o][3] = sum_{sc, lb} dA; shC[sc][o][3] = sum_{sa, lb} dC
+__global__ void k_reduce_p3_a(const double *__restrict__ p3, int nshAO, int nshAux, int nout, int NO,
+                              double *__restrict__ shA)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nshAO * nout * 3) return;
+    const int sa = idx / (nout * 3), o = (idx / 3) % nout, d = idx % 3;
+    double s = 0.0;
+    for (int sc = 0; sc < nshAux; ++sc)
+        for (int lb = 0; lb < 3; ++lb) s += p3[((((size_t)sa * nshAux + sc) * 3 + lb) * NO + o) * 6 + d];
+    shA[idx] = s;
+}
+__global__ void k_reduce_p3_c(const double *__restrict__ p3, int nshAO, int nshAux, int nout, int NO,
+                              double *__restrict__ shC)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nshAux * nout * 3) return;
+    const int sc = idx / (nout * 3), o = (idx / 3) % nout, d = idx % 3;
+    double s = 0.0;
+    for (int sa = 0; sa < nshAO; ++sa)
+        for (int lb = 0; lb < 3; ++lb) s += p3[((((size_t)sa * nshAux + sc) * 3 + lb) * NO + o) * 6 + 3 + d];
+    shC[idx] = s;
+}
+// p2: [nshAux][2][nout][3] -> shP[sp][o][3]
+__global__ void k_reduce_p2(const double *__restrict__ p2, int nshAux, int nout, double *__restrict__ shP)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nshAux * nout * 3) return;
+    const int sp = idx / (nout * 3), o = (idx / 3) % nout, d = idx % 3;
+    shP[idx] = p2[(((size_t)sp * 2 + 0) * nout + o) * 3 + d] + p2[(((size_t)sp * 2 + 1) * nout + o) * 3 + d];
+}
+// grad[o0 + o][X][d] (+)= sum over shells on atom X of the per-shell sums
+__global__ void k_atoms(const double *__restrict__ shA, const int *__restrict__ atomA, int nshA,
+                        const double *__restrict__ shC, const int *__restrict__ atomC, int nshC,
+                        const double *__restrict__ shP, int natm, int nout, double scale, int accumulate,
+                        double *__restrict__ grad)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= natm * nout * 3) return;
+    const int o = idx / (natm * 3), X = (idx / 3) % natm, d = idx % 3;
+    double s = 0.0;
+    for (int sa = 0; sa < nshA; ++sa)
+        if (atomA[sa] == X) s += shA[((size_t)sa * nout + o) * 3 + d];
+    for (int sc = 0; sc < nshC; ++sc)
+        if (atomC[sc] == X) s += shC[((size_t)sc * nout + o) * 3 + d] + (shP ? shP[((size_t)sc * nout + o) * 3 + d] : 0.0);
+    grad[idx] = (accumulate ? grad[idx] : 0.0) + scale * s;
+}
+
+inline unsigned nblk(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t cholesky(double *A, const double *Morig, int n, int *info, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, info, 0);
+    hipError_t e = hipSuccess;
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int b = (n - k0 < NB) ? n - k0 : NB;
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, A, Morig, n, k0, b, info);
+        const int rest = n - k0 - b;
+        if (rest > 0) {
+            hipLaunchKernelGGL(k_trsm_panel, dim3(nblk(rest, 64)), dim3(64), 0, st, A, n, k0, b, info);
+            GemmArgs g{};
+            g.M = rest; g.N = rest; g.K = b;
+            g.transA = false; g.transB = true;
+            g.alpha = -1.0; g.beta = 1.0;
+            g.A = A + (size_t)(k0 + b) * n + k0; g.lda = n;
+            g.B = A + (size_t)(k0 + b) * n + k0; g.ldb = n;
+            g.C = A + (size_t)(k0 + b) * n + k0 + b; g.ldc = n;
+            g.batch = 1; g.nred = 1;
+            e = dgemm(g, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    hipLaunchKernelGGL(k_zero_upper, dim3(nblk((size_t)n * n, 256)), dim3(256), 0, st, A, n);
+    return hipGetLastError();
+}
+
+hipError_t tri_inverse(const double *L, double *Linv, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tri_inverse, dim3(nblk(n, 64)), dim3(64), 0, st, L, Linv, n);
+    return hipGetLastError();
+}
+
+hipError_t fill(double *p, size_t n, double v, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t gather_rows(const double *src, double *dst, const int *perm, int nrow, int ncol, int ld_src, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_rows, dim3(nblk((size_t)nrow * ncol, 256)), dim3(256), 0, st, src, dst, perm, nrow,
+                       ncol, ld_src);
+    return hipGetLastError();
+}
+
+hipError_t scatter_sq(const double *in, double *out, const int *perm, int n, int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter_sq, dim3(nblk((size_t)n * n * nb, 256)), dim3(256), 0, st, in, out, perm, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t make_rl(const double *X, const double *Y, double *R, double *L, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rl, dim3(nblk(n, 256)), dim3(256), 0, st, X, Y, R, L, n);
+    return hipGetLastError();
+}
+
+hipError_t symmetrize(double *A, int n, int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_symmetrize, dim3(nblk((size_t)n * n * nb, 256)), dim3(256), 0, st, A, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t add_de(const double *eps, const double *V, double *out, int nvir, int nocc, int nvec, double s,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_add_de, dim3(nblk((size_t)nvir * nocc * nvec, 256)), dim3(256), 0, st, eps, V, out, nvir,
+                       nocc, nvec, s);
+    return hipGetLastError();
+}
+
+hipError_t axpby(const double *src, double *dst, size_t n, double alpha, double beta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, st, src, dst, n, alpha, beta);
+    return hipGetLastError();
+}
+
+hipError_t assemble_w(const double *Hoo, const double *HRou, const double *HLou, const double *HRuo,
+                      const double *HLuo, const double *HRuu, const double *HLuu, double *W, int o, int nP,
+                      double scale, hipStream_t st)
+{
+    const size_t n = (size_t)9 * o * o * nP;
+    hipLaunchKernelGGL(k_assemble_w, dim3(nblk(n, 256)), dim3(256), 0, st, Hoo, HRou, HLou, HRuo, HLuo, HRuu, HLuu,
+                       W, o, nP, scale);
+    return hipGetLastError();
+}
+
+hipError_t reduce_grad(const double *p3, int nshAO, int nshAux, int nout, int NO, const double *p2,
+                       const int *atomAO, const int *atomAux, int natm, double *shA, double *shC, double *shP,
+                       double scale, int accumulate, double *grad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_p3_a, dim3(nblk((size_t)nshAO * nout * 3, 64)), dim3(64), 0, st, p3, nshAO, nshAux,
+                       nout, NO, shA);
+    hipLaunchKernelGGL(k_reduce_p3_c, dim3(nblk((size_t)nshAux * nout * 3, 64)), dim3(64), 0, st, p3, nshAO,
+                       nshAux, nout, NO, shC);
+    if (p2)
+        hipLaunchKernelGGL(k_reduce_p2, dim3(nblk((size_t)nshAux * nout * 3, 64)), dim3(64), 0, st, p2, nshAux,
+                           nout, shP);
+    hipLaunchKernelGGL(k_atoms, dim3(nblk((size_t)natm * nout * 3, 64)), dim3(64), 0, st, shA, atomAO, nshAO, shC,
+                       atomAux, nshAux, p2 ? shP : nullptr, natm, nout, scale, accumulate, grad);
+    return hipGetLastError();
+}
+
+}  // namespace ris

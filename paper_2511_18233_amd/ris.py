@@ -1,0 +1,237 @@
+"""ctypes binding of libris_hip.so (the C ABI in include/ris.h).
+
+Argument marshalling only: every step of the path runs in the library's gfx950
+kernels.  Large arrays are torch CUDA (HIP) tensors whose device pointers are
+handed to the library; the context enqueues on torch's current stream of the
+tensors' device.  There is no fallback: without the built library or without a
+GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libris_hip.so")
+
+RIS_OK = 0
+STATUS = {0: "RIS_OK", 1: "RIS_E_INVALID", 2: "RIS_E_UNSUPPORTED", 3: "RIS_E_NOMEM", 4: "RIS_E_NOT_PD",
+          5: "RIS_E_DEGENERATE", 6: "RIS_E_ORDER", 7: "RIS_E_DEVICE"}
+OPS = {"A": 0, "B": 1, "A+B": 2, "A-B": 3}
+EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
+           "ris_response_matvec", "ris_grad_contract", "ris_nac_contract",
+           # test-only building blocks (include/ris_test.h)
+           "ris_test_mfma_probe", "ris_test_dgemm")
+
+
+class RisError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Mol(ctypes.Structure):
+    _fields_ = [("natm", ctypes.c_int), ("Z", ctypes.POINTER(ctypes.c_int)),
+                ("xyz", ctypes.POINTER(ctypes.c_double)), ("nshell", ctypes.c_int),
+                ("shell_atom", ctypes.POINTER(ctypes.c_int)), ("shell_l", ctypes.POINTER(ctypes.c_int)),
+                ("shell_exp", ctypes.POINTER(ctypes.c_double))]
+
+
+class _AuxOpts(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("radius_bohr", ctypes.POINTER(ctypes.c_double)),
+                ("j_p_on_heavy", ctypes.c_int)]
+
+
+class _MO(ctypes.Structure):
+    _fields_ = [("nao", ctypes.c_int), ("nmo", ctypes.c_int), ("nocc", ctypes.c_int),
+                ("C", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("alpha_J", ctypes.c_double),
+                ("c_x", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libris_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2511_18233_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    lib.ris_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_size_t]
+    lib.ris_ctx_destroy.argtypes = [vp]
+    lib.ris_ctx_destroy.restype = None
+    lib.ris_last_error.argtypes = [vp]
+    lib.ris_last_error.restype = ctypes.c_char_p
+    lib.ris_ctx_bytes.argtypes = [vp]
+    lib.ris_ctx_bytes.restype = ctypes.c_size_t
+    lib.ris_aux_build.argtypes = [vp, ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ip, ip]
+    lib.ris_int3c.argtypes = [vp, ctypes.POINTER(_MO), vp]
+    lib.ris_response_matvec.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.ris_grad_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp]
+    lib.ris_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, dp, vp]
+    lib.ris_test_mfma_probe.argtypes = [vp, vp, vp]
+    L = ctypes.c_long
+    lib.ris_test_dgemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_double, vp, L, L, vp, L, L, ctypes.c_double, vp, L, L, ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_dev(t, dev, name):
+    import torch
+    if t is None:
+        return
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 tensor on the GPU")
+    if t.device != dev:
+        raise ValueError(f"{name} is on {t.device}, context on {dev}")
+
+
+class RisContext:
+    """One library context on one GPU (torch device), enqueueing on a stream."""
+
+    def __init__(self, device=0, stream=None, hbm_budget: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the ris library runs on MI355X only")
+        self.lib = load_library()
+        self.device = torch.device("cuda", device if isinstance(device, int) else torch.device(device).index or 0)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.ris_ctx_create(ctypes.byref(h), self.device.index, ctypes.c_void_p(stream.cuda_stream),
+                                     ctypes.c_size_t(hbm_budget))
+        if st != RIS_OK:
+            raise RisError(st, "ris_ctx_create failed")
+        self.h = h
+        self.natm = 0
+        self.nJ = self.nK = 0
+        self.nocc = self.nvir = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ris_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != RIS_OK:
+            raise RisError(st, self.lib.ris_last_error(self.h).decode())
+
+    @property
+    def bytes_held(self) -> int:
+        return int(self.lib.ris_ctx_bytes(self.h))
+
+    # -- entry points -----------------------------------------------------
+    def aux_build(self, Z, xyz, shell_atom, shell_l, shell_exp, radius_bohr, theta=0.2, j_p_on_heavy=True):
+        Z = np.ascontiguousarray(Z, dtype=np.int32)
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        sa = np.ascontiguousarray(shell_atom, dtype=np.int32)
+        sl = np.ascontiguousarray(shell_l, dtype=np.int32)
+        se = np.ascontiguousarray(shell_exp, dtype=np.float64)
+        rad = np.ascontiguousarray(radius_bohr, dtype=np.float64)
+        ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+        mol = _Mol(Z.shape[0], Z.ctypes.data_as(ip), xyz.ctypes.data_as(dp), sl.shape[0], sa.ctypes.data_as(ip),
+                   sl.ctypes.data_as(ip), se.ctypes.data_as(dp))
+        opts = _AuxOpts(float(theta), rad.ctypes.data_as(dp), int(bool(j_p_on_heavy)))
+        nJ, nK = ctypes.c_int(), ctypes.c_int()
+        self._chk(self.lib.ris_aux_build(self.h, ctypes.byref(mol), ctypes.byref(opts), ctypes.byref(nJ),
+                                         ctypes.byref(nK)))
+        self.natm = int(Z.shape[0])
+        self.nao = int(sum((l + 1) * (l + 2) // 2 for l in sl))
+        self.nJ, self.nK = nJ.value, nK.value
+        return self.nJ, self.nK
+
+    def int3c(self, C, eps, nocc, alpha_J=2.0, c_x=0.25, precision=0, dbg=None):
+        _check_dev(C, self.device, "C")
+        _check_dev(eps, self.device, "eps")
+        _check_dev(dbg, self.device, "dbg")
+        nao, nmo = C.shape
+        mo = _MO(nao, nmo, int(nocc), C.data_ptr(), eps.data_ptr(), float(alpha_J), float(c_x), int(precision))
+        self._chk(self.lib.ris_int3c(self.h, ctypes.byref(mo), _ptr(dbg)))
+        self.nocc, self.nvir = int(nocc), int(nmo - nocc)
+
+    def response_matvec(self, op, V, out=None):
+        import torch
+        _check_dev(V, self.device, "V")
+        if out is None:
+            out = torch.empty_like(V)
+        _check_dev(out, self.device, "out")
+        nvec = V.shape[0] if V.dim() == 3 else 1
+        self._chk(self.lib.ris_response_matvec(self.h, OPS[op] if isinstance(op, str) else int(op), nvec, _ptr(V),
+                                               _ptr(out)))
+        return out
+
+    def grad_contract(self, X, Y, sel, out=None):
+        import torch
+        _check_dev(X, self.device, "X")
+        _check_dev(Y, self.device, "Y")
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+        if out is None:
+            out = torch.empty((sel.size, self.natm, 3), dtype=torch.float64, device=self.device)
+        _check_dev(out, self.device, "grad")
+        self._chk(self.lib.ris_grad_contract(self.h, X.shape[0], _ptr(X), _ptr(Y), sel.size,
+                                             sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(out)))
+        return out
+
+    def nac_contract(self, X, Y, pairs, omega=None, out=None, allow_degenerate=False):
+        import torch
+        _check_dev(X, self.device, "X")
+        _check_dev(Y, self.device, "Y")
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        if out is None:
+            out = torch.empty((pairs.shape[0], self.natm, 3), dtype=torch.float64, device=self.device)
+        _check_dev(out, self.device, "nac")
+        om = None
+        if omega is not None:
+            om = np.ascontiguousarray(omega, dtype=np.float64)
+        st = self.lib.ris_nac_contract(self.h, X.shape[0], _ptr(X), _ptr(Y), pairs.shape[0],
+                                       pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                       om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if om is not None else None,
+                                       _ptr(out))
+        if st == 5 and allow_degenerate:
+            return out
+        self._chk(st)
+        return out
+
+
+def solve_problem(ctx: RisContext, prob, radius_bohr, outputs, theta=0.2, j_p_on_heavy=True, alpha_J=2.0,
+                  c_x=0.25, dbg=False):
+    """Convenience driver for a molgen.Problem: aux_build -> int3c -> grad/nac.
+    outputs: list of (I, J); I == J are gradients, I != J NAC numerators.
+    Returns a torch tensor [nout][natm][3] on the device."""
+    import torch
+    dev = ctx.device
+    m = prob.mol
+    ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radius_bohr, theta, j_p_on_heavy)
+    C = torch.as_tensor(prob.C, device=dev).contiguous()
+    eps = torch.as_tensor(prob.eps, device=dev).contiguous()
+    X = torch.as_tensor(prob.X, device=dev).contiguous()
+    Y = None if prob.Y is None else torch.as_tensor(prob.Y, device=dev).contiguous()
+    dbg_t = torch.empty((ctx.nJ, m.nao, m.nao), dtype=torch.float64, device=dev) if dbg else None
+    ctx.int3c(C, eps, prob.nocc, alpha_J, c_x, dbg=dbg_t)
+    out = torch.empty((len(outputs), m.natm, 3), dtype=torch.float64, device=dev)
+    grads = [k for k, (I, J) in enumerate(outputs) if I == J]
+    nacs = [k for k, (I, J) in enumerate(outputs) if I != J]
+    if grads:
+        g = ctx.grad_contract(X, Y, [outputs[k][0] for k in grads])
+        out[grads] = g
+    if nacs:
+        n = ctx.nac_contract(X, Y, [outputs[k] for k in nacs])
+        out[nacs] = n
+    return (out, dbg_t) if dbg else out
