@@ -1,0 +1,198 @@
+"""Benchmark: TDDFT-ris excited-state gradients + NAC numerators per second.
+
+One step = the whole hot path on one seeded molecule, inputs resident in HBM:
+ris_aux_build (aux basis, metric, Cholesky, inverse) -> ris_int3c ((mu nu|P)
+and MO blocks) -> ris_response_matvec ((A+B) R_I and (A-B) L_I for every
+state) -> ris_grad_nac_contract (gradients of every state and NAC numerators of
+adjacent pairs, one call).
+Default workload: 200-atom C/N/O chain (seed 2), 10 TDDFT states, 10 gradients
++ 9 NAC numerators per step, FP64.
+
+    python bench.py [--steps K] [--warmup W] [--workload chain200|chain60|ring12]
+                    [--no-cpu-baseline]
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "excited-state grads+NACs/s at 200 atoms; p50/p99 latency; vs plain FP64"
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import molgen
+    prob = molgen.make_problem(name)
+    jp = name != "ring12"
+    ns = prob.nstate
+    outs = [(i, i) for i in range(ns)] + [(i, i + 1) for i in range(ns - 1)]
+    return prob, jp, outs
+
+
+def oracle_sample(prob, jp, outs, radii):
+    """Time the CPU oracle on bounded samples of the same workload and scale
+    each stage linearly to one full step (documented in the design doc)."""
+    from oracle import ris_oracle as O
+    import threadpoolctl  # noqa: F401  (BLAS threads stay at the default: all cores)
+    mol = prob.mol
+    ao = O.ao_shells(mol)
+    aux = O.aux_build(mol, radii, 0.2, jp)
+    nJs, nKs = aux.J.n, aux.K.n
+    nJ, nK = aux.J.nfunc, aux.K.nfunc
+    # (1) three-centre integrals on 2 s + 1 p auxiliary shells
+    pick = [0, 1] + ([nKs] if nJs > nKs else [])
+    sub = O.Shells(aux.J.xyz[pick], aux.J.l[pick], aux.J.exp[pick], aux.J.atom[pick])
+    t = time.perf_counter()
+    t3 = O.int3c(ao, sub)
+    t_int = time.perf_counter() - t
+    nf = sub.nfunc
+    full_int = t_int * (nJ + nK) / nf
+    # (2) exchange weights (Gamma^P, V) for 2 K functions of one output pair
+    RS, LA = O.ao_densities(prob.C, prob.nocc, prob.X[:2], None if prob.Y is None else prob.Y[:2])
+    Ssub = O.Setup(ao, aux, t3[:1], t3[:2], O.int2c(sub)[:1, :1], O.int2c(sub)[:2, :2])
+    t = time.perf_counter()
+    O.pair_weights(Ssub, RS[0], RS[1], False, 2.0, 0.25)
+    t_pw = time.perf_counter() - t
+    full_pw = t_pw * nK / 2 * 2 * len(outs)          # per K function, two pairs per output
+    # (3) derivative contraction over the sampled aux shells, one output
+    W = np.random.default_rng(0).standard_normal((1, nf, mol.nao, mol.nao))
+    t = time.perf_counter()
+    O.int3c_grad(ao, sub, mol.natm, W)
+    t_dr = time.perf_counter() - t
+    full_dr = t_dr * (nJ + nK) / nf * len(outs)     # the oracle contracts one output per pass here
+    total = full_int + full_pw + full_dr
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": len(outs) / total, "unit": "grads+NACs/s", "cores": nthreads, "kind": "oracle",
+        "sample": (f"{mol.natm}-atom workload: int3c on {nf} of {nJ}+{nK} aux functions ({t_int:.1f} s), "
+                   f"exchange weights for 2 of {nK} K functions x 1 pair ({t_pw:.1f} s), derivative "
+                   f"contraction on {nf} aux functions x 1 output ({t_dr:.1f} s); each scaled linearly to "
+                   f"{len(outs)} outputs: est. {total:.0f} s per step"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chain200")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              f"design-only for this path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import molgen
+    from paper_2511_18233_amd import RisContext
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    dev = torch.device("cuda", 0)
+    radii = molgen.radii_bohr_table()
+    log(f"[bench] building workload {args.workload}")
+    prob, jp, outs = make_workload(args.workload)
+    m = prob.mol
+    ns = prob.nstate
+    grads = [i for (i, j) in outs if i == j]
+    pairs = [(i, j) for (i, j) in outs if i != j]
+    C = torch.as_tensor(prob.C, device=dev).contiguous()
+    eps = torch.as_tensor(prob.eps, device=dev).contiguous()
+    X = torch.as_tensor(prob.X, device=dev).contiguous()
+    Y = None if prob.Y is None else torch.as_tensor(prob.Y, device=dev).contiguous()
+    R = (X + Y) if Y is not None else X.clone()
+    L = (X - Y) if Y is not None else X.clone()
+    g_out = torch.empty((len(grads), m.natm, 3), dtype=torch.float64, device=dev)
+    n_out = torch.empty((len(pairs), m.natm, 3), dtype=torch.float64, device=dev)
+    mv_out = torch.empty_like(R)
+    torch.cuda.synchronize()
+    ctx = RisContext(0)
+
+    def step():
+        ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+        ctx.int3c(C, eps, prob.nocc, 2.0, 0.25)
+        ctx.response_matvec("A+B", R, mv_out)
+        ctx.response_matvec("A-B", L, mv_out)
+        ctx.grad_nac_contract(X, Y, grads, pairs, None, g_out, n_out)
+
+    log(f"[bench] natm={m.natm} nao={m.nao} nocc={prob.nocc} states={ns} outputs/step={len(outs)}")
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w}: {time.perf_counter() - t:.3f} s")
+    ctx.set_profiling(True)
+    times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        log(f"[bench] step {k}: {times[-1]:.3f} s")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    stats = ctx.stage_stats()
+    ctx.set_profiling(False)
+
+    per_stage = {}
+    for name, (ms, fl, by, n) in stats.items():
+        per_stage[name] = {"ms_per_step": ms / args.steps, "launches": n,
+                           "tflops": (fl / (ms * 1e-3) / 1e12) if ms > 0 and fl > 0 else None,
+                           "gbs": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None}
+        log(f"[bench] stage {name:7s} {ms / args.steps:10.2f} ms/step  launches={n}"
+            + (f"  {fl / (ms * 1e-3) / 1e12:7.2f} TFLOP/s" if ms > 0 and fl > 0 else ""))
+    # dominant matrix-core kernel: the AO back-transform GEMM of the exchange weights
+    gms, gfl, gby, gn = stats["gamma"]
+    roof = None
+    if gn > 0 and gms > 0:
+        ach = gfl / gn / (gms * 1e-3 / gn) / 1e12
+        roof = {"bound": "mfma", "kernel": "k_dgemm<false,true> (Gamma^P = (F_I W^P) F_J^T, batched over P)",
+                "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": gfl / gn, "avg_launch_ms": gms / gn}
+
+    value = len(outs) * args.steps / total
+    tsorted = np.sort(np.array(times))
+    res = {
+        "metric": METRIC, "value": round(value, 4), "unit": "grads+NACs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * total / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: seeded C/N/O chain, {m.natm} atoms, nao={m.nao}, "
+                               f"nocc={prob.nocc}, nauxJ={ctx.nJ}, nauxK={ctx.nK}, {ns} TDDFT states, "
+                               f"{len(grads)} gradients + {len(pairs)} NAC numerators per step",
+                   "natm": m.natm, "nao": m.nao, "nocc": prob.nocc, "nauxJ": ctx.nJ, "nauxK": ctx.nK,
+                   "nstate": ns, "outputs_per_step": len(outs), "precision": "fp64"},
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(tsorted, 50)), 2),
+                       "p99": round(1e3 * float(np.percentile(tsorted, 99)), 2)},
+        "roofline": roof,
+        "stages": per_stage,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        res["cpu_baseline"] = oracle_sample(prob, jp, outs, radii)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,28 @@ const char *ris_last_error(const ris_ctx *ctx);
 /* Bytes of device memory the context currently holds. */
 size_t ris_ctx_bytes(const ris_ctx *ctx);
 
+/* Instrumented stages of the path (for ris_ctx_stage_stats). */
+enum ris_stage {
+    RIS_STAGE_INT3C = 0,   /* (mu nu|P) integral kernels of ris_int3c */
+    RIS_STAGE_MO = 1,      /* MO-transform and metric GEMMs of ris_int3c */
+    RIS_STAGE_MATVEC = 2,  /* one whole ris_response_matvec call */
+    RIS_STAGE_HBLK = 3,    /* MO-space exchange blocks of one gradient/NAC output */
+    RIS_STAGE_GAMMA = 4,   /* AO back-transform GEMM Gamma^P = (F_I W^P) F_J^T of one output */
+    RIS_STAGE_DERIV = 5,   /* fused three-centre derivative contraction, one output chunk */
+    RIS_STAGE_COUNT = 6
+};
+
+/* Turn per-stage timing on (1) or off (0); either way the counters reset.
+ * When on, each instrumented launch group is bracketed by HIP events on the
+ * context's stream (no extra synchronisation inside the calls). */
+int ris_ctx_set_profiling(ris_ctx *ctx, int enable);
+
+/* Accumulated device time (ms, from the events), algorithmic FLOPs and
+ * algorithmic HBM bytes, and the number of timed launch groups of a stage
+ * since profiling was last enabled.  Synchronises the context's stream.
+ * Any output pointer may be NULL. */
+int ris_ctx_stage_stats(ris_ctx *ctx, int stage, double *ms, double *flops, double *bytes, long *launches);
+
 /* Minimal ris auxiliary basis and its Coulomb metric (Sec. 2.2).
  * Builds the AO shell tables and the J and K auxiliary sets, evaluates
  * M_PQ = (P|Q) on the device, factors M = L L^T (FP64 Cholesky) and forms
@@ -151,6 +173,15 @@ int ris_grad_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y
  * gap is below 1e-12. */
 int ris_nac_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y,
                      int npair, const int *pairs, const double *omega, double *nac);
+
+/* Gradients and NAC numerators in one call (Sec. 2.2, eqs. gI_xi_ris and
+ * gIJ_xi_ris): same outputs and errors as ris_grad_contract followed by
+ * ris_nac_contract on the same amplitudes, but the per-state intermediates
+ * (AO transition-density factors and their exchange blocks) are built once
+ * for all outputs.  Either list may be empty (its pointers may then be NULL). */
+int ris_grad_nac_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y,
+                          int nsel, const int *sel, double *grad,
+                          int npair, const int *pairs, const double *omega, double *nac);
 
 #ifdef __cplusplus
 }

@@ -57,10 +57,27 @@ struct ris_ctx {
     double alphaJ = 2.0, cx = 0.25;
     double *C = nullptr;    // [nao][nmo] internal AO order
     double *eps = nullptr;  // [nmo]
-    double *aiJ = nullptr;  // [nJ][v][o] raw (ai|P)
-    double *rawoo = nullptr, *rawvv = nullptr;        // [nK][o][o], [nK][v][v]
-    double *coo = nullptr, *cvo = nullptr, *cvv = nullptr;  // metric-applied K blocks
+    double *aiJ = nullptr;   // [nJ][v][o]  raw (ai|P), Coulomb set
+    double *coo = nullptr;   // [nK][o][o]  c^P_ij = sum_Q (M_K^-1)_PQ (ij|Q)
+    double *cvo = nullptr;   // [v][nK][o]  c^P_aj
+    double *cvv = nullptr;   // [v][nK][v]  c^P_ab
+    double *rvv = nullptr;   // [v][nK][v]  raw (ab|P), exchange set
+    double *rvo2 = nullptr;  // [v][o][nK]  raw (aj|P), exchange set
     std::vector<void *> int3c_allocs;
+
+    // ---- grow-only scratch shared by the calls
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+
+    // ---- optional per-stage timing
+    struct Mark {
+        int stage;
+        hipEvent_t a, b;
+        double flops, bytes;
+    };
+    bool prof = false;
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
@@ -116,12 +133,36 @@ void dfree(ris_ctx *c, void *p)
         }
 }
 
+// Scratch of at least `bytes` (grow-only; contents not preserved across calls).
+char *ws_get(ris_ctx *c, size_t bytes, int *st)
+{
+    *st = RIS_OK;
+    if (bytes <= c->ws_bytes) return (char *)c->ws;
+    dfree(c, c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->ws = dalloc(c, bytes, st);
+    if (c->ws) c->ws_bytes = bytes;
+    return (char *)c->ws;
+}
+
+// carve consecutive 256-byte aligned pieces out of a scratch block
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t elems)
+    {
+        const size_t o = off;
+        off += (elems * 8 + 255) / 256 * 256;
+        return o;
+    }
+};
+
 void free_int3c(ris_ctx *c)
 {
     for (void *p : c->int3c_allocs) dfree(c, p);
     c->int3c_allocs.clear();
     c->have_int3c = false;
-    c->C = c->eps = c->aiJ = c->rawoo = c->rawvv = c->coo = c->cvo = c->cvv = nullptr;
+    c->C = c->eps = c->aiJ = c->coo = c->cvo = c->cvv = c->rvv = c->rvo2 = nullptr;
 }
 
 void free_aux(ris_ctx *c)
@@ -135,6 +176,45 @@ void free_aux(ris_ctx *c)
     c->ao = AOGeom{};
     c->aux = AuxGeom{};
     c->have_aux = false;
+}
+
+hipEvent_t get_event(ris_ctx *c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+// Bracket a launch group with events when profiling is on:
+//   hipEvent_t t = stage_begin(c); ...launches...; stage_end(c, t, stage, flops, bytes);
+hipEvent_t stage_begin(ris_ctx *c)
+{
+    if (!c->prof) return nullptr;
+    hipEvent_t a = get_event(c);
+    hipEventRecord(a, c->stream);
+    return a;
+}
+
+void stage_end(ris_ctx *c, hipEvent_t a, int stage, double flops, double bytes)
+{
+    if (!a) return;
+    hipEvent_t b = get_event(c);
+    hipEventRecord(b, c->stream);
+    c->marks.push_back({stage, a, b, flops, bytes});
+}
+
+void release_marks(ris_ctx *c)
+{
+    for (auto &m : c->marks) {
+        c->event_pool.push_back(m.a);
+        c->event_pool.push_back(m.b);
+    }
+    c->marks.clear();
 }
 
 // Upload a shell table: 5 double arrays + 2 int arrays in one allocation.
@@ -231,7 +311,42 @@ void ris_ctx_destroy(ris_ctx *c)
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     for (auto &b : c->bufs) hipFree(b.p);
+    release_marks(c);
+    for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
     delete c;
+}
+
+int ris_ctx_set_profiling(ris_ctx *c, int enable)
+{
+    if (!c) return RIS_E_INVALID;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    release_marks(c);
+    c->prof = enable != 0;
+    return RIS_OK;
+}
+
+int ris_ctx_stage_stats(ris_ctx *c, int stage, double *ms, double *flops, double *bytes, long *launches)
+{
+    if (!c || stage < 0 || stage >= RIS_STAGE_COUNT) return RIS_E_INVALID;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double t = 0.0, f = 0.0, by = 0.0;
+    long n = 0;
+    for (auto &m : c->marks) {
+        if (m.stage != stage) continue;
+        float e = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&e, m.a, m.b));
+        t += e;
+        f += m.flops;
+        by += m.bytes;
+        ++n;
+    }
+    if (ms) *ms = t;
+    if (flops) *flops = f;
+    if (bytes) *bytes = by;
+    if (launches) *launches = n;
+    return RIS_OK;
 }
 
 const char *ris_last_error(const ris_ctx *c) { return c ? c->err.c_str() : "null context"; }
@@ -392,12 +507,15 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
     c->alphaJ = mo->alpha_J;
     c->cx = mo->c_x;
     const size_t NN = (size_t)N * N;
+    const long vo = (long)v * o;
 
-    // persistent: C, eps, aiJ, rawoo, rawvv, coo, cvo, cvv ; scratch: X, Z
-    const size_t persist = 8 * ((size_t)N * nmo + nmo + (size_t)nJ * v * o + (size_t)nK * o * o * 2 +
-                                (size_t)nK * v * v * 2 + (size_t)nK * v * o);
-    const size_t scratch = 8 * ((size_t)nJ * NN + (size_t)nJ * N * std::max(o, 1) + (size_t)nK * N * v);
-    if (c->held + persist + scratch > c->budget)
+    // persistent: C, eps, aiJ, coo, cvo, cvv, rvv, rvo2
+    const size_t persist = 8 * ((size_t)N * nmo + nmo + (size_t)nJ * vo + (size_t)nK * o * o + 2 * (size_t)nK * vo +
+                                2 * (size_t)nK * v * v);
+    // scratch: X, Z (max of the two passes), (ij|P), (aj|P) in [a][P][j] order
+    const size_t zel = std::max((size_t)nJ * N * o, (size_t)nK * N * v);
+    const size_t scratch = 8 * ((size_t)nJ * NN + zel + (size_t)nK * o * o + (size_t)nK * vo) + 4 * 256;
+    if (c->held + persist + scratch > c->budget + c->ws_bytes)
         return fail(c, RIS_E_NOMEM, "int3c needs %.2f GB (persistent %.2f GB); budget %.2f GB, %.2f GB held",
                     (persist + scratch) / 1e9, persist / 1e9, c->budget / 1e9, c->held / 1e9);
     int st;
@@ -406,26 +524,29 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
         if (p) c->int3c_allocs.push_back(p);
         return p;
     };
-    if (!(c->C = take((size_t)N * nmo)) || !(c->eps = take(nmo)) || !(c->aiJ = take((size_t)nJ * v * o)) ||
-        !(c->rawoo = take((size_t)nK * o * o)) || !(c->rawvv = take((size_t)nK * v * v)) ||
-        !(c->coo = take((size_t)nK * o * o)) || !(c->cvo = take((size_t)nK * v * o)) ||
-        !(c->cvv = take((size_t)nK * v * v)))
+    if (!(c->C = take((size_t)N * nmo)) || !(c->eps = take(nmo)) || !(c->aiJ = take((size_t)nJ * vo)) ||
+        !(c->coo = take((size_t)nK * o * o)) || !(c->cvo = take((size_t)nK * vo)) ||
+        !(c->cvv = take((size_t)nK * v * v)) || !(c->rvv = take((size_t)nK * v * v)) ||
+        !(c->rvo2 = take((size_t)nK * vo)))
         return st;
-    double *X = (double *)dalloc(c, 8 * (size_t)nJ * NN, &st);
-    if (!X) return st;
-    double *Z = (double *)dalloc(c, 8 * std::max((size_t)nJ * N * o, (size_t)nK * N * v), &st);
-    if (!Z) {
-        dfree(c, X);
-        return st;
-    }
+    Carve cv;
+    const size_t oX = cv.take((size_t)nJ * NN), oZ = cv.take(zel), oOO = cv.take((size_t)nK * o * o),
+                 oVO = cv.take((size_t)nK * vo);
+    char *wsb = ws_get(c, cv.off, &st);
+    if (!wsb) return st;
+    double *X = (double *)(wsb + oX), *Z = (double *)(wsb + oZ), *rawoo = (double *)(wsb + oOO),
+           *rvoP = (double *)(wsb + oVO);
 
     // C rows into the internal (l-sorted) AO order
     HIPCHK(c, gather_rows(mo->C, c->C, c->d_ao_perm, N, nmo, nmo, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->eps, mo->eps, 8 * nmo, hipMemcpyDeviceToDevice, c->stream));
 
     // (mu nu|P)
+    hipEvent_t t_int = stage_begin(c);
     HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, X, c->stream));
+    stage_end(c, t_int, RIS_STAGE_INT3C, 0.0, 8.0 * (double)nJ * NN);
     if (dbg) HIPCHK(c, scatter_sq(X, dbg, c->d_ao_perm, N, nJ, c->stream));
+    hipEvent_t t_mo = stage_begin(c);
 
     const double *CO = c->C, *CV = c->C + o;
     // Z^P = X^P C_O  [nJ][N][o]
@@ -434,29 +555,36 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
     HIPCHK(c, dgemm(g, c->stream));
     // (ai|P) = C_V^T Z^P  [nJ][v][o]
     g = gm(v, o, N, true, false, 1.0, CV, nmo, Z, o, 0.0, c->aiJ, o);
-    g.batch = nJ; g.strideA = 0; g.strideB = (long)N * o; g.strideC = (long)v * o;
+    g.batch = nJ; g.strideA = 0; g.strideB = (long)N * o; g.strideC = vo;
     HIPCHK(c, dgemm(g, c->stream));
-    // (ij|P) = C_O^T Z^P, K functions only  [nK][o][o]
-    g = gm(o, o, N, true, false, 1.0, CO, nmo, Z, o, 0.0, c->rawoo, o);
+    // (ij|P) = C_O^T Z^P for the exchange set, then c_oo = M_K^-1 (ij|.)
+    g = gm(o, o, N, true, false, 1.0, CO, nmo, Z, o, 0.0, rawoo, o);
     g.batch = nK; g.strideA = 0; g.strideB = (long)N * o; g.strideC = (long)o * o;
     HIPCHK(c, dgemm(g, c->stream));
-    // (ab|P) = C_V^T (X^P C_V), K functions only  [nK][v][v]
+    HIPCHK(c, dgemm(gm(nK, o * o, nK, false, false, 1.0, c->MinvK, nK, rawoo, (long)o * o, 0.0, c->coo, (long)o * o),
+                    c->stream));
+    // (ab|P) = C_V^T (X^P C_V) written as [a][P][b]; c_vv[a] = M_K^-1 (a.|.)
     g = gm(N, v, N, false, false, 1.0, X, N, CV, nmo, 0.0, Z, v);
     g.batch = nK; g.strideA = NN; g.strideB = 0; g.strideC = (long)N * v;
     HIPCHK(c, dgemm(g, c->stream));
-    g = gm(v, v, N, true, false, 1.0, CV, nmo, Z, v, 0.0, c->rawvv, v);
-    g.batch = nK; g.strideA = 0; g.strideB = (long)N * v; g.strideC = (long)v * v;
+    g = gm(v, v, N, true, false, 1.0, CV, nmo, Z, v, 0.0, c->rvv, (long)nK * v);
+    g.batch = nK; g.strideA = 0; g.strideB = (long)N * v; g.strideC = v;
     HIPCHK(c, dgemm(g, c->stream));
-    // metric-applied exchange blocks c^P = sum_Q (M_K^-1)_PQ (..|Q)
-    HIPCHK(c, dgemm(gm(nK, o * o, nK, false, false, 1.0, c->MinvK, nK, c->rawoo, (long)o * o, 0.0, c->coo,
-                       (long)o * o), c->stream));
-    HIPCHK(c, dgemm(gm(nK, v * o, nK, false, false, 1.0, c->MinvK, nK, c->aiJ, (long)v * o, 0.0, c->cvo,
-                       (long)v * o), c->stream));
-    HIPCHK(c, dgemm(gm(nK, v * v, nK, false, false, 1.0, c->MinvK, nK, c->rawvv, (long)v * v, 0.0, c->cvv,
-                       (long)v * v), c->stream));
+    g = gm(nK, v, nK, false, false, 1.0, c->MinvK, nK, c->rvv, v, 0.0, c->cvv, v);
+    g.batch = v; g.strideA = 0; g.strideB = (long)nK * v; g.strideC = (long)nK * v;
+    HIPCHK(c, dgemm(g, c->stream));
+    // (aj|P) of the exchange set as [a][P][j] -> c_vo ; and as [a][j][P]
+    HIPCHK(c, permute3(c->aiJ, rvoP, v, nK, o, o, vo, 1, (long)nK * o, o, 1, c->stream));
+    g = gm(nK, o, nK, false, false, 1.0, c->MinvK, nK, rvoP, o, 0.0, c->cvo, o);
+    g.batch = v; g.strideA = 0; g.strideB = (long)nK * o; g.strideC = (long)nK * o;
+    HIPCHK(c, dgemm(g, c->stream));
+    HIPCHK(c, permute3(c->aiJ, c->rvo2, v, o, nK, o, 1, vo, (long)o * nK, nK, 1, c->stream));
+    stage_end(c, t_mo, RIS_STAGE_MO,
+              2.0 * nJ * ((double)N * N * o + (double)N * v * o) +
+                  2.0 * nK * ((double)N * o * o + (double)N * N * v + (double)N * v * v) +
+                  2.0 * (double)nK * nK * ((double)o * o + (double)v * o + (double)v * v),
+              0.0);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    dfree(c, Z);
-    dfree(c, X);
     c->have_int3c = true;
     return RIS_OK;
 }
@@ -473,110 +601,137 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
     if (!V || !out || V == out) return fail(c, RIS_E_INVALID, "null or aliased vector pointer");
     HIPCHK(c, hipSetDevice(c->device));
     const int o = c->nocc, v = c->nvir, nJ = c->nJ, nK = c->nK;
-    const long vo = (long)v * o;
+    const long vo = (long)v * o, oo = (long)o * o;
     // coefficients of Delta, J, K_A, K_B for A, B, A+B, A-B
     static const double cDe[4] = {1, 0, 1, 1}, cJ[4] = {1, 1, 2, 0}, cKA[4] = {1, 0, 1, 1}, cKB[4] = {0, 1, 1, -1};
+    const int chunk = std::min(nvec, 8);
+    Carve cv;
+    const size_t ot = cv.take((size_t)nvec * nJ * 2), oT = cv.take((size_t)chunk * nK * vo),
+                 oS = cv.take((size_t)chunk * nK * oo);
     int st;
-    double *t = (double *)dalloc(c, 8 * (size_t)nvec * nJ * 2, &st);
-    if (!t) return st;
-    double *T = (double *)dalloc(c, 8 * (size_t)nK * std::max(vo, (long)o * o), &st);
-    if (!T) {
-        dfree(c, t);
-        return st;
-    }
-    double *cc = t + (size_t)nvec * nJ;
+    char *wsb = ws_get(c, cv.off, &st);
+    if (!wsb) return st;
+    double *t = (double *)(wsb + ot), *cc = t + (size_t)nvec * nJ, *T = (double *)(wsb + oT),
+           *S = (double *)(wsb + oS);
+    hipEvent_t t_mv = stage_begin(c);
     // Coulomb: t = V (ai|P)^T ; cc = t M_J^-1 ; out = cJ alpha_J cc (ai|P)
     HIPCHK(c, dgemm(gm(nvec, nJ, (int)vo, false, true, 1.0, V, vo, c->aiJ, vo, 0.0, t, nJ), c->stream));
     HIPCHK(c, dgemm(gm(nvec, nJ, nJ, false, false, 1.0, t, nJ, c->MinvJ, nJ, 0.0, cc, nJ), c->stream));
     HIPCHK(c, dgemm(gm(nvec, (int)vo, nJ, false, false, cJ[op] * c->alphaJ, cc, nJ, c->aiJ, vo, 0.0, out, vo),
                     c->stream));
     if (cDe[op] != 0.0) HIPCHK(c, add_de(c->eps, V, out, v, o, nvec, cDe[op], c->stream));
-    for (int k = 0; k < nvec; ++k) {
-        const double *Vk = V + (size_t)k * vo;
-        double *ok = out + (size_t)k * vo;
+    for (int k0 = 0; k0 < nvec; k0 += chunk) {
+        const int nv = std::min(chunk, nvec - k0);
+        const double *Vk = V + (size_t)k0 * vo;
+        double *ok = out + (size_t)k0 * vo;
         if (cKA[op] != 0.0) {
-            // T^P[b][i] = sum_j V[b][j] c_oo^P[i][j] ; out[a][i] -= c_x sum_P sum_b (ab|P) T^P[b][i]
-            GemmArgs g = gm(v, o, o, false, true, 1.0, Vk, o, c->coo, o, 0.0, T, o);
-            g.batch = nK; g.strideA = 0; g.strideB = (long)o * o; g.strideC = vo;
-            HIPCHK(c, dgemm(g, c->stream));
-            g = gm(v, o, v, false, false, -cKA[op] * c->cx, c->rawvv, v, T, o, 1.0, ok, o);
-            g.nred = nK; g.strideAr = (long)v * v; g.strideBr = vo;
+            // T_k[P][b][i] = sum_j V_k[b][j] c_oo^P[i][j];  out_k -= c_x sum_{P,b} (ab|P) T_k[P][b][i]
+            for (int k = 0; k < nv; ++k) {
+                GemmArgs g = gm(v, o, o, false, true, 1.0, Vk + k * vo, o, c->coo, o, 0.0, T + (size_t)k * nK * vo, o);
+                g.batch = nK; g.strideA = 0; g.strideB = oo; g.strideC = vo;
+                HIPCHK(c, dgemm(g, c->stream));
+            }
+            GemmArgs g = gm(v, o, nK * v, false, false, -cKA[op] * c->cx, c->rvv, (long)nK * v, T, o, 1.0, ok, o);
+            g.batch = nv; g.strideA = 0; g.strideB = (long)nK * vo; g.strideC = vo;
             HIPCHK(c, dgemm(g, c->stream));
         }
         if (cKB[op] != 0.0) {
-            // S^P[i][j] = sum_b c_vo^P[b][i] V[b][j] ; out[a][i] -= c_x sum_P sum_j (aj|P) S^P[i][j]
-            GemmArgs g = gm(o, o, v, true, false, 1.0, c->cvo, o, Vk, o, 0.0, T, o);
-            g.batch = nK; g.strideA = vo; g.strideB = 0; g.strideC = (long)o * o;
+            // S_k[j][P][i] = sum_b V_k[b][j] c_vo^P[b][i];  out_k -= c_x sum_{j,P} (aj|P) S_k[j][P][i]
+            GemmArgs g = gm(o, nK * o, v, true, false, 1.0, Vk, o, c->cvo, (long)nK * o, 0.0, S, (long)nK * o);
+            g.batch = nv; g.strideA = vo; g.strideB = 0; g.strideC = (long)nK * oo;
             HIPCHK(c, dgemm(g, c->stream));
-            g = gm(v, o, o, false, true, -cKB[op] * c->cx, c->aiJ, o, T, o, 1.0, ok, o);
-            g.nred = nK; g.strideAr = vo; g.strideBr = (long)o * o;
+            g = gm(v, o, o * nK, false, false, -cKB[op] * c->cx, c->rvo2, (long)o * nK, S, o, 1.0, ok, o);
+            g.batch = nv; g.strideA = 0; g.strideB = (long)nK * oo; g.strideC = vo;
             HIPCHK(c, dgemm(g, c->stream));
         }
     }
+    {
+        const double fJ = 4.0 * (double)vo * nJ + 2.0 * (double)nJ * nJ;
+        const double fA = 2.0 * nK * ((double)v * o * o + (double)v * v * o);
+        const double fB = 4.0 * nK * (double)v * o * o;
+        stage_end(c, t_mv, RIS_STAGE_MATVEC,
+                  nvec * ((cJ[op] != 0 ? fJ : 0.0) + (cKA[op] != 0 ? fA : 0.0) + (cKB[op] != 0 ? fB : 0.0)), 0.0);
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    dfree(c, T);
-    dfree(c, t);
     return RIS_OK;
 }
 
 // ------------------------------------------------------------------------
-// Gradient / NAC numerators for a list of state pairs (I, J):
+// Gradients / NAC numerators for a list of state pairs (I, J):
 //   out[k] = d/dR [ alpha_J sum (mn|ls)_J R^S_I R^S_J - c_x sum (ml|ns)_K (R^S_I R^S_J + L^A_I L^A_J) ]
+// with the exchange weights Gamma^P = D_I C^P D_J^T built from the rank-3o
+// factors F_s = [C_V R_s, C_V L_s, C_O]: Gamma^P = F_I W^P F_J^T.
 static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double *Y, int npair, const int *pI,
                           const int *pJ, double *outg)
 {
     HIPCHK(c, hipSetDevice(c->device));
     const int N = c->nao, nmo = c->nmo, o = c->nocc, v = c->nvir, nJ = c->nJ, nK = c->nK, natm = c->natm;
-    const long vo = (long)v * o, NN = (long)N * N, o3 = 3L * o;
+    const long vo = (long)v * o, NN = (long)N * N, o3 = 3L * o, oo = (long)o * o;
+    const int ns = nstate;
+    const long w2 = 2L * ns * o;  // columns of RLT / Tall: (t, s, i)
     const int NO = kMaxOutChunk;
+    const int nsplit = 64;
+    Carve cv;
+    const size_t oR = cv.take((size_t)ns * vo), oL = cv.take((size_t)ns * vo), oRLT = cv.take((size_t)v * w2),
+                 oF = cv.take((size_t)ns * N * o3), oD = cv.take((size_t)ns * NN), otT = cv.take((size_t)ns * nJ),
+                 ocv = cv.take((size_t)ns * nJ), oTall = cv.take((size_t)v * nK * w2),
+                 oHUO = cv.take((size_t)w2 * nK * o), oHOU = cv.take((size_t)nK * o * w2),
+                 oHUU = cv.take((size_t)2 * nK * oo), oW = cv.take((size_t)nK * o3 * o3),
+                 oHc = cv.take((size_t)nK * o3 * o3), oY = cv.take((size_t)nK * N * o3),
+                 oG = cv.take((size_t)NO * nK * NN), oV2 = cv.take((size_t)NO * nJ * nJ),
+                 oSK = cv.take((size_t)nsplit * nK * nK), op3 = cv.take((size_t)c->nshAO * c->nshJ * 3 * NO * 6),
+                 op2 = cv.take((size_t)c->nshJ * 2 * NO * 3), oshA = cv.take((size_t)c->nshAO * NO * 3),
+                 oshC = cv.take((size_t)c->nshJ * NO * 3), oshP = cv.take((size_t)c->nshJ * NO * 3);
     int st;
-    std::vector<void *> tmp;
-    auto take = [&](size_t elems) -> double * {
-        double *p = (double *)dalloc(c, elems * 8, &st);
-        if (p) tmp.push_back(p);
-        return p;
-    };
-    auto cleanup = [&]() {
-        for (void *p : tmp) dfree(c, p);
-    };
-    double *R, *L, *F, *D, *tT, *cvec, *H, *Tm, *W, *Y3, *G, *V2, *p3, *p2, *shA, *shC, *shP;
-    if (!(R = take((size_t)nstate * vo)) || !(L = take((size_t)nstate * vo)) || !(F = take((size_t)nstate * N * o3)) ||
-        !(D = take((size_t)nstate * NN)) || !(tT = take((size_t)nstate * nJ)) || !(cvec = take((size_t)nstate * nJ)) ||
-        !(H = take((size_t)6 * nK * o * o)) || !(Tm = take((size_t)nK * vo)) || !(W = take((size_t)nK * o3 * o3)) ||
-        !(Y3 = take((size_t)nK * N * o3)) || !(G = take((size_t)NO * nK * NN)) || !(V2 = take((size_t)NO * nJ * nJ)) ||
-        !(p3 = take((size_t)c->nshAO * c->nshJ * 3 * NO * 6)) || !(p2 = take((size_t)c->nshJ * 2 * NO * 3)) ||
-        !(shA = take((size_t)c->nshAO * NO * 3)) || !(shC = take((size_t)c->nshJ * NO * 3)) ||
-        !(shP = take((size_t)c->nshJ * NO * 3))) {
-        cleanup();
-        return st;
-    }
+    char *wsb = ws_get(c, cv.off, &st);
+    if (!wsb) return st;
+    auto P_ = [&](size_t off) { return (double *)(wsb + off); };
+    double *R = P_(oR), *L = P_(oL), *RLT = P_(oRLT), *F = P_(oF), *D = P_(oD), *tT = P_(otT), *cvec = P_(ocv),
+           *Tall = P_(oTall), *HUO = P_(oHUO), *HOU = P_(oHOU), *HUU = P_(oHUU), *W = P_(oW), *Hc = P_(oHc),
+           *Y3 = P_(oY), *G = P_(oG), *V2 = P_(oV2), *SK = P_(oSK), *p3 = P_(op3), *p2 = P_(op2), *shA = P_(oshA),
+           *shC = P_(oshC), *shP = P_(oshP);
     const double *CO = c->C, *CV = c->C + o;
-    HIPCHK(c, make_rl(X, Y, R, L, (size_t)nstate * vo, c->stream));
-    // F_s = [C_V R_s, C_V L_s, C_O]  (N x 3o)
+
+    // ---- per-state intermediates
+    hipEvent_t t_h = stage_begin(c);
+    HIPCHK(c, make_rl(X, Y, R, L, (size_t)ns * vo, c->stream));
+    // RLT[a][t][s][i] = (R, L)_s[a][i]
+    HIPCHK(c, permute3(R, RLT, v, ns, o, o, vo, 1, w2, o, 1, c->stream));
+    HIPCHK(c, permute3(L, RLT + (size_t)ns * o, v, ns, o, o, vo, 1, w2, o, 1, c->stream));
     {
+        // F_s = [C_V R_s, C_V L_s, C_O]  (N x 3o)
         GemmArgs g = gm(N, o, v, false, false, 1.0, CV, nmo, R, o, 0.0, F, o3);
-        g.batch = nstate; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
+        g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
         HIPCHK(c, dgemm(g, c->stream));
         g = gm(N, o, v, false, false, 1.0, CV, nmo, L, o, 0.0, F + o, o3);
-        g.batch = nstate; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
+        g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
         HIPCHK(c, dgemm(g, c->stream));
-        for (int s = 0; s < nstate; ++s)
+        for (int s = 0; s < ns; ++s)
             HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + 2 * o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
                                        hipMemcpyDeviceToDevice, c->stream));
         // D_s = sym(U_Rs C_O^T) = R^S_s
         g = gm(N, N, o, false, true, 1.0, F, o3, CO, nmo, 0.0, D, N);
-        g.batch = nstate; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
+        g.batch = ns; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
         HIPCHK(c, dgemm(g, c->stream));
-        HIPCHK(c, symmetrize(D, N, nstate, c->stream));
+        HIPCHK(c, symmetrize(D, N, ns, c->stream));
         // c_s = M_J^-1 t_s, t_s[P] = sum_ai (ai|P) R_s[a][i]
-        HIPCHK(c, dgemm(gm(nstate, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), c->stream));
-        HIPCHK(c, dgemm(gm(nstate, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
+        HIPCHK(c, dgemm(gm(ns, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), c->stream));
+        HIPCHK(c, dgemm(gm(ns, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
+        // Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j]
+        HIPCHK(c, dgemm(gm(v * nK, (int)w2, v, false, false, 1.0, c->cvv, v, RLT, w2, 0.0, Tall, w2), c->stream));
+        // HUO[(t,s,i)][(P,j)] = sum_a (R,L)_s[a][i] c_vo^P[a][j]  (= H_UO blocks)
+        HIPCHK(c, dgemm(gm((int)w2, nK * o, v, true, false, 1.0, RLT, w2, c->cvo, (long)nK * o, 0.0, HUO,
+                           (long)nK * o), c->stream));
+        // HOU[(P,i)][(t,s,j)] = sum_b c_vo^P[b][i] (R,L)_s[b][j]  (= H_OU blocks)
+        HIPCHK(c, dgemm(gm(nK * o, (int)w2, v, true, false, 1.0, c->cvo, (long)nK * o, RLT, w2, 0.0, HOU, w2),
+                        c->stream));
     }
-    double *Hoo = c->coo;
-    double *HRuo = H, *HLuo = H + (size_t)nK * o * o, *HRou = H + 2 * (size_t)nK * o * o,
-           *HLou = H + 3 * (size_t)nK * o * o, *HRuu = H + 4 * (size_t)nK * o * o, *HLuu = H + 5 * (size_t)nK * o * o;
-    const long oo = (long)o * o;
+    stage_end(c, t_h, RIS_STAGE_HBLK,
+              2.0 * (double)v * nK * w2 * v + 4.0 * (double)w2 * nK * o * v + 2.0 * ns * ((double)N * N * o) +
+                  4.0 * ns * (double)N * v * o,
+              0.0);
 
+    auto blk = [](const double *b, long sP, long si, long sj, double sc) { return BlockSrc{b, sP, si, sj, sc}; };
     for (int k0 = 0; k0 < npair; k0 += NO) {
         const int nb = std::min(NO, npair - k0);
         DerivJob job{};
@@ -595,110 +750,135 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         }
         for (int k = 0; k < nb; ++k) {
             const int I = pI[k0 + k], J = pJ[k0 + k];
-            const double *RI = R + (size_t)I * vo, *RJ = R + (size_t)J * vo;
-            const double *LI = L + (size_t)I * vo, *LJ = L + (size_t)J * vo;
-            // H_UO = R_I^T c_vo^P ; H_OU = c_vo^P^T R_J (o x o per P); same with L
-            auto hb = [&](const double *A, bool tA, long sA, const double *B, bool tB, long sB, double *Cm) {
-                (void)tB;
-                GemmArgs g = gm(o, o, v, tA, false, 1.0, A, o, B, o, 0.0, Cm, o);
-                g.batch = nK; g.strideA = sA; g.strideB = sB; g.strideC = oo;
-                return dgemm(g, c->stream);
-            };
-            HIPCHK(c, hb(RI, true, 0, c->cvo, false, vo, HRuo));
-            HIPCHK(c, hb(LI, true, 0, c->cvo, false, vo, HLuo));
-            HIPCHK(c, hb(c->cvo, true, vo, RJ, false, 0, HRou));
-            HIPCHK(c, hb(c->cvo, true, vo, LJ, false, 0, HLou));
-            // H_UU = R_I^T (c_vv^P R_J)
-            for (int rl = 0; rl < 2; ++rl) {
-                const double *SI = rl ? LI : RI, *SJ = rl ? LJ : RJ;
-                GemmArgs g = gm(v, o, v, false, false, 1.0, c->cvv, v, SJ, o, 0.0, Tm, o);
-                g.batch = nK; g.strideA = (long)v * v; g.strideB = 0; g.strideC = vo;
+            hipEvent_t t_u = stage_begin(c);
+            // H_UU^P = (R,L)_I^T Tall^P_{(R,L) J}
+            for (int t = 0; t < 2; ++t) {
+                GemmArgs g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2,
+                                Tall + (size_t)(t * ns + J) * o, (long)nK * w2, 0.0, HUU + (size_t)t * nK * oo, o);
+                g.batch = nK; g.strideA = 0; g.strideB = w2; g.strideC = oo;
                 HIPCHK(c, dgemm(g, c->stream));
-                HIPCHK(c, hb(SI, true, 0, Tm, false, vo, rl ? HLuu : HRuu));
             }
-            // W^P (3o x 3o), Y^P = F_I W^P, Gamma^P = -2 c_x Y^P F_J^T
-            HIPCHK(c, assemble_w(Hoo, HRou, HLou, HRuo, HLuo, HRuu, HLuu, W, o, nK, 1.0, c->stream));
+            stage_end(c, t_u, RIS_STAGE_HBLK, 4.0 * (double)nK * oo * v, 0.0);
+            const BlockSrc Hoo = blk(c->coo, oo, o, 1, 1.0);
+            const BlockSrc HRuo = blk(HUO + (size_t)I * o * nK * o, o, (long)nK * o, 1, 1.0);
+            const BlockSrc HLuo = blk(HUO + (size_t)(ns + I) * o * nK * o, o, (long)nK * o, 1, 1.0);
+            const BlockSrc HRou = blk(HOU + (size_t)J * o, o * w2, w2, 1, 1.0);
+            const BlockSrc HLou = blk(HOU + (size_t)(ns + J) * o, o * w2, w2, 1, 1.0);
+            const BlockSrc HRuu = blk(HUU, oo, o, 1, 1.0);
+            const BlockSrc HLuu = blk(HUU + (size_t)nK * oo, oo, o, 1, 1.0);
+            const BlockSrc none{nullptr, 0, 0, 0, 0.0};
+            auto sc = [](BlockSrc b, double f) { b.scale *= f; return b; };
+            // exchange weights W^P (rows/cols [U_R, U_L, C_O]) from D = (U C_O^T +- C_O U^T)/2
+            BlockGrid gw{};
+            gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = none;             gw.b[0][2][0] = sc(HRou, 0.25);
+            gw.b[1][0][0] = none;           gw.b[1][1][0] = sc(Hoo, 0.25);   gw.b[1][2][0] = sc(HLou, -0.25);
+            gw.b[2][0][0] = sc(HRuo, 0.25); gw.b[2][1][0] = sc(HLuo, -0.25); gw.b[2][2][0] = sc(HRuu, 0.25);
+            gw.b[2][2][1] = sc(HLuu, 0.25);
+            HIPCHK(c, assemble3(gw, W, o, nK, c->stream));
+            // H^P = F_I^T C^P F_J over the blocks where W is nonzero
+            BlockGrid gh{};
+            gh.b[0][0][0] = HRuu; gh.b[0][2][0] = HRuo;
+            gh.b[1][1][0] = HLuu; gh.b[1][2][0] = HLuo;
+            gh.b[2][0][0] = HRou; gh.b[2][1][0] = HLou; gh.b[2][2][0] = Hoo;
+            HIPCHK(c, assemble3(gh, Hc, o, nK, c->stream));
+            // metric weights: W2 = -alpha_J c_I c_J^T + c_x V, V_PQ = sum_kl H^P_kl W^Q_kl
+            double *V2k = V2 + (size_t)k * nJ * nJ;
+            HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ,
+                               nJ, 0.0, V2k, nJ), c->stream));
+            HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)(o3 * o3), false, true, c->cx, Hc, o3 * o3, W, o3 * o3, 1.0, V2k,
+                                      nJ), nsplit, SK, c->stream));
+            // Y^P = F_I W^P ; Gamma^P = -2 c_x Y^P F_J^T
             GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, F + (size_t)I * N * o3, o3, W, o3, 0.0, Y3, o3);
             g.batch = nK; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
             HIPCHK(c, dgemm(g, c->stream));
             double *Gk = G + (size_t)k * nK * NN;
             g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, F + (size_t)J * N * o3, o3, 0.0, Gk, N);
             g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
+            hipEvent_t t_g = stage_begin(c);
             HIPCHK(c, dgemm(g, c->stream));
+            stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nK * N * N * o3,
+                      8.0 * ((double)nK * N * N + (double)nK * N * o3 + (double)N * o3));
             if (I != J) HIPCHK(c, symmetrize(Gk, N, nK, c->stream));
-            // metric weights: W2 = -alpha_J c_I c_J^T (J set) + c_x V (K block),
-            // V_PQ = sum_kl H^P_kl W^Q_kl over the nonzero exchange blocks
-            double *V2k = V2 + (size_t)k * nJ * nJ;
-            HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ,
-                               nJ, 0.0, V2k, nJ), c->stream));
-            const double q = 0.25 * c->cx;
-            struct Term { const double *a; const double *b; double s; };
-            const Term terms[] = {{HRuu, Hoo, q},   {HLuu, Hoo, q},   {HRuo, HRou, q}, {HLuo, HLou, -q},
-                                  {HRou, HRuo, q},  {HLou, HLuo, -q}, {Hoo, HRuu, q},  {Hoo, HLuu, q}};
-            for (const Term &tm : terms)
-                HIPCHK(c, dgemm(gm(nK, nK, (int)oo, false, true, tm.s, tm.a, oo, tm.b, oo, 1.0, V2k, nJ), c->stream));
         }
         // three-centre derivative contraction + metric derivative, reduced into atoms
         HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * NO * 6, 0.0, c->stream));
+        hipEvent_t t_d = stage_begin(c);
         HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream));
+        stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)nb * nK * NN);
         HIPCHK(c, fill(p2, (size_t)c->nshJ * 2 * nb * 3, 0.0, c->stream));
         HIPCHK(c, launch_int2c_deriv(c->aux, c->boys, nb, V2, p2, c->stream));
-        // the deriv kernel indexes partials with stride NO; pass NO for p3, nb outputs
         HIPCHK(c, reduce_grad(p3, c->nshAO, c->nshJ, nb, NO, p2, c->ao.sh.atom, c->aux.sh.atom, natm, shA, shC, shP,
                               1.0, 0, outg + (size_t)k0 * natm * 3, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    cleanup();
+    return RIS_OK;
+}
+
+int ris_grad_nac_contract(ris_ctx *c, int nstate, const double *X, const double *Y, int nsel, const int *sel,
+                          double *grad, int npair, const int *pairs, const double *omega, double *nac)
+{
+    if (!c) return RIS_E_INVALID;
+    c->err.clear();
+    if (!c->have_int3c) return fail(c, RIS_E_ORDER, "gradient/NAC call before ris_int3c");
+    if (nstate <= 0 || nsel < 0 || npair < 0 || !X || (nsel > 0 && (!sel || !grad)) ||
+        (npair > 0 && (!pairs || !nac)))
+        return fail(c, RIS_E_INVALID, "bad gradient/NAC arguments");
+    const int nout = nsel + npair;
+    if (nout == 0) return RIS_OK;
+    std::vector<int> pI(nout), pJ(nout);
+    for (int k = 0; k < nsel; ++k) {
+        if (sel[k] < 0 || sel[k] >= nstate) return fail(c, RIS_E_INVALID, "sel[%d]=%d out of range", k, sel[k]);
+        pI[k] = pJ[k] = sel[k];
+    }
+    for (int k = 0; k < npair; ++k) {
+        pI[nsel + k] = pairs[2 * k];
+        pJ[nsel + k] = pairs[2 * k + 1];
+        if (pI[nsel + k] < 0 || pI[nsel + k] >= nstate || pJ[nsel + k] < 0 || pJ[nsel + k] >= nstate)
+            return fail(c, RIS_E_INVALID, "pair %d out of range", k);
+    }
+    int st;
+    double *out = nullptr;
+    const size_t per = (size_t)c->natm * 3;
+    if (nsel > 0 && npair > 0) {
+        out = (double *)dalloc(c, 8 * per * nout, &st);
+        if (!out) return st;
+    } else {
+        out = nsel > 0 ? grad : nac;
+    }
+    st = contract_pairs(c, nstate, X, Y, nout, pI.data(), pJ.data(), out);
+    if (st == RIS_OK && nsel > 0 && npair > 0) {
+        HIPCHK(c, hipMemcpyAsync(grad, out, 8 * per * nsel, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(nac, out + per * nsel, 8 * per * npair, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (out != grad && out != nac) dfree(c, out);
+    if (st || !omega || npair == 0) return st;
+    bool degenerate = false;
+    for (int k = 0; k < npair; ++k) {
+        const double gap = omega[pJ[nsel + k]] - omega[pI[nsel + k]];
+        if (std::fabs(gap) < 1e-12) {
+            degenerate = true;
+            continue;
+        }
+        HIPCHK(c, axpby(nac + (size_t)k * per, nac + (size_t)k * per, per, 1.0 / gap, 0.0, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (degenerate) return fail(c, RIS_E_DEGENERATE, "degenerate state pair: numerator left undivided");
     return RIS_OK;
 }
 
 int ris_grad_contract(ris_ctx *c, int nstate, const double *X, const double *Y, int nsel, const int *sel, double *grad)
 {
     if (!c) return RIS_E_INVALID;
-    c->err.clear();
-    if (!c->have_int3c) return fail(c, RIS_E_ORDER, "ris_grad_contract before ris_int3c");
-    if (nstate <= 0 || nsel < 0 || !X || (nsel > 0 && (!sel || !grad)))
-        return fail(c, RIS_E_INVALID, "bad gradient arguments");
-    std::vector<int> pI(nsel), pJ(nsel);
-    for (int k = 0; k < nsel; ++k) {
-        if (sel[k] < 0 || sel[k] >= nstate) return fail(c, RIS_E_INVALID, "sel[%d]=%d out of range", k, sel[k]);
-        pI[k] = pJ[k] = sel[k];
-    }
-    if (nsel == 0) return RIS_OK;
-    return contract_pairs(c, nstate, X, Y, nsel, pI.data(), pJ.data(), grad);
+    if (nsel > 0 && !sel) return fail(c, RIS_E_INVALID, "null selection");
+    return ris_grad_nac_contract(c, nstate, X, Y, nsel, sel, grad, 0, nullptr, nullptr, nullptr);
 }
 
 int ris_nac_contract(ris_ctx *c, int nstate, const double *X, const double *Y, int npair, const int *pairs,
                      const double *omega, double *nac)
 {
     if (!c) return RIS_E_INVALID;
-    c->err.clear();
-    if (!c->have_int3c) return fail(c, RIS_E_ORDER, "ris_nac_contract before ris_int3c");
-    if (nstate <= 0 || npair < 0 || !X || (npair > 0 && (!pairs || !nac)))
-        return fail(c, RIS_E_INVALID, "bad NAC arguments");
-    std::vector<int> pI(npair), pJ(npair);
-    for (int k = 0; k < npair; ++k) {
-        pI[k] = pairs[2 * k];
-        pJ[k] = pairs[2 * k + 1];
-        if (pI[k] < 0 || pI[k] >= nstate || pJ[k] < 0 || pJ[k] >= nstate)
-            return fail(c, RIS_E_INVALID, "pair %d out of range", k);
-    }
-    if (npair == 0) return RIS_OK;
-    int st = contract_pairs(c, nstate, X, Y, npair, pI.data(), pJ.data(), nac);
-    if (st || !omega) return st;
-    bool degenerate = false;
-    for (int k = 0; k < npair; ++k) {
-        const double gap = omega[pJ[k]] - omega[pI[k]];
-        if (std::fabs(gap) < 1e-12) {
-            degenerate = true;
-            continue;
-        }
-        HIPCHK(c, axpby(nac + (size_t)k * c->natm * 3, nac + (size_t)k * c->natm * 3, (size_t)c->natm * 3, 1.0 / gap,
-                        0.0, c->stream));
-    }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (degenerate) return fail(c, RIS_E_DEGENERATE, "degenerate state pair: numerator left undivided");
-    return RIS_OK;
+    return ris_grad_nac_contract(c, nstate, X, Y, 0, nullptr, nullptr, npair, pairs, omega, nac);
 }
 
 }  // extern "C"

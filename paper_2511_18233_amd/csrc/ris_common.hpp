@@ -89,6 +89,9 @@ struct GemmArgs {
     int batch, nred;
 };
 hipError_t dgemm(const GemmArgs &g, hipStream_t st);
+// Same product with K cut into nsplit ranges (batch == 1, nred == 1): partials
+// go to ws (nsplit * M * N doubles) and are summed in a fixed order.
+hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st);
 
 // Dense linear algebra on small matrices (ris_linalg.hip).
 // In-place Cholesky of the n x n SPD matrix (lower triangle written, upper

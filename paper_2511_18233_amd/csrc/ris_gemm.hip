@@ -11,6 +11,8 @@
 // A[l % 16][l / 16], B fragment lane l holds B[l / 16][l % 16], and the four
 // accumulator values of lane l are D[4 i + l / 16][l % 16], i = 0..3 (rows
 // interleaved across the four lane groups; checked by the layout probe test).
+#include <algorithm>
+
 #include "ris_common.hpp"
 
 namespace ris {
@@ -185,3 +187,48 @@ extern "C" int ris_test_dgemm(int M, int N, int K, int transA, int transB, doubl
     if (ris::dgemm(g, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return 7;
     return 0;
 }
+
+// ------------------------------------------------------------ split-K --
+// C = alpha op(A) op(B) + beta C for a GEMM with a small M x N output and a
+// long K: K is cut into nsplit ranges, each range writes its partial product
+// to ws[z][M][N]; a second kernel sums the partials in a fixed order.
+namespace {
+__global__ void k_splitk_reduce(const double *__restrict__ ws, int nsplit, int M, int N, double beta,
+                                double *__restrict__ C, long ldc)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)M * N) return;
+    const int m = (int)(idx / N), n = (int)(idx % N);
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += ws[(size_t)z * M * N + idx];
+    double *cp = C + (long)m * ldc + n;
+    *cp = (beta == 0.0) ? s : s + beta * *cp;
+}
+}  // namespace
+
+namespace ris {
+hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st)
+{
+    if (nsplit <= 1 || g.batch != 1 || g.nred > 1) return dgemm(g, st);
+    const int kc = ((g.K + nsplit - 1) / nsplit + BK - 1) / BK * BK;  // multiple of the k-tile
+    int used = 0;
+    for (int z = 0; z < nsplit; ++z) {
+        const int k0 = z * kc;
+        if (k0 >= g.K) break;
+        GemmArgs p = g;
+        p.K = std::min(kc, g.K - k0);
+        p.A = g.transA ? g.A + (long)k0 * g.lda : g.A + k0;
+        p.B = g.transB ? g.B + k0 : g.B + (long)k0 * g.ldb;
+        p.beta = 0.0;
+        p.C = ws + (size_t)z * g.M * g.N;
+        p.ldc = g.N;
+        hipError_t e = dgemm(p, st);
+        if (e != hipSuccess) return e;
+        ++used;
+    }
+    const long tot = (long)g.M * g.N;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws, used, g.M, g.N,
+                       g.beta, g.C, g.ldc);
+    return hipGetLastError();
+}
+}  // namespace ris

@@ -178,36 +178,36 @@ __global__ void k_axpby(const double *__restrict__ src, double *__restrict__ dst
     dst[i] = alpha * src[i] + (beta == 0.0 ? 0.0 : beta * dst[i]);
 }
 
-// Exchange weight blocks of one output (3o x 3o per K function P):
-//   rows/cols ordered [U_R (o), U_L (o), C_O (o)];
-//   W[UR,UR] = H_OO/4   W[UR,O] =  HR_OU/4
-//   W[UL,UL] = H_OO/4   W[UL,O] = -HL_OU/4
-//   W[O,UR]  = HR_UO/4  W[O,UL] = -HL_UO/4   W[O,O] = (HR_UU + HL_UU)/4
-// (from D1 C^P D2^T with D = (U C_O^T + s C_O U^T)/2, s = +1 for R^S and -1
-// for L^A), scaled by `scale`.
-__global__ void k_assemble_w(const double *__restrict__ Hoo, const double *__restrict__ HRou,
-                             const double *__restrict__ HLou, const double *__restrict__ HRuo,
-                             const double *__restrict__ HLuo, const double *__restrict__ HRuu,
-                             const double *__restrict__ HLuu, double *__restrict__ W, int o, int nP, double scale)
+// Assemble nP matrices of (3o x 3o) from a 3 x 3 grid of o x o blocks; block
+// (bi, bj) is the sum of up to two strided sources
+//   src[P][i][j] = base[P * sP + i * si + j * sj] * scale   (base null = 0).
+__global__ void k_assemble3(BlockGrid g, double *__restrict__ W, int o, int nP)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long oo = (long)o * o;
     const int n3 = 3 * o;
     if (idx >= (long)n3 * n3 * nP) return;
     const long P = idx / ((long)n3 * n3);
     const long r = idx % ((long)n3 * n3);
     const int row = (int)(r / n3), col = (int)(r % n3);
     const int bi = row / o, bj = col / o, i = row % o, j = col % o;
-    const long e = P * oo + (long)i * o + j;
     double v = 0.0;
-    if (bi == 0 && bj == 0) v = Hoo[e];
-    else if (bi == 1 && bj == 1) v = Hoo[e];
-    else if (bi == 0 && bj == 2) v = HRou[e];
-    else if (bi == 1 && bj == 2) v = -HLou[e];
-    else if (bi == 2 && bj == 0) v = HRuo[e];
-    else if (bi == 2 && bj == 1) v = -HLuo[e];
-    else if (bi == 2 && bj == 2) v = HRuu[e] + HLuu[e];
-    W[idx] = 0.25 * scale * v;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const BlockSrc &b = g.b[bi][bj][t];
+        if (b.base) v += b.scale * b.base[P * b.sP + (long)i * b.si + (long)j * b.sj];
+    }
+    W[idx] = v;
+}
+
+// out[i0*o0 + i1*o1 + i2*o2] = in[i0*s0 + i1*s1 + i2*s2] over an n0 x n1 x n2 box
+__global__ void k_permute3(const double *__restrict__ in, double *__restrict__ out, int n0, int n1, int n2,
+                           long s0, long s1, long s2, long o0, long o1, long o2)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n0 * n1 * n2) return;
+    const long i2 = idx % n2, r = idx / n2;
+    const long i1 = r % n1, i0 = r / n1;
+    out[i0 * o0 + i1 * o1 + i2 * o2] = in[i0 * s0 + i1 * s1 + i2 * s2];
 }
 
 // Reduce the triplet partials into per-shell sums (fixed order).
@@ -341,13 +341,19 @@ hipError_t axpby(const double *src, double *dst, size_t n, double alpha, double 
     return hipGetLastError();
 }
 
-hipError_t assemble_w(const double *Hoo, const double *HRou, const double *HLou, const double *HRuo,
-                      const double *HLuo, const double *HRuu, const double *HLuu, double *W, int o, int nP,
-                      double scale, hipStream_t st)
+hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st)
 {
     const size_t n = (size_t)9 * o * o * nP;
-    hipLaunchKernelGGL(k_assemble_w, dim3(nblk(n, 256)), dim3(256), 0, st, Hoo, HRou, HLou, HRuo, HLuo, HRuu, HLuu,
-                       W, o, nP, scale);
+    hipLaunchKernelGGL(k_assemble3, dim3(nblk(n, 256)), dim3(256), 0, st, g, W, o, nP);
+    return hipGetLastError();
+}
+
+hipError_t permute3(const double *in, double *out, int n0, int n1, int n2, long s0, long s1, long s2, long o0,
+                    long o1, long o2, hipStream_t st)
+{
+    const size_t n = (size_t)n0 * n1 * n2;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute3, dim3(nblk(n, 256)), dim3(256), 0, st, in, out, n0, n1, n2, s0, s1, s2, o0, o1, o2);
     return hipGetLastError();
 }
 

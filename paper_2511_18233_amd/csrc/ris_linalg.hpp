@@ -14,9 +14,19 @@ hipError_t symmetrize(double *A, int n, int nb, hipStream_t st);
 hipError_t add_de(const double *eps, const double *V, double *out, int nvir, int nocc, int nvec, double s,
                   hipStream_t st);
 hipError_t axpby(const double *src, double *dst, size_t n, double alpha, double beta, hipStream_t st);
-hipError_t assemble_w(const double *Hoo, const double *HRou, const double *HLou, const double *HRuo,
-                      const double *HLuo, const double *HRuu, const double *HLuu, double *W, int o, int nP,
-                      double scale, hipStream_t st);
+// one o x o source block of a 3 x 3 assembly: base[P*sP + i*si + j*sj] * scale
+struct BlockSrc {
+    const double *base;
+    long sP, si, sj;
+    double scale;
+};
+struct BlockGrid {
+    BlockSrc b[3][3][2];  // up to two summed sources per block; base == nullptr means none
+};
+hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st);
+// out[i0*o0 + i1*o1 + i2*o2] = in[i0*s0 + i1*s1 + i2*s2] over n0 x n1 x n2
+hipError_t permute3(const double *in, double *out, int n0, int n1, int n2, long s0, long s1, long s2, long o0,
+                    long o1, long o2, hipStream_t st);
 hipError_t reduce_grad(const double *p3, int nshAO, int nshAux, int nout, int NO, const double *p2,
                        const int *atomAO, const int *atomAux, int natm, double *shA, double *shC, double *shP,
                        double scale, int accumulate, double *grad, hipStream_t st);

@@ -21,7 +21,9 @@ STATUS = {0: "RIS_OK", 1: "RIS_E_INVALID", 2: "RIS_E_UNSUPPORTED", 3: "RIS_E_NOM
           5: "RIS_E_DEGENERATE", 6: "RIS_E_ORDER", 7: "RIS_E_DEVICE"}
 OPS = {"A": 0, "B": 1, "A+B": 2, "A-B": 3}
 EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
-           "ris_response_matvec", "ris_grad_contract", "ris_nac_contract",
+           "ris_response_matvec", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
+           "ris_ctx_set_profiling",
+           "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
            "ris_test_mfma_probe", "ris_test_dgemm")
 
@@ -74,6 +76,9 @@ def load_library(path: str = LIB_PATH):
     lib.ris_response_matvec.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.ris_grad_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp]
     lib.ris_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, dp, vp]
+    lib.ris_grad_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp, ctypes.c_int, ip, dp, vp]
+    lib.ris_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.ris_ctx_stage_stats.argtypes = [vp, ctypes.c_int, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
     lib.ris_test_mfma_probe.argtypes = [vp, vp, vp]
     L = ctypes.c_long
     lib.ris_test_dgemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -136,6 +141,22 @@ class RisContext:
     @property
     def bytes_held(self) -> int:
         return int(self.lib.ris_ctx_bytes(self.h))
+
+    STAGES = ("int3c", "mo", "matvec", "hblk", "gamma", "deriv")
+
+    def set_profiling(self, on: bool):
+        self._chk(self.lib.ris_ctx_set_profiling(self.h, int(bool(on))))
+
+    def stage_stats(self):
+        """{stage: (ms, flops, bytes, launches)} accumulated since profiling was enabled."""
+        out = {}
+        for k, name in enumerate(self.STAGES):
+            ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            n = ctypes.c_long()
+            self._chk(self.lib.ris_ctx_stage_stats(self.h, k, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by),
+                                                   ctypes.byref(n)))
+            out[name] = (ms.value, fl.value, by.value, n.value)
+        return out
 
     # -- entry points -----------------------------------------------------
     def aux_build(self, Z, xyz, shell_atom, shell_l, shell_exp, radius_bohr, theta=0.2, j_p_on_heavy=True):
@@ -208,6 +229,32 @@ class RisContext:
             return out
         self._chk(st)
         return out
+
+
+def _grad_nac_impl(self, X, Y, sel, pairs, omega=None, grad=None, nac=None, allow_degenerate=False):
+    import torch
+    _check_dev(X, self.device, "X")
+    _check_dev(Y, self.device, "Y")
+    sel = np.ascontiguousarray(sel, dtype=np.int32).reshape(-1)
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    if grad is None:
+        grad = torch.empty((sel.size, self.natm, 3), dtype=torch.float64, device=self.device)
+    if nac is None:
+        nac = torch.empty((pairs.shape[0], self.natm, 3), dtype=torch.float64, device=self.device)
+    _check_dev(grad, self.device, "grad")
+    _check_dev(nac, self.device, "nac")
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    st = self.lib.ris_grad_nac_contract(
+        self.h, X.shape[0], _ptr(X), _ptr(Y), sel.size, sel.ctypes.data_as(ip), _ptr(grad), pairs.shape[0],
+        pairs.ctypes.data_as(ip), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if om is not None else None,
+        _ptr(nac))
+    if not (st == 5 and allow_degenerate):
+        self._chk(st)
+    return grad, nac
+
+
+RisContext.grad_nac_contract = _grad_nac_impl
 
 
 def solve_problem(ctx: RisContext, prob, radius_bohr, outputs, theta=0.2, j_p_on_heavy=True, alpha_J=2.0,

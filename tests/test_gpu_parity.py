@@ -120,6 +120,19 @@ def test_grad_nac_parity(ctx, radii, case):
     assert np.abs(got.sum(1)).max() <= 1e-10
 
 
+def test_combined_call_matches_separate_calls(ctx, radii):
+    prob = molgen.make_chain_problem(12, seed=5, nstate=3, tda=False)
+    _setup(ctx, prob, radii, True)
+    X = _to(prob.X, ctx.device)
+    Y = _to(prob.Y, ctx.device)
+    say("[gpu] combined grad+nac chain12")
+    g1 = ctx.grad_contract(X, Y, [0, 2]).cpu().numpy()
+    n1 = ctx.nac_contract(X, Y, [(0, 1), (2, 1)]).cpu().numpy()
+    g2, n2 = ctx.grad_nac_contract(X, Y, [0, 2], [(0, 1), (2, 1)])
+    assert np.array_equal(g1, g2.cpu().numpy())
+    assert np.array_equal(n1, n2.cpu().numpy())
+
+
 def test_determinism_and_tda(ctx, radii, torch_dev):
     import torch
     prob = molgen.make_problem("ring12")
