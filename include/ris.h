@@ -55,7 +55,15 @@ enum ris_status {
     RIS_E_DEVICE = 7        /* HIP runtime error */
 };
 
-enum ris_precision { RIS_FP64 = 0 };
+/* Arithmetic of the exchange-weight contractions (the products that build
+ * Gamma^P, its MO-space blocks and V_PQ) and of the exchange part of the
+ * matvecs.  Integrals, MO transforms, every metric solve (M^-1 applications),
+ * the Coulomb part and all gradient accumulation stay FP64 in every mode.
+ *   RIS_FP64   : FP64 matrix cores.
+ *   RIS_FP32   : FP32 matrix cores, FP32 accumulation.
+ *   RIS_BF16X3 : split BF16 (x ~ hi + lo), three products hi.hi + hi.lo + lo.hi
+ *                on BF16 matrix cores, FP32 accumulation. */
+enum ris_precision { RIS_FP64 = 0, RIS_FP32 = 1, RIS_BF16X3 = 2 };
 
 /* Response operators of the Casida problem (Sec. 2.1, eqs. casida, A_matrix,
  * B_matrix): A, B, A+B, A-B with the ris kernel. */
@@ -107,6 +115,15 @@ const char *ris_last_error(const ris_ctx *ctx);
 
 /* Bytes of device memory the context currently holds. */
 size_t ris_ctx_bytes(const ris_ctx *ctx);
+
+/* Peak device bytes a context holds for one request of this molecule with
+ * nmo orbitals (nocc occupied), nstate amplitude vectors, matvecs of up to
+ * nvec vectors and nout gradient/NAC outputs (0 for any of the three if that
+ * call is not made).  The sizing is the one the calls themselves use, so a
+ * scheduler can admit requests by HBM footprint.  Host-only, no device work;
+ * returns 0 for invalid input. */
+size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int nocc, int nstate, int nvec,
+                         int nout);
 
 /* Instrumented stages of the path (for ris_ctx_stage_stats). */
 enum ris_stage {

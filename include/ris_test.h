@@ -12,16 +12,26 @@
 extern "C" {
 #endif
 
-/* One v_mfma_f64_16x16x4f64 on one wave: lane l supplies a[l] and b[l]
- * (device arrays of 64 doubles, accumulator starts at 0) and writes its four
- * result doubles to out[4 l + i] (device, 256 doubles).  Synchronous. */
-int ris_test_mfma_probe(const double *a, const double *b, double *out);
+/* One matrix-core instruction on one wave, accumulator starting at 0.
+ * kind 0: v_mfma_f64_16x16x4f64, lane l supplies a[l], b[l];
+ * kind 1: v_mfma_f32_16x16x4f32, lane l supplies a[l], b[l] (rounded to FP32);
+ * kind 2: v_mfma_f32_16x16x32_bf16, lane l supplies a[8l..8l+7], b[8l..8l+7]
+ *         (rounded to BF16).
+ * a, b are device arrays of doubles (64 or 512 values); lane l writes its four
+ * result values to out[4 l + i] (device, 256 doubles).  Synchronous. */
+int ris_test_mfma_probe(int kind, const double *a, const double *b, double *out);
 
 /* C_z = alpha * op(A_z) op(B_z) + beta * C_z for z < batch (row-major, op(A) is
  * M x K, stored K x M when transA; op(B) is K x N, stored N x K when transB),
  * batch strides sA, sB, sC in elements.  Device pointers; synchronous. */
 int ris_test_dgemm(int M, int N, int K, int transA, int transB, double alpha, const double *A, long lda, long sA,
                    const double *B, long ldb, long sB, double beta, double *C, long ldc, long sC, int batch);
+
+/* Same product through the path's reduced-precision GEMM: mode 0 = FP64,
+ * 1 = FP32 matrix cores, 2 = split BF16 with three products; FP64 operands and
+ * result, FP32 accumulation for modes 1 and 2.  Synchronous. */
+int ris_test_gemm(int mode, int M, int N, int K, int transA, int transB, double alpha, const double *A, long lda,
+                  long sA, const double *B, long ldb, long sB, double beta, double *C, long ldc, long sC, int batch);
 
 #ifdef __cplusplus
 }

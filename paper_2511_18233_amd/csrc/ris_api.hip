@@ -55,6 +55,7 @@ struct ris_ctx {
     bool have_int3c = false;
     int nmo = 0, nocc = 0, nvir = 0;
     double alphaJ = 2.0, cx = 0.25;
+    int prec = RIS_FP64;  // arithmetic of the exchange-weight contractions
     double *C = nullptr;    // [nao][nmo] internal AO order
     double *eps = nullptr;  // [nmo]
     double *aiJ = nullptr;   // [nJ][v][o]  raw (ai|P), Coulomb set
@@ -63,10 +64,17 @@ struct ris_ctx {
     double *cvv = nullptr;   // [v][nK][v]  c^P_ab
     double *rvv = nullptr;   // [v][nK][v]  raw (ab|P), exchange set
     double *rvo2 = nullptr;  // [v][o][nK]  raw (aj|P), exchange set
-    std::vector<void *> int3c_allocs;
 
-    // ---- grow-only scratch shared by the calls
-    void *ws = nullptr;
+    // ---- grow-only device regions; after warm-up a request of the same or a
+    // smaller size allocates nothing (hipFree would synchronise the device)
+    struct Pool {
+        void *p = nullptr;
+        size_t bytes = 0;
+    };
+    Pool aux_pool;    // shell tables, permutation, metric and its inverses
+    Pool mo_pool;     // orbitals and the MO blocks kept between calls
+    Pool out_pool;    // staging of combined gradient + NAC outputs
+    void *ws = nullptr;  // scratch shared by the calls
     size_t ws_bytes = 0;
 
     // ---- optional per-stage timing
@@ -125,25 +133,35 @@ void dfree(ris_ctx *c, void *p)
     if (!p) return;
     for (size_t i = 0; i < c->bufs.size(); ++i)
         if (c->bufs[i].p == p) {
-            hipStreamSynchronize(c->stream);
-            hipFree(p);
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipFree(p);
             c->held -= c->bufs[i].bytes;
             c->bufs.erase(c->bufs.begin() + i);
             return;
         }
 }
 
-// Scratch of at least `bytes` (grow-only; contents not preserved across calls).
-char *ws_get(ris_ctx *c, size_t bytes, int *st)
+// Region of at least `bytes` (grow-only; contents not preserved when it grows).
+char *pool_get(ris_ctx *c, ris_ctx::Pool &pl, size_t bytes, int *st)
 {
     *st = RIS_OK;
-    if (bytes <= c->ws_bytes) return (char *)c->ws;
-    dfree(c, c->ws);
-    c->ws = nullptr;
-    c->ws_bytes = 0;
-    c->ws = dalloc(c, bytes, st);
-    if (c->ws) c->ws_bytes = bytes;
-    return (char *)c->ws;
+    if (bytes <= pl.bytes) return (char *)pl.p;
+    dfree(c, pl.p);
+    pl.p = nullptr;
+    pl.bytes = 0;
+    pl.p = dalloc(c, bytes, st);
+    if (pl.p) pl.bytes = bytes;
+    return (char *)pl.p;
+}
+
+// Scratch of at least `bytes` shared by all calls of the context.
+char *ws_get(ris_ctx *c, size_t bytes, int *st)
+{
+    ris_ctx::Pool pl{c->ws, c->ws_bytes};
+    char *p = pool_get(c, pl, bytes, st);
+    c->ws = pl.p;
+    c->ws_bytes = pl.bytes;
+    return p;
 }
 
 // carve consecutive 256-byte aligned pieces out of a scratch block
@@ -159,8 +177,6 @@ struct Carve {
 
 void free_int3c(ris_ctx *c)
 {
-    for (void *p : c->int3c_allocs) dfree(c, p);
-    c->int3c_allocs.clear();
     c->have_int3c = false;
     c->C = c->eps = c->aiJ = c->coo = c->cvo = c->cvv = c->rvv = c->rvo2 = nullptr;
 }
@@ -168,9 +184,6 @@ void free_int3c(ris_ctx *c)
 void free_aux(ris_ctx *c)
 {
     free_int3c(c);
-    for (void *p : {(void *)c->d_ao_perm, (void *)c->MJ, (void *)c->LinvJ, (void *)c->MinvJ, (void *)c->MinvK,
-                    (void *)c->ao.sh.x, (void *)c->aux.sh.x})
-        dfree(c, p);
     c->d_ao_perm = nullptr;
     c->MJ = c->LinvJ = c->MinvJ = c->MinvK = nullptr;
     c->ao = AOGeom{};
@@ -186,7 +199,7 @@ hipEvent_t get_event(ris_ctx *c)
         return e;
     }
     hipEvent_t e = nullptr;
-    hipEventCreate(&e);
+    (void)hipEventCreate(&e);
     return e;
 }
 
@@ -196,7 +209,7 @@ hipEvent_t stage_begin(ris_ctx *c)
 {
     if (!c->prof) return nullptr;
     hipEvent_t a = get_event(c);
-    hipEventRecord(a, c->stream);
+    (void)hipEventRecord(a, c->stream);
     return a;
 }
 
@@ -204,7 +217,7 @@ void stage_end(ris_ctx *c, hipEvent_t a, int stage, double flops, double bytes)
 {
     if (!a) return;
     hipEvent_t b = get_event(c);
-    hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, c->stream);
     c->marks.push_back({stage, a, b, flops, bytes});
 }
 
@@ -217,15 +230,14 @@ void release_marks(ris_ctx *c)
     c->marks.clear();
 }
 
-// Upload a shell table: 5 double arrays + 2 int arrays in one allocation.
+// Shell table: 5 double arrays + 2 int arrays, bytes needed and upload into dst.
+size_t shell_bytes(int n) { return ((size_t)5 * n * 8 + ((size_t)2 * n + 1) * 4 + 255) / 256 * 256; }
+
 int upload_shells(ris_ctx *c, int n, const std::vector<double> &x, const std::vector<double> &y,
                   const std::vector<double> &z, const std::vector<double> &e, const std::vector<double> &nrm,
-                  const std::vector<int> &atom, const std::vector<int> &off, ShellTab *out)
+                  const std::vector<int> &atom, const std::vector<int> &off, char *base, ShellTab *out)
 {
     const size_t nd = (size_t)5 * n, ni = (size_t)2 * n + 1;
-    int st;
-    char *base = (char *)dalloc(c, nd * 8 + ni * 4, &st);
-    if (!base) return st;
     std::vector<char> h(nd * 8 + ni * 4);
     double *hd = (double *)h.data();
     memcpy(hd + 0 * n, x.data(), 8 * n);
@@ -268,6 +280,125 @@ GemmArgs gm(int M, int N, int K, bool tA, bool tB, double alpha, const double *A
 
 }  // namespace
 
+// ---- sizes of every device region, shared by the calls and ris_request_bytes
+struct Dims {
+    int N, nmo, o, v, nJ, nK, nshAO, nshJ, natm;
+};
+
+struct MoLayout {
+    size_t oC, oE, oA, oOO, oVO, oVV, oRVV, oRVO, total;
+};
+MoLayout mo_layout(const Dims &d)
+{
+    Carve pv;
+    MoLayout L;
+    const long vo = (long)d.v * d.o;
+    L.oC = pv.take((size_t)d.N * d.nmo);
+    L.oE = pv.take(d.nmo);
+    L.oA = pv.take((size_t)d.nJ * vo);
+    L.oOO = pv.take((size_t)d.nK * d.o * d.o);
+    L.oVO = pv.take((size_t)d.nK * vo);
+    L.oVV = pv.take((size_t)d.nK * d.v * d.v);
+    L.oRVV = pv.take((size_t)d.nK * d.v * d.v);
+    L.oRVO = pv.take((size_t)d.nK * vo);
+    L.total = pv.off;
+    return L;
+}
+
+struct Int3cWs {
+    size_t oX, oZ, oOO, oVO, total;
+};
+Int3cWs int3c_ws(const Dims &d)
+{
+    Carve cv;
+    Int3cWs L;
+    const size_t NN = (size_t)d.N * d.N;
+    const size_t zel = std::max((size_t)d.nJ * d.N * d.o, (size_t)d.nK * d.N * d.v);
+    L.oX = cv.take((size_t)d.nJ * NN);
+    L.oZ = cv.take(zel);
+    L.oOO = cv.take((size_t)d.nK * d.o * d.o);
+    L.oVO = cv.take((size_t)d.nK * d.v * d.o);
+    L.total = cv.off;
+    return L;
+}
+
+struct MatvecWs {
+    size_t ot, oT, oS, total;
+};
+MatvecWs matvec_ws(const Dims &d, int nvec)
+{
+    Carve cv;
+    MatvecWs L;
+    const int chunk = std::min(nvec, 8);
+    const long vo = (long)d.v * d.o, oo = (long)d.o * d.o;
+    L.ot = cv.take((size_t)nvec * d.nJ * 2);
+    L.oT = cv.take((size_t)chunk * d.nK * vo);
+    L.oS = cv.take((size_t)chunk * d.nK * oo);
+    L.total = cv.off;
+    return L;
+}
+
+constexpr int kSplitV = 64;  // K-split of the V_PQ products
+struct ContractWs {
+    size_t oR, oL, oRLT, oF, oD, otT, ocv, oTall, oHUO, oHOU, oHUU, oW, oHc, oY, oG, oV2, oSK, op3, op2, oshA, oshC,
+        oshP, total;
+};
+ContractWs contract_ws(const Dims &d, int ns)
+{
+    Carve cv;
+    ContractWs L;
+    const long vo = (long)d.v * d.o, NN = (long)d.N * d.N, o3 = 3L * d.o, oo = (long)d.o * d.o;
+    const long w2 = 2L * ns * d.o;
+    const int NO = kMaxOutChunk;
+    L.oR = cv.take((size_t)ns * vo);
+    L.oL = cv.take((size_t)ns * vo);
+    L.oRLT = cv.take((size_t)d.v * w2);
+    L.oF = cv.take((size_t)ns * d.N * o3);
+    L.oD = cv.take((size_t)ns * NN);
+    L.otT = cv.take((size_t)ns * d.nJ);
+    L.ocv = cv.take((size_t)ns * d.nJ);
+    L.oTall = cv.take((size_t)d.v * d.nK * w2);
+    L.oHUO = cv.take((size_t)w2 * d.nK * d.o);
+    L.oHOU = cv.take((size_t)d.nK * d.o * w2);
+    L.oHUU = cv.take((size_t)2 * d.nK * oo);
+    L.oW = cv.take((size_t)d.nK * o3 * o3);
+    L.oHc = cv.take((size_t)d.nK * o3 * o3);
+    L.oY = cv.take((size_t)d.nK * d.N * o3);
+    L.oG = cv.take((size_t)NO * d.nK * NN);
+    L.oV2 = cv.take((size_t)NO * d.nJ * d.nJ);
+    L.oSK = cv.take((size_t)kSplitV * d.nK * d.nK);
+    L.op3 = cv.take((size_t)d.nshAO * d.nshJ * 3 * NO * 6);
+    L.op2 = cv.take((size_t)d.nshJ * 2 * NO * 3);
+    L.oshA = cv.take((size_t)d.nshAO * NO * 3);
+    L.oshC = cv.take((size_t)d.nshJ * NO * 3);
+    L.oshP = cv.take((size_t)d.nshJ * NO * 3);
+    L.total = cv.off;
+    return L;
+}
+
+struct AuxLayout {
+    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, total;
+};
+AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
+{
+    Carve cv;
+    AuxLayout L;
+    L.oAO = cv.take(shell_bytes(nsh) / 8 + 1);
+    L.oAX = cv.take(shell_bytes(nshJ) / 8 + 1);
+    L.oP = cv.take(nao / 2 + 1);
+    L.oMJ = cv.take((size_t)nJ * nJ);
+    L.oLJ = cv.take((size_t)nJ * nJ);
+    L.oIJ = cv.take((size_t)nJ * nJ);
+    L.oIK = cv.take((size_t)nK * nK);
+    L.total = cv.off;
+    return L;
+}
+
+Dims ctx_dims(const ris_ctx *c)
+{
+    return Dims{c->nao, c->nmo, c->nocc, c->nvir, c->nJ, c->nK, c->nshAO, c->nshJ, c->natm};
+}
+
 // ========================================================================
 extern "C" {
 
@@ -308,12 +439,31 @@ int ris_ctx_create(ris_ctx **out, int device, void *hip_stream, size_t hbm_budge
 void ris_ctx_destroy(ris_ctx *c)
 {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
-    for (auto &b : c->bufs) hipFree(b.p);
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &b : c->bufs) (void)hipFree(b.p);
     release_marks(c);
     for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
     delete c;
+}
+
+size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int nocc, int nstate, int nvec,
+                         int nout)
+{
+    if (!mol || !opts || mol->natm <= 0 || mol->nshell <= 0 || nocc <= 0 || nmo <= nocc) return 0;
+    int nao = 0, nheavy = 0;
+    for (int s = 0; s < mol->nshell; ++s) nao += ncart(mol->shell_l[s]);
+    for (int a = 0; a < mol->natm; ++a) nheavy += (mol->Z[a] > 1);
+    const int natm = mol->natm;
+    const int nshJ = natm + (opts->j_p_on_heavy ? nheavy : 0);
+    const int nJ = natm + (opts->j_p_on_heavy ? 3 * nheavy : 0);
+    const Dims d{nao, nmo, nocc, nmo - nocc, nJ, natm, mol->shell_l ? mol->nshell : 0, nshJ, natm};
+    size_t ws = int3c_ws(d).total;
+    if (nvec > 0) ws = std::max(ws, matvec_ws(d, nvec).total);
+    if (nstate > 0) ws = std::max(ws, contract_ws(d, nstate).total);
+    const size_t fixed = (size_t)8 * kBoysNGrid * kBoysCols + 64;
+    return fixed + aux_layout(mol->nshell, nshJ, nao, nJ, natm).total + mo_layout(d).total + ws +
+           (size_t)8 * std::max(nout, 0) * natm * 3;
 }
 
 int ris_ctx_set_profiling(ris_ctx *c, int enable)
@@ -408,8 +558,6 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         f += ncart(l);
     }
     off[nsh] = f;
-    int st = upload_shells(c, nsh, x, y, z, e, nr, at, off, &c->ao.sh);
-    if (st) return st;
     c->ao.nshell = nsh;
     c->ao.nao = nao;
     c->h_ao_atom = at;
@@ -437,8 +585,22 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         f += ncart(jl[i]);
     }
     aoff[nshJ] = f;
-    st = upload_shells(c, nshJ, ax, ay, az, ae, anr, aat, aoff, &c->aux.sh);
-    if (st) return st;
+    // one region for the tables, the permutation and the metric matrices
+    {
+        const AuxLayout AL = aux_layout(nsh, nshJ, nao, f, natm);
+        int st0;
+        char *base = pool_get(c, c->aux_pool, AL.total, &st0);
+        if (!base) return st0;
+        int st1 = upload_shells(c, nsh, x, y, z, e, nr, at, off, base + AL.oAO, &c->ao.sh);
+        if (st1) return st1;
+        st1 = upload_shells(c, nshJ, ax, ay, az, ae, anr, aat, aoff, base + AL.oAX, &c->aux.sh);
+        if (st1) return st1;
+        c->d_ao_perm = (int *)(base + AL.oP);
+        c->MJ = (double *)(base + AL.oMJ);
+        c->LinvJ = (double *)(base + AL.oLJ);
+        c->MinvJ = (double *)(base + AL.oIJ);
+        c->MinvK = (double *)(base + AL.oIK);
+    }
     c->aux.nshell = nshJ;
     c->aux.nfunc = f;
     c->auxl_beg[0] = 0;
@@ -453,20 +615,10 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
     c->nshJ = nshJ;
     c->nsJ = natm;
 
-    c->d_ao_perm = (int *)dalloc(c, sizeof(int) * nao, &st);
-    if (!c->d_ao_perm) return st;
     HIPCHK(c, hipMemcpyAsync(c->d_ao_perm, c->h_ao_perm.data(), sizeof(int) * nao, hipMemcpyHostToDevice, c->stream));
 
     // --- metric, Cholesky, inverses
     const int nJ = c->nJ, nK = c->nK;
-    c->MJ = (double *)dalloc(c, sizeof(double) * nJ * nJ, &st);
-    if (!c->MJ) return st;
-    c->LinvJ = (double *)dalloc(c, sizeof(double) * nJ * nJ, &st);
-    if (!c->LinvJ) return st;
-    c->MinvJ = (double *)dalloc(c, sizeof(double) * nJ * nJ, &st);
-    if (!c->MinvJ) return st;
-    c->MinvK = (double *)dalloc(c, sizeof(double) * nK * nK, &st);
-    if (!c->MinvK) return st;
     HIPCHK(c, launch_int2c(c->aux, c->boys, c->MJ, c->stream));
     // factor a copy (MJ keeps the metric itself)
     HIPCHK(c, hipMemcpyAsync(c->MinvJ, c->MJ, sizeof(double) * nJ * nJ, hipMemcpyDeviceToDevice, c->stream));
@@ -496,7 +648,8 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
     if (mo->nao != c->nao) return fail(c, RIS_E_INVALID, "nao %d does not match the basis (%d)", mo->nao, c->nao);
     if (mo->nocc <= 0 || mo->nocc >= mo->nmo || mo->nmo > mo->nao)
         return fail(c, RIS_E_INVALID, "need 0 < nocc < nmo <= nao (nocc=%d nmo=%d)", mo->nocc, mo->nmo);
-    if (mo->precision != RIS_FP64) return fail(c, RIS_E_UNSUPPORTED, "precision mode %d not built", mo->precision);
+    if (mo->precision < RIS_FP64 || mo->precision > RIS_BF16X3)
+        return fail(c, RIS_E_UNSUPPORTED, "precision mode %d not built", mo->precision);
     HIPCHK(c, hipSetDevice(c->device));
     free_int3c(c);
 
@@ -506,36 +659,34 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
     c->nvir = v;
     c->alphaJ = mo->alpha_J;
     c->cx = mo->c_x;
+    c->prec = mo->precision;
     const size_t NN = (size_t)N * N;
     const long vo = (long)v * o;
 
-    // persistent: C, eps, aiJ, coo, cvo, cvv, rvv, rvo2
-    const size_t persist = 8 * ((size_t)N * nmo + nmo + (size_t)nJ * vo + (size_t)nK * o * o + 2 * (size_t)nK * vo +
-                                2 * (size_t)nK * v * v);
-    // scratch: X, Z (max of the two passes), (ij|P), (aj|P) in [a][P][j] order
-    const size_t zel = std::max((size_t)nJ * N * o, (size_t)nK * N * v);
-    const size_t scratch = 8 * ((size_t)nJ * NN + zel + (size_t)nK * o * o + (size_t)nK * vo) + 4 * 256;
-    if (c->held + persist + scratch > c->budget + c->ws_bytes)
+    const Dims dm = ctx_dims(c);
+    const MoLayout ML = mo_layout(dm);
+    const Int3cWs IW = int3c_ws(dm);
+    const size_t other = c->held - c->mo_pool.bytes - c->ws_bytes;  // what stays allocated meanwhile
+    if (other + ML.total + std::max(IW.total, c->ws_bytes) > c->budget)
         return fail(c, RIS_E_NOMEM, "int3c needs %.2f GB (persistent %.2f GB); budget %.2f GB, %.2f GB held",
-                    (persist + scratch) / 1e9, persist / 1e9, c->budget / 1e9, c->held / 1e9);
+                    (ML.total + IW.total) / 1e9, ML.total / 1e9, c->budget / 1e9, other / 1e9);
     int st;
-    auto take = [&](size_t elems) -> double * {
-        double *p = (double *)dalloc(c, elems * 8, &st);
-        if (p) c->int3c_allocs.push_back(p);
-        return p;
-    };
-    if (!(c->C = take((size_t)N * nmo)) || !(c->eps = take(nmo)) || !(c->aiJ = take((size_t)nJ * vo)) ||
-        !(c->coo = take((size_t)nK * o * o)) || !(c->cvo = take((size_t)nK * vo)) ||
-        !(c->cvv = take((size_t)nK * v * v)) || !(c->rvv = take((size_t)nK * v * v)) ||
-        !(c->rvo2 = take((size_t)nK * vo)))
-        return st;
-    Carve cv;
-    const size_t oX = cv.take((size_t)nJ * NN), oZ = cv.take(zel), oOO = cv.take((size_t)nK * o * o),
-                 oVO = cv.take((size_t)nK * vo);
-    char *wsb = ws_get(c, cv.off, &st);
+    {
+        char *pb = pool_get(c, c->mo_pool, ML.total, &st);
+        if (!pb) return st;
+        c->C = (double *)(pb + ML.oC);
+        c->eps = (double *)(pb + ML.oE);
+        c->aiJ = (double *)(pb + ML.oA);
+        c->coo = (double *)(pb + ML.oOO);
+        c->cvo = (double *)(pb + ML.oVO);
+        c->cvv = (double *)(pb + ML.oVV);
+        c->rvv = (double *)(pb + ML.oRVV);
+        c->rvo2 = (double *)(pb + ML.oRVO);
+    }
+    char *wsb = ws_get(c, IW.total, &st);
     if (!wsb) return st;
-    double *X = (double *)(wsb + oX), *Z = (double *)(wsb + oZ), *rawoo = (double *)(wsb + oOO),
-           *rvoP = (double *)(wsb + oVO);
+    double *X = (double *)(wsb + IW.oX), *Z = (double *)(wsb + IW.oZ), *rawoo = (double *)(wsb + IW.oOO),
+           *rvoP = (double *)(wsb + IW.oVO);
 
     // C rows into the internal (l-sorted) AO order
     HIPCHK(c, gather_rows(mo->C, c->C, c->d_ao_perm, N, nmo, nmo, c->stream));
@@ -605,14 +756,12 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
     // coefficients of Delta, J, K_A, K_B for A, B, A+B, A-B
     static const double cDe[4] = {1, 0, 1, 1}, cJ[4] = {1, 1, 2, 0}, cKA[4] = {1, 0, 1, 1}, cKB[4] = {0, 1, 1, -1};
     const int chunk = std::min(nvec, 8);
-    Carve cv;
-    const size_t ot = cv.take((size_t)nvec * nJ * 2), oT = cv.take((size_t)chunk * nK * vo),
-                 oS = cv.take((size_t)chunk * nK * oo);
+    const MatvecWs MW = matvec_ws(ctx_dims(c), nvec);
     int st;
-    char *wsb = ws_get(c, cv.off, &st);
+    char *wsb = ws_get(c, MW.total, &st);
     if (!wsb) return st;
-    double *t = (double *)(wsb + ot), *cc = t + (size_t)nvec * nJ, *T = (double *)(wsb + oT),
-           *S = (double *)(wsb + oS);
+    double *t = (double *)(wsb + MW.ot), *cc = t + (size_t)nvec * nJ, *T = (double *)(wsb + MW.oT),
+           *S = (double *)(wsb + MW.oS);
     hipEvent_t t_mv = stage_begin(c);
     // Coulomb: t = V (ai|P)^T ; cc = t M_J^-1 ; out = cJ alpha_J cc (ai|P)
     HIPCHK(c, dgemm(gm(nvec, nJ, (int)vo, false, true, 1.0, V, vo, c->aiJ, vo, 0.0, t, nJ), c->stream));
@@ -629,20 +778,20 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
             for (int k = 0; k < nv; ++k) {
                 GemmArgs g = gm(v, o, o, false, true, 1.0, Vk + k * vo, o, c->coo, o, 0.0, T + (size_t)k * nK * vo, o);
                 g.batch = nK; g.strideA = 0; g.strideB = oo; g.strideC = vo;
-                HIPCHK(c, dgemm(g, c->stream));
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
             GemmArgs g = gm(v, o, nK * v, false, false, -cKA[op] * c->cx, c->rvv, (long)nK * v, T, o, 1.0, ok, o);
             g.batch = nv; g.strideA = 0; g.strideB = (long)nK * vo; g.strideC = vo;
-            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
         }
         if (cKB[op] != 0.0) {
             // S_k[j][P][i] = sum_b V_k[b][j] c_vo^P[b][i];  out_k -= c_x sum_{j,P} (aj|P) S_k[j][P][i]
             GemmArgs g = gm(o, nK * o, v, true, false, 1.0, Vk, o, c->cvo, (long)nK * o, 0.0, S, (long)nK * o);
             g.batch = nv; g.strideA = vo; g.strideB = 0; g.strideC = (long)nK * oo;
-            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             g = gm(v, o, o * nK, false, false, -cKB[op] * c->cx, c->rvo2, (long)o * nK, S, o, 1.0, ok, o);
             g.batch = nv; g.strideA = 0; g.strideB = (long)nK * oo; g.strideC = vo;
-            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
         }
     }
     {
@@ -670,26 +819,16 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
     const int ns = nstate;
     const long w2 = 2L * ns * o;  // columns of RLT / Tall: (t, s, i)
     const int NO = kMaxOutChunk;
-    const int nsplit = 64;
-    Carve cv;
-    const size_t oR = cv.take((size_t)ns * vo), oL = cv.take((size_t)ns * vo), oRLT = cv.take((size_t)v * w2),
-                 oF = cv.take((size_t)ns * N * o3), oD = cv.take((size_t)ns * NN), otT = cv.take((size_t)ns * nJ),
-                 ocv = cv.take((size_t)ns * nJ), oTall = cv.take((size_t)v * nK * w2),
-                 oHUO = cv.take((size_t)w2 * nK * o), oHOU = cv.take((size_t)nK * o * w2),
-                 oHUU = cv.take((size_t)2 * nK * oo), oW = cv.take((size_t)nK * o3 * o3),
-                 oHc = cv.take((size_t)nK * o3 * o3), oY = cv.take((size_t)nK * N * o3),
-                 oG = cv.take((size_t)NO * nK * NN), oV2 = cv.take((size_t)NO * nJ * nJ),
-                 oSK = cv.take((size_t)nsplit * nK * nK), op3 = cv.take((size_t)c->nshAO * c->nshJ * 3 * NO * 6),
-                 op2 = cv.take((size_t)c->nshJ * 2 * NO * 3), oshA = cv.take((size_t)c->nshAO * NO * 3),
-                 oshC = cv.take((size_t)c->nshJ * NO * 3), oshP = cv.take((size_t)c->nshJ * NO * 3);
+    const int nsplit = kSplitV;
+    const ContractWs CW = contract_ws(ctx_dims(c), ns);
     int st;
-    char *wsb = ws_get(c, cv.off, &st);
+    char *wsb = ws_get(c, CW.total, &st);
     if (!wsb) return st;
     auto P_ = [&](size_t off) { return (double *)(wsb + off); };
-    double *R = P_(oR), *L = P_(oL), *RLT = P_(oRLT), *F = P_(oF), *D = P_(oD), *tT = P_(otT), *cvec = P_(ocv),
-           *Tall = P_(oTall), *HUO = P_(oHUO), *HOU = P_(oHOU), *HUU = P_(oHUU), *W = P_(oW), *Hc = P_(oHc),
-           *Y3 = P_(oY), *G = P_(oG), *V2 = P_(oV2), *SK = P_(oSK), *p3 = P_(op3), *p2 = P_(op2), *shA = P_(oshA),
-           *shC = P_(oshC), *shP = P_(oshP);
+    double *R = P_(CW.oR), *L = P_(CW.oL), *RLT = P_(CW.oRLT), *F = P_(CW.oF), *D = P_(CW.oD), *tT = P_(CW.otT),
+           *cvec = P_(CW.ocv), *Tall = P_(CW.oTall), *HUO = P_(CW.oHUO), *HOU = P_(CW.oHOU), *HUU = P_(CW.oHUU),
+           *W = P_(CW.oW), *Hc = P_(CW.oHc), *Y3 = P_(CW.oY), *G = P_(CW.oG), *V2 = P_(CW.oV2), *SK = P_(CW.oSK),
+           *p3 = P_(CW.op3), *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP);
     const double *CO = c->C, *CV = c->C + o;
 
     // ---- per-state intermediates
@@ -718,13 +857,14 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         HIPCHK(c, dgemm(gm(ns, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), c->stream));
         HIPCHK(c, dgemm(gm(ns, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
         // Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j]
-        HIPCHK(c, dgemm(gm(v * nK, (int)w2, v, false, false, 1.0, c->cvv, v, RLT, w2, 0.0, Tall, w2), c->stream));
+        HIPCHK(c, gemm_mp(gm(v * nK, (int)w2, v, false, false, 1.0, c->cvv, v, RLT, w2, 0.0, Tall, w2), c->prec,
+                          c->stream));
         // HUO[(t,s,i)][(P,j)] = sum_a (R,L)_s[a][i] c_vo^P[a][j]  (= H_UO blocks)
-        HIPCHK(c, dgemm(gm((int)w2, nK * o, v, true, false, 1.0, RLT, w2, c->cvo, (long)nK * o, 0.0, HUO,
-                           (long)nK * o), c->stream));
+        HIPCHK(c, gemm_mp(gm((int)w2, nK * o, v, true, false, 1.0, RLT, w2, c->cvo, (long)nK * o, 0.0, HUO,
+                             (long)nK * o), c->prec, c->stream));
         // HOU[(P,i)][(t,s,j)] = sum_b c_vo^P[b][i] (R,L)_s[b][j]  (= H_OU blocks)
-        HIPCHK(c, dgemm(gm(nK * o, (int)w2, v, true, false, 1.0, c->cvo, (long)nK * o, RLT, w2, 0.0, HOU, w2),
-                        c->stream));
+        HIPCHK(c, gemm_mp(gm(nK * o, (int)w2, v, true, false, 1.0, c->cvo, (long)nK * o, RLT, w2, 0.0, HOU, w2),
+                          c->prec, c->stream));
     }
     stage_end(c, t_h, RIS_STAGE_HBLK,
               2.0 * (double)v * nK * w2 * v + 4.0 * (double)w2 * nK * o * v + 2.0 * ns * ((double)N * N * o) +
@@ -756,7 +896,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
                 GemmArgs g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2,
                                 Tall + (size_t)(t * ns + J) * o, (long)nK * w2, 0.0, HUU + (size_t)t * nK * oo, o);
                 g.batch = nK; g.strideA = 0; g.strideB = w2; g.strideC = oo;
-                HIPCHK(c, dgemm(g, c->stream));
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
             stage_end(c, t_u, RIS_STAGE_HBLK, 4.0 * (double)nK * oo * v, 0.0);
             const BlockSrc Hoo = blk(c->coo, oo, o, 1, 1.0);
@@ -790,12 +930,12 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             // Y^P = F_I W^P ; Gamma^P = -2 c_x Y^P F_J^T
             GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, F + (size_t)I * N * o3, o3, W, o3, 0.0, Y3, o3);
             g.batch = nK; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
-            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             double *Gk = G + (size_t)k * nK * NN;
             g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, F + (size_t)J * N * o3, o3, 0.0, Gk, N);
             g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
             hipEvent_t t_g = stage_begin(c);
-            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nK * N * N * o3,
                       8.0 * ((double)nK * N * N + (double)nK * N * o3 + (double)N * o3));
             if (I != J) HIPCHK(c, symmetrize(Gk, N, nK, c->stream));
@@ -840,7 +980,7 @@ int ris_grad_nac_contract(ris_ctx *c, int nstate, const double *X, const double 
     double *out = nullptr;
     const size_t per = (size_t)c->natm * 3;
     if (nsel > 0 && npair > 0) {
-        out = (double *)dalloc(c, 8 * per * nout, &st);
+        out = (double *)pool_get(c, c->out_pool, 8 * per * nout, &st);
         if (!out) return st;
     } else {
         out = nsel > 0 ? grad : nac;
@@ -851,7 +991,6 @@ int ris_grad_nac_contract(ris_ctx *c, int nstate, const double *X, const double 
         HIPCHK(c, hipMemcpyAsync(nac, out + per * nsel, 8 * per * npair, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    if (out != grad && out != nac) dfree(c, out);
     if (st || !omega || npair == 0) return st;
     bool degenerate = false;
     for (int k = 0; k < npair; ++k) {

@@ -92,6 +92,10 @@ hipError_t dgemm(const GemmArgs &g, hipStream_t st);
 // Same product with K cut into nsplit ranges (batch == 1, nred == 1): partials
 // go to ws (nsplit * M * N doubles) and are summed in a fixed order.
 hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st);
+// Same contract with the products on reduced-precision matrix cores (FP64 in
+// and out, FP32 accumulation): mode 0 = FP64 (dgemm), 1 = FP32, 2 = split BF16
+// with three products (ris_gemm_mp.hip).
+hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st);
 
 // Dense linear algebra on small matrices (ris_linalg.hip).
 // In-place Cholesky of the n x n SPD matrix (lower triangle written, upper

@@ -20,26 +20,50 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int PAD = 2;  // LDS row padding (doubles) against bank conflicts on the transposing stores
+constexpr int PAD = 2;    // LDS row padding (doubles) against bank conflicts on the transposing stores
+constexpr int NXCD = 8;   // accelerator complex dies on MI355X, each with its own L2
+constexpr int GROUP_M = 2;  // m-tiles swept together so their A panels stay in L2
+
+// Linear workgroup id -> (batch, m-tile, n-tile).  Workgroups are dispatched
+// round-robin over the XCDs, so id b runs on XCD b % 8; remapping gives each
+// XCD one contiguous range of tiles.  Inside a batch the tiles are walked in
+// groups of GROUP_M m-tiles with the n-tile as the slower index, so one B
+// panel serves GROUP_M consecutive tiles and the group's A panels stay hot.
+__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, int &z, int &mt, int &nt)
+{
+    const int q = total / NXCD, r = total % NXCD;
+    const int xcd = b % NXCD, local = b / NXCD;
+    const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+    const int per = tm * tn;
+    z = lin / per;
+    const int t = lin % per;
+    const int gsz = GROUP_M * tn;                  // tiles per full group
+    const int g = t / gsz, tg = t % gsz;
+    const int m0 = g * GROUP_M;
+    const int gm = min(GROUP_M, tm - m0);          // rows in this (possibly short) group
+    mt = m0 + tg % gm;
+    nt = tg / gm;
+}
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                long lda, long sA, long sAr, const double *__restrict__ B, long ldb,
                                                long sB, long sBr, double beta, double *__restrict__ C, long ldc,
-                                               long sC, int nred)
+                                               long sC, int nred, int tm, int tn, int total)
 {
-    __shared__ double As[BK][BM + PAD];
-    __shared__ double Bs[BK][BN + PAD];
+    __shared__ double As[2][BK][BM + PAD];
+    __shared__ double Bs[2][BK][BN + PAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const long bz = blockIdx.z;
-    A += bz * sA;
-    B += bz * sB;
-    C += bz * sC;
+    int bz, mt, nt;
+    tile_of(blockIdx.x, total, tm, tn, bz, mt, nt);
+    const int m0 = mt * BM, n0 = nt * BN;
+    A += (long)bz * sA;
+    B += (long)bz * sB;
+    C += (long)bz * sC;
 
     v4d acc[4][4];
 #pragma unroll
@@ -50,7 +74,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
     // global -> register staging: 8 doubles of A and 8 of B per thread
     double ra[8], rb[8];
     const int ktiles = (K + BK - 1) / BK;
-    const int total = ktiles * nred;
+    const int niter = ktiles * nred;
 
     auto load = [&](int it) {
         const int r = it / ktiles;
@@ -79,35 +103,41 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
             }
         }
     };
-    auto store = [&]() {
+    auto store = [&](int stg) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            if (!TA) As[tid & 15][(tid >> 4) + 16 * q] = ra[q];
-            else As[(tid >> 7) + 2 * q][tid & 127] = ra[q];
-            if (!TB) Bs[(tid >> 7) + 2 * q][tid & 127] = rb[q];
-            else Bs[tid & 15][(tid >> 4) + 16 * q] = rb[q];
+            if (!TA) As[stg][tid & 15][(tid >> 4) + 16 * q] = ra[q];
+            else As[stg][(tid >> 7) + 2 * q][tid & 127] = ra[q];
+            if (!TB) Bs[stg][(tid >> 7) + 2 * q][tid & 127] = rb[q];
+            else Bs[stg][tid & 15][(tid >> 4) + 16 * q] = rb[q];
         }
     };
 
-    if (total > 0) load(0);
-    for (int it = 0; it < total; ++it) {
-        __syncthreads();
-        store();
-        __syncthreads();
-        if (it + 1 < total) load(it + 1);
+    if (niter > 0) {
+        load(0);
+        store(0);
+    }
+    __syncthreads();
+    for (int it = 0; it < niter; ++it) {
+        const int cur = it & 1;
+        // the next slab is in flight while the current one feeds the matrix cores
+        if (it + 1 < niter) load(it + 1);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double fa[4], fb[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fa[i] = As[kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
+            for (int i = 0; i < 4; ++i) fa[i] = As[cur][kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) fb[j] = Bs[kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
+            for (int j = 0; j < 4; ++j) fb[j] = Bs[cur][kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
         }
+        // the other stage was last read in iteration it-1, before the barrier that ended it
+        if (it + 1 < niter) store(cur ^ 1);
+        __syncthreads();
     }
 
 #pragma unroll
@@ -132,20 +162,20 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
 hipError_t dgemm(const GemmArgs &g, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
+    const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    const long total = (long)tm * tn * g.batch;
+    if (total > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)total);
     const int nred = g.nred > 0 ? g.nred : 1;
-    if (!g.transA && !g.transB)
-        hipLaunchKernelGGL((k_dgemm<false, false>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,
-                           g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred);
-    else if (g.transA && !g.transB)
-        hipLaunchKernelGGL((k_dgemm<true, false>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,
-                           g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred);
-    else if (!g.transA && g.transB)
-        hipLaunchKernelGGL((k_dgemm<false, true>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,
-                           g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred);
-    else
-        hipLaunchKernelGGL((k_dgemm<true, true>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,
-                           g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred);
+#define RIS_GEMM_LAUNCH(TA, TB)                                                                                   \
+    hipLaunchKernelGGL((k_dgemm<TA, TB>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.strideA,   \
+                       g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, \
+                       (int)total)
+    if (!g.transA && !g.transB) RIS_GEMM_LAUNCH(false, false);
+    else if (g.transA && !g.transB) RIS_GEMM_LAUNCH(true, false);
+    else if (!g.transA && g.transB) RIS_GEMM_LAUNCH(false, true);
+    else RIS_GEMM_LAUNCH(true, true);
+#undef RIS_GEMM_LAUNCH
     return hipGetLastError();
 }
 
@@ -153,20 +183,43 @@ hipError_t dgemm(const GemmArgs &g, hipStream_t st)
 
 // ---------------------------------------------------------------- tests --
 namespace {
-__global__ __launch_bounds__(64) void k_mfma_probe(const double *a, const double *b, double *out)
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
+
+// kind 0: v_mfma_f64_16x16x4f64 (1 value per lane); kind 1: v_mfma_f32_16x16x4f32
+// (1 value per lane); kind 2: v_mfma_f32_16x16x32_bf16 (8 values per lane).
+__global__ __launch_bounds__(64) void k_mfma_probe(int kind, const double *a, const double *b, double *out)
 {
     const int lane = threadIdx.x;
-    ris::v4d acc = ris::v4d{0.0, 0.0, 0.0, 0.0};
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lane], b[lane], acc, 0, 0, 0);
+    if (kind == 0) {
+        ris::v4d acc = ris::v4d{0.0, 0.0, 0.0, 0.0};
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[lane], b[lane], acc, 0, 0, 0);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) out[4 * lane + e] = acc[e];
+        for (int e = 0; e < 4; ++e) out[4 * lane + e] = acc[e];
+    } else if (kind == 1) {
+        v4f_t acc = v4f_t{0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[lane], (float)b[lane], acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[4 * lane + e] = acc[e];
+    } else {
+        v8bf_t av, bv;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            av[i] = (__bf16)(float)a[8 * lane + i];
+            bv[i] = (__bf16)(float)b[8 * lane + i];
+        }
+        v4f_t acc = v4f_t{0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[4 * lane + e] = acc[e];
+    }
 }
 }  // namespace
 
-extern "C" int ris_test_mfma_probe(const double *a, const double *b, double *out)
+extern "C" int ris_test_mfma_probe(int kind, const double *a, const double *b, double *out)
 {
-    if (!a || !b || !out) return 1;
-    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, 0, a, b, out);
+    if (!a || !b || !out || kind < 0 || kind > 2) return 1;
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, 0, kind, a, b, out);
     if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) return 7;
     return 0;
 }

@@ -20,12 +20,14 @@ RIS_OK = 0
 STATUS = {0: "RIS_OK", 1: "RIS_E_INVALID", 2: "RIS_E_UNSUPPORTED", 3: "RIS_E_NOMEM", 4: "RIS_E_NOT_PD",
           5: "RIS_E_DEGENERATE", 6: "RIS_E_ORDER", 7: "RIS_E_DEVICE"}
 OPS = {"A": 0, "B": 1, "A+B": 2, "A-B": 3}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
            "ris_response_matvec", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
+           "ris_request_bytes",
            "ris_ctx_set_profiling",
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
-           "ris_test_mfma_probe", "ris_test_dgemm")
+           "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm")
 
 
 class RisError(RuntimeError):
@@ -76,15 +78,37 @@ def load_library(path: str = LIB_PATH):
     lib.ris_response_matvec.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.ris_grad_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp]
     lib.ris_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, dp, vp]
+    lib.ris_request_bytes.argtypes = [ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.ris_request_bytes.restype = ctypes.c_size_t
     lib.ris_grad_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp, ctypes.c_int, ip, dp, vp]
     lib.ris_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.ris_ctx_stage_stats.argtypes = [vp, ctypes.c_int, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
-    lib.ris_test_mfma_probe.argtypes = [vp, vp, vp]
+    lib.ris_test_mfma_probe.argtypes = [ctypes.c_int, vp, vp, vp]
     L = ctypes.c_long
     lib.ris_test_dgemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_double, vp, L, L, vp, L, L, ctypes.c_double, vp, L, L, ctypes.c_int]
+    lib.ris_test_gemm.argtypes = [ctypes.c_int] + lib.ris_test_dgemm.argtypes
     _lib = lib
     return lib
+
+
+def request_bytes(Z, shell_atom, shell_l, radius_bohr, nmo, nocc, nstate, nvec=0, nout=0, theta=0.2,
+                  j_p_on_heavy=True) -> int:
+    """Device bytes one request needs (host-only sizing from the library)."""
+    lib = load_library()
+    Z = np.ascontiguousarray(Z, dtype=np.int32)
+    sa = np.ascontiguousarray(shell_atom, dtype=np.int32)
+    sl = np.ascontiguousarray(shell_l, dtype=np.int32)
+    se = np.ones(sl.shape[0])
+    xyz = np.zeros((Z.shape[0], 3))
+    rad = np.ascontiguousarray(radius_bohr, dtype=np.float64)
+    ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    mol = _Mol(Z.shape[0], Z.ctypes.data_as(ip), xyz.ctypes.data_as(dp), sl.shape[0], sa.ctypes.data_as(ip),
+               sl.ctypes.data_as(ip), se.ctypes.data_as(dp))
+    opts = _AuxOpts(float(theta), rad.ctypes.data_as(dp), int(bool(j_p_on_heavy)))
+    return int(lib.ris_request_bytes(ctypes.byref(mol), ctypes.byref(opts), int(nmo), int(nocc), int(nstate),
+                                     int(nvec), int(nout)))
 
 
 def _ptr(t):
@@ -183,6 +207,8 @@ class RisContext:
         _check_dev(eps, self.device, "eps")
         _check_dev(dbg, self.device, "dbg")
         nao, nmo = C.shape
+        if isinstance(precision, str):
+            precision = PRECISION[precision]
         mo = _MO(nao, nmo, int(nocc), C.data_ptr(), eps.data_ptr(), float(alpha_J), float(c_x), int(precision))
         self._chk(self.lib.ris_int3c(self.h, ctypes.byref(mo), _ptr(dbg)))
         self.nocc, self.nvir = int(nocc), int(nmo - nocc)

@@ -31,7 +31,7 @@ def test_mfma_lane_layout(lib):
     da = torch.tensor(a, device="cuda")
     db = torch.tensor(b, device="cuda")
     out = torch.zeros(256, dtype=torch.float64, device="cuda")
-    assert lib.ris_test_mfma_probe(_p(da), _p(db), _p(out)) == 0
+    assert lib.ris_test_mfma_probe(0, _p(da), _p(db), _p(out)) == 0
     got = out.cpu().numpy().reshape(64, 4)
     # layout: A[l%16][l/16] = a[l], B[l/16][l%16] = b[l], out[l][e] = D[4e + l/16][l%16]
     A = np.zeros((16, 4))
@@ -43,6 +43,37 @@ def test_mfma_lane_layout(lib):
     ref = np.array([[D[4 * e + l // 16, l % 16] for e in range(4)] for l in range(64)])
     print("mfma layout max err", np.abs(got - ref).max(), flush=True)
     assert np.abs(got - ref).max() < 1e-13
+
+
+def _probe_onehot(lib, kind, width):
+    """Run the one-hot probe: for every (lane, slot) of A set a single 1, with
+    distinct small integers in B; returns {(lane, slot): [(out_lane, e, value)]}."""
+    import torch
+    b = (np.arange(64 * width) % 97 + 1).astype(np.float64)
+    db = torch.tensor(b, device="cuda")
+    res = {}
+    for la in range(64):
+        for sl in range(width):
+            a = np.zeros(64 * width)
+            a[la * width + sl] = 1.0
+            out = torch.zeros(256, dtype=torch.float64, device="cuda")
+            assert lib.ris_test_mfma_probe(kind, _p(torch.tensor(a, device="cuda")), _p(db), _p(out)) == 0
+            o = out.cpu().numpy().reshape(64, 4)
+            res[(la, sl)] = [(int(l), int(e), o[l, e]) for (l, e) in np.argwhere(o != 0)]
+    return b, res
+
+
+@pytest.mark.parametrize("kind,width", [(1, 1), (2, 8)])
+def test_mfma_f32_bf16_lane_layouts(lib, kind, width):
+    """A[i][k] from lane i%16 ... : lane l, slot s holds A[l % 16][width*(l // 16) + s] and
+    B[width*(l // 16) + s][l % 16]; out[l][e] = D[4e + l // 16][l % 16] (as for FP64)."""
+    b, res = _probe_onehot(lib, kind, width)
+    for (la, sl), hits in res.items():
+        i, k = la % 16, width * (la // 16) + sl
+        # row i of D equals row k of B
+        exp = {(16 * ((i % 4)) + j, i // 4): b[(16 * (k // width) + j) * width + (k % width)] for j in range(16)}
+        got = {(l, e): v for (l, e, v) in hits}
+        assert got == exp, (kind, la, sl)
 
 
 @pytest.mark.parametrize("M,N,K,tA,tB,batch", [
@@ -68,3 +99,32 @@ def test_dgemm_vs_numpy(lib, M, N, K, tA, tB, batch):
     err = np.abs(dC.cpu().numpy() - ref).max()
     print("  err", err, flush=True)
     assert err < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("M,N,K,tA,tB,batch", [(200, 77, 45, 0, 0, 2), (77, 200, 300, 1, 0, 1),
+                                               (131, 129, 1000, 0, 1, 1), (45, 45, 133, 1, 1, 2)])
+def test_reduced_precision_gemm(lib, mode, M, N, K, tA, tB, batch):
+    """FP32 and split-BF16 products against numpy: the error of a K-term sum of
+    products rounded to FP32 (2^-24) or split BF16 (~2^-16 per product) stays
+    below eps_mode * sqrt(K) * max|a| max|b| * 8."""
+    import torch
+    rng = np.random.default_rng(M + 13 * N + K + 1000 * mode)
+    As = (K, M) if tA else (M, K)
+    Bs = (N, K) if tB else (K, N)
+    A = rng.standard_normal((batch,) + As)
+    B = rng.standard_normal((batch,) + Bs)
+    C0 = rng.standard_normal((batch, M, N))
+    dA, dB, dC = (torch.tensor(x, device="cuda") for x in (A, B, C0))
+    print(f"gemm mode={mode} M={M} N={N} K={K} tA={tA} tB={tB}", flush=True)
+    st = lib.ris_test_gemm(mode, M, N, K, tA, tB, 1.3, _p(dA), As[1], int(np.prod(As)), _p(dB), Bs[1],
+                           int(np.prod(Bs)), 0.5, _p(dC), N, M * N, batch)
+    assert st == 0
+    opA = A.transpose(0, 2, 1) if tA else A
+    opB = B.transpose(0, 2, 1) if tB else B
+    ref = 1.3 * opA @ opB + 0.5 * C0
+    err = np.abs(dC.cpu().numpy() - ref).max()
+    eps = 2.0 ** -24 if mode == 1 else 2.0 ** -16
+    bound = 8 * eps * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() * 1.3
+    print("  err", err, "bound", bound, flush=True)
+    assert err < bound

@@ -120,6 +120,30 @@ def test_grad_nac_parity(ctx, radii, case):
     assert np.abs(got.sum(1)).max() <= 1e-10
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["tiny_mixed_tddft", "chain12_tddft"])
+def test_mixed_precision_error(ctx, radii, case, precision):
+    """Reduced-precision exchange contractions: gradients and NAC numerators
+    within 1e-6 Ha/Bohr of the FP64 oracle; the error is printed per case."""
+    import torch
+    make, jp = CASES[case]
+    prob = make()
+    m = prob.mol
+    ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+    say(f"[gpu] int3c {case} precision={precision}")
+    ctx.int3c(_to(prob.C, ctx.device), _to(prob.eps, ctx.device), prob.nocc, 2.0, 0.25, precision=precision)
+    outs = _outputs(prob.nstate)
+    X = _to(prob.X, ctx.device)
+    Y = _to(prob.Y, ctx.device)
+    g, n = ctx.grad_nac_contract(X, Y, [i for (i, j) in outs if i == j], [(i, j) for (i, j) in outs if i != j])
+    got = np.concatenate([g.cpu().numpy(), n.cpu().numpy()])
+    ref = O.grad_nac(prob, radii, outs, j_p_on_heavy=jp)
+    err = np.abs(got - ref).max()
+    say(f"[gpu]   {precision}: max |dgrad| {err:.3e} Ha/Bohr (max |grad| {np.abs(ref).max():.3e})")
+    assert err <= 1e-6
+    torch.cuda.synchronize()
+
+
 def test_combined_call_matches_separate_calls(ctx, radii):
     prob = molgen.make_chain_problem(12, seed=5, nstate=3, tda=False)
     _setup(ctx, prob, radii, True)
