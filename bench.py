@@ -87,6 +87,76 @@ def oracle_sample(prob, jp, outs, radii):
     }
 
 
+def compare_precisions(ctx, prob, jp, grads, pairs, radii, C, eps, X, Y):
+    """Run the step once per precision mode; max |d grad| and |d NAC| against
+    the FP64 GPU result (itself pinned to the oracle by the parity tests)."""
+    import time as _t
+    import torch
+    m = prob.mol
+    out = {}
+    ref = None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+        torch.cuda.synchronize()
+        t = _t.perf_counter()
+        ctx.int3c(C, eps, prob.nocc, 2.0, 0.25, precision=prec)
+        g, n = ctx.grad_nac_contract(X, Y, grads, pairs)
+        torch.cuda.synchronize()
+        dt = _t.perf_counter() - t
+        g, n = g.cpu().numpy(), n.cpu().numpy()
+        if ref is None:
+            ref = (g, n)
+        out[prec] = {"int3c_plus_contract_s": round(dt, 4),
+                     "max_abs_dgrad": float(np.abs(g - ref[0]).max()),
+                     "max_abs_dnac": float(np.abs(n - ref[1]).max()) if n.size else None,
+                     "max_abs_grad": float(np.abs(ref[0]).max())}
+        log(f"[bench] precision {prec}: {dt:.3f} s, max|dgrad| {out[prec]['max_abs_dgrad']:.2e}")
+    return out
+
+
+def serve_bench(nreq, nslots, radii):
+    """Serving trace (chain molecules 20-120 atoms, 2 gradients + 1 NAC each):
+    sequential FP64 rate first, then a Poisson trace at 1.5x that rate through
+    (a) one FP64 slot and (b) nslots slots with the exchange contractions in
+    FP32; throughput and p50/p99 latency of each."""
+    from paper_2511_18233_amd.serve import GpuExecutor, Server, latency_stats, make_trace
+    log(f"[bench] serving: building a {nreq}-request trace")
+    reqs = make_trace(nreq, max(1, nreq // 16), rate_hz=1.0, seed=1000)
+    seq = Server([GpuExecutor(0, 0, radii, "fp64")], 200 << 30)
+    warm = seq.run_trace(reqs[:2], realtime=False)  # warm the slot's regions
+    del warm
+    seq.close()
+    seq = Server([GpuExecutor(0, 0, radii, "fp64")], 200 << 30)
+    t = time.perf_counter()
+    r0 = seq.run_trace(reqs, realtime=False)
+    t_seq = time.perf_counter() - t
+    seq.close()
+    rate = nreq / t_seq
+    lam = 1.5 * rate
+    gaps = np.random.default_rng(7).exponential(1.0 / lam, nreq)
+    arr = np.cumsum(gaps) - gaps[0]
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    out = {"requests": nreq, "outputs_per_request": 3, "sequential_fp64_back_to_back_req_s": rate,
+           "arrival_rate_req_s": lam}
+    for name, execs in (("fifo_fp64_1slot", lambda: [GpuExecutor(0, 0, radii, "fp64")]),
+                        (f"batched_fp32_{nslots}slots",
+                         lambda: [GpuExecutor(k, 0, radii, "fp32") for k in range(nslots)])):
+        srv = Server(execs(), 200 << 30)
+        t = time.perf_counter()
+        rr = srv.run_trace(reqs, realtime=True)
+        wall = time.perf_counter() - t
+        srv.close()
+        st = latency_stats(rr)
+        errs = [x.error for x in rr.values() if x.error]
+        dmax = max(float(max(np.abs(rr[k].grad - r0[k].grad).max(), np.abs(rr[k].nac - r0[k].nac).max()))
+                   for k in rr if rr[k].error is None)
+        out[name] = {"req_s": nreq / wall, "grads_nacs_s": 3 * nreq / wall, "p50_ms": st["p50_ms"],
+                     "p99_ms": st["p99_ms"], "errors": len(errs), "max_abs_diff_vs_fp64": dmax}
+        log(f"[bench] serving {name}: {nreq / wall:.2f} req/s p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +164,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="chain200")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--compare-precisions", action="store_true",
+                    help="also run fp32 and bf16x3 once and report their max |d grad| vs the FP64 result")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="also replay a serving trace of this many requests (20-120 atoms)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
@@ -128,7 +204,7 @@ def main():
 
     def step():
         ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
-        ctx.int3c(C, eps, prob.nocc, 2.0, 0.25)
+        ctx.int3c(C, eps, prob.nocc, 2.0, 0.25, precision=args.precision)
         ctx.response_matvec("A+B", R, mv_out)
         ctx.response_matvec("A-B", L, mv_out)
         ctx.grad_nac_contract(X, Y, grads, pairs, None, g_out, n_out)
@@ -176,18 +252,24 @@ def main():
     res = {
         "metric": METRIC, "value": round(value, 4), "unit": "grads+NACs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * total / args.steps, 2),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32 (exchange contractions), f64 elsewhere",
+                  "bf16x3": "bf16x3 (exchange contractions), f64 elsewhere"}[args.precision], "data": "synthetic",
         "config": {"workload": f"{args.workload}: seeded C/N/O chain, {m.natm} atoms, nao={m.nao}, "
                                f"nocc={prob.nocc}, nauxJ={ctx.nJ}, nauxK={ctx.nK}, {ns} TDDFT states, "
                                f"{len(grads)} gradients + {len(pairs)} NAC numerators per step",
                    "natm": m.natm, "nao": m.nao, "nocc": prob.nocc, "nauxJ": ctx.nJ, "nauxK": ctx.nK,
-                   "nstate": ns, "outputs_per_step": len(outs), "precision": "fp64"},
+                   "nstate": ns, "outputs_per_step": len(outs), "precision": args.precision},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(tsorted, 50)), 2),
                        "p99": round(1e3 * float(np.percentile(tsorted, 99)), 2)},
         "roofline": roof,
         "stages": per_stage,
     }
+    if args.compare_precisions:
+        res["precision_errors"] = compare_precisions(ctx, prob, jp, grads, pairs, radii, C, eps, X, Y)
     ctx.close()
+    if args.serve > 0:
+        res["serving"] = serve_bench(args.serve, args.serve_slots, radii)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         res["cpu_baseline"] = oracle_sample(prob, jp, outs, radii)
