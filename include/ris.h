@@ -133,7 +133,10 @@ enum ris_stage {
     RIS_STAGE_HBLK = 3,    /* MO-space exchange blocks of one gradient/NAC output */
     RIS_STAGE_GAMMA = 4,   /* AO back-transform GEMM Gamma^P = (F_I W^P) F_J^T of one output */
     RIS_STAGE_DERIV = 5,   /* fused three-centre derivative contraction, one output chunk */
-    RIS_STAGE_COUNT = 6
+    RIS_STAGE_AUX = 6,     /* one whole ris_aux_build (metric, Cholesky, inverses) */
+    RIS_STAGE_YW = 7,      /* Y^P = F_I W^P of one output (W assembly included) */
+    RIS_STAGE_VPQ = 8,     /* metric weights V_PQ of one output */
+    RIS_STAGE_COUNT = 9
 };
 
 /* Turn per-stage timing on (1) or off (0); either way the counters reset.

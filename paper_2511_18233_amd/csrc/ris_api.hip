@@ -619,6 +619,7 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
 
     // --- metric, Cholesky, inverses
     const int nJ = c->nJ, nK = c->nK;
+    hipEvent_t t_aux = stage_begin(c);
     HIPCHK(c, launch_int2c(c->aux, c->boys, c->MJ, c->stream));
     // factor a copy (MJ keeps the metric itself)
     HIPCHK(c, hipMemcpyAsync(c->MinvJ, c->MJ, sizeof(double) * nJ * nJ, hipMemcpyDeviceToDevice, c->stream));
@@ -631,6 +632,7 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
     // M_J^-1 = L^-T L^-1 ; M_K = leading nK block, so L_K^-1 = leading block of L_J^-1
     HIPCHK(c, dgemm(gm(nJ, nJ, nJ, true, false, 1.0, c->LinvJ, nJ, c->LinvJ, nJ, 0.0, c->MinvJ, nJ), c->stream));
     HIPCHK(c, dgemm(gm(nK, nK, nK, true, false, 1.0, c->LinvJ, nJ, c->LinvJ, nJ, 0.0, c->MinvK, nK), c->stream));
+    stage_end(c, t_aux, RIS_STAGE_AUX, 2.0 * (double)nJ * nJ * nJ + 2.0 * (double)nK * nK * nK, 0.0);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_aux = true;
     if (nauxJ) *nauxJ = nJ;
@@ -909,6 +911,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             const BlockSrc none{nullptr, 0, 0, 0, 0.0};
             auto sc = [](BlockSrc b, double f) { b.scale *= f; return b; };
             // exchange weights W^P (rows/cols [U_R, U_L, C_O]) from D = (U C_O^T +- C_O U^T)/2
+            hipEvent_t t_yw = stage_begin(c);
             BlockGrid gw{};
             gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = none;             gw.b[0][2][0] = sc(HRou, 0.25);
             gw.b[1][0][0] = none;           gw.b[1][1][0] = sc(Hoo, 0.25);   gw.b[1][2][0] = sc(HLou, -0.25);
@@ -921,16 +924,21 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             gh.b[1][1][0] = HLuu; gh.b[1][2][0] = HLuo;
             gh.b[2][0][0] = HRou; gh.b[2][1][0] = HLou; gh.b[2][2][0] = Hoo;
             HIPCHK(c, assemble3(gh, Hc, o, nK, c->stream));
+            stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 2.0 * 9.0 * (double)oo * nK);
+            hipEvent_t t_v = stage_begin(c);
             // metric weights: W2 = -alpha_J c_I c_J^T + c_x V, V_PQ = sum_kl H^P_kl W^Q_kl
             double *V2k = V2 + (size_t)k * nJ * nJ;
             HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ,
                                nJ, 0.0, V2k, nJ), c->stream));
             HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)(o3 * o3), false, true, c->cx, Hc, o3 * o3, W, o3 * o3, 1.0, V2k,
                                       nJ), nsplit, SK, c->stream));
+            stage_end(c, t_v, RIS_STAGE_VPQ, 2.0 * (double)nK * nK * o3 * o3, 0.0);
             // Y^P = F_I W^P ; Gamma^P = -2 c_x Y^P F_J^T
             GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, F + (size_t)I * N * o3, o3, W, o3, 0.0, Y3, o3);
             g.batch = nK; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
+            hipEvent_t t_y = stage_begin(c);
             HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+            stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nK * N * o3 * o3, 0.0);
             double *Gk = G + (size_t)k * nK * NN;
             g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, F + (size_t)J * N * o3, o3, 0.0, Gk, N);
             g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;

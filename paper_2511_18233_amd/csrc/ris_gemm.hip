@@ -49,7 +49,7 @@ template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                long lda, long sA, long sAr, const double *__restrict__ B, long ldb,
                                                long sB, long sBr, double beta, double *__restrict__ C, long ldc,
-                                               long sC, int nred, int tm, int tn, int total)
+                                               long sC, int nred, int tm, int tn, int total, int kc)
 {
     __shared__ double As[2][BK][BM + PAD];
     __shared__ double Bs[2][BK][BN + PAD];
@@ -61,6 +61,9 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
     int bz, mt, nt;
     tile_of(blockIdx.x, total, tm, tn, bz, mt, nt);
     const int m0 = mt * BM, n0 = nt * BN;
+    // kc > 0: split-K, the batch index selects the k-range [bz*kc, bz*kc + kc)
+    const int kbeg = kc > 0 ? bz * kc : 0;
+    const int kend = kc > 0 ? min(K, kbeg + kc) : K;
     A += (long)bz * sA;
     B += (long)bz * sB;
     C += (long)bz * sC;
@@ -73,12 +76,12 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
 
     // global -> register staging: 8 doubles of A and 8 of B per thread
     double ra[8], rb[8];
-    const int ktiles = (K + BK - 1) / BK;
+    const int ktiles = (kend - kbeg + BK - 1) / BK;
     const int niter = ktiles * nred;
 
     auto load = [&](int it) {
         const int r = it / ktiles;
-        const int k0 = (it % ktiles) * BK;
+        const int k0 = kbeg + (it % ktiles) * BK;
         const double *Ar = A + (long)r * sAr;
         const double *Br = B + (long)r * sBr;
 #pragma unroll
@@ -86,20 +89,20 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
             if (!TA) {  // A is M x K: element (m, k) at Ar[m*lda + k]; 16 threads per row
                 const int k = tid & 15, m = (tid >> 4) + 16 * q;
                 const int gm = m0 + m, gk = k0 + k;
-                ra[q] = (gm < M && gk < K) ? Ar[(long)gm * lda + gk] : 0.0;
+                ra[q] = (gm < M && gk < kend) ? Ar[(long)gm * lda + gk] : 0.0;
             } else {    // A stored K x M: element (m, k) at Ar[k*lda + m]
                 const int m = tid & 127, k = (tid >> 7) + 2 * q;
                 const int gm = m0 + m, gk = k0 + k;
-                ra[q] = (gm < M && gk < K) ? Ar[(long)gk * lda + gm] : 0.0;
+                ra[q] = (gm < M && gk < kend) ? Ar[(long)gk * lda + gm] : 0.0;
             }
             if (!TB) {  // B is K x N: element (k, n) at Br[k*ldb + n]
                 const int n = tid & 127, k = (tid >> 7) + 2 * q;
                 const int gn = n0 + n, gk = k0 + k;
-                rb[q] = (gn < N && gk < K) ? Br[(long)gk * ldb + gn] : 0.0;
+                rb[q] = (gn < N && gk < kend) ? Br[(long)gk * ldb + gn] : 0.0;
             } else {    // B stored N x K: element (k, n) at Br[n*ldb + k]
                 const int k = tid & 15, n = (tid >> 4) + 16 * q;
                 const int gn = n0 + n, gk = k0 + k;
-                rb[q] = (gn < N && gk < K) ? Br[(long)gn * ldb + gk] : 0.0;
+                rb[q] = (gn < N && gk < kend) ? Br[(long)gn * ldb + gk] : 0.0;
             }
         }
     };
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
 
 }  // namespace
 
-hipError_t dgemm(const GemmArgs &g, hipStream_t st)
+hipError_t dgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
@@ -170,7 +173,7 @@ hipError_t dgemm(const GemmArgs &g, hipStream_t st)
 #define RIS_GEMM_LAUNCH(TA, TB)                                                                                   \
     hipLaunchKernelGGL((k_dgemm<TA, TB>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.strideA,   \
                        g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, \
-                       (int)total)
+                       (int)total, kc)
     if (!g.transA && !g.transB) RIS_GEMM_LAUNCH(false, false);
     else if (g.transA && !g.transB) RIS_GEMM_LAUNCH(true, false);
     else if (!g.transA && g.transB) RIS_GEMM_LAUNCH(false, true);
@@ -178,6 +181,8 @@ hipError_t dgemm(const GemmArgs &g, hipStream_t st)
 #undef RIS_GEMM_LAUNCH
     return hipGetLastError();
 }
+
+hipError_t dgemm(const GemmArgs &g, hipStream_t st) { return dgemm_kc(g, 0, st); }
 
 }  // namespace ris
 
@@ -264,21 +269,18 @@ hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t s
 {
     if (nsplit <= 1 || g.batch != 1 || g.nred > 1) return dgemm(g, st);
     const int kc = ((g.K + nsplit - 1) / nsplit + BK - 1) / BK * BK;  // multiple of the k-tile
-    int used = 0;
-    for (int z = 0; z < nsplit; ++z) {
-        const int k0 = z * kc;
-        if (k0 >= g.K) break;
-        GemmArgs p = g;
-        p.K = std::min(kc, g.K - k0);
-        p.A = g.transA ? g.A + (long)k0 * g.lda : g.A + k0;
-        p.B = g.transB ? g.B + k0 : g.B + (long)k0 * g.ldb;
-        p.beta = 0.0;
-        p.C = ws + (size_t)z * g.M * g.N;
-        p.ldc = g.N;
-        hipError_t e = dgemm(p, st);
-        if (e != hipSuccess) return e;
-        ++used;
-    }
+    const int used = (g.K + kc - 1) / kc;
+    // one launch: batch index = k-range, partial products into ws[z][M][N]
+    GemmArgs p = g;
+    p.batch = used;
+    p.strideA = 0;
+    p.strideB = 0;
+    p.beta = 0.0;
+    p.C = ws;
+    p.ldc = g.N;
+    p.strideC = (long)g.M * g.N;
+    hipError_t e = dgemm_kc(p, kc, st);
+    if (e != hipSuccess) return e;
     const long tot = (long)g.M * g.N;
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws, used, g.M, g.N,
                        g.beta, g.C, g.ldc);

@@ -10,8 +10,9 @@
 // Same contract as the FP64 dgemm (batch, batch-reduce, transposes, alpha,
 // beta) and the same XCD-aware tile order.  Lane layouts (checked by the probe
 // tests): FP32 16x16x4 as FP64 (A[l%16][l/16], B[l/16][l%16]); BF16 16x16x32
-// lane l holds A[l%16][8(l/16)+s], B[8(l/16)+s][l%16], s = 0..7; all three
-// write D[4e + l/16][l%16] to accumulator element e.
+// lane l holds A[l%16][8(l/16)+s], B[8(l/16)+s][l%16], s = 0..7; both write
+// D[4(l/16) + e][l%16] to accumulator element e (rows in blocks of four, unlike
+// the interleaved rows of the FP64 instruction).
 #include <algorithm>
 
 #include "ris_common.hpp"
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, double alpha
             const int col = n0 + wn * 64 + j * 16 + (lane & 15);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = m0 + wm * 64 + i * 16 + 4 * e + (lane >> 4);
+                const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
                 if (row < M && col < N) {
                     double *cp = C + (long)row * ldc + col;
                     const double v = alpha * (double)acc[i][j][e];
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(256) void k_bgemm3(int M, int N, int K, double alph
             const int col = n0 + wn * 64 + j * 16 + (lane & 15);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = m0 + wm * 64 + i * 16 + 4 * e + (lane >> 4);
+                const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
                 if (row < M && col < N) {
                     double *cp = C + (long)row * ldc + col;
                     const double v = alpha * (double)acc[i][j][e];

@@ -166,7 +166,7 @@ class RisContext:
     def bytes_held(self) -> int:
         return int(self.lib.ris_ctx_bytes(self.h))
 
-    STAGES = ("int3c", "mo", "matvec", "hblk", "gamma", "deriv")
+    STAGES = ("int3c", "mo", "matvec", "hblk", "gamma", "deriv", "aux", "yw", "vpq")
 
     def set_profiling(self, on: bool):
         self._chk(self.lib.ris_ctx_set_profiling(self.h, int(bool(on))))

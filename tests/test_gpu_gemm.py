@@ -65,13 +65,13 @@ def _probe_onehot(lib, kind, width):
 
 @pytest.mark.parametrize("kind,width", [(1, 1), (2, 8)])
 def test_mfma_f32_bf16_lane_layouts(lib, kind, width):
-    """A[i][k] from lane i%16 ... : lane l, slot s holds A[l % 16][width*(l // 16) + s] and
-    B[width*(l // 16) + s][l % 16]; out[l][e] = D[4e + l // 16][l % 16] (as for FP64)."""
+    """Lane l, slot s holds A[l % 16][width*(l // 16) + s] and B[width*(l // 16) + s][l % 16];
+    out[l][e] = D[4 (l // 16) + e][l % 16] (rows in blocks of four, unlike FP64)."""
     b, res = _probe_onehot(lib, kind, width)
     for (la, sl), hits in res.items():
         i, k = la % 16, width * (la // 16) + sl
         # row i of D equals row k of B
-        exp = {(16 * ((i % 4)) + j, i // 4): b[(16 * (k // width) + j) * width + (k % width)] for j in range(16)}
+        exp = {(16 * (i // 4) + j, i % 4): b[(16 * (k // width) + j) * width + (k % width)] for j in range(16)}
         got = {(l, e): v for (l, e, v) in hits}
         assert got == exp, (kind, la, sl)
 
