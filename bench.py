@@ -30,6 +30,11 @@ if ROOT not in sys.path:
 METRIC = "excited-state grads+NACs/s at 200 atoms; p50/p99 latency; vs plain FP64"
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the Gamma back-transform GEMM from the FETCH_SIZE /
+# WRITE_SIZE counter runs on the 199-atom workload (fetch scaled by 2.0, write by
+# 1.0 after a 1 GiB copy calibration), valid only for the GEMM source they were
+# measured on (sha256 prefix below); null otherwise.
+GAMMA_TRAFFIC = {"gemm_src_sha256": "aefeea86a121bf42", "workload": "chain200", "bytes_per_launch": 63.26e9}
 
 
 def log(*a):
@@ -242,10 +247,16 @@ def main():
     roof = None
     if gn > 0 and gms > 0:
         ach = gfl / gn / (gms * 1e-3 / gn) / 1e12
+        import hashlib
+        src = os.path.join(ROOT, "paper_2511_18233_amd", "csrc", "ris_gemm.hip")
+        same = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == GAMMA_TRAFFIC["gemm_src_sha256"]
+        traffic = GAMMA_TRAFFIC["bytes_per_launch"] if (same and args.workload == GAMMA_TRAFFIC["workload"]
+                                                        and args.precision == "fp64") else None
         roof = {"bound": "mfma", "kernel": "k_dgemm<false,true> (Gamma^P = (F_I W^P) F_J^T, batched over P)",
                 "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                "flops_per_launch": gfl / gn, "avg_launch_ms": gms / gn}
+                "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                "flops_per_launch": gfl / gn, "avg_launch_ms": gms / gn,
+                "algorithmic_bytes_per_launch": gby / gn}
 
     value = len(outs) * args.steps / total
     tsorted = np.sort(np.array(times))

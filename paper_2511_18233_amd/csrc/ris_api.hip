@@ -323,17 +323,18 @@ Int3cWs int3c_ws(const Dims &d)
 }
 
 struct MatvecWs {
-    size_t ot, oT, oS, total;
+    size_t ot, oT, oU, total;
 };
+constexpr int kMatvecChunk = 10;  // vectors whose exchange terms share one GEMM
 MatvecWs matvec_ws(const Dims &d, int nvec)
 {
     Carve cv;
     MatvecWs L;
-    const int chunk = std::min(nvec, 8);
+    const int chunk = std::min(nvec, kMatvecChunk);
     const long vo = (long)d.v * d.o, oo = (long)d.o * d.o;
     L.ot = cv.take((size_t)nvec * d.nJ * 2);
-    L.oT = cv.take((size_t)chunk * d.nK * vo);
-    L.oS = cv.take((size_t)chunk * d.nK * oo);
+    L.oT = cv.take((size_t)chunk * d.nK * std::max(vo, oo));  // T (exchange A) or S (exchange B)
+    L.oU = cv.take((size_t)chunk * vo);                        // [a][k][i] product before the permuted add
     L.total = cv.off;
     return L;
 }
@@ -757,13 +758,13 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
     const long vo = (long)v * o, oo = (long)o * o;
     // coefficients of Delta, J, K_A, K_B for A, B, A+B, A-B
     static const double cDe[4] = {1, 0, 1, 1}, cJ[4] = {1, 1, 2, 0}, cKA[4] = {1, 0, 1, 1}, cKB[4] = {0, 1, 1, -1};
-    const int chunk = std::min(nvec, 8);
+    const int chunk = std::min(nvec, kMatvecChunk);
     const MatvecWs MW = matvec_ws(ctx_dims(c), nvec);
     int st;
     char *wsb = ws_get(c, MW.total, &st);
     if (!wsb) return st;
     double *t = (double *)(wsb + MW.ot), *cc = t + (size_t)nvec * nJ, *T = (double *)(wsb + MW.oT),
-           *S = (double *)(wsb + MW.oS);
+           *U = (double *)(wsb + MW.oU);
     hipEvent_t t_mv = stage_begin(c);
     // Coulomb: t = V (ai|P)^T ; cc = t M_J^-1 ; out = cJ alpha_J cc (ai|P)
     HIPCHK(c, dgemm(gm(nvec, nJ, (int)vo, false, true, 1.0, V, vo, c->aiJ, vo, 0.0, t, nJ), c->stream));
@@ -775,25 +776,31 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
         const int nv = std::min(chunk, nvec - k0);
         const double *Vk = V + (size_t)k0 * vo;
         double *ok = out + (size_t)k0 * vo;
+        const long nvo = (long)nv * o;  // columns (k, i) of the chunk
         if (cKA[op] != 0.0) {
-            // T_k[P][b][i] = sum_j V_k[b][j] c_oo^P[i][j];  out_k -= c_x sum_{P,b} (ab|P) T_k[P][b][i]
+            // T[P][b][k][i] = sum_j V_k[b][j] c_oo^P[i][j]
             for (int k = 0; k < nv; ++k) {
-                GemmArgs g = gm(v, o, o, false, true, 1.0, Vk + k * vo, o, c->coo, o, 0.0, T + (size_t)k * nK * vo, o);
-                g.batch = nK; g.strideA = 0; g.strideB = oo; g.strideC = vo;
+                GemmArgs g = gm(v, o, o, false, true, 1.0, Vk + k * vo, o, c->coo, o, 0.0, T + (size_t)k * o, nvo);
+                g.batch = nK; g.strideA = 0; g.strideB = oo; g.strideC = (long)v * nvo;
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
-            GemmArgs g = gm(v, o, nK * v, false, false, -cKA[op] * c->cx, c->rvv, (long)nK * v, T, o, 1.0, ok, o);
-            g.batch = nv; g.strideA = 0; g.strideB = (long)nK * vo; g.strideC = vo;
-            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+            // U[a][(k,i)] = sum_{(P,b)} (ab|P) T[(P,b)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
+            HIPCHK(c, gemm_mp(gm(v, (int)nvo, nK * v, false, false, 1.0, c->rvv, (long)nK * v, T, nvo, 0.0, U, nvo),
+                              c->prec, c->stream));
+            HIPCHK(c, permute3(U, ok, nv, v, o, o, nvo, 1, vo, o, 1, c->stream, -cKA[op] * c->cx, 1.0));
         }
         if (cKB[op] != 0.0) {
-            // S_k[j][P][i] = sum_b V_k[b][j] c_vo^P[b][i];  out_k -= c_x sum_{j,P} (aj|P) S_k[j][P][i]
-            GemmArgs g = gm(o, nK * o, v, true, false, 1.0, Vk, o, c->cvo, (long)nK * o, 0.0, S, (long)nK * o);
-            g.batch = nv; g.strideA = vo; g.strideB = 0; g.strideC = (long)nK * oo;
-            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-            g = gm(v, o, o * nK, false, false, -cKB[op] * c->cx, c->rvo2, (long)o * nK, S, o, 1.0, ok, o);
-            g.batch = nv; g.strideA = 0; g.strideB = (long)nK * oo; g.strideC = vo;
-            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+            // S[j][P][k][i] = sum_b V_k[b][j] c_vo^P[b][i]
+            for (int k = 0; k < nv; ++k) {
+                GemmArgs g = gm(o, o, v, true, false, 1.0, Vk + k * vo, o, c->cvo, (long)nK * o, 0.0,
+                                T + (size_t)k * o, (long)nK * nvo);
+                g.batch = nK; g.strideA = 0; g.strideB = o; g.strideC = nvo;
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+            }
+            // U[a][(k,i)] = sum_{(j,P)} (aj|P) S[(j,P)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
+            HIPCHK(c, gemm_mp(gm(v, (int)nvo, o * nK, false, false, 1.0, c->rvo2, (long)o * nK, T, nvo, 0.0, U, nvo),
+                              c->prec, c->stream));
+            HIPCHK(c, permute3(U, ok, nv, v, o, o, nvo, 1, vo, o, 1, c->stream, -cKB[op] * c->cx, 1.0));
         }
     }
     {

@@ -199,15 +199,17 @@ __global__ void k_assemble3(BlockGrid g, double *__restrict__ W, int o, int nP)
     W[idx] = v;
 }
 
-// out[i0*o0 + i1*o1 + i2*o2] = in[i0*s0 + i1*s1 + i2*s2] over an n0 x n1 x n2 box
+// out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] (+ beta * out) over n0 x n1 x n2
 __global__ void k_permute3(const double *__restrict__ in, double *__restrict__ out, int n0, int n1, int n2,
-                           long s0, long s1, long s2, long o0, long o1, long o2)
+                           long s0, long s1, long s2, long o0, long o1, long o2, double alpha, double beta)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n0 * n1 * n2) return;
     const long i2 = idx % n2, r = idx / n2;
     const long i1 = r % n1, i0 = r / n1;
-    out[i0 * o0 + i1 * o1 + i2 * o2] = in[i0 * s0 + i1 * s1 + i2 * s2];
+    double *d = out + i0 * o0 + i1 * o1 + i2 * o2;
+    const double v = alpha * in[i0 * s0 + i1 * s1 + i2 * s2];
+    *d = (beta == 0.0) ? v : v + beta * *d;
 }
 
 // Reduce the triplet partials into per-shell sums (fixed order).
@@ -349,11 +351,12 @@ hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t s
 }
 
 hipError_t permute3(const double *in, double *out, int n0, int n1, int n2, long s0, long s1, long s2, long o0,
-                    long o1, long o2, hipStream_t st)
+                    long o1, long o2, hipStream_t st, double alpha, double beta)
 {
     const size_t n = (size_t)n0 * n1 * n2;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_permute3, dim3(nblk(n, 256)), dim3(256), 0, st, in, out, n0, n1, n2, s0, s1, s2, o0, o1, o2);
+    hipLaunchKernelGGL(k_permute3, dim3(nblk(n, 256)), dim3(256), 0, st, in, out, n0, n1, n2, s0, s1, s2, o0, o1, o2,
+                       alpha, beta);
     return hipGetLastError();
 }
 

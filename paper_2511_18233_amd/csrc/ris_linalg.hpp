@@ -24,9 +24,9 @@ struct BlockGrid {
     BlockSrc b[3][3][2];  // up to two summed sources per block; base == nullptr means none
 };
 hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st);
-// out[i0*o0 + i1*o1 + i2*o2] = in[i0*s0 + i1*s1 + i2*s2] over n0 x n1 x n2
+// out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] + beta * out over n0 x n1 x n2
 hipError_t permute3(const double *in, double *out, int n0, int n1, int n2, long s0, long s1, long s2, long o0,
-                    long o1, long o2, hipStream_t st);
+                    long o1, long o2, hipStream_t st, double alpha = 1.0, double beta = 0.0);
 hipError_t reduce_grad(const double *p3, int nshAO, int nshAux, int nout, int NO, const double *p2,
                        const int *atomAO, const int *atomAux, int natm, double *shA, double *shC, double *shP,
                        double scale, int accumulate, double *grad, hipStream_t st);
