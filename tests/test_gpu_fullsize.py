@@ -1,0 +1,109 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+* 60-atom chain: GPU gradients / NAC numerators against the FP64 oracle on
+  sampled outputs (the oracle computes them one by one).
+* 199-atom chain (the headline workload): properties that hold at any size --
+  the GPU gradient equals central finite differences of the GPU's own energy
+  functional E_II = 1/2 R.(A+B-D)R + 1/2 L.(A-B-D)L evaluated from its matvecs
+  with C, X, Y held fixed (fixed AO densities), per-atom gradients sum to zero,
+  and the mixed-precision results stay within 1e-6 Ha/Bohr of FP64."""
+import sys
+
+import numpy as np
+import pytest
+
+import molgen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_problem(ctx, prob, radii, jp, xyz=None, precision="fp64"):
+    import torch
+    m = prob.mol
+    ctx.aux_build(m.Z, m.xyz if xyz is None else xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+    ctx.int3c(torch.as_tensor(prob.C, device=ctx.device), torch.as_tensor(prob.eps, device=ctx.device), prob.nocc,
+              2.0, 0.25, precision=precision)
+
+
+def _energy(ctx, prob, I, X, Y):
+    import torch
+    R = (X[I] + Y[I]) if Y is not None else X[I].clone()
+    L = (X[I] - Y[I]) if Y is not None else X[I].clone()
+    de = torch.as_tensor(prob.eps[prob.nocc:][:, None] - prob.eps[:prob.nocc][None, :], device=ctx.device)
+    apb = ctx.response_matvec("A+B", R[None].contiguous())[0] - de * R
+    amb = ctx.response_matvec("A-B", L[None].contiguous())[0] - de * L
+    return float(0.5 * (R * apb).sum() + 0.5 * (L * amb).sum())
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_18233_amd import RisContext
+    c = RisContext(0)
+    yield c
+    c.close()
+
+
+def test_chain60_vs_oracle_sampled(ctx, radii):
+    import torch
+    from oracle import ris_oracle as O
+    prob = molgen.make_problem("chain60")
+    say(f"[gpu] chain60 natm={prob.mol.natm} nao={prob.mol.nao}")
+    _gpu_problem(ctx, prob, radii, True)
+    X = torch.as_tensor(prob.X, device=ctx.device)
+    Y = torch.as_tensor(prob.Y, device=ctx.device)
+    g, n = ctx.grad_nac_contract(X, Y, list(range(prob.nstate)), [(i, i + 1) for i in range(prob.nstate - 1)])
+    g, n = g.cpu().numpy(), n.cpu().numpy()
+    assert np.abs(g.sum(1)).max() <= 1e-10 and np.abs(n.sum(1)).max() <= 1e-10
+    say("[gpu] chain60 oracle for outputs (3,3) and (4,5)")
+    ref = O.grad_nac(prob, radii, [(3, 3), (4, 5)])
+    err = max(np.abs(g[3] - ref[0]).max(), np.abs(n[4] - ref[1]).max())
+    say(f"[gpu]   max |dgrad| {err:.3e} (max {np.abs(ref).max():.3e})")
+    assert err <= 1e-8
+
+
+def test_chain200_finite_difference_and_invariance(ctx, radii):
+    import torch
+    prob = molgen.make_problem("chain200")
+    m = prob.mol
+    say(f"[gpu] chain200 natm={m.natm} nao={m.nao}")
+    X = torch.as_tensor(prob.X, device=ctx.device)
+    Y = torch.as_tensor(prob.Y, device=ctx.device)
+    _gpu_problem(ctx, prob, radii, True)
+    g, n = ctx.grad_nac_contract(X, Y, [0, 7], [(2, 3)])
+    g = g.cpu().numpy()
+    assert np.abs(g.sum(1)).max() <= 1e-10 and np.abs(n.cpu().numpy().sum(1)).max() <= 1e-10
+    h = 2e-3
+    for (A, d) in [(0, 0), (57, 2), (150, 1)]:
+        vals = {}
+        for k in (-2, -1, 1, 2):
+            xyz = m.xyz.copy()
+            xyz[A, d] += k * h
+            _gpu_problem(ctx, prob, radii, True, xyz=xyz)
+            vals[k] = _energy(ctx, prob, 0, X, Y)
+        fd = (8 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12 * h)
+        say(f"[gpu]   atom {A} dir {d}: analytic {g[0, A, d]:.10e} fd {fd:.10e} diff {abs(fd - g[0, A, d]):.2e}")
+        assert abs(fd - g[0, A, d]) <= 1e-8
+
+
+def test_chain200_mixed_precision(ctx, radii):
+    import torch
+    prob = molgen.make_problem("chain200")
+    X = torch.as_tensor(prob.X, device=ctx.device)
+    Y = torch.as_tensor(prob.Y, device=ctx.device)
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        _gpu_problem(ctx, prob, radii, True, precision=prec)
+        g, n = ctx.grad_nac_contract(X, Y, [0, 9], [(4, 5)])
+        res[prec] = np.concatenate([g.cpu().numpy(), n.cpu().numpy()])
+    for prec in ("fp32", "bf16x3"):
+        err = np.abs(res[prec] - res["fp64"]).max()
+        say(f"[gpu] chain200 {prec}: max |d| vs fp64 {err:.3e} Ha/Bohr")
+        assert err <= 1e-6
