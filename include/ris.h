@@ -139,6 +139,18 @@ enum ris_stage {
     RIS_STAGE_COUNT = 9
 };
 
+/* AO shell-pair screen of the three-centre derivative contraction (the
+ * (mu nu|P)^xi term of the three-term RI derivative, last equation of
+ * Sec. 2.2; the screen itself is an implementation choice: a pair whose
+ * Gaussian product is negligible contributes nothing above roundoff).
+ * A pair of shells with exponents a, b on centres
+ * A, B is skipped when exp(-a b / (a + b) |A - B|^2) < threshold; 0 keeps
+ * every pair.  Default 1e-15.  Takes effect at once (the lists are rebuilt if
+ * the molecule is already set) and stays for later ris_aux_build calls.
+ * kept_pairs (may be NULL) receives the number of ordered shell pairs kept,
+ * or -1 before the first ris_aux_build.  RIS_E_INVALID unless 0 <= threshold < 1. */
+int ris_ctx_set_screening(ris_ctx *ctx, double threshold, long *kept_pairs);
+
 /* Turn per-stage timing on (1) or off (0); either way the counters reset.
  * When on, each instrumented launch group is bracketed by HIP events on the
  * context's stream (no extra synchronisation inside the calls). */

@@ -50,6 +50,11 @@ struct ris_ctx {
     int auxl_beg[kMaxAuxL + 2] = {0, 0, 0};
     int *d_ao_perm = nullptr;
     double *MJ = nullptr, *LinvJ = nullptr, *MinvJ = nullptr, *MinvK = nullptr;
+    // AO shell-pair screen of the derivative contraction (internal shell order)
+    double screen = kDefaultScreen;
+    std::vector<double> h_sh_xyz, h_sh_exp;  // [nsh][3], [nsh]
+    int *d_pair_ptr = nullptr, *d_pair_idx = nullptr;
+    long npair_kept = 0;
 
     // ---- int3c state
     bool have_int3c = false;
@@ -185,6 +190,7 @@ void free_aux(ris_ctx *c)
 {
     free_int3c(c);
     c->d_ao_perm = nullptr;
+    c->d_pair_ptr = c->d_pair_idx = nullptr;
     c->MJ = c->LinvJ = c->MinvJ = c->MinvK = nullptr;
     c->ao = AOGeom{};
     c->aux = AuxGeom{};
@@ -278,6 +284,36 @@ GemmArgs gm(int M, int N, int K, bool tA, bool tB, double alpha, const double *A
     return g;
 }
 
+// Partner lists of the AO shell-pair screen: pair (a, b) is kept when its
+// Gaussian product prefactor exp(-a b / (a + b) |A - B|^2) is >= c->screen
+// (every pair when the threshold is 0).  Lists are grouped by the partner's
+// class so each derivative kernel reads the partners of its own class.
+int build_pairs(ris_ctx *c)
+{
+    const int nsh = c->nshAO, ncls = kMaxAOL + 1;
+    std::vector<int> ptr((size_t)ncls * nsh + 1, 0), idx;
+    idx.reserve((size_t)nsh * 16);
+    const double thr = c->screen;
+    const double *X = c->h_sh_xyz.data(), *E = c->h_sh_exp.data();
+    for (int a = 0; a < nsh; ++a)
+        for (int l = 0; l < ncls; ++l) {
+            ptr[(size_t)ncls * a + l] = (int)idx.size();
+            for (int b = c->ao.lbeg[l]; b < c->ao.lbeg[l + 1]; ++b) {
+                const double dx = X[3 * a] - X[3 * b], dy = X[3 * a + 1] - X[3 * b + 1], dz = X[3 * a + 2] - X[3 * b + 2];
+                const double ea = E[a], eb = E[b];
+                if (thr <= 0.0 || std::exp(-ea * eb / (ea + eb) * (dx * dx + dy * dy + dz * dz)) >= thr)
+                    idx.push_back(b);
+            }
+        }
+    ptr[(size_t)ncls * nsh] = (int)idx.size();
+    c->npair_kept = (long)idx.size();
+    HIPCHK(c, hipMemcpyAsync(c->d_pair_ptr, ptr.data(), 4 * ptr.size(), hipMemcpyHostToDevice, c->stream));
+    if (!idx.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_pair_idx, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RIS_OK;
+}
+
 }  // namespace
 
 // ---- sizes of every device region, shared by the calls and ris_request_bytes
@@ -323,7 +359,7 @@ Int3cWs int3c_ws(const Dims &d)
 }
 
 struct MatvecWs {
-    size_t ot, oT, oU, total;
+    size_t ot, oT, oU, oSK, total;
 };
 constexpr int kMatvecChunk = 10;  // vectors whose exchange terms share one GEMM
 MatvecWs matvec_ws(const Dims &d, int nvec)
@@ -335,6 +371,7 @@ MatvecWs matvec_ws(const Dims &d, int nvec)
     L.ot = cv.take((size_t)nvec * d.nJ * 2);
     L.oT = cv.take((size_t)chunk * d.nK * std::max(vo, oo));  // T (exchange A) or S (exchange B)
     L.oU = cv.take((size_t)chunk * vo);                        // [a][k][i] product before the permuted add
+    L.oSK = cv.take((size_t)64 * nvec * d.nJ);                 // split-K partials of t = V (ai|P)^T
     L.total = cv.off;
     return L;
 }
@@ -367,7 +404,7 @@ ContractWs contract_ws(const Dims &d, int ns)
     L.oY = cv.take((size_t)d.nK * d.N * o3);
     L.oG = cv.take((size_t)NO * d.nK * NN);
     L.oV2 = cv.take((size_t)NO * d.nJ * d.nJ);
-    L.oSK = cv.take((size_t)kSplitV * d.nK * d.nK);
+    L.oSK = cv.take((size_t)kSplitV * std::max((size_t)d.nK * d.nK, (size_t)ns * d.nJ));
     L.op3 = cv.take((size_t)d.nshAO * d.nshJ * 3 * NO * 6);
     L.op2 = cv.take((size_t)d.nshJ * 2 * NO * 3);
     L.oshA = cv.take((size_t)d.nshAO * NO * 3);
@@ -378,7 +415,7 @@ ContractWs contract_ws(const Dims &d, int ns)
 }
 
 struct AuxLayout {
-    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, total;
+    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, oPP, oPI, total;
 };
 AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
 {
@@ -391,6 +428,9 @@ AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
     L.oLJ = cv.take((size_t)nJ * nJ);
     L.oIJ = cv.take((size_t)nJ * nJ);
     L.oIK = cv.take((size_t)nK * nK);
+    // screened pair lists sized for the unscreened worst case (ints, 2 per slot)
+    L.oPP = cv.take(((size_t)(kMaxAOL + 1) * nsh + 2) / 2);
+    L.oPI = cv.take(((size_t)nsh * nsh + 1) / 2);
     L.total = cv.off;
     return L;
 }
@@ -465,6 +505,21 @@ size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, 
     const size_t fixed = (size_t)8 * kBoysNGrid * kBoysCols + 64;
     return fixed + aux_layout(mol->nshell, nshJ, nao, nJ, natm).total + mo_layout(d).total + ws +
            (size_t)8 * std::max(nout, 0) * natm * 3;
+}
+
+int ris_ctx_set_screening(ris_ctx *c, double threshold, long *kept_pairs)
+{
+    if (!c) return RIS_E_INVALID;
+    c->err.clear();
+    if (!(threshold >= 0.0 && threshold < 1.0)) return fail(c, RIS_E_INVALID, "screening threshold must be in [0, 1)");
+    HIPCHK(c, hipSetDevice(c->device));
+    c->screen = threshold;
+    if (c->have_aux) {
+        const int sp = build_pairs(c);
+        if (sp) return sp;
+    }
+    if (kept_pairs) *kept_pairs = c->have_aux ? c->npair_kept : -1;
+    return RIS_OK;
 }
 
 int ris_ctx_set_profiling(ris_ctx *c, int enable)
@@ -559,6 +614,13 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         f += ncart(l);
     }
     off[nsh] = f;
+    c->h_sh_xyz.resize(3 * (size_t)nsh);
+    for (int i = 0; i < nsh; ++i) {
+        c->h_sh_xyz[3 * i] = x[i];
+        c->h_sh_xyz[3 * i + 1] = y[i];
+        c->h_sh_xyz[3 * i + 2] = z[i];
+    }
+    c->h_sh_exp = e;
     c->ao.nshell = nsh;
     c->ao.nao = nao;
     c->h_ao_atom = at;
@@ -601,6 +663,8 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         c->LinvJ = (double *)(base + AL.oLJ);
         c->MinvJ = (double *)(base + AL.oIJ);
         c->MinvK = (double *)(base + AL.oIK);
+        c->d_pair_ptr = (int *)(base + AL.oPP);
+        c->d_pair_idx = (int *)(base + AL.oPI);
     }
     c->aux.nshell = nshJ;
     c->aux.nfunc = f;
@@ -617,6 +681,10 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
     c->nsJ = natm;
 
     HIPCHK(c, hipMemcpyAsync(c->d_ao_perm, c->h_ao_perm.data(), sizeof(int) * nao, hipMemcpyHostToDevice, c->stream));
+    {
+        const int sp = build_pairs(c);
+        if (sp) return sp;
+    }
 
     // --- metric, Cholesky, inverses
     const int nJ = c->nJ, nK = c->nK;
@@ -764,10 +832,11 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
     char *wsb = ws_get(c, MW.total, &st);
     if (!wsb) return st;
     double *t = (double *)(wsb + MW.ot), *cc = t + (size_t)nvec * nJ, *T = (double *)(wsb + MW.oT),
-           *U = (double *)(wsb + MW.oU);
+           *U = (double *)(wsb + MW.oU), *SKm = (double *)(wsb + MW.oSK);
     hipEvent_t t_mv = stage_begin(c);
-    // Coulomb: t = V (ai|P)^T ; cc = t M_J^-1 ; out = cJ alpha_J cc (ai|P)
-    HIPCHK(c, dgemm(gm(nvec, nJ, (int)vo, false, true, 1.0, V, vo, c->aiJ, vo, 0.0, t, nJ), c->stream));
+    // Coulomb: t = V (ai|P)^T (tiny output, K = nvir*nocc: split-K) ; cc = t M_J^-1 ; out = cJ alpha_J cc (ai|P)
+    HIPCHK(c, dgemm_splitk(gm(nvec, nJ, (int)vo, false, true, 1.0, V, vo, c->aiJ, vo, 0.0, t, nJ), 64, SKm,
+                           c->stream));
     HIPCHK(c, dgemm(gm(nvec, nJ, nJ, false, false, 1.0, t, nJ, c->MinvJ, nJ, 0.0, cc, nJ), c->stream));
     HIPCHK(c, dgemm(gm(nvec, (int)vo, nJ, false, false, cJ[op] * c->alphaJ, cc, nJ, c->aiJ, vo, 0.0, out, vo),
                     c->stream));
@@ -863,7 +932,8 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         HIPCHK(c, dgemm(g, c->stream));
         HIPCHK(c, symmetrize(D, N, ns, c->stream));
         // c_s = M_J^-1 t_s, t_s[P] = sum_ai (ai|P) R_s[a][i]
-        HIPCHK(c, dgemm(gm(ns, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), c->stream));
+        HIPCHK(c, dgemm_splitk(gm(ns, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), kSplitV, SK,
+                               c->stream));
         HIPCHK(c, dgemm(gm(ns, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
         // Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j]
         HIPCHK(c, gemm_mp(gm(v * nK, (int)w2, v, false, false, 1.0, c->cvv, v, RLT, w2, 0.0, Tall, w2), c->prec,
@@ -892,6 +962,8 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         job.nJ = nJ;
         job.alphaJ = c->alphaJ;
         job.partial = p3;
+        job.pair_ptr = c->screen > 0.0 ? c->d_pair_ptr : nullptr;
+        job.pair_idx = c->d_pair_idx;
         for (int k = 0; k < NO; ++k) {
             const int kk = k0 + std::min(k, nb - 1);
             job.stI[k] = pI[kk];
@@ -947,13 +1019,34 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nK * N * o3 * o3, 0.0);
             double *Gk = G + (size_t)k * nK * NN;
-            g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, F + (size_t)J * N * o3, o3, 0.0, Gk, N);
-            g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
-            hipEvent_t t_g = stage_begin(c);
-            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-            stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nK * N * N * o3,
-                      8.0 * ((double)nK * N * N + (double)nK * N * o3 + (double)N * o3));
-            if (I != J) HIPCHK(c, symmetrize(Gk, N, nK, c->stream));
+            const double *FJ = F + (size_t)J * N * o3;
+            if (c->prec == RIS_FP64) {
+                // only the symmetric part of Gamma^P enters (integrals symmetric in mu nu):
+                // gradients: Y F_I^T is symmetric -> lower tiles + mirror (half the work);
+                // NACs: -c_x (Y F_J^T + F_J Y^T) on lower tiles + mirror
+                const double sc = (I == J) ? -2.0 * c->cx : -c->cx;
+                g = gm(N, N, (int)o3, false, true, sc, Y3, o3, FJ, o3, 0.0, Gk, N);
+                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
+                hipEvent_t t_g = stage_begin(c);
+                HIPCHK(c, dgemm(g, c->stream));
+                if (I != J) {
+                    g = gm(N, N, (int)o3, false, true, sc, FJ, o3, Y3, o3, 1.0, Gk, N);
+                    g.batch = nK; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
+                    HIPCHK(c, dgemm(g, c->stream));
+                }
+                const double nprod = (I == J) ? 1.0 : 2.0;
+                stage_end(c, t_g, RIS_STAGE_GAMMA, nprod * (double)nK * N * (N + 1) * o3,
+                          8.0 * ((double)nK * N * (N + 1) / 2 * (nprod + 1) + nprod * ((double)nK * N * o3 + N * o3)));
+                HIPCHK(c, mirror_lower_tiles(Gk, N, NN, nK, c->stream));
+            } else {
+                g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
+                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
+                hipEvent_t t_g = stage_begin(c);
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nK * N * N * o3,
+                          8.0 * ((double)nK * N * N + (double)nK * N * o3 + (double)N * o3));
+                if (I != J) HIPCHK(c, symmetrize(Gk, N, nK, c->stream));
+            }
         }
         // three-centre derivative contraction + metric derivative, reduced into atoms
         HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * NO * 6, 0.0, c->stream));

@@ -10,6 +10,10 @@ namespace ris {
 
 constexpr int kMaxAOL = 2;   // AO shells up to d (Cartesian)
 constexpr int kMaxAuxL = 1;  // auxiliary shells up to p
+// AO shell pairs whose Gaussian product prefactor is below this are skipped
+// in the derivative contraction (their integrals and derivatives are below
+// roundoff of the kept terms)
+constexpr double kDefaultScreen = 1e-15;
 
 __host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
@@ -64,6 +68,10 @@ struct DerivJob {
     int stI[8], stJ[8];        // state pair of each output
     double alphaJ;
     double *partial;           // [nshellAO][nshellAux][nout][6] (dA xyz, dC xyz)
+    // AO shell-pair screen (null: every pair): the partners of internal shell sa
+    // in class l are pair_idx[pair_ptr[(kMaxAOL+1) sa + l] .. pair_ptr[(kMaxAOL+1) sa + l + 1])
+    const int *pair_ptr;
+    const int *pair_idx;
 };
 constexpr int kMaxOutChunk = 4;
 hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],
@@ -87,11 +95,15 @@ struct GemmArgs {
     double *C;
     long ldc, strideC;
     int batch, nred;
+    bool lower;  // M == N: compute only the 128 x 128 tiles on or below the diagonal
 };
 hipError_t dgemm(const GemmArgs &g, hipStream_t st);
 // Same product with K cut into nsplit ranges (batch == 1, nred == 1): partials
 // go to ws (nsplit * M * N doubles) and are summed in a fixed order.
 hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st);
+// Copy the strictly-upper 128 x 128 tiles of nb square n x n matrices from the
+// transposes of their lower tiles (completes a `lower` GEMM of a symmetric result).
+hipError_t mirror_lower_tiles(double *C, int n, long stride, int nb, hipStream_t st);
 // Same contract with the products on reduced-precision matrix cores (FP64 in
 // and out, FP32 accumulation): mode 0 = FP64 (dgemm), 1 = FP32, 2 = split BF16
 // with three products (ris_gemm_mp.hip).

@@ -29,11 +29,22 @@ constexpr int GROUP_M = 2;  // m-tiles swept together so their A panels stay in 
 // XCD one contiguous range of tiles.  Inside a batch the tiles are walked in
 // groups of GROUP_M m-tiles with the n-tile as the slower index, so one B
 // panel serves GROUP_M consecutive tiles and the group's A panels stay hot.
-__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, int &z, int &mt, int &nt)
+__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool lower, int &z, int &mt, int &nt)
 {
     const int q = total / NXCD, r = total % NXCD;
     const int xcd = b % NXCD, local = b / NXCD;
     const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+    if (lower) {  // tiles (mt >= nt) of a square tm x tm grid, row by row
+        const int per = tm * (tm + 1) / 2;
+        z = lin / per;
+        const int t = lin % per;
+        int m = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (m * (m + 1) / 2 > t) --m;
+        while ((m + 1) * (m + 2) / 2 <= t) ++m;
+        mt = m;
+        nt = t - m * (m + 1) / 2;
+        return;
+    }
     const int per = tm * tn;
     z = lin / per;
     const int t = lin % per;
@@ -49,7 +60,7 @@ template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                long lda, long sA, long sAr, const double *__restrict__ B, long ldb,
                                                long sB, long sBr, double beta, double *__restrict__ C, long ldc,
-                                               long sC, int nred, int tm, int tn, int total, int kc)
+                                               long sC, int nred, int tm, int tn, int total, int kc, bool lower)
 {
     __shared__ double As[2][BK][BM + PAD];
     __shared__ double Bs[2][BK][BN + PAD];
@@ -59,7 +70,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
     const int wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     int bz, mt, nt;
-    tile_of(blockIdx.x, total, tm, tn, bz, mt, nt);
+    tile_of(blockIdx.x, total, tm, tn, lower, bz, mt, nt);
     const int m0 = mt * BM, n0 = nt * BN;
     // kc > 0: split-K, the batch index selects the k-range [bz*kc, bz*kc + kc)
     const int kbeg = kc > 0 ? bz * kc : 0;
@@ -166,14 +177,15 @@ hipError_t dgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
-    const long total = (long)tm * tn * g.batch;
+    if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
+    const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
     if (total > 0x7fffffffL) return hipErrorInvalidValue;
     dim3 grid((unsigned)total);
     const int nred = g.nred > 0 ? g.nred : 1;
 #define RIS_GEMM_LAUNCH(TA, TB)                                                                                   \
     hipLaunchKernelGGL((k_dgemm<TA, TB>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.strideA,   \
                        g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, \
-                       (int)total, kc)
+                       (int)total, kc, g.lower)
     if (!g.transA && !g.transB) RIS_GEMM_LAUNCH(false, false);
     else if (g.transA && !g.transB) RIS_GEMM_LAUNCH(true, false);
     else if (!g.transA && g.transB) RIS_GEMM_LAUNCH(false, true);
@@ -265,6 +277,37 @@ __global__ void k_splitk_reduce(const double *__restrict__ ws, int nsplit, int M
 }  // namespace
 
 namespace ris {
+namespace {
+// one 32 x 32 block of an upper tile per workgroup: dst[i][j] = src[j][i] via LDS
+__global__ __launch_bounds__(256) void k_mirror(double *C, int n, long stride, int nblk32)
+{
+    __shared__ double T[32][33];
+    const int z = blockIdx.y;
+    // enumerate 32-blocks (bi, bj) with bi / 4 < bj / 4 (strictly upper 128-tiles)
+    const int b = blockIdx.x;
+    const int bi = b / nblk32, bj = b % nblk32;
+    if (bi / 4 >= bj / 4) return;
+    double *M = C + (long)z * stride;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bj * 32 + r, j = bi * 32 + tx;  // read the lower block (bj, bi)
+        if (i < n && j < n) T[r][tx] = M[(long)i * n + j];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        if (i < n && j < n) M[(long)i * n + j] = T[tx][r];
+    }
+}
+}  // namespace
+
+hipError_t mirror_lower_tiles(double *C, int n, long stride, int nb, hipStream_t st)
+{
+    const int nblk32 = (n + 31) / 32;
+    hipLaunchKernelGGL(k_mirror, dim3(nblk32 * nblk32, nb), dim3(256), 0, st, C, n, stride, nblk32);
+    return hipGetLastError();
+}
+
 hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st)
 {
     if (nsplit <= 1 || g.batch != 1 || g.nred > 1) return dgemm(g, st);

@@ -286,6 +286,7 @@ hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st)
 {
     if (mode == 0) return dgemm(g, st);
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.lower) return hipErrorInvalidValue;  // lower-tile mode is FP64-only
     const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
     const long total = (long)tm * tn * g.batch;
     if (total > 0x7fffffffL) return hipErrorInvalidValue;

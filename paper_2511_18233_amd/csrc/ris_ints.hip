@@ -243,10 +243,18 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
                                                     ShellTab aux, int c0, int nc, int nshAux,
                                                     const double *__restrict__ boys, DerivJob job)
 {
-    const int wid = blockIdx.x;
-    if (wid >= na * nc) return;
-    const int sa = a0 + wid % na;
-    const int sc = c0 + wid / na;
+    // Waves are dispatched round-robin over the 8 XCDs; remap so each XCD walks
+    // a contiguous range with the C shell fastest: waves resident together on
+    // one XCD share the A shell and reuse its density rows from that XCD's L2.
+    const int total = na * nc;
+    if ((int)blockIdx.x >= total) return;
+    int lin;
+    {
+        const int q = total / 8, r = total % 8, x = blockIdx.x % 8, local = blockIdx.x / 8;
+        lin = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + local;
+    }
+    const int sa = a0 + lin / nc;
+    const int sc = c0 + lin % nc;
     const int lane = threadIdx.x;
 
     constexpr int L = LA + LB + LC + 1;
@@ -272,8 +280,16 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
             cJ[o][k] = job.cvec[(size_t)job.stJ[o] * job.nJ + P0 + k];
         }
 
-    for (int ib = lane; ib < nb; ib += 64) {
-        const int sb = b0 + ib;
+    // partners of sa in class LB: all of them, or the screened list
+    int cnt = nb;
+    const int *lst = nullptr;
+    if (job.pair_ptr) {
+        const int q0 = job.pair_ptr[(kMaxAOL + 1) * sa + LB];
+        cnt = job.pair_ptr[(kMaxAOL + 1) * sa + LB + 1] - q0;
+        lst = job.pair_idx + q0;
+    }
+    for (int ib = lane; ib < cnt; ib += 64) {
+        const int sb = lst ? lst[ib] : b0 + ib;
         const double a = ao.exp[sa], b = ao.exp[sb];
         const double p = a + b, ip = 1.0 / p;
         const double Bx = ao.x[sb], By = ao.y[sb], Bz = ao.z[sb];
@@ -293,33 +309,41 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
         const int nu0 = ao.off[sb];
         const double twoa = 2.0 * a;
 
-        sfor<ncart(LC)>([&](auto kc) {
-            constexpr int sx = cpow(LC, kc, 0), sy = cpow(LC, kc, 1), sz = cpow(LC, kc, 2);
-            sfor<ncart(LA)>([&](auto ka) {
-                constexpr int ix = cpow(LA, ka, 0), iy = cpow(LA, ka, 1), iz = cpow(LA, ka, 2);
-                sfor<ncart(LB)>([&](auto kb) {
-                    constexpr int jx = cpow(LB, kb, 0), jy = cpow(LB, kb, 1), jz = cpow(LB, kb, 2);
-                    const double *ex = Ex.e[ix][jx];
-                    const double *ey = Ey.e[iy][jy];
-                    const double *ez = Ez.e[iz][jz];
-                    // derivative coefficients 2a E_{i+1} - i E_{i-1} per direction
-                    double dx[ix + jx + 2], dy[iy + jy + 2], dz[iz + jz + 2];
-                    sfor<ix + jx + 2>([&](auto t) {
-                        double v = twoa * Ex.e[ix + 1][jx][t];
-                        if constexpr (ix > 0 && t <= ix - 1 + jx) v -= ix * Ex.e[ix - 1][jx][t];
-                        dx[t] = v;
-                    });
-                    sfor<iy + jy + 2>([&](auto t) {
-                        double v = twoa * Ey.e[iy + 1][jy][t];
-                        if constexpr (iy > 0 && t <= iy - 1 + jy) v -= iy * Ey.e[iy - 1][jy][t];
-                        dy[t] = v;
-                    });
-                    sfor<iz + jz + 2>([&](auto t) {
-                        double v = twoa * Ez.e[iz + 1][jz][t];
-                        if constexpr (iz > 0 && t <= iz - 1 + jz) v -= iz * Ez.e[iz - 1][jz][t];
-                        dz[t] = v;
-                    });
-                    constexpr int NX = ix + jx + 1, NY = iy + jy + 1, NZ = iz + jz + 1;
+        sfor<ncart(LA)>([&](auto ka) {
+            constexpr int ix = cpow(LA, ka, 0), iy = cpow(LA, ka, 1), iz = cpow(LA, ka, 2);
+            sfor<ncart(LB)>([&](auto kb) {
+                constexpr int jx = cpow(LB, kb, 0), jy = cpow(LB, kb, 1), jz = cpow(LB, kb, 2);
+                const double *ex = Ex.e[ix][jx];
+                const double *ey = Ey.e[iy][jy];
+                const double *ez = Ez.e[iz][jz];
+                // derivative coefficients 2a E_{i+1} - i E_{i-1} per direction
+                double dx[ix + jx + 2], dy[iy + jy + 2], dz[iz + jz + 2];
+                sfor<ix + jx + 2>([&](auto t) {
+                    double v = twoa * Ex.e[ix + 1][jx][t];
+                    if constexpr (ix > 0 && t <= ix - 1 + jx) v -= ix * Ex.e[ix - 1][jx][t];
+                    dx[t] = v;
+                });
+                sfor<iy + jy + 2>([&](auto t) {
+                    double v = twoa * Ey.e[iy + 1][jy][t];
+                    if constexpr (iy > 0 && t <= iy - 1 + jy) v -= iy * Ey.e[iy - 1][jy][t];
+                    dy[t] = v;
+                });
+                sfor<iz + jz + 2>([&](auto t) {
+                    double v = twoa * Ez.e[iz + 1][jz][t];
+                    if constexpr (iz > 0 && t <= iz - 1 + jz) v -= iz * Ez.e[iz - 1][jz][t];
+                    dz[t] = v;
+                });
+                constexpr int NX = ix + jx + 1, NY = iy + jy + 1, NZ = iz + jz + 1;
+                const size_t mn = (size_t)(mu0 + ka) * nao + nu0 + kb;
+                // Coulomb densities of this (mu, nu): loaded once for all auxiliary components
+                double dI[NO], dJ[NO];
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    dI[o] = (o < job.nout) ? job.alphaJ * job.dens[(size_t)job.stI[o] * nao2 + mn] : 0.0;
+                    dJ[o] = (o < job.nout) ? job.alphaJ * job.dens[(size_t)job.stJ[o] * nao2 + mn] : 0.0;
+                }
+                sfor<ncart(LC)>([&](auto kc) {
+                    constexpr int sx = cpow(LC, kc, 0), sy = cpow(LC, kc, 1), sz = cpow(LC, kc, 2);
                     const double f = pref * cfac * cnorm(LA, ka) * cnorm(LB, kb);
                     double dA[3], dC[3];
                     dA[0] = f * hsum<NX + 1, NY, NZ, sx, sy, sz>(dx, ey, ez, r);
@@ -328,12 +352,10 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
                     dC[0] = -f * hsum<NX, NY, NZ, sx + 1, sy, sz>(ex, ey, ez, r);
                     dC[1] = -f * hsum<NX, NY, NZ, sx, sy + 1, sz>(ex, ey, ez, r);
                     dC[2] = -f * hsum<NX, NY, NZ, sx, sy, sz + 1>(ex, ey, ez, r);
-                    const size_t mn = (size_t)(mu0 + ka) * nao + nu0 + kb;
 #pragma unroll
                     for (int o = 0; o < NO; ++o) {
                         if (o < job.nout) {
-                            double w = job.alphaJ * (job.dens[(size_t)job.stI[o] * nao2 + mn] * cJ[o][kc] +
-                                                     job.dens[(size_t)job.stJ[o] * nao2 + mn] * cI[o][kc]);
+                            double w = dI[o] * cJ[o][kc] + dJ[o] * cI[o][kc];
                             if (inK && job.gammaK)
                                 w += job.gammaK[((size_t)o * job.nK + P0 + kc) * nao2 + mn];
                             const double w2 = 2.0 * w;

@@ -24,7 +24,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
            "ris_response_matvec", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
            "ris_request_bytes",
-           "ris_ctx_set_profiling",
+           "ris_ctx_set_profiling", "ris_ctx_set_screening",
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
            "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm")
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib.ris_request_bytes.restype = ctypes.c_size_t
     lib.ris_grad_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp, ctypes.c_int, ip, dp, vp]
     lib.ris_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.ris_ctx_set_screening.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_long)]
     lib.ris_ctx_stage_stats.argtypes = [vp, ctypes.c_int, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
     lib.ris_test_mfma_probe.argtypes = [ctypes.c_int, vp, vp, vp]
     L = ctypes.c_long
@@ -167,6 +168,13 @@ class RisContext:
         return int(self.lib.ris_ctx_bytes(self.h))
 
     STAGES = ("int3c", "mo", "matvec", "hblk", "gamma", "deriv", "aux", "yw", "vpq")
+
+    def set_screening(self, threshold: float) -> int:
+        """Shell-pair screen threshold of the derivative contraction (0: off);
+        returns the number of ordered shell pairs kept (-1 before aux_build)."""
+        kept = ctypes.c_long(0)
+        self._chk(self.lib.ris_ctx_set_screening(self.h, float(threshold), ctypes.byref(kept)))
+        return int(kept.value)
 
     def set_profiling(self, on: bool):
         self._chk(self.lib.ris_ctx_set_profiling(self.h, int(bool(on))))

@@ -107,3 +107,27 @@ def test_chain200_mixed_precision(ctx, radii):
         err = np.abs(res[prec] - res["fp64"]).max()
         say(f"[gpu] chain200 {prec}: max |d| vs fp64 {err:.3e} Ha/Bohr")
         assert err <= 1e-6
+
+
+def test_chain200_pair_screen_error(ctx, radii):
+    """The default shell-pair screen of the derivative contraction changes the
+    199-atom results by at most 1e-11 Ha/Bohr (against the unscreened GPU path,
+    which the smaller parity cases tie to the oracle) while skipping most pairs."""
+    import torch
+    prob = molgen.make_problem("chain200")
+    X = torch.as_tensor(prob.X, device=ctx.device)
+    Y = torch.as_tensor(prob.Y, device=ctx.device)
+    _gpu_problem(ctx, prob, radii, True)
+    nsh = len(prob.mol.shell_l)
+    try:
+        kept = ctx.set_screening(1e-15)
+        say(f"[gpu] chain200 screen 1e-15 keeps {kept} of {nsh * nsh} shell pairs")
+        assert 0 < kept < 0.3 * nsh * nsh
+        g1, n1 = ctx.grad_nac_contract(X, Y, [0, 5], [(1, 2)])
+        assert ctx.set_screening(0.0) == nsh * nsh
+        g0, n0 = ctx.grad_nac_contract(X, Y, [0, 5], [(1, 2)])
+    finally:
+        ctx.set_screening(1e-15)
+    err = max(float((g1 - g0).abs().max()), float((n1 - n0).abs().max()))
+    say(f"[gpu]   screened vs unscreened max diff {err:.3e} (max |g| {float(g0.abs().max()):.3e})")
+    assert err <= 1e-11
