@@ -1020,23 +1020,14 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nK * N * o3 * o3, 0.0);
             double *Gk = G + (size_t)k * nK * NN;
             const double *FJ = F + (size_t)J * N * o3;
-            if (c->prec == RIS_FP64) {
-                // only the symmetric part of Gamma^P enters (integrals symmetric in mu nu):
-                // gradients: Y F_I^T is symmetric -> lower tiles + mirror (half the work);
-                // NACs: -c_x (Y F_J^T + F_J Y^T) on lower tiles + mirror
-                const double sc = (I == J) ? -2.0 * c->cx : -c->cx;
-                g = gm(N, N, (int)o3, false, true, sc, Y3, o3, FJ, o3, 0.0, Gk, N);
+            if (c->prec == RIS_FP64 && I == J) {
+                // gradients: Gamma^P = -2 c_x Y F_I^T is symmetric -> lower tiles + mirror (half the work)
+                g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
                 g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
                 hipEvent_t t_g = stage_begin(c);
                 HIPCHK(c, dgemm(g, c->stream));
-                if (I != J) {
-                    g = gm(N, N, (int)o3, false, true, sc, FJ, o3, Y3, o3, 1.0, Gk, N);
-                    g.batch = nK; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
-                    HIPCHK(c, dgemm(g, c->stream));
-                }
-                const double nprod = (I == J) ? 1.0 : 2.0;
-                stage_end(c, t_g, RIS_STAGE_GAMMA, nprod * (double)nK * N * (N + 1) * o3,
-                          8.0 * ((double)nK * N * (N + 1) / 2 * (nprod + 1) + nprod * ((double)nK * N * o3 + N * o3)));
+                stage_end(c, t_g, RIS_STAGE_GAMMA, (double)nK * N * (N + 1) * o3,
+                          8.0 * ((double)nK * N * (N + 1) / 2 + (double)nK * N * o3 + (double)N * o3));
                 HIPCHK(c, mirror_lower_tiles(Gk, N, NN, nK, c->stream));
             } else {
                 g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);

@@ -56,7 +56,11 @@ __device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool l
     nt = tg / gm;
 }
 
-template <bool TA, bool TB>
+// alpha scales the A slabs on their way to LDS and, unless BETA, the
+// accumulators are stored as they are: arithmetic in the epilogue makes the
+// compiler stage all 64 accumulator values through VGPRs at once, which
+// halves the occupancy (one wave per SIMD instead of two).
+template <bool TA, bool TB, bool BETA>
 __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                long lda, long sA, long sAr, const double *__restrict__ B, long ldb,
                                                long sB, long sBr, double beta, double *__restrict__ C, long ldc,
@@ -106,6 +110,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
                 const int gm = m0 + m, gk = k0 + k;
                 ra[q] = (gm < M && gk < kend) ? Ar[(long)gk * lda + gm] : 0.0;
             }
+            if (alpha != 1.0) ra[q] *= alpha;
             if (!TB) {  // B is K x N: element (k, n) at Br[k*ldb + n]
                 const int n = tid & 127, k = (tid >> 7) + 2 * q;
                 const int gn = n0 + n, gk = k0 + k;
@@ -164,8 +169,8 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
                 const int row = m0 + wm * 64 + i * 16 + 4 * e + (lane >> 4);
                 if (row < M && col < N) {
                     double *cp = C + (long)row * ldc + col;
-                    const double v = alpha * acc[i][j][e];
-                    *cp = (beta == 0.0) ? v : v + beta * *cp;
+                    if constexpr (BETA) *cp = acc[i][j][e] + beta * *cp;
+                    else *cp = acc[i][j][e];
                 }
             }
         }
@@ -183,14 +188,17 @@ hipError_t dgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
     dim3 grid((unsigned)total);
     const int nred = g.nred > 0 ? g.nred : 1;
 #define RIS_GEMM_LAUNCH(TA, TB)                                                                                   \
-    hipLaunchKernelGGL((k_dgemm<TA, TB>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.strideA,   \
+    if (g.beta != 0.0) RIS_GEMM_LAUNCH1(TA, TB, true) else RIS_GEMM_LAUNCH1(TA, TB, false)
+#define RIS_GEMM_LAUNCH1(TA, TB, BETA)                                                                            \
+    hipLaunchKernelGGL((k_dgemm<TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.strideA,   \
                        g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, \
-                       (int)total, kc, g.lower)
-    if (!g.transA && !g.transB) RIS_GEMM_LAUNCH(false, false);
-    else if (g.transA && !g.transB) RIS_GEMM_LAUNCH(true, false);
-    else if (!g.transA && g.transB) RIS_GEMM_LAUNCH(false, true);
-    else RIS_GEMM_LAUNCH(true, true);
+                       (int)total, kc, g.lower);
+    if (!g.transA && !g.transB) { RIS_GEMM_LAUNCH(false, false) }
+    else if (g.transA && !g.transB) { RIS_GEMM_LAUNCH(true, false) }
+    else if (!g.transA && g.transB) { RIS_GEMM_LAUNCH(false, true) }
+    else { RIS_GEMM_LAUNCH(true, true) }
 #undef RIS_GEMM_LAUNCH
+#undef RIS_GEMM_LAUNCH1
     return hipGetLastError();
 }
 
