@@ -126,7 +126,8 @@ def serve_bench(nreq, nslots, radii):
     FP32; throughput and p50/p99 latency of each."""
     from paper_2511_18233_amd.serve import GpuExecutor, Server, latency_stats, make_trace
     log(f"[bench] serving: building a {nreq}-request trace")
-    reqs = make_trace(nreq, max(1, nreq // 16), rate_hz=1.0, seed=1000)
+    reqs = make_trace(nreq, max(1, nreq // 16), rate_hz=1.0, seed=1000,
+                      progress=lambda k, n: log(f"[bench] serving: built {k}/{n} requests"))
     seq = Server([GpuExecutor(0, 0, radii, "fp64")], 200 << 30)
     warm = seq.run_trace(reqs[:2], realtime=False)  # warm the slot's regions
     del warm

@@ -56,15 +56,28 @@ __device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool l
     nt = tg / gm;
 }
 
+// element at a uniform base plus a 32-bit element offset (byte offset < 2^32)
+__device__ __forceinline__ double ld_off(const double *base, int off)
+{
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + ((unsigned)off << 3));
+}
+
+// Main loop per 16-deep k-slab: the next slab's global loads are issued at
+// the top, the matrix-core work of the current slab runs from LDS, and the
+// next slab is written to the other LDS buffer before one barrier.  Loads use
+// clamped addresses and a 0/1 factor instead of per-element branches, so the
+// whole slab is one basic block and the scheduler can interleave the memory
+// instructions with the 64 MFMAs of the slab (group barriers below); two
+// waves per SIMD (256 unified registers each) keep the matrix cores fed.
+//
 // alpha scales the A slabs on their way to LDS and, unless BETA, the
-// accumulators are stored as they are: arithmetic in the epilogue makes the
-// compiler stage all 64 accumulator values through VGPRs at once, which
-// halves the occupancy (one wave per SIMD instead of two).
+// accumulators are stored as they are (arithmetic on them in the epilogue
+// makes the compiler stage all 64 values through registers at once).
 template <bool TA, bool TB, bool BETA>
-__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha, const double *__restrict__ A,
-                                               long lda, long sA, long sAr, const double *__restrict__ B, long ldb,
-                                               long sB, long sBr, double beta, double *__restrict__ C, long ldc,
-                                               long sC, int nred, int tm, int tn, int total, int kc, bool lower)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dgemm(
+    int M, int N, int K, double alpha, const double *__restrict__ A, long lda, long sA, long sAr,
+    const double *__restrict__ B, long ldb, long sB, long sBr, double beta, double *__restrict__ C, long ldc, long sC,
+    int nred, int tm, int tn, int total, int kc, bool lower)
 {
     __shared__ double As[2][BK][BM + PAD];
     __shared__ double Bs[2][BK][BN + PAD];
@@ -89,7 +102,30 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    // global -> register staging: 8 doubles of A and 8 of B per thread
+    // per-thread element coordinates of the staging pattern:
+    //   k-fast (A not transposed / B transposed): k = tid & 15, row = (tid >> 4) + 16 q
+    //   m/n-fast (A transposed / B not transposed): col = tid & 127, k = (tid >> 7) + 2 q
+    const int kf = tid & 15, rf = tid >> 4;
+    const int cf = tid & 127, kr = tid >> 7;
+    // Addresses: a uniform panel base (scalar registers) plus a 32-bit
+    // per-thread element offset, clamped into the operand so every load is
+    // valid; out-of-range elements are zeroed by a 0/1 factor (a product, not
+    // a select, so the compiler keeps the loads unconditional).  The launcher
+    // guarantees that every byte offset fits 32 bits (scalar base + 32-bit
+    // vector offset addressing).
+    int offA[8], offB[8];
+    double mA[8], mB[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int gm = m0 + rf + 16 * q, gn = n0 + rf + 16 * q;
+        mA[q] = gm < M ? 1.0 : 0.0;
+        mB[q] = gn < N ? 1.0 : 0.0;
+        offA[q] = (min(gm, M - 1) - m0) * (int)lda;
+        offB[q] = (min(gn, N - 1) - n0) * (int)ldb;
+    }
+    const double mAc = m0 + cf < M ? 1.0 : 0.0, mBc = n0 + cf < N ? 1.0 : 0.0;
+    const int cA = min(m0 + cf, M - 1) - m0, cB = min(n0 + cf, N - 1) - n0;
+
     double ra[8], rb[8];
     const int ktiles = (kend - kbeg + BK - 1) / BK;
     const int niter = ktiles * nred;
@@ -97,38 +133,39 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
     auto load = [&](int it) {
         const int r = it / ktiles;
         const int k0 = kbeg + (it % ktiles) * BK;
-        const double *Ar = A + (long)r * sAr;
-        const double *Br = B + (long)r * sBr;
+        // panel bases: k-fast operands start at row m0 / n0, the others at row k0
+        const double *pA = A + (long)r * sAr + (TA ? (long)k0 * lda + m0 : (long)m0 * lda);
+        const double *pB = B + (long)r * sBr + (TB ? (long)n0 * ldb : (long)k0 * ldb + n0);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            if (!TA) {  // A is M x K: element (m, k) at Ar[m*lda + k]; 16 threads per row
-                const int k = tid & 15, m = (tid >> 4) + 16 * q;
-                const int gm = m0 + m, gk = k0 + k;
-                ra[q] = (gm < M && gk < kend) ? Ar[(long)gm * lda + gk] : 0.0;
-            } else {    // A stored K x M: element (m, k) at Ar[k*lda + m]
-                const int m = tid & 127, k = (tid >> 7) + 2 * q;
-                const int gm = m0 + m, gk = k0 + k;
-                ra[q] = (gm < M && gk < kend) ? Ar[(long)gk * lda + gm] : 0.0;
+            if (!TA) {
+                const int gk = k0 + kf;
+                const double x = ld_off(pA, offA[q] + min(gk, kend - 1));
+                ra[q] = x * (gk < kend ? mA[q] : 0.0);
+            } else {
+                const int gk = k0 + kr + 2 * q;
+                const double x = ld_off(pA, (min(gk, kend - 1) - k0) * (int)lda + cA);
+                ra[q] = x * (gk < kend ? mAc : 0.0);
             }
-            if (alpha != 1.0) ra[q] *= alpha;
-            if (!TB) {  // B is K x N: element (k, n) at Br[k*ldb + n]
-                const int n = tid & 127, k = (tid >> 7) + 2 * q;
-                const int gn = n0 + n, gk = k0 + k;
-                rb[q] = (gn < N && gk < kend) ? Br[(long)gk * ldb + gn] : 0.0;
-            } else {    // B stored N x K: element (k, n) at Br[n*ldb + k]
-                const int k = tid & 15, n = (tid >> 4) + 16 * q;
-                const int gn = n0 + n, gk = k0 + k;
-                rb[q] = (gn < N && gk < kend) ? Br[(long)gn * ldb + gk] : 0.0;
+            if (!TB) {
+                const int gk = k0 + kr + 2 * q;
+                const double x = ld_off(pB, (min(gk, kend - 1) - k0) * (int)ldb + cB);
+                rb[q] = x * (gk < kend ? mBc : 0.0);
+            } else {
+                const int gk = k0 + kf;
+                const double x = ld_off(pB, offB[q] + min(gk, kend - 1));
+                rb[q] = x * (gk < kend ? mB[q] : 0.0);
             }
         }
     };
     auto store = [&](int stg) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            if (!TA) As[stg][tid & 15][(tid >> 4) + 16 * q] = ra[q];
-            else As[stg][(tid >> 7) + 2 * q][tid & 127] = ra[q];
-            if (!TB) Bs[stg][(tid >> 7) + 2 * q][tid & 127] = rb[q];
-            else Bs[stg][tid & 15][(tid >> 4) + 16 * q] = rb[q];
+            const double x = ra[q] * alpha;
+            if (!TA) As[stg][kf][rf + 16 * q] = x;
+            else As[stg][kr + 2 * q][cf] = x;
+            if (!TB) Bs[stg][kr + 2 * q][cf] = rb[q];
+            else Bs[stg][kf][rf + 16 * q] = rb[q];
         }
     };
 
@@ -139,8 +176,8 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
     __syncthreads();
     for (int it = 0; it < niter; ++it) {
         const int cur = it & 1;
-        // the next slab is in flight while the current one feeds the matrix cores
-        if (it + 1 < niter) load(it + 1);
+        // next slab (the last iteration reloads its own slab: in bounds, never read)
+        load(min(it + 1, niter - 1));
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double fa[4], fb[4];
@@ -154,8 +191,30 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, double alpha
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
         }
-        // the other stage was last read in iteration it-1, before the barrier that ended it
-        if (it + 1 < niter) store(cur ^ 1);
+        // the other buffer was last read in iteration it-1, before the barrier that ended it
+        store(cur ^ 1);
+        // schedule: fragment reads of the first k-step, then the 16 global loads
+        // one per MFMA, the remaining fragment reads one per MFMA, and the 16
+        // LDS writes one per MFMA over the last k-step
+#pragma unroll
+        for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 24; ++u) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
         __syncthreads();
     }
 
@@ -185,6 +244,10 @@ hipError_t dgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
     if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
     const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
     if (total > 0x7fffffffL) return hipErrorInvalidValue;
+    // every operand byte offset from a panel base must fit 32 bits
+    const long spanA = g.transA ? (BK - 1) * g.lda + g.M : (BM - 1) * g.lda + g.K;
+    const long spanB = g.transB ? (BN - 1) * g.ldb + g.K : (BK - 1) * g.ldb + g.N;
+    if (8 * std::max(spanA, spanB) >= (1L << 32)) return hipErrorInvalidValue;
     dim3 grid((unsigned)total);
     const int nred = g.nred > 0 ? g.nred : 1;
 #define RIS_GEMM_LAUNCH(TA, TB)                                                                                   \

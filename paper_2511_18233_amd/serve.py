@@ -226,13 +226,14 @@ def latency_stats(results) -> dict:
 
 # --------------------------------------------------------------- traces --
 def make_trace(n_requests: int, n_traj: int, rate_hz: float, seed: int = 1000, natm_range=(20, 120),
-               nstate: int = 3, step_ang: float = 0.01):
+               nstate: int = 3, step_ang: float = 0.01, progress=None):
     """Surface-hopping-shaped trace: n_traj seeded trajectories of chain
     molecules (size uniform in natm_range), each request one step of its
     trajectory (previous geometry + N(0, step_ang) per coordinate, C = S^-1/2 Q
     recomputed, Q, eps and amplitudes fixed per trajectory), asking for the
     gradients of states 0 and 1 and the NAC numerator (0, 1); arrivals Poisson
-    with the given rate."""
+    with the given rate.  progress(done, total), if given, is called every 32
+    requests built."""
     import molgen
     rng = np.random.default_rng(seed)
     trajs = []
@@ -258,4 +259,6 @@ def make_trace(n_requests: int, n_traj: int, rate_hz: float, seed: int = 1000, n
         C = (V * (1.0 / np.sqrt(w))) @ V.T @ Q
         reqs.append(Request(k, float(arrivals[k]), mol.Z, mol.xyz, mol.shell_atom, mol.shell_l, mol.shell_exp,
                             np.ascontiguousarray(C), p.eps, p.nocc, p.X, p.Y, [0, 1], [(0, 1)]))
+        if progress is not None and (k + 1) % 32 == 0:
+            progress(k + 1, n_requests)
     return reqs
