@@ -1020,12 +1020,12 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nK * N * o3 * o3, 0.0);
             double *Gk = G + (size_t)k * nK * NN;
             const double *FJ = F + (size_t)J * N * o3;
-            if (c->prec == RIS_FP64 && I == J) {
+            if (c->prec != RIS_BF16X3 && I == J) {
                 // gradients: Gamma^P = -2 c_x Y F_I^T is symmetric -> lower tiles + mirror (half the work)
                 g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
                 g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
                 hipEvent_t t_g = stage_begin(c);
-                HIPCHK(c, dgemm(g, c->stream));
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
                 stage_end(c, t_g, RIS_STAGE_GAMMA, (double)nK * N * (N + 1) * o3,
                           8.0 * ((double)nK * N * (N + 1) / 2 + (double)nK * N * o3 + (double)N * o3));
                 HIPCHK(c, mirror_lower_tiles(Gk, N, NN, nK, c->stream));

@@ -108,6 +108,9 @@ hipError_t mirror_lower_tiles(double *C, int n, long stride, int nb, hipStream_t
 // and out, FP32 accumulation): mode 0 = FP64 (dgemm), 1 = FP32, 2 = split BF16
 // with three products (ris_gemm_mp.hip).
 hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st);
+// The matrix-core GEMM itself for mode 0 (FP64) or 1 (FP32); kc > 0 splits K
+// into ranges of kc indexed by the batch (ris_gemm.hip).
+hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st);
 
 // Dense linear algebra on small matrices (ris_linalg.hip).
 // In-place Cholesky of the n x n SPD matrix (lower triangle written, upper

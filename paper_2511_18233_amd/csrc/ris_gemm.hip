@@ -17,6 +17,7 @@
 
 namespace ris {
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 128, BN = 128, BK = 16;
@@ -62,25 +63,53 @@ __device__ __forceinline__ double ld_off(const double *base, int off)
     return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + ((unsigned)off << 3));
 }
 
-// Main loop per 16-deep k-slab: the next slab's global loads are issued at
-// the top, the matrix-core work of the current slab runs from LDS, and the
-// next slab is written to the other LDS buffer before one barrier.  Loads use
-// clamped addresses and a 0/1 factor instead of per-element branches, so the
-// whole slab is one basic block and the scheduler can interleave the memory
-// instructions with the 64 MFMAs of the slab (group barriers below); two
-// waves per SIMD (256 unified registers each) keep the matrix cores fed.
+// Matrix-core flavours of the one kernel below:
+//   MODE 0: FP64 operands in LDS, v_mfma_f64_16x16x4f64, k-slab 16;
+//   MODE 1: operands rounded to FP32 in LDS, v_mfma_f32_16x16x4f32 with FP32
+//           accumulation, k-slab 32 (same matrix-core time per slab, since
+//           the FP32 instruction runs at twice the FP64 rate).
+// The FP32 instruction leaves D[4 (l/16) + e][l % 16] in accumulator element
+// e of lane l (rows in blocks of four), the FP64 one D[4 e + l/16][l % 16].
+template <int MODE> struct MfmaCfg;
+template <> struct MfmaCfg<0> {
+    typedef double T;
+    typedef v4d V;
+    static constexpr int BKm = 16;
+    static __device__ __forceinline__ V mfma(T a, T b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int row(int lane, int e) { return 4 * e + (lane >> 4); }
+};
+template <> struct MfmaCfg<1> {
+    typedef float T;
+    typedef v4f V;
+    static constexpr int BKm = 32;
+    static __device__ __forceinline__ V mfma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+
+// Main loop per k-slab: the next slab's global loads are issued at the top,
+// the matrix-core work of the current slab runs from LDS, and the next slab
+// is written to the other LDS buffer before one barrier.  Loads use clamped
+// addresses and a 0/1 factor instead of per-element branches, so a slab is
+// one basic block and the scheduler can interleave the memory instructions
+// with the MFMAs of the slab (group barriers below); two waves per SIMD (256
+// unified registers each) keep the matrix cores fed.
 //
 // alpha scales the A slabs on their way to LDS and, unless BETA, the
 // accumulators are stored as they are (arithmetic on them in the epilogue
-// makes the compiler stage all 64 values through registers at once).
-template <bool TA, bool TB, bool BETA>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_dgemm(
+// makes the compiler stage all of them through registers at once).
+template <int MODE, bool TA, bool TB, bool BETA>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm(
     int M, int N, int K, double alpha, const double *__restrict__ A, long lda, long sA, long sAr,
     const double *__restrict__ B, long ldb, long sB, long sBr, double beta, double *__restrict__ C, long ldc, long sC,
     int nred, int tm, int tn, int total, int kc, bool lower)
 {
-    __shared__ double As[2][BK][BM + PAD];
-    __shared__ double Bs[2][BK][BN + PAD];
+    typedef MfmaCfg<MODE> Cfg;
+    typedef typename Cfg::T T;
+    constexpr int SK = Cfg::BKm;       // k-slab depth
+    constexpr int NQ = BM * SK / 256;  // elements per thread per operand and slab
+    constexpr int KF = SK;             // threads per row in the k-fast staging pattern
+    __shared__ T As[2][SK][BM + PAD];
+    __shared__ T Bs[2][SK][BN + PAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -96,16 +125,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     B += (long)bz * sB;
     C += (long)bz * sC;
 
-    v4d acc[4][4];
+    typename Cfg::V acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
 
-    // per-thread element coordinates of the staging pattern:
-    //   k-fast (A not transposed / B transposed): k = tid & 15, row = (tid >> 4) + 16 q
+    // staging patterns (element q of a thread):
+    //   k-fast (A not transposed / B transposed): k = tid % SK, row = tid / SK + (256 / SK) q
     //   m/n-fast (A transposed / B not transposed): col = tid & 127, k = (tid >> 7) + 2 q
-    const int kf = tid & 15, rf = tid >> 4;
+    const int kf = tid % KF, rf = tid / KF;
+    constexpr int RSTEP = 256 / KF;
     const int cf = tid & 127, kr = tid >> 7;
     // Addresses: a uniform panel base (scalar registers) plus a 32-bit
     // per-thread element offset, clamped into the operand so every load is
@@ -113,11 +145,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // a select, so the compiler keeps the loads unconditional).  The launcher
     // guarantees that every byte offset fits 32 bits (scalar base + 32-bit
     // vector offset addressing).
-    int offA[8], offB[8];
-    double mA[8], mB[8];
+    int offA[NQ], offB[NQ];
+    double mA[NQ], mB[NQ];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int gm = m0 + rf + 16 * q, gn = n0 + rf + 16 * q;
+    for (int q = 0; q < NQ; ++q) {
+        const int gm = m0 + rf + RSTEP * q, gn = n0 + rf + RSTEP * q;
         mA[q] = gm < M ? 1.0 : 0.0;
         mB[q] = gn < N ? 1.0 : 0.0;
         offA[q] = (min(gm, M - 1) - m0) * (int)lda;
@@ -126,18 +158,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const double mAc = m0 + cf < M ? 1.0 : 0.0, mBc = n0 + cf < N ? 1.0 : 0.0;
     const int cA = min(m0 + cf, M - 1) - m0, cB = min(n0 + cf, N - 1) - n0;
 
-    double ra[8], rb[8];
-    const int ktiles = (kend - kbeg + BK - 1) / BK;
+    double ra[NQ], rb[NQ];
+    const int ktiles = (kend - kbeg + SK - 1) / SK;
     const int niter = ktiles * nred;
 
     auto load = [&](int it) {
         const int r = it / ktiles;
-        const int k0 = kbeg + (it % ktiles) * BK;
+        const int k0 = kbeg + (it % ktiles) * SK;
         // panel bases: k-fast operands start at row m0 / n0, the others at row k0
         const double *pA = A + (long)r * sAr + (TA ? (long)k0 * lda + m0 : (long)m0 * lda);
         const double *pB = B + (long)r * sBr + (TB ? (long)n0 * ldb : (long)k0 * ldb + n0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < NQ; ++q) {
             if (!TA) {
                 const int gk = k0 + kf;
                 const double x = ld_off(pA, offA[q] + min(gk, kend - 1));
@@ -160,12 +192,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     };
     auto store = [&](int stg) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const double x = ra[q] * alpha;
-            if (!TA) As[stg][kf][rf + 16 * q] = x;
+        for (int q = 0; q < NQ; ++q) {
+            const T x = (T)(ra[q] * alpha), y = (T)rb[q];
+            if (!TA) As[stg][kf][rf + RSTEP * q] = x;
             else As[stg][kr + 2 * q][cf] = x;
-            if (!TB) Bs[stg][kr + 2 * q][cf] = rb[q];
-            else Bs[stg][kf][rf + 16 * q] = rb[q];
+            if (!TB) Bs[stg][kr + 2 * q][cf] = y;
+            else Bs[stg][kf][rf + RSTEP * q] = y;
         }
     };
 
@@ -179,8 +211,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         // next slab (the last iteration reloads its own slab: in bounds, never read)
         load(min(it + 1, niter - 1));
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            double fa[4], fb[4];
+        for (int kk = 0; kk < SK; kk += 4) {
+            T fa[4], fb[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) fa[i] = As[cur][kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
@@ -188,30 +220,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 4; ++j) acc[i][j] = Cfg::mfma(fa[i], fb[j], acc[i][j]);
         }
         // the other buffer was last read in iteration it-1, before the barrier that ended it
         store(cur ^ 1);
-        // schedule: fragment reads of the first k-step, then the 16 global loads
-        // one per MFMA, the remaining fragment reads one per MFMA, and the 16
-        // LDS writes one per MFMA over the last k-step
+        // schedule: fragment reads of the first k-step, then the global loads
+        // one per MFMA, the remaining fragment reads one per MFMA, and the LDS
+        // writes one per MFMA over the last MFMAs of the slab
+        constexpr int NMF = 16 * (SK / 4), NLD = 2 * NQ, NDR = 8 * (SK / 4), NDW = 2 * NQ;
 #pragma unroll
         for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < NLD; ++u) {
             __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         }
 #pragma unroll
-        for (int u = 0; u < 24; ++u) {
+        for (int u = 0; u < NDR - 8; ++u) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        for (int u = 0; u < NMF - NLD - (NDR - 8) - NDW; ++u) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < NDW; ++u) {
             __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         }
@@ -225,11 +257,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const int col = n0 + wn * 64 + j * 16 + (lane & 15);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = m0 + wm * 64 + i * 16 + 4 * e + (lane >> 4);
+                const int row = m0 + wm * 64 + i * 16 + Cfg::row(lane, e);
                 if (row < M && col < N) {
                     double *cp = C + (long)row * ldc + col;
-                    if constexpr (BETA) *cp = acc[i][j][e] + beta * *cp;
-                    else *cp = acc[i][j][e];
+                    if constexpr (BETA) *cp = (double)acc[i][j][e] + beta * *cp;
+                    else *cp = (double)acc[i][j][e];
                 }
             }
         }
@@ -237,33 +269,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 }  // namespace
 
-hipError_t dgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
+// Launch of the matrix-core GEMM (mode 0 FP64, 1 FP32); kc > 0: split-K ranges.
+hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (mode != 0 && mode != 1) return hipErrorInvalidValue;
     const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
     if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
     const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
     if (total > 0x7fffffffL) return hipErrorInvalidValue;
     // every operand byte offset from a panel base must fit 32 bits
-    const long spanA = g.transA ? (BK - 1) * g.lda + g.M : (BM - 1) * g.lda + g.K;
-    const long spanB = g.transB ? (BN - 1) * g.ldb + g.K : (BK - 1) * g.ldb + g.N;
+    const long SKm = mode == 0 ? 16 : 32;
+    const long spanA = g.transA ? (SKm - 1) * g.lda + g.M : (BM - 1) * g.lda + g.K;
+    const long spanB = g.transB ? (BN - 1) * g.ldb + g.K : (SKm - 1) * g.ldb + g.N;
     if (8 * std::max(spanA, spanB) >= (1L << 32)) return hipErrorInvalidValue;
     dim3 grid((unsigned)total);
     const int nred = g.nred > 0 ? g.nred : 1;
-#define RIS_GEMM_LAUNCH(TA, TB)                                                                                   \
-    if (g.beta != 0.0) RIS_GEMM_LAUNCH1(TA, TB, true) else RIS_GEMM_LAUNCH1(TA, TB, false)
-#define RIS_GEMM_LAUNCH1(TA, TB, BETA)                                                                            \
-    hipLaunchKernelGGL((k_dgemm<TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.strideA,   \
-                       g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, \
-                       (int)total, kc, g.lower);
-    if (!g.transA && !g.transB) { RIS_GEMM_LAUNCH(false, false) }
-    else if (g.transA && !g.transB) { RIS_GEMM_LAUNCH(true, false) }
-    else if (!g.transA && g.transB) { RIS_GEMM_LAUNCH(false, true) }
-    else { RIS_GEMM_LAUNCH(true, true) }
+#define RIS_GEMM_LAUNCH1(MODE, TA, TB, BETA)                                                                     \
+    hipLaunchKernelGGL((k_gemm<MODE, TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,  \
+                       g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC,     \
+                       nred, tm, tn, (int)total, kc, g.lower);
+#define RIS_GEMM_LAUNCH2(MODE, TA, TB)                                                                           \
+    if (g.beta != 0.0) { RIS_GEMM_LAUNCH1(MODE, TA, TB, true) } else { RIS_GEMM_LAUNCH1(MODE, TA, TB, false) }
+#define RIS_GEMM_LAUNCH(MODE)                                                                                    \
+    if (!g.transA && !g.transB) { RIS_GEMM_LAUNCH2(MODE, false, false) }                                         \
+    else if (g.transA && !g.transB) { RIS_GEMM_LAUNCH2(MODE, true, false) }                                      \
+    else if (!g.transA && g.transB) { RIS_GEMM_LAUNCH2(MODE, false, true) }                                      \
+    else { RIS_GEMM_LAUNCH2(MODE, true, true) }
+    if (mode == 0) { RIS_GEMM_LAUNCH(0) }
+    else { RIS_GEMM_LAUNCH(1) }
 #undef RIS_GEMM_LAUNCH
 #undef RIS_GEMM_LAUNCH1
+#undef RIS_GEMM_LAUNCH2
     return hipGetLastError();
 }
+
+hipError_t dgemm_kc(const GemmArgs &g, int kc, hipStream_t st) { return gemm_kc(g, 0, kc, st); }
 
 hipError_t dgemm(const GemmArgs &g, hipStream_t st) { return dgemm_kc(g, 0, st); }
 

@@ -1,7 +1,8 @@
 // Reduced-precision GEMMs for the exchange-weight contractions (FP64 in HBM,
 // reduced precision on the matrix cores, FP32 accumulation, FP64 out).
 //
-//   mode 1 (FP32): operands rounded to FP32, v_mfma_f32_16x16x4f32.
+//   mode 1 (FP32): operands rounded to FP32, v_mfma_f32_16x16x4f32 (the
+//          matrix-core GEMM of ris_gemm.hip in its FP32 flavour).
 //   mode 2 (split BF16, three products): x32 = fl32(x), hi = bf16(x32),
 //          lo = bf16(x32 - hi); a.b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b with
 //          v_mfma_f32_16x16x32_bf16 (the lo_a lo_b term, ~2^-16 relative, is
@@ -41,106 +42,6 @@ __device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, int &z
     const int gm = min(GROUP_M, tm - m0);
     mt = m0 + tg % gm;
     nt = tg / gm;
-}
-
-// ---------------------------------------------------------------- FP32 --
-constexpr int BK1 = 16;
-constexpr int PAD1 = 4;
-
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, double alpha, const double *__restrict__ A,
-                                               long lda, long sA, long sAr, const double *__restrict__ B, long ldb,
-                                               long sB, long sBr, double beta, double *__restrict__ C, long ldc,
-                                               long sC, int nred, int tm, int tn, int total)
-{
-    __shared__ float As[2][BK1][BM + PAD1];
-    __shared__ float Bs[2][BK1][BN + PAD1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    int bz, mt, nt;
-    tile_of(blockIdx.x, total, tm, tn, bz, mt, nt);
-    const int m0 = mt * BM, n0 = nt * BN;
-    A += (long)bz * sA;
-    B += (long)bz * sB;
-    C += (long)bz * sC;
-    v4f acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    float ra[8], rb[8];
-    const int ktiles = (K + BK1 - 1) / BK1;
-    const int niter = ktiles * nred;
-    auto load = [&](int it) {
-        const int r = it / ktiles, k0 = (it % ktiles) * BK1;
-        const double *Ar = A + (long)r * sAr;
-        const double *Br = B + (long)r * sBr;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (!TA) {
-                const int k = tid & 15, m = (tid >> 4) + 16 * q, gm = m0 + m, gk = k0 + k;
-                ra[q] = (gm < M && gk < K) ? (float)Ar[(long)gm * lda + gk] : 0.f;
-            } else {
-                const int m = tid & 127, k = (tid >> 7) + 2 * q, gm = m0 + m, gk = k0 + k;
-                ra[q] = (gm < M && gk < K) ? (float)Ar[(long)gk * lda + gm] : 0.f;
-            }
-            if (!TB) {
-                const int n = tid & 127, k = (tid >> 7) + 2 * q, gn = n0 + n, gk = k0 + k;
-                rb[q] = (gn < N && gk < K) ? (float)Br[(long)gk * ldb + gn] : 0.f;
-            } else {
-                const int k = tid & 15, n = (tid >> 4) + 16 * q, gn = n0 + n, gk = k0 + k;
-                rb[q] = (gn < N && gk < K) ? (float)Br[(long)gn * ldb + gk] : 0.f;
-            }
-        }
-    };
-    auto store = [&](int stg) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (!TA) As[stg][tid & 15][(tid >> 4) + 16 * q] = ra[q];
-            else As[stg][(tid >> 7) + 2 * q][tid & 127] = ra[q];
-            if (!TB) Bs[stg][(tid >> 7) + 2 * q][tid & 127] = rb[q];
-            else Bs[stg][tid & 15][(tid >> 4) + 16 * q] = rb[q];
-        }
-    };
-    if (niter > 0) {
-        load(0);
-        store(0);
-    }
-    __syncthreads();
-    for (int it = 0; it < niter; ++it) {
-        const int cur = it & 1;
-        if (it + 1 < niter) load(it + 1);
-#pragma unroll
-        for (int kk = 0; kk < BK1; kk += 4) {
-            float fa[4], fb[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) fa[i] = As[cur][kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) fb[j] = Bs[cur][kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
-        }
-        if (it + 1 < niter) store(cur ^ 1);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = n0 + wn * 64 + j * 16 + (lane & 15);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
-                if (row < M && col < N) {
-                    double *cp = C + (long)row * ldc + col;
-                    const double v = alpha * (double)acc[i][j][e];
-                    *cp = (beta == 0.0) ? v : v + beta * *cp;
-                }
-            }
-        }
 }
 
 // ----------------------------------------------------------- split BF16 --
@@ -284,9 +185,9 @@ __global__ __launch_bounds__(256) void k_bgemm3(int M, int N, int K, double alph
 
 hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st)
 {
-    if (mode == 0) return dgemm(g, st);
+    if (mode == 0 || mode == 1) return gemm_kc(g, mode, 0, st);
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    if (g.lower) return hipErrorInvalidValue;  // lower-tile mode is FP64-only
+    if (g.lower) return hipErrorInvalidValue;  // lower-tile mode: FP64 / FP32 kernel only
     const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
     const long total = (long)tm * tn * g.batch;
     if (total > 0x7fffffffL) return hipErrorInvalidValue;
@@ -296,17 +197,10 @@ hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st)
     hipLaunchKernelGGL((KERN<TA, TB>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.strideA,      \
                        g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, \
                        (int)total)
-    if (mode == 1) {
-        if (!g.transA && !g.transB) RIS_MP_LAUNCH(k_sgemm, false, false);
-        else if (g.transA && !g.transB) RIS_MP_LAUNCH(k_sgemm, true, false);
-        else if (!g.transA && g.transB) RIS_MP_LAUNCH(k_sgemm, false, true);
-        else RIS_MP_LAUNCH(k_sgemm, true, true);
-    } else {
-        if (!g.transA && !g.transB) RIS_MP_LAUNCH(k_bgemm3, false, false);
-        else if (g.transA && !g.transB) RIS_MP_LAUNCH(k_bgemm3, true, false);
-        else if (!g.transA && g.transB) RIS_MP_LAUNCH(k_bgemm3, false, true);
-        else RIS_MP_LAUNCH(k_bgemm3, true, true);
-    }
+    if (!g.transA && !g.transB) RIS_MP_LAUNCH(k_bgemm3, false, false);
+    else if (g.transA && !g.transB) RIS_MP_LAUNCH(k_bgemm3, true, false);
+    else if (!g.transA && g.transB) RIS_MP_LAUNCH(k_bgemm3, false, true);
+    else RIS_MP_LAUNCH(k_bgemm3, true, true);
 #undef RIS_MP_LAUNCH
     return hipGetLastError();
 }
