@@ -362,6 +362,12 @@ struct MatvecWs {
     size_t ot, oT, oU, oSK, total;
 };
 constexpr int kMatvecChunk = 10;  // vectors whose exchange terms share one GEMM
+// K-split of the exchange products U (v x chunk*o output, K = nK v or o nK)
+int matvec_u_splits(const Dims &d, int chunk)
+{
+    return balanced_splits((long)((d.v + 127) / 128) * ((chunk * d.o + 127) / 128), 8);
+}
+
 MatvecWs matvec_ws(const Dims &d, int nvec)
 {
     Carve cv;
@@ -371,12 +377,21 @@ MatvecWs matvec_ws(const Dims &d, int nvec)
     L.ot = cv.take((size_t)nvec * d.nJ * 2);
     L.oT = cv.take((size_t)chunk * d.nK * std::max(vo, oo));  // T (exchange A) or S (exchange B)
     L.oU = cv.take((size_t)chunk * vo);                        // [a][k][i] product before the permuted add
-    L.oSK = cv.take((size_t)64 * nvec * d.nJ);                 // split-K partials of t = V (ai|P)^T
+    // split-K partials of t = V (ai|P)^T and of the exchange products U
+    L.oSK = cv.take(std::max((size_t)64 * nvec * d.nJ,
+                             (size_t)matvec_u_splits(d, chunk) * d.v * chunk * d.o));
     L.total = cv.off;
     return L;
 }
 
-constexpr int kSplitV = 64;  // K-split of the V_PQ products
+constexpr int kSplitV = 64;  // K-split of the long-K Coulomb products
+// K-split of the V_PQ product (nK x nK output, K = 9 o^2): about 1024
+// workgroups over its 128 x 128 tiles
+int vpq_splits(int nK)
+{
+    const int t = (nK + 127) / 128;
+    return std::max(1, std::min(256, 1024 / (t * t)));
+}
 struct ContractWs {
     size_t oR, oL, oRLT, oF, oD, otT, ocv, oTall, oHUO, oHOU, oHUU, oW, oHc, oY, oG, oV2, oSK, op3, op2, oshA, oshC,
         oshP, total;
@@ -404,7 +419,7 @@ ContractWs contract_ws(const Dims &d, int ns)
     L.oY = cv.take((size_t)d.nK * d.N * o3);
     L.oG = cv.take((size_t)NO * d.nK * NN);
     L.oV2 = cv.take((size_t)NO * d.nJ * d.nJ);
-    L.oSK = cv.take((size_t)kSplitV * std::max((size_t)d.nK * d.nK, (size_t)ns * d.nJ));
+    L.oSK = cv.take(std::max((size_t)kSplitV * ns * d.nJ, (size_t)vpq_splits(d.nK) * d.nK * d.nK));
     L.op3 = cv.take((size_t)d.nshAO * d.nshJ * 3 * NO * 6);
     L.op2 = cv.take((size_t)d.nshJ * 2 * NO * 3);
     L.oshA = cv.take((size_t)d.nshAO * NO * 3);
@@ -841,8 +856,11 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
     HIPCHK(c, dgemm(gm(nvec, (int)vo, nJ, false, false, cJ[op] * c->alphaJ, cc, nJ, c->aiJ, vo, 0.0, out, vo),
                     c->stream));
     if (cDe[op] != 0.0) HIPCHK(c, add_de(c->eps, V, out, v, o, nvec, cDe[op], c->stream));
+    // K-split of U within the partials region (sized in matvec_ws for full chunks)
+    const size_t skcap = std::max((size_t)64 * nvec * nJ, (size_t)matvec_u_splits(ctx_dims(c), chunk) * v * chunk * o);
     for (int k0 = 0; k0 < nvec; k0 += chunk) {
         const int nv = std::min(chunk, nvec - k0);
+        const int usplit = (int)std::min((size_t)matvec_u_splits(ctx_dims(c), nv), skcap / ((size_t)v * nv * o));
         const double *Vk = V + (size_t)k0 * vo;
         double *ok = out + (size_t)k0 * vo;
         const long nvo = (long)nv * o;  // columns (k, i) of the chunk
@@ -854,8 +872,8 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
             // U[a][(k,i)] = sum_{(P,b)} (ab|P) T[(P,b)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
-            HIPCHK(c, gemm_mp(gm(v, (int)nvo, nK * v, false, false, 1.0, c->rvv, (long)nK * v, T, nvo, 0.0, U, nvo),
-                              c->prec, c->stream));
+            HIPCHK(c, gemm_splitk(gm(v, (int)nvo, nK * v, false, false, 1.0, c->rvv, (long)nK * v, T, nvo, 0.0, U, nvo),
+                                  c->prec, usplit, SKm, c->stream));
             HIPCHK(c, permute3(U, ok, nv, v, o, o, nvo, 1, vo, o, 1, c->stream, -cKA[op] * c->cx, 1.0));
         }
         if (cKB[op] != 0.0) {
@@ -867,8 +885,8 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
             // U[a][(k,i)] = sum_{(j,P)} (aj|P) S[(j,P)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
-            HIPCHK(c, gemm_mp(gm(v, (int)nvo, o * nK, false, false, 1.0, c->rvo2, (long)o * nK, T, nvo, 0.0, U, nvo),
-                              c->prec, c->stream));
+            HIPCHK(c, gemm_splitk(gm(v, (int)nvo, o * nK, false, false, 1.0, c->rvo2, (long)o * nK, T, nvo, 0.0, U, nvo),
+                                  c->prec, usplit, SKm, c->stream));
             HIPCHK(c, permute3(U, ok, nv, v, o, o, nvo, 1, vo, o, 1, c->stream, -cKB[op] * c->cx, 1.0));
         }
     }
@@ -897,7 +915,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
     const int ns = nstate;
     const long w2 = 2L * ns * o;  // columns of RLT / Tall: (t, s, i)
     const int NO = kMaxOutChunk;
-    const int nsplit = kSplitV;
+    const int nsplit = vpq_splits(nK);
     const ContractWs CW = contract_ws(ctx_dims(c), ns);
     int st;
     char *wsb = ws_get(c, CW.total, &st);
@@ -1020,24 +1038,33 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nK * N * o3 * o3, 0.0);
             double *Gk = G + (size_t)k * nK * NN;
             const double *FJ = F + (size_t)J * N * o3;
-            if (c->prec != RIS_BF16X3 && I == J) {
-                // gradients: Gamma^P = -2 c_x Y F_I^T is symmetric -> lower tiles + mirror (half the work)
+            // only the lower triangle of the symmetric Gamma^P is formed (and read):
+            // gradients: -2 c_x Y F_I^T is symmetric; NACs: the symmetric part
+            // -c_x (Y F_J^T + F_J Y^T) as two lower-tile products
+            const bool lowt = c->prec != RIS_BF16X3;
+            hipEvent_t t_g = stage_begin(c);
+            if (I == J || !lowt) {
                 g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
-                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
-                hipEvent_t t_g = stage_begin(c);
+                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = lowt;
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-                stage_end(c, t_g, RIS_STAGE_GAMMA, (double)nK * N * (N + 1) * o3,
-                          8.0 * ((double)nK * N * (N + 1) / 2 + (double)nK * N * o3 + (double)N * o3));
-                HIPCHK(c, mirror_lower_tiles(Gk, N, NN, nK, c->stream));
             } else {
-                g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
-                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
-                hipEvent_t t_g = stage_begin(c);
+                g = gm(N, N, (int)o3, false, true, -c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
+                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-                stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nK * N * N * o3,
-                          8.0 * ((double)nK * N * N + (double)nK * N * o3 + (double)N * o3));
-                if (I != J) HIPCHK(c, symmetrize(Gk, N, nK, c->stream));
+                g = gm(N, N, (int)o3, false, true, -c->cx, FJ, o3, Y3, o3, 1.0, Gk, N);
+                g.batch = nK; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
+            {
+                const double nprod = (I == J) ? 1.0 : 2.0;  // lower-tile products
+                if (lowt)
+                    stage_end(c, t_g, RIS_STAGE_GAMMA, nprod * (double)nK * N * (N + 1) * o3,
+                              8.0 * ((double)nK * N * (N + 1) / 2 * (2 * nprod - 1) + nprod * ((double)nK * N * o3 + N * o3)));
+                else
+                    stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nK * N * N * o3,
+                              8.0 * ((double)nK * N * N + (double)nK * N * o3 + (double)N * o3));
+            }
+            if (I != J && !lowt) HIPCHK(c, symmetrize(Gk, N, nK, c->stream));
         }
         // three-centre derivative contraction + metric derivative, reduced into atoms
         HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * NO * 6, 0.0, c->stream));

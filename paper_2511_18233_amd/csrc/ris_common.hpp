@@ -60,7 +60,7 @@ hipError_t launch_int3c(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxA
 // Fused three-centre derivative contraction (see ris_ints.hip).
 struct DerivJob {
     int nout;                  // outputs in this launch (<= kMaxOutChunk)
-    const double *gammaK;      // [nout][nK][nao][nao] symmetric K weights, may be null
+    const double *gammaK;      // [nout][nK][nao][nao] symmetric K weights (lower triangle read), may be null
     int nK;                    // K functions (first nK J functions)
     const double *dens;        // [nstate][nao][nao] symmetric AO densities R^S
     const double *cvec;        // [nstate][nJ] c_I = M_J^-1 t_I
@@ -101,9 +101,11 @@ hipError_t dgemm(const GemmArgs &g, hipStream_t st);
 // Same product with K cut into nsplit ranges (batch == 1, nred == 1): partials
 // go to ws (nsplit * M * N doubles) and are summed in a fixed order.
 hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st);
-// Copy the strictly-upper 128 x 128 tiles of nb square n x n matrices from the
-// transposes of their lower tiles (completes a `lower` GEMM of a symmetric result).
-hipError_t mirror_lower_tiles(double *C, int n, long stride, int nb, hipStream_t st);
+// Same for mode 0 / 1 (FP64 / FP32 matrix cores); mode 2 runs unsplit.
+hipError_t gemm_splitk(const GemmArgs &g, int mode, int nsplit, double *ws, hipStream_t st);
+// K-split count in [1, smax] that fills whole waves of workgroups best for a
+// product of `tiles` 128 x 128 output tiles (1 for large tile counts).
+int balanced_splits(long tiles, int smax);
 // Same contract with the products on reduced-precision matrix cores (FP64 in
 // and out, FP32 accumulation): mode 0 = FP64 (dgemm), 1 = FP32, 2 = split BF16
 // with three products (ris_gemm_mp.hip).

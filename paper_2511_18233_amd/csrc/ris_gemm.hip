@@ -12,6 +12,7 @@
 // accumulator values of lane l are D[4 i + l / 16][l % 16], i = 0..3 (rows
 // interleaved across the four lane groups; checked by the layout probe test).
 #include <algorithm>
+#include <cmath>
 
 #include "ris_common.hpp"
 
@@ -389,41 +390,11 @@ __global__ void k_splitk_reduce(const double *__restrict__ ws, int nsplit, int M
 }  // namespace
 
 namespace ris {
-namespace {
-// one 32 x 32 block of an upper tile per workgroup: dst[i][j] = src[j][i] via LDS
-__global__ __launch_bounds__(256) void k_mirror(double *C, int n, long stride, int nblk32)
-{
-    __shared__ double T[32][33];
-    const int z = blockIdx.y;
-    // enumerate 32-blocks (bi, bj) with bi / 4 < bj / 4 (strictly upper 128-tiles)
-    const int b = blockIdx.x;
-    const int bi = b / nblk32, bj = b % nblk32;
-    if (bi / 4 >= bj / 4) return;
-    double *M = C + (long)z * stride;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    for (int r = ty; r < 32; r += 8) {
-        const int i = bj * 32 + r, j = bi * 32 + tx;  // read the lower block (bj, bi)
-        if (i < n && j < n) T[r][tx] = M[(long)i * n + j];
-    }
-    __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int i = bi * 32 + r, j = bj * 32 + tx;
-        if (i < n && j < n) M[(long)i * n + j] = T[tx][r];
-    }
-}
-}  // namespace
 
-hipError_t mirror_lower_tiles(double *C, int n, long stride, int nb, hipStream_t st)
+hipError_t gemm_splitk(const GemmArgs &g, int mode, int nsplit, double *ws, hipStream_t st)
 {
-    const int nblk32 = (n + 31) / 32;
-    hipLaunchKernelGGL(k_mirror, dim3(nblk32 * nblk32, nb), dim3(256), 0, st, C, n, stride, nblk32);
-    return hipGetLastError();
-}
-
-hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st)
-{
-    if (nsplit <= 1 || g.batch != 1 || g.nred > 1) return dgemm(g, st);
-    const int kc = ((g.K + nsplit - 1) / nsplit + BK - 1) / BK * BK;  // multiple of the k-tile
+    if (nsplit <= 1 || g.batch != 1 || g.nred > 1 || mode == 2) return gemm_mp(g, mode, st);
+    const int kc = ((g.K + nsplit - 1) / nsplit + 31) / 32 * 32;  // multiple of both k-slab depths
     const int used = (g.K + kc - 1) / kc;
     // one launch: batch index = k-range, partial products into ws[z][M][N]
     GemmArgs p = g;
@@ -434,11 +405,35 @@ hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t s
     p.C = ws;
     p.ldc = g.N;
     p.strideC = (long)g.M * g.N;
-    hipError_t e = dgemm_kc(p, kc, st);
+    hipError_t e = gemm_kc(p, mode, kc, st);
     if (e != hipSuccess) return e;
     const long tot = (long)g.M * g.N;
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws, used, g.M, g.N,
                        g.beta, g.C, g.ldc);
     return hipGetLastError();
+}
+
+hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st)
+{
+    return gemm_splitk(g, 0, nsplit, ws, st);
+}
+
+int balanced_splits(long tiles, int smax)
+{
+    // workgroup slots: 256 CUs x 2 resident workgroups
+    constexpr double kSlots = 512.0;
+    if (tiles >= 4 * (long)kSlots) return 1;
+    int best = 1;
+    double beff = 0.0;
+    for (int sp = 1; sp <= smax; ++sp) {
+        const double w = (double)tiles * sp / kSlots;
+        const double eff = w / std::ceil(w);
+        if (eff > beff + 1e-9) {
+            beff = eff;
+            best = sp;
+        }
+        if (eff >= 0.95) break;
+    }
+    return best;
 }
 }  // namespace ris

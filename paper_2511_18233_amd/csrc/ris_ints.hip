@@ -335,6 +335,8 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
                 });
                 constexpr int NX = ix + jx + 1, NY = iy + jy + 1, NZ = iz + jz + 1;
                 const size_t mn = (size_t)(mu0 + ka) * nao + nu0 + kb;
+                // the symmetric K weights are read from their lower triangle (row >= column)
+                const size_t mnl = (mu0 + ka >= nu0 + kb) ? mn : (size_t)(nu0 + kb) * nao + mu0 + ka;
                 // Coulomb densities of this (mu, nu): loaded once for all auxiliary components
                 double dI[NO], dJ[NO];
 #pragma unroll
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
                         if (o < job.nout) {
                             double w = dI[o] * cJ[o][kc] + dJ[o] * cI[o][kc];
                             if (inK && job.gammaK)
-                                w += job.gammaK[((size_t)o * job.nK + P0 + kc) * nao2 + mn];
+                                w += job.gammaK[((size_t)o * job.nK + P0 + kc) * nao2 + mnl];
                             const double w2 = 2.0 * w;
                             acc[o][0] += w2 * dA[0];
                             acc[o][1] += w2 * dA[1];

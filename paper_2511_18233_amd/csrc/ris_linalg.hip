@@ -181,22 +181,21 @@ __global__ void k_axpby(const double *__restrict__ src, double *__restrict__ dst
 // Assemble nP matrices of (3o x 3o) from a 3 x 3 grid of o x o blocks; block
 // (bi, bj) is the sum of up to two strided sources
 //   src[P][i][j] = base[P * sP + i * si + j * sj] * scale   (base null = 0).
+// grid: (column chunks of 256, 3o rows, nP); 32-bit index arithmetic only
 __global__ void k_assemble3(BlockGrid g, double *__restrict__ W, int o, int nP)
 {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int n3 = 3 * o;
-    if (idx >= (long)n3 * n3 * nP) return;
-    const long P = idx / ((long)n3 * n3);
-    const long r = idx % ((long)n3 * n3);
-    const int row = (int)(r / n3), col = (int)(r % n3);
-    const int bi = row / o, bj = col / o, i = row % o, j = col % o;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= n3) return;
+    const int row = blockIdx.y, P = blockIdx.z;
+    const int bi = row / o, bj = col / o, i = row - bi * o, j = col - bj * o;
     double v = 0.0;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const BlockSrc &b = g.b[bi][bj][t];
         if (b.base) v += b.scale * b.base[P * b.sP + (long)i * b.si + (long)j * b.sj];
     }
-    W[idx] = v;
+    W[((long)P * n3 + row) * n3 + col] = v;
 }
 
 // out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] (+ beta * out) over n0 x n1 x n2
@@ -345,8 +344,8 @@ hipError_t axpby(const double *src, double *dst, size_t n, double alpha, double 
 
 hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st)
 {
-    const size_t n = (size_t)9 * o * o * nP;
-    hipLaunchKernelGGL(k_assemble3, dim3(nblk(n, 256)), dim3(256), 0, st, g, W, o, nP);
+    if (o <= 0 || nP <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_assemble3, dim3(nblk((size_t)3 * o, 256), 3 * o, nP), dim3(256), 0, st, g, W, o, nP);
     return hipGetLastError();
 }
 
