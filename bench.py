@@ -30,11 +30,12 @@ if ROOT not in sys.path:
 METRIC = "excited-state grads+NACs/s at 200 atoms; p50/p99 latency; vs plain FP64"
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of the Gamma back-transform GEMM from the FETCH_SIZE /
-# WRITE_SIZE counter runs on the 199-atom workload (fetch scaled by 2.0, write by
-# 1.0 after a 1 GiB copy calibration), valid only for the GEMM source they were
-# measured on (sha256 prefix below); null otherwise.
-GAMMA_TRAFFIC = {"gemm_src_sha256": "aefeea86a121bf42", "workload": "chain200", "bytes_per_launch": 63.26e9}
+# HBM bytes per launch of the lower-tile Gamma back-transform GEMM from the
+# FETCH_SIZE / WRITE_SIZE counter runs on the 199-atom workload (fetch scaled by
+# 2.0, write by 1.0 after a 1 GiB copy calibration), averaged over the 28
+# launches of a step (19 plain: 29.66 + 3.81 GB, 9 accumulating: 26.93 + 4.36 GB);
+# valid only for the GEMM source it was measured on (sha256 prefix); null otherwise.
+GAMMA_TRAFFIC = {"gemm_src_sha256": "46a16cf5265bf066", "workload": "chain200", "bytes_per_launch": 32.77e9}
 
 
 def log(*a):
@@ -122,8 +123,9 @@ def compare_precisions(ctx, prob, jp, grads, pairs, radii, C, eps, X, Y):
 def serve_bench(nreq, nslots, radii):
     """Serving trace (chain molecules 20-120 atoms, 2 gradients + 1 NAC each):
     sequential FP64 rate first, then a Poisson trace at 1.5x that rate through
-    (a) one FP64 slot and (b) nslots slots with the exchange contractions in
-    FP32; throughput and p50/p99 latency of each."""
+    (a) one FP64 slot, (b) nslots FP64 slots (equal accuracy) and (c) nslots
+    slots with the exchange contractions in FP32; throughput and p50/p99
+    latency of each, and the max deviation from the sequential FP64 results."""
     from paper_2511_18233_amd.serve import GpuExecutor, Server, latency_stats, make_trace
     log(f"[bench] serving: building a {nreq}-request trace")
     reqs = make_trace(nreq, max(1, nreq // 16), rate_hz=1.0, seed=1000,
@@ -146,6 +148,8 @@ def serve_bench(nreq, nslots, radii):
     out = {"requests": nreq, "outputs_per_request": 3, "sequential_fp64_back_to_back_req_s": rate,
            "arrival_rate_req_s": lam}
     for name, execs in (("fifo_fp64_1slot", lambda: [GpuExecutor(0, 0, radii, "fp64")]),
+                        (f"batched_fp64_{nslots}slots",
+                         lambda: [GpuExecutor(k, 0, radii, "fp64") for k in range(nslots)]),
                         (f"batched_fp32_{nslots}slots",
                          lambda: [GpuExecutor(k, 0, radii, "fp32") for k in range(nslots)])):
         srv = Server(execs(), 200 << 30)
@@ -253,7 +257,7 @@ def main():
         same = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == GAMMA_TRAFFIC["gemm_src_sha256"]
         traffic = GAMMA_TRAFFIC["bytes_per_launch"] if (same and args.workload == GAMMA_TRAFFIC["workload"]
                                                         and args.precision == "fp64") else None
-        roof = {"bound": "mfma", "kernel": "k_dgemm<false,true> (Gamma^P = (F_I W^P) F_J^T, batched over P)",
+        roof = {"bound": "mfma", "kernel": "k_gemm<0,false,true,*> lower tiles (Gamma^P = (F_I W^P) F_J^T, batched over P)",
                 "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                 "flops_per_launch": gfl / gn, "avg_launch_ms": gms / gn,

@@ -131,7 +131,8 @@ enum ris_stage {
     RIS_STAGE_MO = 1,      /* MO-transform and metric GEMMs of ris_int3c */
     RIS_STAGE_MATVEC = 2,  /* one whole ris_response_matvec call */
     RIS_STAGE_HBLK = 3,    /* MO-space exchange blocks of one gradient/NAC output */
-    RIS_STAGE_GAMMA = 4,   /* AO back-transform GEMM Gamma^P = (F_I W^P) F_J^T of one output */
+    RIS_STAGE_GAMMA = 4,   /* one AO back-transform GEMM launch of Gamma^P = (F_I W^P) F_J^T (lower tiles;
+                              a NAC output takes two) */
     RIS_STAGE_DERIV = 5,   /* fused three-centre derivative contraction, one output chunk */
     RIS_STAGE_AUX = 6,     /* one whole ris_aux_build (metric, Cholesky, inverses) */
     RIS_STAGE_YW = 7,      /* Y^P = F_I W^P of one output (W assembly included) */

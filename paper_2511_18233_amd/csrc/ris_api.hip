@@ -1042,27 +1042,31 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             // gradients: -2 c_x Y F_I^T is symmetric; NACs: the symmetric part
             // -c_x (Y F_J^T + F_J Y^T) as two lower-tile products
             const bool lowt = c->prec != RIS_BF16X3;
-            hipEvent_t t_g = stage_begin(c);
+            // one timed group per GEMM launch; a lower-tile launch does
+            // nK N (N + 1) 3o flops and moves Y, F_J and the lower half of Gamma
+            const double fl_low = (double)nK * N * (N + 1) * o3;
+            const double by_low = 8.0 * ((double)nK * N * o3 + (double)N * o3 + (double)nK * N * (N + 1) / 2);
             if (I == J || !lowt) {
                 g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
                 g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = lowt;
+                hipEvent_t t_g = stage_begin(c);
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-            } else {
-                g = gm(N, N, (int)o3, false, true, -c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
-                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
-                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-                g = gm(N, N, (int)o3, false, true, -c->cx, FJ, o3, Y3, o3, 1.0, Gk, N);
-                g.batch = nK; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
-                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-            }
-            {
-                const double nprod = (I == J) ? 1.0 : 2.0;  // lower-tile products
-                if (lowt)
-                    stage_end(c, t_g, RIS_STAGE_GAMMA, nprod * (double)nK * N * (N + 1) * o3,
-                              8.0 * ((double)nK * N * (N + 1) / 2 * (2 * nprod - 1) + nprod * ((double)nK * N * o3 + N * o3)));
+                if (lowt) stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
                 else
                     stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nK * N * N * o3,
                               8.0 * ((double)nK * N * N + (double)nK * N * o3 + (double)N * o3));
+            } else {
+                g = gm(N, N, (int)o3, false, true, -c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
+                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
+                hipEvent_t t_g = stage_begin(c);
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
+                g = gm(N, N, (int)o3, false, true, -c->cx, FJ, o3, Y3, o3, 1.0, Gk, N);
+                g.batch = nK; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
+                t_g = stage_begin(c);
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                // the accumulating launch also reads the lower half of Gamma
+                stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low + 8.0 * (double)nK * N * (N + 1) / 2);
             }
             if (I != J && !lowt) HIPCHK(c, symmetrize(Gk, N, nK, c->stream));
         }
