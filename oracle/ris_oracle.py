@@ -29,6 +29,12 @@ What it computes, and where the paper defines it:
   (Sec. 2.2, last equation): (pq|A)^x M^-1 (B|sr) + (pq|A) M^-1 (B|sr)^x
   - (pq|A) M^-1 M^x M^-1 (B|sr).
 
+* ris-approximated Z-vector solve: (A+B)^ris Z = rhs with the ris kernel
+  in the (A+B) matrix of the Z-vector equation (Sec. 4.2; the equation is
+  eq. Z_vector of Sec. 2.1, restated in Appendix A.2), solved here by its
+  definition: the dense (A+B)^ris assembled column by column from the matvec
+  and a direct solve.
+
 Readings where the paper is silent or ambiguous (each one a parameter here):
 a_J (closed-shell Coulomb factor, default 2), c_x (default 0.25, PBE0),
 the exchange index order for antisymmetric L^A (chosen so that E_II equals
@@ -248,6 +254,25 @@ def response_matvec(S: Setup, C, eps, nocc, V: np.ndarray, op: str,
         Bv = jterm - c_x * kB
         out[k] = {"A": Av, "B": Bv, "A+B": Av + Bv, "A-B": Av - Bv}[op]
     return out
+
+
+def dense_apb(S: Setup, C, eps, nocc, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX) -> np.ndarray:
+    """(A+B)^ris as a dense (vo x vo) matrix, columns = matvecs of unit vectors."""
+    o = nocc
+    v = C.shape[1] - o
+    E = np.eye(v * o).reshape(v * o, v, o)
+    cols = response_matvec(S, C, eps, nocc, E, "A+B", alpha_J, c_x)
+    return cols.reshape(v * o, v * o).T
+
+
+def zvector_solve(S: Setup, C, eps, nocc, rhs: np.ndarray, alpha_J=DEFAULT_ALPHA_J,
+                  c_x=DEFAULT_CX) -> np.ndarray:
+    """Z[k] = ((A+B)^ris)^-1 rhs[k] for rhs[nrhs][nvir][nocc] (Sec. 4.2 with
+    eq. Z_vector of Sec. 2.1), by a direct dense solve."""
+    M = dense_apb(S, C, eps, nocc, alpha_J, c_x)
+    rhs = np.asarray(rhs, dtype=np.float64)
+    Z = np.linalg.solve(M, rhs.reshape(rhs.shape[0], -1).T).T
+    return Z.reshape(rhs.shape)
 
 
 def ao_densities(C, nocc, X, Y):

@@ -268,6 +268,29 @@ def test_matvec_vs_dense_ris_matrices(ring):
     assert np.abs(Ax - w[0] * x).max() < 1e-11
 
 
+def test_zvector_dense_solve(ring):
+    """The ris Z-vector operator (A+B)^ris assembled from matvecs equals the
+    brute-force four-index A+B and is symmetric; with model orbitals (random
+    rotation, uniform orbital energies) it is indefinite but nonsingular, which
+    is why the GPU path uses MINRES rather than conjugate gradients; the solve
+    inverts it."""
+    p, rad, S = ring
+    A, B = _dense_AB(S, p.C, p.eps, p.nocc, 2.0, 0.25)
+    M = O.dense_apb(S, p.C, p.eps, p.nocc)
+    assert np.abs(M - (A + B)).max() < 1e-11 * np.abs(A + B).max()
+    assert np.abs(M - M.T).max() < 1e-10 * np.abs(M).max()
+    w = np.abs(np.linalg.eigvalsh(0.5 * (M + M.T)))
+    assert w.min() > 1e-8 * w.max()
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2,) + p.X.shape[1:])
+    rhs = np.array([((A + B) @ xi.ravel()).reshape(xi.shape) for xi in x])
+    Z = O.zvector_solve(S, p.C, p.eps, p.nocc, rhs)
+    cond = w.max() / w.min()
+    assert np.abs(Z - x).max() < 1e-13 * cond * np.abs(x).max()
+    # a zero right-hand side gives Z = 0
+    assert np.abs(O.zvector_solve(S, p.C, p.eps, p.nocc, np.zeros_like(rhs[:1]))).max() == 0.0
+
+
 def test_energy_consistency(ring):
     """E_II from AO traces equals 1/2 R.(A+B-D)R + 1/2 L.(A-B-D)L (TDDFT Y != 0)."""
     p0, rad, S = ring
