@@ -93,6 +93,32 @@ def oracle_sample(prob, jp, outs, radii):
     }
 
 
+def zvector_bench(ctx, prob, jp, radii, C, eps, nrhs, tol, maxit=20):
+    """ris Z-vector solve (A+B)^ris Z = rhs for nrhs seeded right-hand sides on
+    the workload (FP64), capped at maxit iterations: wall time, matvecs per
+    second and the true relative residual reached.  With model orbitals the
+    operator is indefinite and nearly singular at this size, so the cap, not
+    the tolerance, ends the run; the rate is what is measured."""
+    import time as _t
+    import torch
+    m = prob.mol
+    ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+    ctx.int3c(C, eps, prob.nocc, 2.0, 0.25)
+    rng = np.random.default_rng(2024)
+    rhs = torch.as_tensor(rng.standard_normal((nrhs,) + prob.X.shape[1:]), device=C.device)
+    ctx.zvector_solve(rhs, tol=1e-2, maxit=2, allow_noconv=True)  # warm the regions
+    torch.cuda.synchronize()
+    t = _t.perf_counter()
+    Z, it, res = ctx.zvector_solve(rhs, tol=tol, maxit=maxit, allow_noconv=True)
+    torch.cuda.synchronize()
+    dt = _t.perf_counter() - t
+    out = {"nrhs": nrhs, "tol": tol, "iterations": it, "seconds": round(dt, 4),
+           "matvecs_per_s": round(nrhs * (it + 1) / dt, 2), "true_rel_residual": res}
+    log(f"[bench] zvector: {nrhs} rhs, {it} iterations, {dt:.2f} s, {out['matvecs_per_s']} matvecs/s, "
+        f"residual {res:.2e}")
+    return out
+
+
 def compare_precisions(ctx, prob, jp, grads, pairs, radii, C, eps, X, Y):
     """Run the step once per precision mode; max |d grad| and |d NAC| against
     the FP64 GPU result (itself pinned to the oracle by the parity tests)."""
@@ -180,6 +206,8 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="also replay a serving trace of this many requests (20-120 atoms)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--zvector", type=int, default=0,
+                    help="also time the ris Z-vector solve for this many right-hand sides")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
@@ -281,6 +309,11 @@ def main():
         "roofline": roof,
         "stages": per_stage,
     }
+    mv = per_stage.get("matvec")
+    if mv and mv["ms_per_step"] > 0:
+        res["matvecs_per_s"] = round(2 * ns / (mv["ms_per_step"] * 1e-3), 2)
+    if args.zvector > 0:
+        res["zvector"] = zvector_bench(ctx, prob, jp, radii, C, eps, args.zvector, 1e-8)
     if args.compare_precisions:
         res["precision_errors"] = compare_precisions(ctx, prob, jp, grads, pairs, radii, C, eps, X, Y)
     ctx.close()

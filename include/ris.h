@@ -52,7 +52,8 @@ enum ris_status {
     RIS_E_NOT_PD = 4,       /* auxiliary metric not positive definite */
     RIS_E_DEGENERATE = 5,   /* |omega_J - omega_I| < 1e-12 (numerator still written) */
     RIS_E_ORDER = 6,        /* calls out of order (aux_build -> int3c -> others) */
-    RIS_E_DEVICE = 7        /* HIP runtime error */
+    RIS_E_DEVICE = 7,       /* HIP runtime error */
+    RIS_E_NOCONV = 8        /* iterative solve stopped at its iteration limit */
 };
 
 /* Arithmetic of the exchange-weight contractions (the products that build
@@ -139,6 +140,25 @@ enum ris_stage {
     RIS_STAGE_VPQ = 8,     /* metric weights V_PQ of one output */
     RIS_STAGE_COUNT = 9
 };
+
+/* ris-approximated Z-vector solve (Sec. 4.2: the ris kernel also in the
+ * (A+B) matrix of the Z-vector equation, eq. Z_vector of Sec. 2.1): solves
+ * (A+B)^ris Z_k = rhs_k for k < nrhs with the same (A+B) as
+ * ris_response_matvec(RIS_OP_APB) in the context's precision mode.  Method:
+ * MINRES (the operator is symmetric; it need not be positive definite for
+ * model orbitals) preconditioned by the orbital-energy differences
+ * max(|e_a - e_i|, 1e-4), all right-hand sides advanced together (one
+ * batched matvec per iteration), the scalar recurrences on the device.
+ * rhs: [nrhs][nvir][nocc] device, read only; Z: [nrhs][nvir][nocc] device,
+ * overwritten (the start vector is 0), must not alias rhs.  A right-hand side
+ * stops when its preconditioned residual estimate falls to tol times its
+ * initial value (0 < tol < 1).  iters (may be NULL) receives the iterations
+ * run; rel_resid (may be NULL) the largest true relative residual
+ * ||rhs_k - (A+B) Z_k|| / ||rhs_k|| after the solve (one extra matvec).
+ * Returns RIS_E_NOCONV if maxit iterations end before every right-hand side
+ * has stopped (Z holds the last iterate), RIS_E_ORDER before ris_int3c. */
+int ris_zvector_solve(ris_ctx *ctx, int nrhs, const double *rhs, double *Z, double tol, int maxit, int *iters,
+                      double *rel_resid);
 
 /* AO shell-pair screen of the three-centre derivative contraction (the
  * (mu nu|P)^xi term of the three-term RI derivative, last equation of

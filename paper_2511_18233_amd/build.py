@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libris_hip.so")
-SOURCES = ["ris_api.hip", "ris_ints.hip", "ris_gemm.hip", "ris_gemm_mp.hip", "ris_linalg.hip"]
+SOURCES = ["ris_api.hip", "ris_ints.hip", "ris_gemm.hip", "ris_gemm_mp.hip", "ris_linalg.hip", "ris_minres.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

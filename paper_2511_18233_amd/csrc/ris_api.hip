@@ -16,6 +16,7 @@
 #include "../../include/ris.h"
 #include "ris_common.hpp"
 #include "ris_linalg.hpp"
+#include "ris_minres.hpp"
 
 using namespace ris;
 
@@ -79,6 +80,7 @@ struct ris_ctx {
     Pool aux_pool;    // shell tables, permutation, metric and its inverses
     Pool mo_pool;     // orbitals and the MO blocks kept between calls
     Pool out_pool;    // staging of combined gradient + NAC outputs
+    Pool zv_pool;     // vectors of the Z-vector solve (the matvec uses the scratch below)
     void *ws = nullptr;  // scratch shared by the calls
     size_t ws_bytes = 0;
 
@@ -520,6 +522,103 @@ size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, 
     const size_t fixed = (size_t)8 * kBoysNGrid * kBoysCols + 64;
     return fixed + aux_layout(mol->nshell, nshJ, nao, nJ, natm).total + mo_layout(d).total + ws +
            (size_t)8 * std::max(nout, 0) * natm * 3;
+}
+
+int ris_zvector_solve(ris_ctx *c, int nrhs, const double *rhs, double *Z, double tol, int maxit, int *iters,
+                      double *rel_resid)
+{
+    if (!c) return RIS_E_INVALID;
+    c->err.clear();
+    if (iters) *iters = 0;
+    if (rel_resid) *rel_resid = 0.0;
+    if (!c->have_int3c) return fail(c, RIS_E_ORDER, "ris_zvector_solve before ris_int3c");
+    if (nrhs < 0 || maxit < 0) return fail(c, RIS_E_INVALID, "nrhs and maxit must be >= 0");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(c, RIS_E_INVALID, "tol must be in (0, 1)");
+    if (nrhs == 0) return RIS_OK;
+    if (!rhs || !Z || rhs == Z) return fail(c, RIS_E_INVALID, "null or aliased rhs / Z pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int o = c->nocc, v = c->nvir, nb = nrhs;
+    const long n = (long)v * o;
+    const size_t nv = (size_t)nb * n;
+    // v, q, r1, r2, yz, w, w1, w2 (nb vectors each), de, dot partials, state rows
+    Carve cv;
+    size_t ob[8];
+    for (int i = 0; i < 8; ++i) ob[i] = cv.take(nv);
+    const size_t ode = cv.take(n), opart = cv.take(bdot_partials(n, nb)), ost = cv.take((size_t)nb * kMrStride);
+    int stc;
+    char *base = pool_get(c, c->zv_pool, cv.off, &stc);
+    if (!base) return stc;
+    double *buf[8];
+    for (int i = 0; i < 8; ++i) buf[i] = (double *)(base + ob[i]);
+    double *V = buf[0], *Q = buf[1], *R1 = buf[2], *R2 = buf[3], *YZ = buf[4], *Wv = buf[5], *W1 = buf[6],
+           *W2 = buf[7];
+    double *de = (double *)(base + ode), *part = (double *)(base + opart);
+    MrState *st = (MrState *)(base + ost);
+    double *stp = (double *)st;
+
+    // preconditioner e_a - e_i, start: Z = 0, r2 = rhs, y = M^-1 rhs, beta1^2 = <rhs, y>
+    HIPCHK(c, orbital_gaps(c->eps, v, o, de, c->stream));
+    HIPCHK(c, fill(Z, nv, 0.0, c->stream));
+    HIPCHK(c, fill(Wv, nv, 0.0, c->stream));
+    HIPCHK(c, fill(W1, nv, 0.0, c->stream));
+    HIPCHK(c, fill(W2, nv, 0.0, c->stream));
+    HIPCHK(c, fill(R1, nv, 0.0, c->stream));
+    HIPCHK(c, hipMemcpyAsync(R2, rhs, nv * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, precond(R2, de, YZ, n, nb, c->stream));
+    HIPCHK(c, bdot(R2, YZ, n, nb, part, stp + offsetof(MrState, beta2) / sizeof(double), kMrStride, c->stream));
+    HIPCHK(c, mr_init(st, nb, tol, c->stream));
+
+    std::vector<MrState> hs(nb);
+    int it = 0;
+    bool all_done = false;
+    HIPCHK(c, hipMemcpyAsync(hs.data(), st, sizeof(MrState) * nb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    all_done = std::all_of(hs.begin(), hs.end(), [](const MrState &x) { return x.active == 0.0; });
+    while (!all_done && it < maxit) {
+        ++it;
+        HIPCHK(c, mr_v(st, YZ, V, n, nb, c->stream));
+        {
+            const int sm = ris_response_matvec(c, RIS_OP_APB, nb, V, Q);
+            if (sm != RIS_OK) return sm;
+        }
+        HIPCHK(c, mr_y1(st, R1, Q, n, nb, it >= 2 ? 1 : 0, c->stream));
+        HIPCHK(c, bdot(V, Q, n, nb, part, stp + offsetof(MrState, alfa) / sizeof(double), kMrStride, c->stream));
+        HIPCHK(c, mr_y2(st, R2, Q, n, nb, c->stream));
+        std::swap(R1, R2);  // r1 <- r2
+        std::swap(R2, Q);   // r2 <- y; the old r1 buffer receives the next matvec
+        HIPCHK(c, precond(R2, de, YZ, n, nb, c->stream));
+        HIPCHK(c, bdot(R2, YZ, n, nb, part, stp + offsetof(MrState, beta2) / sizeof(double), kMrStride, c->stream));
+        HIPCHK(c, mr_scal(st, nb, c->stream));
+        // w1 <- w2, w2 <- w, w <- (v - oldeps w1 - delta w2) denom, x += phi w
+        double *nw = W1;
+        W1 = W2;
+        W2 = Wv;
+        Wv = nw;
+        HIPCHK(c, mr_w(st, V, W1, W2, Wv, Z, n, nb, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hs.data(), st, sizeof(MrState) * nb, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        all_done = std::all_of(hs.begin(), hs.end(), [](const MrState &x) { return x.active == 0.0; });
+    }
+    // true residual rhs - (A+B) Z
+    {
+        const int sm = ris_response_matvec(c, RIS_OP_APB, nb, Z, Q);
+        if (sm != RIS_OK) return sm;
+    }
+    HIPCHK(c, vsub(rhs, Q, R1, nv, c->stream));
+    std::vector<double> rr(nb), bb(nb);
+    // the dots land in the first nb doubles of two free vector buffers
+    HIPCHK(c, bdot(R1, R1, n, nb, part, YZ, 1, c->stream));
+    HIPCHK(c, bdot(rhs, rhs, n, nb, part, W1, 1, c->stream));
+    HIPCHK(c, hipMemcpyAsync(rr.data(), YZ, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(bb.data(), W1, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double rel = 0.0;
+    for (int k = 0; k < nb; ++k)
+        if (bb[k] > 0.0) rel = std::max(rel, std::sqrt(rr[k] / bb[k]));
+    if (iters) *iters = it;
+    if (rel_resid) *rel_resid = rel;
+    if (!all_done) return fail(c, RIS_E_NOCONV, "Z-vector solve: %d iterations, relative residual %.3e", it, rel);
+    return RIS_OK;
 }
 
 int ris_ctx_set_screening(ris_ctx *c, double threshold, long *kept_pairs)

@@ -1,0 +1,248 @@
+// Device pieces of the preconditioned MINRES solve of (A+B)^ris Z = rhs:
+// batched deterministic dot products, the elementwise vector updates and the
+// per-right-hand-side scalar recurrence (Paige and Saunders' MINRES with a
+// symmetric positive definite preconditioner).  Every right-hand side k owns a
+// row of MrState in device memory; the vector kernels read their
+// coefficients from it, so an iteration needs no host round trip.
+#include <cmath>
+
+#include "ris_minres.hpp"
+
+namespace ris {
+namespace {
+
+inline unsigned nb_of(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+constexpr int kDotThreads = 256;
+constexpr int kDotPerThread = 8;
+constexpr int kDotChunk = kDotThreads * kDotPerThread;
+
+// partial[k][blk] = sum over the chunk blk of x_k * y_k (fixed order)
+__global__ __launch_bounds__(kDotThreads) void k_bdot_partial(const double *__restrict__ x,
+                                                              const double *__restrict__ y, long n, int nblk,
+                                                              double *__restrict__ partial)
+{
+    __shared__ double red[kDotThreads];
+    const int k = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
+    const double *xk = x + (long)k * n, *yk = y + (long)k * n;
+    const long base = (long)blk * kDotChunk;
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kDotPerThread; ++u) {
+        const long i = base + (long)u * kDotThreads + t;
+        if (i < n) s += xk[i] * yk[i];
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int h = kDotThreads / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) partial[(long)k * nblk + blk] = red[0];
+}
+
+__global__ void k_bdot_final(const double *__restrict__ partial, int nblk, int nb, double *__restrict__ out,
+                             int stride)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[(long)k * nblk + b];
+    out[(long)k * stride] = s;
+}
+
+// z_k[i] = r_k[i] / de[i]
+__global__ void k_precond(const double *__restrict__ r, const double *__restrict__ de, double *__restrict__ z,
+                          long n, int nb)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nb) return;
+    z[idx] = r[idx] / de[idx % n];
+}
+
+__global__ void k_mr_init(MrState *st, int nb, double tol)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    MrState &s = st[k];
+    const double b1 = sqrt(fmax(s.beta2, 0.0));
+    s.beta1 = b1;
+    s.beta = b1;
+    s.oldb = 0.0;
+    s.dbar = 0.0;
+    s.epsln = 0.0;
+    s.oldeps = 0.0;
+    s.phibar = b1;
+    s.cs = -1.0;
+    s.sn = 0.0;
+    s.delta = 0.0;
+    s.phi = 0.0;
+    s.denom = 0.0;
+    s.tol = tol;
+    s.active = b1 > 0.0 ? 1.0 : 0.0;
+}
+
+// v = y / beta (0 once a right-hand side has stopped)
+__global__ void k_mr_v(const MrState *st, const double *__restrict__ y, double *__restrict__ v, long n, int nb)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nb) return;
+    const MrState &s = st[idx / n];
+    v[idx] = s.active != 0.0 ? y[idx] / s.beta : 0.0;
+}
+
+// y -= (beta / oldb) r1 in place on the matvec result (from the second iteration on)
+__global__ void k_mr_y1(const MrState *st, const double *__restrict__ r1, double *__restrict__ y, long n, int nb,
+                        int second)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nb) return;
+    const MrState &s = st[idx / n];
+    const double c = (second && s.active != 0.0) ? s.beta / s.oldb : 0.0;
+    y[idx] -= c * r1[idx];
+}
+
+// y -= (alfa / beta) r2
+__global__ void k_mr_y2(const MrState *st, const double *__restrict__ r2, double *__restrict__ y, long n, int nb)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nb) return;
+    const MrState &s = st[idx / n];
+    const double c = s.active != 0.0 ? s.alfa / s.beta : 0.0;
+    y[idx] -= c * r2[idx];
+}
+
+// one Lanczos step of the scalar recurrence (Givens rotation of the
+// tridiagonal system); stops the right-hand side once the preconditioned
+// residual estimate phibar is within tol * beta1
+__global__ void k_mr_scal(MrState *st, int nb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    MrState &s = st[k];
+    if (s.active == 0.0) {
+        s.phi = 0.0;
+        s.denom = 0.0;
+        s.oldeps = 0.0;
+        s.delta = 0.0;
+        return;
+    }
+    s.oldb = s.beta;
+    s.beta = sqrt(fmax(s.beta2, 0.0));
+    s.oldeps = s.epsln;
+    s.delta = s.cs * s.dbar + s.sn * s.alfa;
+    const double gbar = s.sn * s.dbar - s.cs * s.alfa;
+    s.epsln = s.sn * s.beta;
+    s.dbar = -s.cs * s.beta;
+    double gamma = hypot(gbar, s.beta);
+    if (gamma < 1e-300) gamma = 1e-300;
+    s.cs = gbar / gamma;
+    s.sn = s.beta / gamma;
+    s.phi = s.cs * s.phibar;
+    s.phibar = s.sn * s.phibar;
+    s.denom = 1.0 / gamma;
+    if (s.phibar <= s.tol * s.beta1 || s.beta == 0.0) s.active = 0.0;
+}
+
+// w = (v - oldeps w1 - delta w2) denom ; x += phi w
+__global__ void k_mr_w(const MrState *st, const double *__restrict__ v, const double *__restrict__ w1,
+                       const double *__restrict__ w2, double *__restrict__ w, double *__restrict__ x, long n, int nb)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nb) return;
+    const MrState &s = st[idx / n];
+    const double wn = (v[idx] - s.oldeps * w1[idx] - s.delta * w2[idx]) * s.denom;
+    w[idx] = wn;
+    x[idx] += s.phi * wn;
+}
+
+// preconditioner diagonal max(|e_a - e_i|, kMinGap), [a][i] order
+__global__ void k_gaps(const double *__restrict__ eps, int nvir, int nocc, double *__restrict__ de)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nvir * nocc) return;
+    const int a = (int)(idx / nocc), i = (int)(idx % nocc);
+    de[idx] = fmax(fabs(eps[nocc + a] - eps[i]), kMinGap);
+}
+
+// d = a - b
+__global__ void k_sub(const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ d, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = a[i] - b[i];
+}
+
+}  // namespace
+
+size_t bdot_partials(long n, int nb) { return (size_t)nb * ((n + kDotChunk - 1) / kDotChunk); }
+
+hipError_t bdot(const double *x, const double *y, long n, int nb, double *partial, double *out, int stride,
+                hipStream_t st)
+{
+    if (nb <= 0) return hipSuccess;
+    const int nblk = (int)((n + kDotChunk - 1) / kDotChunk);
+    if (nblk > 0)
+        hipLaunchKernelGGL(k_bdot_partial, dim3(nblk, nb), dim3(kDotThreads), 0, st, x, y, n, nblk, partial);
+    hipLaunchKernelGGL(k_bdot_final, dim3(nb_of(nb, 64)), dim3(64), 0, st, partial, nblk, nb, out, stride);
+    return hipGetLastError();
+}
+
+hipError_t precond(const double *r, const double *de, double *z, long n, int nb, hipStream_t st)
+{
+    if (n * nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_precond, dim3(nb_of((size_t)n * nb, 256)), dim3(256), 0, st, r, de, z, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t mr_init(MrState *s, int nb, double tol, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mr_init, dim3(nb_of(nb, 64)), dim3(64), 0, st, s, nb, tol);
+    return hipGetLastError();
+}
+
+hipError_t mr_v(const MrState *s, const double *y, double *v, long n, int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mr_v, dim3(nb_of((size_t)n * nb, 256)), dim3(256), 0, st, s, y, v, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t mr_y1(const MrState *s, const double *r1, double *y, long n, int nb, int second, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mr_y1, dim3(nb_of((size_t)n * nb, 256)), dim3(256), 0, st, s, r1, y, n, nb, second);
+    return hipGetLastError();
+}
+
+hipError_t mr_y2(const MrState *s, const double *r2, double *y, long n, int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mr_y2, dim3(nb_of((size_t)n * nb, 256)), dim3(256), 0, st, s, r2, y, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t mr_scal(MrState *s, int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mr_scal, dim3(nb_of(nb, 64)), dim3(64), 0, st, s, nb);
+    return hipGetLastError();
+}
+
+hipError_t mr_w(const MrState *s, const double *v, const double *w1, const double *w2, double *w, double *x, long n,
+                int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mr_w, dim3(nb_of((size_t)n * nb, 256)), dim3(256), 0, st, s, v, w1, w2, w, x, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t orbital_gaps(const double *eps, int nvir, int nocc, double *de, hipStream_t st)
+{
+    if ((long)nvir * nocc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gaps, dim3(nb_of((size_t)nvir * nocc, 256)), dim3(256), 0, st, eps, nvir, nocc, de);
+    return hipGetLastError();
+}
+
+hipError_t vsub(const double *a, const double *b, double *d, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sub, dim3(nb_of(n, 256)), dim3(256), 0, st, a, b, d, n);
+    return hipGetLastError();
+}
+
+}  // namespace ris

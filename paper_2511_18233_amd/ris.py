@@ -18,13 +18,13 @@ LIB_PATH = os.path.join(HERE, "libris_hip.so")
 
 RIS_OK = 0
 STATUS = {0: "RIS_OK", 1: "RIS_E_INVALID", 2: "RIS_E_UNSUPPORTED", 3: "RIS_E_NOMEM", 4: "RIS_E_NOT_PD",
-          5: "RIS_E_DEGENERATE", 6: "RIS_E_ORDER", 7: "RIS_E_DEVICE"}
+          5: "RIS_E_DEGENERATE", 6: "RIS_E_ORDER", 7: "RIS_E_DEVICE", 8: "RIS_E_NOCONV"}
 OPS = {"A": 0, "B": 1, "A+B": 2, "A-B": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
            "ris_response_matvec", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
            "ris_request_bytes",
-           "ris_ctx_set_profiling", "ris_ctx_set_screening",
+           "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_zvector_solve",
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
            "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm")
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     lib.ris_grad_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp, ctypes.c_int, ip, dp, vp]
     lib.ris_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.ris_ctx_set_screening.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_long)]
+    lib.ris_zvector_solve.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, ctypes.c_int, ip, dp]
     lib.ris_ctx_stage_stats.argtypes = [vp, ctypes.c_int, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
     lib.ris_test_mfma_probe.argtypes = [ctypes.c_int, vp, vp, vp]
     L = ctypes.c_long
@@ -231,6 +232,23 @@ class RisContext:
         self._chk(self.lib.ris_response_matvec(self.h, OPS[op] if isinstance(op, str) else int(op), nvec, _ptr(V),
                                                _ptr(out)))
         return out
+
+    def zvector_solve(self, rhs, tol=1e-10, maxit=200, out=None, allow_noconv=False):
+        """(A+B)^ris Z = rhs for rhs[nrhs][nvir][nocc] (device FP64); returns
+        (Z, iterations, largest true relative residual).  RIS_E_NOCONV raises
+        unless allow_noconv."""
+        import torch
+        _check_dev(rhs, self.device, "rhs")
+        if out is None:
+            out = torch.empty_like(rhs)
+        _check_dev(out, self.device, "Z")
+        nrhs = rhs.shape[0] if rhs.dim() == 3 else 1
+        it, res = ctypes.c_int(0), ctypes.c_double(0.0)
+        st = self.lib.ris_zvector_solve(self.h, nrhs, _ptr(rhs), _ptr(out), float(tol), int(maxit), ctypes.byref(it),
+                                        ctypes.byref(res))
+        if not (st == 8 and allow_noconv):
+            self._chk(st)
+        return out, int(it.value), float(res.value)
 
     def grad_contract(self, X, Y, sel, out=None):
         import torch
