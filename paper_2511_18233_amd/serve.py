@@ -29,6 +29,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import md
+
 
 @dataclass
 class Request:
@@ -47,6 +49,7 @@ class Request:
     sel: list                       # gradients wanted
     pairs: list                     # NAC numerators wanted
     j_p_on_heavy: bool = True
+    velocity: np.ndarray | None = None  # [natm][3] nuclear velocities (for T_IJ)
 
 
 @dataclass
@@ -60,6 +63,7 @@ class Result:
     slot: int = -1
     need_bytes: int = 0
     error: str | None = None
+    tdc: np.ndarray | None = None   # T_IJ = g_IJ . v per requested pair (NAC numerators)
 
     @property
     def latency(self) -> float:
@@ -174,6 +178,8 @@ class Server:
             r, res = item
             try:
                 res.grad, res.nac = self.ex[k].run(r)
+                if r.velocity is not None and res.nac is not None:
+                    res.tdc = np.array([md.time_derivative_coupling(n, r.velocity) for n in res.nac])
             except Exception as e:  # one failing request does not stop the others
                 res.error = f"{type(e).__name__}: {e}"
             res.done = self.now()
@@ -226,14 +232,18 @@ def latency_stats(results) -> dict:
 
 # --------------------------------------------------------------- traces --
 def make_trace(n_requests: int, n_traj: int, rate_hz: float, seed: int = 1000, natm_range=(20, 120),
-               nstate: int = 3, step_ang: float = 0.01, progress=None):
+               nstate: int = 3, step_ang: float = 0.01, progress=None, random_phase: bool = True):
     """Surface-hopping-shaped trace: n_traj seeded trajectories of chain
     molecules (size uniform in natm_range), each request one step of its
     trajectory (previous geometry + N(0, step_ang) per coordinate, C = S^-1/2 Q
     recomputed, Q, eps and amplitudes fixed per trajectory), asking for the
     gradients of states 0 and 1 and the NAC numerator (0, 1); arrivals Poisson
     with the given rate.  progress(done, total), if given, is called every 32
-    requests built."""
+    requests built.  Each request carries seeded nuclear velocities (the
+    server returns T_IJ = g_IJ . v).  With random_phase, every step's
+    amplitudes get an arbitrary sign per state, as an eigensolver would
+    return them, and are then aligned to the previous step with
+    md.phase_signs, as an MD driver does before using the NACs."""
     import molgen
     rng = np.random.default_rng(seed)
     trajs = []
@@ -243,22 +253,34 @@ def make_trace(n_requests: int, n_traj: int, rate_hz: float, seed: int = 1000, n
         S = molgen.overlap_matrix(p.mol)
         w, V = np.linalg.eigh(S)
         Q = (V * np.sqrt(w)) @ V.T @ p.C          # C = S^-1/2 Q  =>  Q = S^1/2 C
-        trajs.append([p, Q, p.mol.xyz.copy()])
+        trajs.append([p, Q, p.mol.xyz.copy(), None, None])  # ..., previous C, previous aligned X
     gaps = rng.exponential(1.0 / rate_hz, n_requests)
     arrivals = np.cumsum(gaps) - gaps[0]
     reqs = []
     bohr = molgen.ANGSTROM_TO_BOHR
     for k in range(n_requests):
         t = k % n_traj
-        p, Q, xyz = trajs[t]
+        p, Q, xyz, C_prev, X_prev = trajs[t]
         xyz = xyz + rng.normal(0.0, step_ang * bohr, xyz.shape)
         trajs[t][2] = xyz
         mol = p.mol.with_xyz(xyz)
         S = molgen.overlap_matrix(mol)
         w, V = np.linalg.eigh(S)
         C = (V * (1.0 / np.sqrt(w))) @ V.T @ Q
+        X, Y = p.X, p.Y
+        if random_phase:
+            sg = np.where(rng.random(X.shape[0]) < 0.5, -1.0, 1.0)
+            X = sg[:, None, None] * X
+            Y = None if Y is None else sg[:, None, None] * Y
+            if X_prev is not None:
+                fix = md.phase_signs(X_prev, X, C_prev, C, S, p.nocc)
+                X = fix[:, None, None] * X
+                Y = None if Y is None else fix[:, None, None] * Y
+        trajs[t][3], trajs[t][4] = C, X
+        vel = rng.normal(0.0, 1e-3, xyz.shape)
         reqs.append(Request(k, float(arrivals[k]), mol.Z, mol.xyz, mol.shell_atom, mol.shell_l, mol.shell_exp,
-                            np.ascontiguousarray(C), p.eps, p.nocc, p.X, p.Y, [0, 1], [(0, 1)]))
+                            np.ascontiguousarray(C), p.eps, p.nocc, np.ascontiguousarray(X),
+                            None if Y is None else np.ascontiguousarray(Y), [0, 1], [(0, 1)], velocity=vel))
         if progress is not None and (k + 1) % 32 == 0:
             progress(k + 1, n_requests)
     return reqs
