@@ -29,6 +29,10 @@ What it computes, and where the paper defines it:
   (Sec. 2.2, last equation): (pq|A)^x M^-1 (B|sr) + (pq|A) M^-1 (B|sr)^x
   - (pq|A) M^-1 M^x M^-1 (B|sr).
 
+* TDA-ris excitation energies: the lowest eigenpairs of the symmetric A^ris
+  (Sec. 2.1 eq. casida with B = 0, the TDA; the ris kernel in A), here the
+  dense A^ris assembled column by column from the matvec and a full
+  symmetric eigendecomposition.
 * ris-approximated Z-vector solve: (A+B)^ris Z = rhs with the ris kernel
   in the (A+B) matrix of the Z-vector equation (Sec. 4.2; the equation is
   eq. Z_vector of Sec. 2.1, restated in Appendix A.2), solved here by its
@@ -263,6 +267,25 @@ def dense_apb(S: Setup, C, eps, nocc, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX) -
     E = np.eye(v * o).reshape(v * o, v, o)
     cols = response_matvec(S, C, eps, nocc, E, "A+B", alpha_J, c_x)
     return cols.reshape(v * o, v * o).T
+
+
+def dense_a(S: Setup, C, eps, nocc, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX) -> np.ndarray:
+    """A^ris as a dense (vo x vo) matrix, columns = matvecs of unit vectors."""
+    o = nocc
+    v = C.shape[1] - o
+    E = np.eye(v * o).reshape(v * o, v, o)
+    cols = response_matvec(S, C, eps, nocc, E, "A", alpha_J, c_x)
+    return cols.reshape(v * o, v * o).T
+
+
+def tda_eigen(S: Setup, C, eps, nocc, nroots: int, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX):
+    """Lowest nroots eigenpairs of A^ris (TDA): omega[nroots] ascending and
+    X[nroots][nvir][nocc] with unit norm (signs as numpy returns them)."""
+    A = dense_a(S, C, eps, nocc, alpha_J, c_x)
+    w, U = np.linalg.eigh(0.5 * (A + A.T))
+    o = nocc
+    v = C.shape[1] - o
+    return w[:nroots], U[:, :nroots].T.reshape(nroots, v, o)
 
 
 def zvector_solve(S: Setup, C, eps, nocc, rhs: np.ndarray, alpha_J=DEFAULT_ALPHA_J,

@@ -291,6 +291,21 @@ def test_zvector_dense_solve(ring):
     assert np.abs(O.zvector_solve(S, p.C, p.eps, p.nocc, np.zeros_like(rhs[:1]))).max() == 0.0
 
 
+def test_tda_eigen(ring):
+    """TDA-ris eigenpairs from the matvec-assembled A are eigenpairs of the
+    brute-force four-index A, ascending, orthonormal, and the lowest ones."""
+    p, rad, S = ring
+    A, _ = _dense_AB(S, p.C, p.eps, p.nocc, 2.0, 0.25)
+    w, X = O.tda_eigen(S, p.C, p.eps, p.nocc, 4)
+    U = X.reshape(4, -1)
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(U @ U.T - np.eye(4)).max() < 1e-12
+    for k in range(4):
+        assert np.abs(A @ U[k] - w[k] * U[k]).max() < 1e-11 * np.abs(A).max()
+    wall = np.linalg.eigvalsh(A)
+    assert np.abs(w - wall[:4]).max() < 1e-11 * np.abs(wall).max()
+
+
 def test_energy_consistency(ring):
     """E_II from AO traces equals 1/2 R.(A+B-D)R + 1/2 L.(A-B-D)L (TDDFT Y != 0)."""
     p0, rad, S = ring
