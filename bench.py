@@ -119,6 +119,26 @@ def zvector_bench(ctx, prob, jp, radii, C, eps, nrhs, tol, maxit=20):
     return out
 
 
+def davidson_bench(ctx, prob, jp, radii, C, eps, nroots, tol=1e-6, maxit=60):
+    """TDA-ris excitation energies of the workload (FP64) by block Davidson:
+    iterations, wall time, the lowest roots and whether the residual
+    tolerance was reached within maxit."""
+    import time as _t
+    import torch
+    m = prob.mol
+    ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+    ctx.int3c(C, eps, prob.nocc, 2.0, 0.25)
+    torch.cuda.synchronize()
+    t = _t.perf_counter()
+    w, X, it = ctx.tda_davidson(nroots, tol=tol, maxit=maxit, allow_noconv=True)
+    torch.cuda.synchronize()
+    dt = _t.perf_counter() - t
+    out = {"nroots": nroots, "tol": tol, "iterations": it, "seconds": round(dt, 4),
+           "omega_ha": [round(float(x), 8) for x in w], "converged": it < maxit}
+    log(f"[bench] davidson: {nroots} roots, {it} iterations, {dt:.2f} s, lowest {w[0]:.6f} Ha")
+    return out
+
+
 def compare_precisions(ctx, prob, jp, grads, pairs, radii, C, eps, X, Y):
     """Run the step once per precision mode; max |d grad| and |d NAC| against
     the FP64 GPU result (itself pinned to the oracle by the parity tests)."""
@@ -206,6 +226,8 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="also replay a serving trace of this many requests (20-120 atoms)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--davidson", type=int, default=0,
+                    help="also time the TDA-ris Davidson solve for this many roots")
     ap.add_argument("--zvector", type=int, default=0,
                     help="also time the ris Z-vector solve for this many right-hand sides")
     args = ap.parse_args()
@@ -312,6 +334,8 @@ def main():
     mv = per_stage.get("matvec")
     if mv and mv["ms_per_step"] > 0:
         res["matvecs_per_s"] = round(2 * ns / (mv["ms_per_step"] * 1e-3), 2)
+    if args.davidson > 0:
+        res["davidson"] = davidson_bench(ctx, prob, jp, radii, C, eps, args.davidson)
     if args.zvector > 0:
         res["zvector"] = zvector_bench(ctx, prob, jp, radii, C, eps, args.zvector, 1e-8)
     if args.compare_precisions:

@@ -160,6 +160,22 @@ enum ris_stage {
 int ris_zvector_solve(ris_ctx *ctx, int nrhs, const double *rhs, double *Z, double tol, int maxit, int *iters,
                       double *rel_resid);
 
+/* TDA-ris excitation energies (Sec. 2.1, eq. casida with B = 0; the ris
+ * kernel of Sec. 2.2 in A): the nroots lowest eigenpairs of the symmetric
+ * A^ris by block Davidson on ris_response_matvec(RIS_OP_A) in the context's
+ * precision mode.  Start vectors: unit vectors on the 2 nroots smallest
+ * orbital-energy gaps; corrections r / (theta - (e_a - e_i)); subspace
+ * eigenproblem on the device (one-workgroup Jacobi); the subspace collapses
+ * to the Ritz vectors when it would exceed max_space (0 = min(nvir nocc,
+ * max(8 nroots, 32)); at most 256 and at least min(2 nroots, nvir nocc)).
+ * A root is converged when its residual norm ||A x - w x|| <= tol.
+ * omega: host [nroots], ascending; X: device [nroots][nvir][nocc], unit
+ * vectors (sign arbitrary but reproducible).  iters (may be NULL): iterations
+ * run.  RIS_E_NOCONV after maxit iterations or when no new direction is left
+ * (omega and X hold the last Ritz pairs), RIS_E_ORDER before ris_int3c. */
+int ris_tda_davidson(ris_ctx *ctx, int nroots, double tol, int maxit, int max_space, double *omega, double *X,
+                     int *iters);
+
 /* AO shell-pair screen of the three-centre derivative contraction (the
  * (mu nu|P)^xi term of the three-term RI derivative, last equation of
  * Sec. 2.2; the screen itself is an implementation choice: a pair whose

@@ -33,6 +33,12 @@ int ris_test_dgemm(int M, int N, int K, int transA, int transB, double alpha, co
 int ris_test_gemm(int mode, int M, int N, int K, int transA, int transB, double alpha, const double *A, long lda,
                   long sA, const double *B, long ldb, long sB, double beta, double *C, long ldc, long sC, int batch);
 
+/* Eigen-decomposition of a small symmetric m x m matrix by the path's
+ * one-workgroup Jacobi kernel (used for Davidson subspaces): A (device,
+ * row-major, m x m) is replaced by the eigenvectors as rows, w (device, m)
+ * receives the eigenvalues ascending.  Synchronous; allocates its own work. */
+int ris_test_sym_eig(int m, double *A, double *w);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,7 @@ struct ris_ctx {
     Pool mo_pool;     // orbitals and the MO blocks kept between calls
     Pool out_pool;    // staging of combined gradient + NAC outputs
     Pool zv_pool;     // vectors of the Z-vector solve (the matvec uses the scratch below)
+    Pool dv_pool;     // subspace of the TDA Davidson solve
     void *ws = nullptr;  // scratch shared by the calls
     size_t ws_bytes = 0;
 
@@ -387,6 +388,7 @@ MatvecWs matvec_ws(const Dims &d, int nvec)
 }
 
 constexpr int kSplitV = 64;  // K-split of the long-K Coulomb products
+constexpr int kDavMaxSpace = 256;  // largest Davidson subspace (the Jacobi eigensolver's size)
 // K-split of the V_PQ product (nK x nK output, K = 9 o^2): about 1024
 // workgroups over its 128 x 128 tiles
 int vpq_splits(int nK)
@@ -618,6 +620,122 @@ int ris_zvector_solve(ris_ctx *c, int nrhs, const double *rhs, double *Z, double
     if (iters) *iters = it;
     if (rel_resid) *rel_resid = rel;
     if (!all_done) return fail(c, RIS_E_NOCONV, "Z-vector solve: %d iterations, relative residual %.3e", it, rel);
+    return RIS_OK;
+}
+
+int ris_tda_davidson(ris_ctx *c, int nroots, double tol, int maxit, int max_space, double *omega, double *X,
+                     int *iters)
+{
+    if (!c) return RIS_E_INVALID;
+    c->err.clear();
+    if (iters) *iters = 0;
+    if (!c->have_int3c) return fail(c, RIS_E_ORDER, "ris_tda_davidson before ris_int3c");
+    const int o = c->nocc, v = c->nvir;
+    const long n = (long)v * o;
+    if (nroots <= 0 || nroots > n) return fail(c, RIS_E_INVALID, "nroots must be in [1, nvir*nocc]");
+    if (!(tol > 0.0) || maxit <= 0) return fail(c, RIS_E_INVALID, "tol must be > 0 and maxit >= 1");
+    if (!omega || !X) return fail(c, RIS_E_INVALID, "null omega or X pointer");
+    const long cap = std::min<long>(n, kDavMaxSpace);
+    int ms = max_space > 0 ? max_space : (int)std::min<long>(cap, std::max(8 * nroots, 32));
+    if (ms > cap || ms < std::min<long>(n, 2L * nroots))
+        return fail(c, RIS_E_INVALID, "max_space must be in [min(2 nroots, nvir*nocc), %ld]", cap);
+    HIPCHK(c, hipSetDevice(c->device));
+    const int k0 = (int)std::min<long>(ms, std::min<long>(n, 2L * nroots));  // start vectors
+    // layout: V, AV [ms][n]; Ritz X, AX, residual / corrections R [nroots][n]; H, work [ms][ms]; w, cs [ms + 1];
+    // gaps [n]; dot partials; start indices
+    Carve cv;
+    const size_t oV = cv.take((size_t)ms * n), oAV = cv.take((size_t)ms * n), oX = cv.take((size_t)nroots * n),
+                 oAX = cv.take((size_t)nroots * n), oR = cv.take((size_t)nroots * n), oH = cv.take((size_t)ms * ms),
+                 oWk = cv.take((size_t)ms * ms), ow = cv.take(ms + 1), ocs = cv.take(ms + 1), ode = cv.take(n),
+                 opt = cv.take(bdot_partials(n, std::max(ms, nroots))), onr = cv.take(std::max(ms, nroots)),
+                 oid = cv.take((k0 + 1) / 2 + 1);
+    int stc;
+    char *base = pool_get(c, c->dv_pool, cv.off, &stc);
+    if (!base) return stc;
+    auto D = [&](size_t off) { return (double *)(base + off); };
+    double *Vb = D(oV), *AVb = D(oAV), *Xr = D(oX), *AXr = D(oAX), *Rb = D(oR), *H = D(oH), *Wk = D(oWk), *w = D(ow),
+           *csb = D(ocs), *de = D(ode), *part = D(opt), *nrm = D(onr);
+    int *didx = (int *)(base + oid);
+
+    // start: unit vectors on the k0 smallest orbital-energy gaps
+    HIPCHK(c, orbital_gaps_plain(c->eps, v, o, de, c->stream));
+    std::vector<double> hde(n);
+    HIPCHK(c, hipMemcpyAsync(hde.data(), de, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<int> order(n);
+    for (long i = 0; i < n; ++i) order[i] = (int)i;
+    std::partial_sort(order.begin(), order.begin() + k0, order.end(),
+                      [&](int a, int b) { return hde[a] < hde[b] || (hde[a] == hde[b] && a < b); });
+    HIPCHK(c, hipMemcpyAsync(didx, order.data(), sizeof(int) * k0, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, fill(Vb, (size_t)k0 * n, 0.0, c->stream));
+    HIPCHK(c, set_units(Vb, didx, k0, n, c->stream));
+    int m = k0;
+    {
+        const int sm = ris_response_matvec(c, RIS_OP_A, m, Vb, AVb);
+        if (sm != RIS_OK) return sm;
+    }
+    std::vector<double> hw(nroots), hn(nroots);
+    int it = 0;
+    bool conv = false;
+    while (it < maxit) {
+        ++it;
+        // subspace matrix H = V AV^T (symmetrised), its eigenpairs, Ritz pairs
+        HIPCHK(c, dgemm(gm(m, m, (int)n, false, true, 1.0, Vb, n, AVb, n, 0.0, H, m), c->stream));
+        HIPCHK(c, symmetrize(H, m, 1, c->stream));
+        HIPCHK(c, sym_eig_small(H, Wk, m, w, csb, c->stream));
+        HIPCHK(c, dgemm(gm(nroots, (int)n, m, false, false, 1.0, H, m, Vb, n, 0.0, Xr, n), c->stream));
+        HIPCHK(c, dgemm(gm(nroots, (int)n, m, false, false, 1.0, H, m, AVb, n, 0.0, AXr, n), c->stream));
+        HIPCHK(c, ritz_residual(AXr, Xr, w, Rb, n, nroots, c->stream));
+        HIPCHK(c, bdot(Rb, Rb, n, nroots, part, nrm, 1, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hw.data(), w, sizeof(double) * nroots, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(hn.data(), nrm, sizeof(double) * nroots, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        std::vector<int> todo;
+        for (int j = 0; j < nroots; ++j)
+            if (std::sqrt(std::max(hn[j], 0.0)) > tol) todo.push_back(j);
+        if (todo.empty()) {
+            conv = true;
+            break;
+        }
+        if (it == maxit) break;
+        // corrections of the unconverged roots, in place in R
+        for (int j : todo) HIPCHK(c, davidson_correction(Rb + (size_t)j * n, hw[j], de, Rb + (size_t)j * n, n, c->stream));
+        // collapse to the Ritz vectors when the new ones would not fit
+        if (m + (int)todo.size() > ms) {
+            HIPCHK(c, hipMemcpyAsync(Vb, Xr, sizeof(double) * nroots * n, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(AVb, AXr, sizeof(double) * nroots * n, hipMemcpyDeviceToDevice, c->stream));
+            m = nroots;
+        }
+        // append each correction after two Gram-Schmidt passes against the basis
+        const int m0 = m;
+        for (int j : todo) {
+            double *t = Rb + (size_t)j * n;
+            HIPCHK(c, bdot(t, t, n, 1, part, nrm, 1, c->stream));
+            double before = 0.0;
+            HIPCHK(c, hipMemcpyAsync(&before, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            for (int pass = 0; pass < 2; ++pass) {
+                HIPCHK(c, dgemm(gm(1, m, (int)n, false, true, 1.0, t, n, Vb, n, 0.0, csb, m), c->stream));
+                HIPCHK(c, dgemm(gm(1, (int)n, m, false, false, -1.0, csb, m, Vb, n, 1.0, t, n), c->stream));
+            }
+            HIPCHK(c, bdot(t, t, n, 1, part, nrm, 1, c->stream));
+            double after = 0.0;
+            HIPCHK(c, hipMemcpyAsync(&after, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (!(after > 1e-20 * std::max(before, 1e-300)) || m >= ms) continue;  // dependent: dropped
+            HIPCHK(c, axpby(t, Vb + (size_t)m * n, n, 1.0 / std::sqrt(after), 0.0, c->stream));
+            ++m;
+        }
+        if (m == m0) break;  // no new direction: the iteration has stalled
+        {
+            const int sm = ris_response_matvec(c, RIS_OP_A, m - m0, Vb + (size_t)m0 * n, AVb + (size_t)m0 * n);
+            if (sm != RIS_OK) return sm;
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(X, Xr, sizeof(double) * nroots * n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int j = 0; j < nroots; ++j) omega[j] = hw[j];
+    if (iters) *iters = it;
+    if (!conv) return fail(c, RIS_E_NOCONV, "TDA Davidson: %d iterations without convergence", it);
     return RIS_OK;
 }
 

@@ -246,3 +246,226 @@ hipError_t vsub(const double *a, const double *b, double *d, size_t n, hipStream
 }
 
 }  // namespace ris
+
+// ---------------------------------------------------------------------------
+// Small dense symmetric eigensolver for Davidson subspaces: cyclic Jacobi with
+// the round-robin (tournament) ordering, all disjoint rotations of a round in
+// parallel, one workgroup, matrices in global memory (m is at most a few
+// hundred; the cost is negligible next to one matvec).
+namespace ris {
+namespace {
+
+constexpr int kJacThreads = 256;
+
+// player j of round r in the circle method over mp (even) players
+__device__ __forceinline__ int jac_player(int j, int r, int mp) { return j == 0 ? 0 : ((j - 1 + r) % (mp - 1)) + 1; }
+
+__global__ __launch_bounds__(kJacThreads) void k_jacobi(double *__restrict__ A, double *__restrict__ V, int m,
+                                                        double *__restrict__ w, double *__restrict__ cs_buf,
+                                                        int max_sweeps)
+{
+    const int t = threadIdx.x;
+    const int mp = m + (m & 1);  // a dummy player pads odd sizes
+    const int npair = mp / 2;
+    __shared__ double red[kJacThreads];
+    __shared__ int stop;
+    for (long idx = t; idx < (long)m * m; idx += kJacThreads) V[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        // convergence: off-diagonal Frobenius norm against the whole matrix
+        double off = 0.0, all = 0.0;
+        for (long idx = t; idx < (long)m * m; idx += kJacThreads) {
+            const double a = A[idx];
+            all += a * a;
+            if (idx / m != idx % m) off += a * a;
+        }
+        red[t] = off;
+        __syncthreads();
+        for (int h = kJacThreads / 2; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        const double offs = red[0];
+        __syncthreads();
+        red[t] = all;
+        __syncthreads();
+        for (int h = kJacThreads / 2; h > 0; h >>= 1) {
+            if (t < h) red[t] += red[t + h];
+            __syncthreads();
+        }
+        if (t == 0) stop = (offs <= 1e-30 * red[0]) ? 1 : 0;
+        __syncthreads();
+        if (stop) break;
+        for (int r = 0; r < mp - 1; ++r) {
+            // rotation of each pair: symmetric 2 x 2 Schur decomposition
+            for (int k = t; k < npair; k += kJacThreads) {
+                int p = jac_player(k, r, mp), q = jac_player(mp - 1 - k, r, mp);
+                if (p > q) { const int x = p; p = q; q = x; }
+                double c = 1.0, s = 0.0;
+                if (q < m) {
+                    const double apq = A[(long)p * m + q];
+                    if (apq != 0.0) {
+                        const double tau = (A[(long)q * m + q] - A[(long)p * m + p]) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        s = tt * c;
+                    }
+                }
+                cs_buf[2 * k] = c;
+                cs_buf[2 * k + 1] = s;
+            }
+            __syncthreads();
+            // rows p, q of A  (A <- J^T A)
+            for (long idx = t; idx < (long)npair * m; idx += kJacThreads) {
+                const int k = (int)(idx / m), col = (int)(idx % m);
+                int p = jac_player(k, r, mp), q = jac_player(mp - 1 - k, r, mp);
+                if (p > q) { const int x = p; p = q; q = x; }
+                if (q >= m) continue;
+                const double c = cs_buf[2 * k], s = cs_buf[2 * k + 1];
+                const double ap = A[(long)p * m + col], aq = A[(long)q * m + col];
+                A[(long)p * m + col] = c * ap - s * aq;
+                A[(long)q * m + col] = s * ap + c * aq;
+            }
+            __syncthreads();
+            // columns p, q of A and of V  (A <- A J, V <- V J)
+            for (long idx = t; idx < (long)npair * m; idx += kJacThreads) {
+                const int k = (int)(idx / m), row = (int)(idx % m);
+                int p = jac_player(k, r, mp), q = jac_player(mp - 1 - k, r, mp);
+                if (p > q) { const int x = p; p = q; q = x; }
+                if (q >= m) continue;
+                const double c = cs_buf[2 * k], s = cs_buf[2 * k + 1];
+                const double ap = A[(long)row * m + p], aq = A[(long)row * m + q];
+                A[(long)row * m + p] = c * ap - s * aq;
+                A[(long)row * m + q] = s * ap + c * aq;
+                const double vp = V[(long)row * m + p], vq = V[(long)row * m + q];
+                V[(long)row * m + p] = c * vp - s * vq;
+                V[(long)row * m + q] = s * vp + c * vq;
+            }
+            __syncthreads();
+        }
+    }
+    // eigenvalues ascending; w[j] and the permutation into cs_buf (as doubles)
+    if (t == 0) {
+        for (int j = 0; j < m; ++j) {
+            w[j] = A[(long)j * m + j];
+            cs_buf[j] = (double)j;
+        }
+        for (int i = 1; i < m; ++i) {  // insertion sort (stable)
+            const double x = w[i], xi = cs_buf[i];
+            int j = i - 1;
+            while (j >= 0 && w[j] > x) {
+                w[j + 1] = w[j];
+                cs_buf[j + 1] = cs_buf[j];
+                --j;
+            }
+            w[j + 1] = x;
+            cs_buf[j + 1] = xi;
+        }
+    }
+    __syncthreads();
+    // sorted eigenvectors as rows of A: A[j][:] = V[:, perm[j]]
+    for (long idx = t; idx < (long)m * m; idx += kJacThreads) {
+        const int j = (int)(idx / m), row = (int)(idx % m);
+        A[idx] = V[(long)row * m + (int)cs_buf[j]];
+    }
+}
+
+}  // namespace
+
+hipError_t sym_eig_small(double *A, double *work, int m, double *w, double *cs_buf, hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacThreads), 0, st, A, work, m, w, cs_buf, 60);
+    return hipGetLastError();
+}
+
+}  // namespace ris
+
+// ---------------------------------------------------------------------------
+// Element kernels of the TDA Davidson iteration.
+namespace ris {
+namespace {
+
+__global__ void k_set_units(double *__restrict__ V, const int *__restrict__ idx, int k, long n)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < k) V[(long)j * n + idx[j]] = 1.0;
+}
+
+// R_j = AX_j - w[j] X_j
+__global__ void k_ritz_res(const double *__restrict__ AX, const double *__restrict__ X, const double *__restrict__ w,
+                           double *__restrict__ R, long n, int nb)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nb) return;
+    R[idx] = AX[idx] - w[idx / n] * X[idx];
+}
+
+// t = r / (theta - d), the denominator kept at least kDavFloor away from 0
+__global__ void k_dav_corr(const double *__restrict__ r, double theta, const double *__restrict__ de,
+                           double *__restrict__ t, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = theta - de[i];
+    if (fabs(d) < kDavFloor) d = d < 0.0 ? -kDavFloor : kDavFloor;
+    t[i] = r[i] / d;
+}
+
+// de[a][i] = e_a - e_i (unfloored: the Davidson shift uses the plain gaps)
+__global__ void k_gaps_plain(const double *__restrict__ eps, int nvir, int nocc, double *__restrict__ de)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nvir * nocc) return;
+    de[idx] = eps[nocc + (int)(idx / nocc)] - eps[(int)(idx % nocc)];
+}
+
+}  // namespace
+
+hipError_t set_units(double *V, const int *idx, int k, long n, hipStream_t st)
+{
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_units, dim3(nb_of(k, 64)), dim3(64), 0, st, V, idx, k, n);
+    return hipGetLastError();
+}
+
+hipError_t ritz_residual(const double *AX, const double *X, const double *w, double *R, long n, int nb,
+                         hipStream_t st)
+{
+    if (n * nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ritz_res, dim3(nb_of((size_t)n * nb, 256)), dim3(256), 0, st, AX, X, w, R, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t davidson_correction(const double *r, double theta, const double *de, double *t, long n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dav_corr, dim3(nb_of((size_t)n, 256)), dim3(256), 0, st, r, theta, de, t, n);
+    return hipGetLastError();
+}
+
+hipError_t orbital_gaps_plain(const double *eps, int nvir, int nocc, double *de, hipStream_t st)
+{
+    if ((long)nvir * nocc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gaps_plain, dim3(nb_of((size_t)nvir * nocc, 256)), dim3(256), 0, st, eps, nvir, nocc, de);
+    return hipGetLastError();
+}
+
+}  // namespace ris
+
+extern "C" int ris_test_sym_eig(int m, double *A, double *w)
+{
+    if (m < 0 || (m > 0 && (!A || !w))) return 1;
+    if (m == 0) return 0;
+    double *work = nullptr, *cs = nullptr;
+    if (hipMalloc(&work, sizeof(double) * m * m) != hipSuccess) return 3;
+    if (hipMalloc(&cs, sizeof(double) * (m + 2)) != hipSuccess) {
+        (void)hipFree(work);
+        return 3;
+    }
+    const hipError_t e = ris::sym_eig_small(A, work, m, w, cs, 0);
+    const hipError_t s = hipDeviceSynchronize();
+    (void)hipFree(work);
+    (void)hipFree(cs);
+    return (e != hipSuccess || s != hipSuccess) ? 7 : 0;
+}

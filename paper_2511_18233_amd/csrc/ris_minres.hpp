@@ -36,4 +36,21 @@ hipError_t vsub(const double *a, const double *b, double *d, size_t n, hipStream
 constexpr double kMinGap = 1e-4;
 hipError_t orbital_gaps(const double *eps, int nvir, int nocc, double *de, hipStream_t st);
 
+// Eigen-decomposition of a small symmetric m x m matrix A (device, row-major,
+// destroyed): on return w[m] holds the eigenvalues ascending and row j of A the
+// unit eigenvector of w[j].  work: m * m doubles; cs_buf: max(m, m + 1) doubles.
+// One workgroup (cyclic Jacobi, tournament ordering).
+hipError_t sym_eig_small(double *A, double *work, int m, double *w, double *cs_buf, hipStream_t st);
+
+// TDA Davidson element steps: unit start vectors V[j][idx[j]] = 1 (V zeroed
+// before); Ritz residuals R_j = AX_j - w[j] X_j; the diagonal correction
+// t = r / (theta - (e_a - e_i)) with the denominator kept >= kDavFloor in
+// magnitude; the plain orbital gaps e_a - e_i.
+constexpr double kDavFloor = 1e-8;
+hipError_t set_units(double *V, const int *idx, int k, long n, hipStream_t st);
+hipError_t ritz_residual(const double *AX, const double *X, const double *w, double *R, long n, int nb,
+                         hipStream_t st);
+hipError_t davidson_correction(const double *r, double theta, const double *de, double *t, long n, hipStream_t st);
+hipError_t orbital_gaps_plain(const double *eps, int nvir, int nocc, double *de, hipStream_t st);
+
 }  // namespace ris

@@ -24,10 +24,10 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
            "ris_response_matvec", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
            "ris_request_bytes",
-           "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_zvector_solve",
+           "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_zvector_solve", "ris_tda_davidson",
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
-           "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm")
+           "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm", "ris_test_sym_eig")
 
 
 class RisError(RuntimeError):
@@ -85,12 +85,14 @@ def load_library(path: str = LIB_PATH):
     lib.ris_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.ris_ctx_set_screening.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_long)]
     lib.ris_zvector_solve.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, ctypes.c_int, ip, dp]
+    lib.ris_tda_davidson.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, vp, ip]
     lib.ris_ctx_stage_stats.argtypes = [vp, ctypes.c_int, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
     lib.ris_test_mfma_probe.argtypes = [ctypes.c_int, vp, vp, vp]
     L = ctypes.c_long
     lib.ris_test_dgemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_double, vp, L, L, vp, L, L, ctypes.c_double, vp, L, L, ctypes.c_int]
     lib.ris_test_gemm.argtypes = [ctypes.c_int] + lib.ris_test_dgemm.argtypes
+    lib.ris_test_sym_eig.argtypes = [ctypes.c_int, vp, vp]
     _lib = lib
     return lib
 
@@ -249,6 +251,22 @@ class RisContext:
         if not (st == 8 and allow_noconv):
             self._chk(st)
         return out, int(it.value), float(res.value)
+
+    def tda_davidson(self, nroots, tol=1e-8, maxit=100, max_space=0, out=None, allow_noconv=False):
+        """Lowest nroots TDA-ris eigenpairs: (omega numpy[nroots], X device
+        [nroots][nvir][nocc], iterations).  RIS_E_NOCONV raises unless
+        allow_noconv."""
+        import torch
+        if out is None:
+            out = torch.empty((int(nroots), self.nvir, self.nocc), dtype=torch.float64, device=self.device)
+        _check_dev(out, self.device, "X")
+        w = np.zeros(int(nroots))
+        it = ctypes.c_int(0)
+        st = self.lib.ris_tda_davidson(self.h, int(nroots), float(tol), int(maxit), int(max_space),
+                                       w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(out), ctypes.byref(it))
+        if not (st == 8 and allow_noconv):
+            self._chk(st)
+        return w, out, int(it.value)
 
     def grad_contract(self, X, Y, sel, out=None):
         import torch
