@@ -33,6 +33,14 @@ What it computes, and where the paper defines it:
   (Sec. 2.1 eq. casida with B = 0, the TDA; the ris kernel in A), here the
   dense A^ris assembled column by column from the matvec and a full
   symmetric eigendecomposition.
+* ris terms of the Z-vector right-hand side (Appendix A.3, eqs.
+  g_I_pp_ris and g_IJ_pp_ris): in the MO basis, for a gradient
+  4 [R^S_I g^ris[R^S_I]] - 4 [L^A_I g^ris[L^A_I]], for a NAC pair
+  2 [R^S_I g[R^S_J]] - 2 [L^A_I g[L^A_J]] + 2 [R^S_J g[R^S_I]] - 2 [L^A_J g[L^A_I]],
+  with R^S = [[0, R^T/2], [R/2, 0]], L^A = [[0, -L^T/2], [L/2, 0]] (occupied
+  first) and g^ris[D]_mn = a_J sum (mn|ls)_J D_ls - c_x sum (ml|ns)_K D_ls,
+  the convention under which sum_mn D1_mn g[D2]_mn is the bilinear ris
+  functional E (reading A2); built here from explicit four-index tensors.
 * ris-approximated Z-vector solve: (A+B)^ris Z = rhs with the ris kernel
   in the (A+B) matrix of the Z-vector equation (Sec. 4.2; the equation is
   eq. Z_vector of Sec. 2.1, restated in Appendix A.2), solved here by its
@@ -267,6 +275,53 @@ def dense_apb(S: Setup, C, eps, nocc, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX) -
     E = np.eye(v * o).reshape(v * o, v, o)
     cols = response_matvec(S, C, eps, nocc, E, "A+B", alpha_J, c_x)
     return cols.reshape(v * o, v * o).T
+
+
+def g_ris_ao(S: Setup, D: np.ndarray, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX) -> np.ndarray:
+    """g^ris[D] in the AO basis from the explicit four-index RI tensors (small
+    molecules only): a_J sum (mn|ls)_J D_ls - c_x sum (ml|ns)_K D_ls."""
+    eriJ = np.einsum("Pmn,PQ,Qls->mnls", S.int3J, np.linalg.inv(S.MJ), S.int3J, optimize=True)
+    eriK = np.einsum("Pmn,PQ,Qls->mnls", S.int3K, np.linalg.inv(S.MK), S.int3K, optimize=True)
+    return alpha_J * np.einsum("mnls,ls->mn", eriJ, D) - c_x * np.einsum("mlns,ls->mn", eriK, D)
+
+
+def mo_densities(X, Y, nocc, nmo):
+    """R^S_I and L^A_I in the MO basis (occupied first), Appendix A.2."""
+    R = X if Y is None else X + Y
+    L = X if Y is None else X - Y
+    o = nocc
+    RS = np.zeros((X.shape[0], nmo, nmo))
+    LA = np.zeros((X.shape[0], nmo, nmo))
+    for I in range(X.shape[0]):
+        RS[I, o:, :o] = 0.5 * R[I]
+        RS[I, :o, o:] = 0.5 * R[I].T
+        LA[I, o:, :o] = 0.5 * L[I]
+        LA[I, :o, o:] = -0.5 * L[I].T
+    return RS, LA
+
+
+def zrhs_ris_terms(S: Setup, C, nocc, X, Y, pairs, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX) -> np.ndarray:
+    """The ris terms of g^(pp') (Appendix A.3) per output pair (I, J), as
+    [npair][nmo][nmo] MO matrices: I == J the gradient form, I != J the four
+    ris terms of Q_IJ."""
+    nmo = C.shape[1]
+    RS, LA = mo_densities(X, Y, nocc, nmo)
+    cache = {}
+
+    def g_mo(kind, I):
+        if (kind, I) not in cache:
+            D = RS[I] if kind == "R" else LA[I]
+            cache[(kind, I)] = C.T @ g_ris_ao(S, C @ D @ C.T, alpha_J, c_x) @ C
+        return cache[(kind, I)]
+
+    out = np.zeros((len(pairs), nmo, nmo))
+    for k, (I, J) in enumerate(pairs):
+        if I == J:
+            out[k] = 4.0 * RS[I] @ g_mo("R", I) - 4.0 * LA[I] @ g_mo("L", I)
+        else:
+            out[k] = (2.0 * RS[I] @ g_mo("R", J) - 2.0 * LA[I] @ g_mo("L", J)
+                      + 2.0 * RS[J] @ g_mo("R", I) - 2.0 * LA[J] @ g_mo("L", I))
+    return out
 
 
 def dense_a(S: Setup, C, eps, nocc, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX) -> np.ndarray:

@@ -306,6 +306,47 @@ def test_tda_eigen(ring):
     assert np.abs(w - wall[:4]).max() < 1e-11 * np.abs(wall).max()
 
 
+def test_zrhs_ris_terms(ring):
+    """ris terms of the Z-vector right-hand side: g^ris[D] is symmetric for
+    the symmetric R^S and antisymmetric for L^A, sum D1 . g[D2] over the MO
+    indices reproduces the bilinear functional E_IJ (computed independently
+    from three-centre contractions), so tr G_II = 4 E_II and tr Q_IJ = 4 E_IJ."""
+    p, rad, S = ring
+    rng = np.random.default_rng(8)
+    X, Y = molgen.make_amplitudes(p.eps, p.nocc, 2, False, rng)
+    nmo = p.C.shape[1]
+    RS, LA = O.mo_densities(X, Y, p.nocc, nmo)
+    RSa, LAa = O.ao_densities(p.C, p.nocc, X, Y)
+    assert np.abs(p.C @ RS[0] @ p.C.T - RSa[0]).max() < 1e-13
+    assert np.abs(p.C @ LA[1] @ p.C.T - LAa[1]).max() < 1e-13
+    gR = p.C.T @ O.g_ris_ao(S, RSa[0]) @ p.C
+    gL = p.C.T @ O.g_ris_ao(S, LAa[0]) @ p.C
+    assert np.abs(gR - gR.T).max() < 1e-12 * np.abs(gR).max()
+    assert np.abs(gL + gL.T).max() < 1e-12 * np.abs(gL).max()
+    G = O.zrhs_ris_terms(S, p.C, p.nocc, X, Y, [(0, 0), (0, 1)])
+    E00 = O.energy_functional(S, RSa[0], RSa[0], LAa[0], LAa[0])
+    E01 = O.energy_functional(S, RSa[0], RSa[1], LAa[0], LAa[1])
+    assert abs(np.trace(G[0]) - 4.0 * E00) < 1e-11 * max(1.0, abs(E00))
+    assert abs(np.trace(G[1]) - 4.0 * E01) < 1e-11 * max(1.0, abs(E01))
+    # a flipped sign on the L^A terms is caught (their share of the trace is not zero)
+    Gbad = 4.0 * RS[0] @ gR + 4.0 * LA[0] @ gL
+    assert abs(np.trace(Gbad) - 4.0 * E00) > 1e-6 * abs(E00)
+    # orbital-rotation derivative: rotating MOs p, q by theta (amplitudes fixed in
+    # the MO basis) changes E_II at the rate -(G_pq - G_qp): 5-point differences
+    o = p.nocc
+    h = 1e-3
+    for (pp, qq) in ((o + 3, 2), (o + 10, o - 1), (1, 5), (o + 2, o + 7)):
+        def E_rot(th):
+            c, s_ = np.cos(th), np.sin(th)
+            C2 = p.C.copy()
+            C2[:, pp], C2[:, qq] = c * p.C[:, pp] - s_ * p.C[:, qq], s_ * p.C[:, pp] + c * p.C[:, qq]
+            R2, L2 = O.ao_densities(C2, o, X[:1], Y[:1])
+            return O.energy_functional(S, R2[0], R2[0], L2[0], L2[0])
+        fd = (E_rot(-2 * h) - 8 * E_rot(-h) + 8 * E_rot(h) - E_rot(2 * h)) / (12 * h)
+        an = -(G[0][pp, qq] - G[0][qq, pp])
+        assert abs(fd - an) < 1e-8 * max(1.0, abs(an)), (pp, qq, fd, an)
+
+
 def test_energy_consistency(ring):
     """E_II from AO traces equals 1/2 R.(A+B-D)R + 1/2 L.(A-B-D)L (TDDFT Y != 0)."""
     p0, rad, S = ring
