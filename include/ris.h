@@ -160,6 +160,24 @@ enum ris_stage {
 int ris_zvector_solve(ris_ctx *ctx, int nrhs, const double *rhs, double *Z, double tol, int maxit, int *iters,
                       double *rel_resid);
 
+/* ris terms of the right-hand side of the Z-vector equation and of W
+ * (Appendix A.3, eqs. g_I_pp_ris and g_IJ_pp_ris): for each output pair
+ * (I, J) the MO-basis matrix
+ *   I == J: 4 [R^S_I g^ris[R^S_I]] - 4 [L^A_I g^ris[L^A_I]]
+ *   I != J: 2 [R^S_I g^ris[R^S_J]] - 2 [L^A_I g^ris[L^A_J]]
+ *         + 2 [R^S_J g^ris[R^S_I]] - 2 [L^A_J g^ris[L^A_I]]
+ * with R^S = [[0, R^T/2], [R/2, 0]], L^A = [[0, -L^T/2], [L/2, 0]] in the MO
+ * basis (occupied first), R = X + Y, L = X - Y, and
+ * g^ris[D]_mn = alpha_J sum (mn|ls)_J D_ls - c_x sum (ml|ns)_K D_ls.
+ * The Z-vector right-hand side takes its VO block minus the transposed OV
+ * block (eq. Z_vector of Sec. 2.1), W its OO and VV blocks.  FP64 in every
+ * precision mode.  X, Y: [nstate][nvir][nocc] device (Y = NULL: TDA);
+ * pairs: host [npair][2]; G: device [npair][nmo][nmo], rows and columns in
+ * the MO order of ris_int3c's C.  Recomputes (mu nu|P) into the context's
+ * scratch (nJ nao^2 doubles).  RIS_E_ORDER before ris_int3c. */
+int ris_zrhs_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y, int npair, const int *pairs,
+                      double *G);
+
 /* TDA-ris excitation energies (Sec. 2.1, eq. casida with B = 0; the ris
  * kernel of Sec. 2.2 in A): the nroots lowest eigenpairs of the symmetric
  * A^ris by block Davidson on ris_response_matvec(RIS_OP_A) in the context's

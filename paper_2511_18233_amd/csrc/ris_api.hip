@@ -649,6 +649,9 @@ int ris_tda_davidson(ris_ctx *c, int nroots, double tol, int maxit, int max_spac
                  oWk = cv.take((size_t)ms * ms), ow = cv.take(ms + 1), ocs = cv.take(ms + 1), ode = cv.take(n),
                  opt = cv.take(bdot_partials(n, std::max(ms, nroots))), onr = cv.take(std::max(ms, nroots)),
                  oid = cv.take((k0 + 1) / 2 + 1);
+    // K-split of the subspace products (m x m or 1 x m outputs, K = nvir nocc)
+    const int nsk = (int)std::max<long>(1, std::min<long>(256, n / 4096));
+    const size_t osk = cv.take((size_t)nsk * ms * ms);
     int stc;
     char *base = pool_get(c, c->dv_pool, cv.off, &stc);
     if (!base) return stc;
@@ -656,6 +659,7 @@ int ris_tda_davidson(ris_ctx *c, int nroots, double tol, int maxit, int max_spac
     double *Vb = D(oV), *AVb = D(oAV), *Xr = D(oX), *AXr = D(oAX), *Rb = D(oR), *H = D(oH), *Wk = D(oWk), *w = D(ow),
            *csb = D(ocs), *de = D(ode), *part = D(opt), *nrm = D(onr);
     int *didx = (int *)(base + oid);
+    double *skb = D(osk);
 
     // start: unit vectors on the k0 smallest orbital-energy gaps
     HIPCHK(c, orbital_gaps_plain(c->eps, v, o, de, c->stream));
@@ -680,7 +684,7 @@ int ris_tda_davidson(ris_ctx *c, int nroots, double tol, int maxit, int max_spac
     while (it < maxit) {
         ++it;
         // subspace matrix H = V AV^T (symmetrised), its eigenpairs, Ritz pairs
-        HIPCHK(c, dgemm(gm(m, m, (int)n, false, true, 1.0, Vb, n, AVb, n, 0.0, H, m), c->stream));
+        HIPCHK(c, dgemm_splitk(gm(m, m, (int)n, false, true, 1.0, Vb, n, AVb, n, 0.0, H, m), nsk, skb, c->stream));
         HIPCHK(c, symmetrize(H, m, 1, c->stream));
         HIPCHK(c, sym_eig_small(H, Wk, m, w, csb, c->stream));
         HIPCHK(c, dgemm(gm(nroots, (int)n, m, false, false, 1.0, H, m, Vb, n, 0.0, Xr, n), c->stream));
@@ -714,7 +718,8 @@ int ris_tda_davidson(ris_ctx *c, int nroots, double tol, int maxit, int max_spac
             double before = 0.0;
             HIPCHK(c, hipMemcpyAsync(&before, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
             for (int pass = 0; pass < 2; ++pass) {
-                HIPCHK(c, dgemm(gm(1, m, (int)n, false, true, 1.0, t, n, Vb, n, 0.0, csb, m), c->stream));
+                HIPCHK(c, dgemm_splitk(gm(1, m, (int)n, false, true, 1.0, t, n, Vb, n, 0.0, csb, m), nsk, skb,
+                                       c->stream));
                 HIPCHK(c, dgemm(gm(1, (int)n, m, false, false, -1.0, csb, m, Vb, n, 1.0, t, n), c->stream));
             }
             HIPCHK(c, bdot(t, t, n, 1, part, nrm, 1, c->stream));
@@ -736,6 +741,113 @@ int ris_tda_davidson(ris_ctx *c, int nroots, double tol, int maxit, int max_spac
     for (int j = 0; j < nroots; ++j) omega[j] = hw[j];
     if (iters) *iters = it;
     if (!conv) return fail(c, RIS_E_NOCONV, "TDA Davidson: %d iterations without convergence", it);
+    return RIS_OK;
+}
+
+int ris_zrhs_contract(ris_ctx *c, int nstate, const double *X, const double *Y, int npair, const int *pairs,
+                      double *G)
+{
+    if (!c) return RIS_E_INVALID;
+    c->err.clear();
+    if (!c->have_int3c) return fail(c, RIS_E_ORDER, "ris_zrhs_contract before ris_int3c");
+    if (nstate <= 0 || npair < 0) return fail(c, RIS_E_INVALID, "nstate must be > 0 and npair >= 0");
+    if (npair == 0) return RIS_OK;
+    if (!X || !pairs || !G) return fail(c, RIS_E_INVALID, "null X, pairs or G pointer");
+    std::vector<char> used(nstate, 0);
+    for (int k = 0; k < npair; ++k) {
+        const int I = pairs[2 * k], J = pairs[2 * k + 1];
+        if (I < 0 || J < 0 || I >= nstate || J >= nstate) return fail(c, RIS_E_INVALID, "pair %d out of range", k);
+        used[I] = used[J] = 1;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    const int N = c->nao, nmo = c->nmo, o = c->nocc, v = c->nvir, nJ = c->nJ, nK = c->nK, ns = nstate;
+    const long vo = (long)v * o, NN = (long)N * N, MM = (long)nmo * nmo, Ko = (long)nK * o;
+    Carve cv;
+    const size_t oR = cv.take((size_t)ns * vo), oL = cv.take((size_t)ns * vo), oUR = cv.take((size_t)ns * N * o),
+                 oUL = cv.take((size_t)ns * N * o), otT = cv.take((size_t)ns * nJ), ocv = cv.take((size_t)ns * nJ),
+                 oSK = cv.take((size_t)kSplitV * ns * nJ), oX3 = cv.take((size_t)nJ * NN),
+                 oBk = cv.take((size_t)nK * NN), oZ1 = cv.take((size_t)N * Ko), oZ2 = cv.take((size_t)N * Ko),
+                 oY1 = cv.take((size_t)N * Ko), oY2 = cv.take((size_t)N * Ko), oJ = cv.take((size_t)ns * NN),
+                 ogA = cv.take(NN), oT1 = cv.take((size_t)N * nmo), ogM = cv.take((size_t)ns * 2 * MM),
+                 oEm = cv.take((size_t)4 * MM);
+    // K-split of the two exchange products (N x N output, K = nK o)
+    const int ksp = balanced_splits((long)((N + 127) / 128) * ((N + 127) / 128), 8);
+    const size_t oSK2 = cv.take((size_t)ksp * NN);
+    int st;
+    char *wsb = ws_get(c, cv.off, &st);
+    if (!wsb) return st;
+    auto P_ = [&](size_t off) { return (double *)(wsb + off); };
+    double *R = P_(oR), *L = P_(oL), *UR = P_(oUR), *UL = P_(oUL), *tT = P_(otT), *cvec = P_(ocv), *SK = P_(oSK),
+           *X3 = P_(oX3), *Bk = P_(oBk), *Z1 = P_(oZ1), *Z2 = P_(oZ2), *Y1 = P_(oY1), *Y2 = P_(oY2), *Jao = P_(oJ),
+           *gA = P_(ogA), *T1 = P_(oT1), *gM = P_(ogM), *Em = P_(oEm), *SK2 = P_(oSK2);
+    const double *CO = c->C, *CV = c->C + o;
+
+    // R, L, the AO factors U = C_V R, U' = C_V L and the Coulomb vectors c = M_J^-1 t
+    HIPCHK(c, make_rl(X, Y, R, L, (size_t)ns * vo, c->stream));
+    for (int t = 0; t < 2; ++t) {
+        GemmArgs g = gm(N, o, v, false, false, 1.0, CV, nmo, t ? L : R, o, 0.0, t ? UL : UR, o);
+        g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o;
+        HIPCHK(c, dgemm(g, c->stream));
+    }
+    HIPCHK(c, dgemm_splitk(gm(ns, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), kSplitV, SK,
+                           c->stream));
+    HIPCHK(c, dgemm(gm(ns, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
+    // AO three-centre integrals again, the metric-applied exchange set, the Coulomb matrices
+    HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, X3, c->stream));
+    HIPCHK(c, dgemm(gm(nK, (int)NN, nK, false, false, 1.0, c->MinvK, nK, X3, NN, 0.0, Bk, NN), c->stream));
+    HIPCHK(c, dgemm(gm(ns, (int)NN, nJ, false, false, c->alphaJ, cvec, nJ, X3, NN, 0.0, Jao, NN), c->stream));
+    // Z1^P = B^P C_O, Z2^P = (mu nu|P) C_O as [mu][P][i]
+    for (int t = 0; t < 2; ++t) {
+        GemmArgs g = gm(N, o, N, false, false, 1.0, t ? X3 : Bk, N, CO, nmo, 0.0, t ? Z2 : Z1, Ko);
+        g.batch = nK; g.strideA = NN; g.strideB = 0; g.strideC = o;
+        HIPCHK(c, dgemm(g, c->stream));
+    }
+    // g^ris[D] in the MO basis for D = R^S_s (t = 0) and L^A_s (t = 1) of every state used:
+    //   K[D] = sum_P B^P D (mu nu|P) = (Y1 Z2^T +- Z1 Y2^T) / 2, Y1 = B^P U, Y2 = (.|P) U
+    for (int s = 0; s < ns; ++s) {
+        if (!used[s]) continue;
+        for (int t = 0; t < 2; ++t) {
+            const double *U = (t ? UL : UR) + (size_t)s * N * o;
+            for (int q = 0; q < 2; ++q) {
+                GemmArgs g = gm(N, o, N, false, false, 1.0, q ? X3 : Bk, N, U, o, 0.0, q ? Y2 : Y1, Ko);
+                g.batch = nK; g.strideA = NN; g.strideB = 0; g.strideC = o;
+                HIPCHK(c, dgemm(g, c->stream));
+            }
+            if (t == 0)
+                HIPCHK(c, hipMemcpyAsync(gA, Jao + (size_t)s * NN, sizeof(double) * NN, hipMemcpyDeviceToDevice,
+                                         c->stream));
+            else
+                HIPCHK(c, fill(gA, NN, 0.0, c->stream));
+            const double sgn = t ? -1.0 : 1.0;
+            HIPCHK(c, dgemm_splitk(gm(N, N, (int)Ko, false, true, -0.5 * c->cx, Y1, Ko, Z2, Ko, 1.0, gA, N), ksp,
+                                   SK2, c->stream));
+            HIPCHK(c, dgemm_splitk(gm(N, N, (int)Ko, false, true, -0.5 * c->cx * sgn, Z1, Ko, Y2, Ko, 1.0, gA, N),
+                                   ksp, SK2, c->stream));
+            HIPCHK(c, dgemm(gm(N, nmo, N, false, false, 1.0, gA, N, c->C, nmo, 0.0, T1, nmo), c->stream));
+            HIPCHK(c, dgemm(gm(nmo, nmo, N, true, false, 1.0, c->C, nmo, T1, nmo, 0.0, gM + ((size_t)s * 2 + t) * MM,
+                               nmo), c->stream));
+        }
+    }
+    // per output: 4 [R^S g[R^S]] - 4 [L^A g[L^A]] (I == J), or the four ris terms of Q_IJ
+    double *RSI = Em, *LAI = Em + MM, *RSJ = Em + 2 * MM, *LAJ = Em + 3 * MM;
+    for (int k = 0; k < npair; ++k) {
+        const int I = pairs[2 * k], J = pairs[2 * k + 1];
+        double *Gk = G + (size_t)k * MM;
+        const double *gRI = gM + ((size_t)I * 2) * MM, *gLI = gM + ((size_t)I * 2 + 1) * MM;
+        const double *gRJ = gM + ((size_t)J * 2) * MM, *gLJ = gM + ((size_t)J * 2 + 1) * MM;
+        HIPCHK(c, embed_rl(R + (size_t)I * vo, L + (size_t)I * vo, nmo, o, RSI, LAI, c->stream));
+        if (I == J) {
+            HIPCHK(c, dgemm(gm(nmo, nmo, nmo, false, false, 4.0, RSI, nmo, gRI, nmo, 0.0, Gk, nmo), c->stream));
+            HIPCHK(c, dgemm(gm(nmo, nmo, nmo, false, false, -4.0, LAI, nmo, gLI, nmo, 1.0, Gk, nmo), c->stream));
+        } else {
+            HIPCHK(c, embed_rl(R + (size_t)J * vo, L + (size_t)J * vo, nmo, o, RSJ, LAJ, c->stream));
+            HIPCHK(c, dgemm(gm(nmo, nmo, nmo, false, false, 2.0, RSI, nmo, gRJ, nmo, 0.0, Gk, nmo), c->stream));
+            HIPCHK(c, dgemm(gm(nmo, nmo, nmo, false, false, -2.0, LAI, nmo, gLJ, nmo, 1.0, Gk, nmo), c->stream));
+            HIPCHK(c, dgemm(gm(nmo, nmo, nmo, false, false, 2.0, RSJ, nmo, gRI, nmo, 1.0, Gk, nmo), c->stream));
+            HIPCHK(c, dgemm(gm(nmo, nmo, nmo, false, false, -2.0, LAJ, nmo, gLI, nmo, 1.0, Gk, nmo), c->stream));
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return RIS_OK;
 }
 

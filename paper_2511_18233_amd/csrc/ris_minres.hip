@@ -469,3 +469,36 @@ extern "C" int ris_test_sym_eig(int m, double *A, double *w)
     (void)hipFree(cs);
     return (e != hipSuccess || s != hipSuccess) ? 7 : 0;
 }
+
+// ---------------------------------------------------------------------------
+// Dense MO-basis transition densities (occupied first):
+//   RS = [[0, R^T/2], [R/2, 0]],  LA = [[0, -L^T/2], [L/2, 0]]
+namespace ris {
+namespace {
+__global__ void k_embed_rl(const double *__restrict__ R, const double *__restrict__ L, int nmo, int nocc,
+                           double *__restrict__ RS, double *__restrict__ LA)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nmo * nmo) return;
+    const int p = (int)(idx / nmo), q = (int)(idx % nmo);
+    double rs = 0.0, la = 0.0;
+    if (p < nocc && q >= nocc) {
+        const long e = (long)(q - nocc) * nocc + p;
+        rs = 0.5 * R[e];
+        la = -0.5 * L[e];
+    } else if (p >= nocc && q < nocc) {
+        const long e = (long)(p - nocc) * nocc + q;
+        rs = 0.5 * R[e];
+        la = 0.5 * L[e];
+    }
+    RS[idx] = rs;
+    LA[idx] = la;
+}
+}  // namespace
+
+hipError_t embed_rl(const double *R, const double *L, int nmo, int nocc, double *RS, double *LA, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_embed_rl, dim3(nb_of((size_t)nmo * nmo, 256)), dim3(256), 0, st, R, L, nmo, nocc, RS, LA);
+    return hipGetLastError();
+}
+}  // namespace ris

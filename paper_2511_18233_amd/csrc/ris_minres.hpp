@@ -53,4 +53,8 @@ hipError_t ritz_residual(const double *AX, const double *X, const double *w, dou
 hipError_t davidson_correction(const double *r, double theta, const double *de, double *t, long n, hipStream_t st);
 hipError_t orbital_gaps_plain(const double *eps, int nvir, int nocc, double *de, hipStream_t st);
 
+// RS = [[0, R^T/2], [R/2, 0]] and LA = [[0, -L^T/2], [L/2, 0]] as dense
+// nmo x nmo matrices (occupied first) from R, L [nvir][nocc].
+hipError_t embed_rl(const double *R, const double *L, int nmo, int nocc, double *RS, double *LA, hipStream_t st);
+
 }  // namespace ris

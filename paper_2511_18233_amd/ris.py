@@ -25,6 +25,7 @@ EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes
            "ris_response_matvec", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
            "ris_request_bytes",
            "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_zvector_solve", "ris_tda_davidson",
+           "ris_zrhs_contract",
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
            "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm", "ris_test_sym_eig")
@@ -86,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     lib.ris_ctx_set_screening.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_long)]
     lib.ris_zvector_solve.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, ctypes.c_int, ip, dp]
     lib.ris_tda_davidson.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, vp, ip]
+    lib.ris_zrhs_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp]
     lib.ris_ctx_stage_stats.argtypes = [vp, ctypes.c_int, dp, dp, dp, ctypes.POINTER(ctypes.c_long)]
     lib.ris_test_mfma_probe.argtypes = [ctypes.c_int, vp, vp, vp]
     L = ctypes.c_long
@@ -251,6 +253,21 @@ class RisContext:
         if not (st == 8 and allow_noconv):
             self._chk(st)
         return out, int(it.value), float(res.value)
+
+    def zrhs_contract(self, X, Y, pairs, out=None):
+        """ris terms of the Z-vector right-hand side per pair (I, J) as device
+        [npair][nmo][nmo] MO matrices (gradient form for I == J)."""
+        import torch
+        _check_dev(X, self.device, "X")
+        _check_dev(Y, self.device, "Y")
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        nmo = self.nocc + self.nvir
+        if out is None:
+            out = torch.empty((pr.shape[0], nmo, nmo), dtype=torch.float64, device=self.device)
+        _check_dev(out, self.device, "G")
+        self._chk(self.lib.ris_zrhs_contract(self.h, X.shape[0], _ptr(X), _ptr(Y), pr.shape[0],
+                                             pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(out)))
+        return out
 
     def tda_davidson(self, nroots, tol=1e-8, maxit=100, max_space=0, out=None, allow_noconv=False):
         """Lowest nroots TDA-ris eigenpairs: (omega numpy[nroots], X device
