@@ -119,6 +119,24 @@ def zvector_bench(ctx, prob, jp, radii, C, eps, nrhs, tol, maxit=20):
     return out
 
 
+def zrhs_bench(ctx, prob, jp, radii, C, eps, X, Y, outs):
+    """ris terms of the Z-vector right-hand side for the step's outputs (FP64):
+    wall time of one ris_zrhs_contract call after ris_int3c."""
+    import time as _t
+    import torch
+    m = prob.mol
+    ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+    ctx.int3c(C, eps, prob.nocc, 2.0, 0.25)
+    G = ctx.zrhs_contract(X, Y, outs)  # warm the scratch
+    torch.cuda.synchronize()
+    t = _t.perf_counter()
+    G = ctx.zrhs_contract(X, Y, outs, out=G)
+    torch.cuda.synchronize()
+    dt = _t.perf_counter() - t
+    log(f"[bench] zrhs: {len(outs)} outputs in {dt:.3f} s")
+    return {"outputs": len(outs), "seconds": round(dt, 4), "outputs_per_s": round(len(outs) / dt, 3)}
+
+
 def davidson_bench(ctx, prob, jp, radii, C, eps, nroots, tol=1e-6, maxit=15):
     """TDA-ris excitation energies of the workload (FP64) by block Davidson,
     capped at maxit iterations: wall time per iteration and the lowest Ritz
@@ -228,6 +246,8 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="also replay a serving trace of this many requests (20-120 atoms)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--zrhs", action="store_true",
+                    help="also time the ris Z-vector right-hand-side terms for the step's outputs")
     ap.add_argument("--davidson", type=int, default=0,
                     help="also time the TDA-ris Davidson solve for this many roots")
     ap.add_argument("--zvector", type=int, default=0,
@@ -336,6 +356,8 @@ def main():
     mv = per_stage.get("matvec")
     if mv and mv["ms_per_step"] > 0:
         res["matvecs_per_s"] = round(2 * ns / (mv["ms_per_step"] * 1e-3), 2)
+    if args.zrhs:
+        res["zrhs"] = zrhs_bench(ctx, prob, jp, radii, C, eps, X, Y, outs)
     if args.davidson > 0:
         res["davidson"] = davidson_bench(ctx, prob, jp, radii, C, eps, args.davidson)
     if args.zvector > 0:
