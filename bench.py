@@ -53,7 +53,9 @@ def make_workload(name):
 
 def oracle_sample(prob, jp, outs, radii):
     """Time the CPU oracle on bounded samples of the same workload and scale
-    each stage linearly to one full step (documented in the design doc)."""
+    each stage linearly to one full step: (mu nu|P) for a few auxiliary
+    shells, the exchange weights of two K functions for one output pair, and
+    the derivative contraction over those functions for one output."""
     from oracle import ris_oracle as O
     import threadpoolctl  # noqa: F401  (BLAS threads stay at the default: all cores)
     mol = prob.mol
