@@ -1041,7 +1041,12 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
     HIPCHK(c, hipMemcpyAsync(&info, c->info, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (info != 0) return fail(c, RIS_E_NOT_PD, "auxiliary metric not positive definite (column %d)", info);
-    HIPCHK(c, tri_inverse(c->MinvJ, c->LinvJ, nJ, c->stream));
+    {
+        int stw;
+        char *tw = ws_get(c, sizeof(double) * (size_t)kTriBlock * nJ, &stw);
+        if (!tw) return stw;
+        HIPCHK(c, tri_inverse(c->MinvJ, c->LinvJ, nJ, (double *)tw, c->stream));
+    }
     // M_J^-1 = L^-T L^-1 ; M_K = leading nK block, so L_K^-1 = leading block of L_J^-1
     HIPCHK(c, dgemm(gm(nJ, nJ, nJ, true, false, 1.0, c->LinvJ, nJ, c->LinvJ, nJ, 0.0, c->MinvJ, nJ), c->stream));
     HIPCHK(c, dgemm(gm(nK, nK, nK, true, false, 1.0, c->LinvJ, nJ, c->LinvJ, nJ, 0.0, c->MinvK, nK), c->stream));

@@ -120,6 +120,9 @@ hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st);
 // below 1e-13 of Morig's diagonal (the unfactored matrix, may be null) fails.
 hipError_t cholesky(double *A, const double *Morig, int n, int *info, hipStream_t st);
 // Linv = L^-1 for lower-triangular L (n x n), full matrix written.
-hipError_t tri_inverse(const double *L, double *Linv, int n, hipStream_t st);
+// Blocks of kTriBlock rows: diagonal blocks by substitution, the rest by GEMMs;
+// tmp holds kTriBlock * n doubles.
+constexpr int kTriBlock = 64;
+hipError_t tri_inverse(const double *L, double *Linv, int n, double *tmp, hipStream_t st);
 
 }  // namespace ris

@@ -90,17 +90,20 @@ __global__ void k_zero_upper(double *A, int n)
     if (j > i) A[idx] = 0.0;
 }
 
-// column j of L^-1 by forward substitution (one thread per column)
-__global__ void k_tri_inverse(const double *__restrict__ L, double *__restrict__ X, int n)
+// inverse of each kTriBlock x kTriBlock diagonal block of L by forward
+// substitution: workgroup k owns block k, thread j its column j (X zeroed before)
+__global__ void k_tri_inv_diag(const double *__restrict__ L, double *__restrict__ X, int n)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    for (int i = 0; i < j; ++i) X[(size_t)i * n + j] = 0.0;
-    X[(size_t)j * n + j] = 1.0 / L[(size_t)j * n + j];
-    for (int i = j + 1; i < n; ++i) {
+    const int r0 = blockIdx.x * kTriBlock, j = threadIdx.x;
+    const int nb = min(kTriBlock, n - r0);
+    if (j >= nb) return;
+    const int cj = r0 + j;
+    X[(size_t)cj * n + cj] = 1.0 / L[(size_t)cj * n + cj];
+    for (int i = j + 1; i < nb; ++i) {
+        const int ri = r0 + i;
         double s = 0.0;
-        for (int k = j; k < i; ++k) s += L[(size_t)i * n + k] * X[(size_t)k * n + j];
-        X[(size_t)i * n + j] = -s / L[(size_t)i * n + i];
+        for (int k = j; k < i; ++k) s += L[(size_t)ri * n + r0 + k] * X[(size_t)(r0 + k) * n + cj];
+        X[(size_t)ri * n + cj] = -s / L[(size_t)ri * n + ri];
     }
 }
 
@@ -181,21 +184,23 @@ __global__ void k_axpby(const double *__restrict__ src, double *__restrict__ dst
 // Assemble nP matrices of (3o x 3o) from a 3 x 3 grid of o x o blocks; block
 // (bi, bj) is the sum of up to two strided sources
 //   src[P][i][j] = base[P * sP + i * si + j * sj] * scale   (base null = 0).
-// grid: (column chunks of 256, 3o rows, nP); 32-bit index arithmetic only
-__global__ void k_assemble3(BlockGrid g, double *__restrict__ W, int o, int nP)
+// grid: (3 column blocks x chunks of 256 columns, 3o rows, nP); the column
+// block, hence the source descriptors, is uniform per workgroup
+__global__ void k_assemble3(BlockGrid g, double *__restrict__ W, int o, int nP, int nchunk)
 {
     const int n3 = 3 * o;
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= n3) return;
+    const int bj = blockIdx.x / nchunk;
+    const int j = (blockIdx.x - bj * nchunk) * blockDim.x + threadIdx.x;
+    if (j >= o) return;
     const int row = blockIdx.y, P = blockIdx.z;
-    const int bi = row / o, bj = col / o, i = row - bi * o, j = col - bj * o;
+    const int bi = row / o, i = row - bi * o;
     double v = 0.0;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        const BlockSrc &b = g.b[bi][bj][t];
+        const BlockSrc b = g.b[bi][bj][t];
         if (b.base) v += b.scale * b.base[P * b.sP + (long)i * b.si + (long)j * b.sj];
     }
-    W[((long)P * n3 + row) * n3 + col] = v;
+    W[((long)P * n3 + row) * n3 + bj * o + j] = v;
 }
 
 // out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] (+ beta * out) over n0 x n1 x n2
@@ -290,10 +295,29 @@ hipError_t cholesky(double *A, const double *Morig, int n, int *info, hipStream_
     return hipGetLastError();
 }
 
-hipError_t tri_inverse(const double *L, double *Linv, int n, hipStream_t st)
+hipError_t tri_inverse(const double *L, double *Linv, int n, double *tmp, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tri_inverse, dim3(nblk(n, 64)), dim3(64), 0, st, L, Linv, n);
-    return hipGetLastError();
+    if (n <= 0) return hipSuccess;
+    hipError_t e = fill(Linv, (size_t)n * n, 0.0, st);
+    if (e != hipSuccess) return e;
+    const int nb = (n + kTriBlock - 1) / kTriBlock;
+    hipLaunchKernelGGL(k_tri_inv_diag, dim3(nb), dim3(kTriBlock), 0, st, L, Linv, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // block rows below: X[i, :i] = -X_ii (L[i, :i] X[:i, :i])
+    for (int i = 1; i < nb; ++i) {
+        const int r0 = i * kTriBlock, rows = std::min(kTriBlock, n - r0);
+        GemmArgs g{};
+        g.M = rows; g.N = r0; g.K = r0; g.alpha = 1.0; g.beta = 0.0;
+        g.A = L + (size_t)r0 * n; g.lda = n; g.B = Linv; g.ldb = n; g.C = tmp; g.ldc = r0;
+        g.batch = 1; g.nred = 1;
+        if ((e = dgemm(g, st)) != hipSuccess) return e;
+        GemmArgs h{};
+        h.M = rows; h.N = r0; h.K = rows; h.alpha = -1.0; h.beta = 0.0;
+        h.A = Linv + (size_t)r0 * n + r0; h.lda = n; h.B = tmp; h.ldb = r0; h.C = Linv + (size_t)r0 * n; h.ldc = n;
+        h.batch = 1; h.nred = 1;
+        if ((e = dgemm(h, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t fill(double *p, size_t n, double v, hipStream_t st)
@@ -345,7 +369,8 @@ hipError_t axpby(const double *src, double *dst, size_t n, double alpha, double 
 hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st)
 {
     if (o <= 0 || nP <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_assemble3, dim3(nblk((size_t)3 * o, 256), 3 * o, nP), dim3(256), 0, st, g, W, o, nP);
+    const int nchunk = (int)nblk((size_t)o, 256);
+    hipLaunchKernelGGL(k_assemble3, dim3(3 * nchunk, 3 * o, nP), dim3(256), 0, st, g, W, o, nP, nchunk);
     return hipGetLastError();
 }
 
