@@ -29,6 +29,8 @@ if ROOT not in sys.path:
 
 METRIC = "excited-state grads+NACs/s at 200 atoms; p50/p99 latency; vs plain FP64"
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 (matrix)
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 (matrix)
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the lower-tile Gamma back-transform GEMM from the
 # FETCH_SIZE / WRITE_SIZE counter runs on the 199-atom workload (fetch scaled by
@@ -331,9 +333,21 @@ def main():
         same = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == GAMMA_TRAFFIC["gemm_src_sha256"]
         traffic = GAMMA_TRAFFIC["bytes_per_launch"] if (same and args.workload == GAMMA_TRAFFIC["workload"]
                                                         and args.precision == "fp64") else None
-        roof = {"bound": "mfma", "kernel": "k_gemm<0,false,true,*> lower tiles (Gamma^P = (F_I W^P) F_J^T, batched over P)",
-                "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+        # each precision is priced against the matrix-core peak of the type it
+        # multiplies in; the split-BF16 product runs three BF16 GEMMs per
+        # useful product, so its achieved rate counts all three
+        kern, peak = {
+            "fp64": ("k_gemm<0,false,true,*> lower tiles, f64 (Gamma^P = (F_I W^P) F_J^T, batched over P)",
+                     PEAK_FP64_TFLOPS),
+            "fp32": ("k_gemm<1,false,true,*,float,float,double> lower tiles, f32 inputs "
+                     "(Gamma^P = (F_I W^P) F_J^T, batched over P)", PEAK_FP32_TFLOPS),
+            "bf16x3": ("k_bgemm3 full tiles, three bf16 products (Gamma^P = (F_I W^P) F_J^T, batched over P)",
+                       PEAK_BF16_TFLOPS)}[args.precision]
+        if args.precision == "bf16x3":
+            ach *= 3.0
+        roof = {"bound": "mfma", "kernel": kern,
+                "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": traffic,
                 "flops_per_launch": gfl / gn, "avg_launch_ms": gms / gn,
                 "algorithmic_bytes_per_launch": gby / gn}
 

@@ -398,7 +398,7 @@ int vpq_splits(int nK)
 }
 struct ContractWs {
     size_t oR, oL, oRLT, oF, oD, otT, ocv, oTall, oHUO, oHOU, oHUU, oW, oHc, oY, oG, oV2, oSK, op3, op2, oshA, oshC,
-        oshP, total;
+        oshP, oFf, oWf, total;
 };
 ContractWs contract_ws(const Dims &d, int ns)
 {
@@ -421,6 +421,9 @@ ContractWs contract_ws(const Dims &d, int ns)
     L.oW = cv.take((size_t)d.nK * o3 * o3);
     L.oHc = cv.take((size_t)d.nK * o3 * o3);
     L.oY = cv.take((size_t)d.nK * d.N * o3);
+    // FP32 copies of F_s and W^P for the FP32 mode (float elements, two per slot)
+    L.oFf = cv.take(((size_t)ns * d.N * o3 + 1) / 2);
+    L.oWf = cv.take(((size_t)d.nK * o3 * o3 + 1) / 2);
     L.oG = cv.take((size_t)NO * d.nK * NN);
     L.oV2 = cv.take((size_t)NO * d.nJ * d.nJ);
     L.oSK = cv.take(std::max((size_t)kSplitV * ns * d.nJ, (size_t)vpq_splits(d.nK) * d.nK * d.nK));
@@ -1259,6 +1262,10 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
            *cvec = P_(CW.ocv), *Tall = P_(CW.oTall), *HUO = P_(CW.oHUO), *HOU = P_(CW.oHOU), *HUU = P_(CW.oHUU),
            *W = P_(CW.oW), *Hc = P_(CW.oHc), *Y3 = P_(CW.oY), *G = P_(CW.oG), *V2 = P_(CW.oV2), *SK = P_(CW.oSK),
            *p3 = P_(CW.op3), *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP);
+    // FP32 mode: F, W and Y stored as float for the two products that build Gamma
+    // (their FP32 kernel rounds the operands to FP32 anyway: same results)
+    const bool f32 = c->prec == RIS_FP32;
+    float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf), *Y3f = (float *)Y3;
     const double *CO = c->C, *CV = c->C + o;
 
     // ---- per-state intermediates
@@ -1278,6 +1285,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         for (int s = 0; s < ns; ++s)
             HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + 2 * o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
                                        hipMemcpyDeviceToDevice, c->stream));
+        if (f32) HIPCHK(c, to_float(F, Ff, (size_t)ns * N * o3, c->stream));
         // D_s = sym(U_Rs C_O^T) = R^S_s
         g = gm(N, N, o, false, true, 1.0, F, o3, CO, nmo, 0.0, D, N);
         g.batch = ns; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
@@ -1348,7 +1356,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             gw.b[1][0][0] = none;           gw.b[1][1][0] = sc(Hoo, 0.25);   gw.b[1][2][0] = sc(HLou, -0.25);
             gw.b[2][0][0] = sc(HRuo, 0.25); gw.b[2][1][0] = sc(HLuo, -0.25); gw.b[2][2][0] = sc(HRuu, 0.25);
             gw.b[2][2][1] = sc(HLuu, 0.25);
-            HIPCHK(c, assemble3(gw, W, o, nK, c->stream));
+            HIPCHK(c, assemble3(gw, W, o, nK, c->stream, f32 ? Wf : nullptr));
             // H^P = F_I^T C^P F_J over the blocks where W is nonzero
             BlockGrid gh{};
             gh.b[0][0][0] = HRuu; gh.b[0][2][0] = HRuo;
@@ -1367,6 +1375,12 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             // Y^P = F_I W^P ; Gamma^P = -2 c_x Y^P F_J^T
             GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, F + (size_t)I * N * o3, o3, W, o3, 0.0, Y3, o3);
             g.batch = nK; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
+            if (f32) {
+                g.A = (const double *)(Ff + (size_t)I * N * o3);
+                g.B = (const double *)Wf;
+                g.C = (double *)Y3f;
+                g.ftypes = kF32A | kF32B | kF32C;
+            }
             hipEvent_t t_y = stage_begin(c);
             HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nK * N * o3 * o3, 0.0);
@@ -1377,12 +1391,20 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             // -c_x (Y F_J^T + F_J Y^T) as two lower-tile products
             const bool lowt = c->prec != RIS_BF16X3;
             // one timed group per GEMM launch; a lower-tile launch does
-            // nK N (N + 1) 3o flops and moves Y, F_J and the lower half of Gamma
+            // nK N (N + 1) 3o flops and moves Y, F_J (float in the FP32 mode)
+            // and the lower half of Gamma (always double)
             const double fl_low = (double)nK * N * (N + 1) * o3;
-            const double by_low = 8.0 * ((double)nK * N * o3 + (double)N * o3 + (double)nK * N * (N + 1) / 2);
+            const double ein = f32 ? 4.0 : 8.0;
+            const double by_low = ein * ((double)nK * N * o3 + (double)N * o3) + 8.0 * (double)nK * N * (N + 1) / 2;
+            const float *FJf = Ff + (size_t)J * N * o3;
             if (I == J || !lowt) {
                 g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
                 g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = lowt;
+                if (f32) {
+                    g.A = (const double *)Y3f;
+                    g.B = (const double *)FJf;
+                    g.ftypes = kF32A | kF32B;
+                }
                 hipEvent_t t_g = stage_begin(c);
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
                 if (lowt) stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
@@ -1392,11 +1414,21 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             } else {
                 g = gm(N, N, (int)o3, false, true, -c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
                 g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
+                if (f32) {
+                    g.A = (const double *)Y3f;
+                    g.B = (const double *)FJf;
+                    g.ftypes = kF32A | kF32B;
+                }
                 hipEvent_t t_g = stage_begin(c);
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
                 stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
                 g = gm(N, N, (int)o3, false, true, -c->cx, FJ, o3, Y3, o3, 1.0, Gk, N);
                 g.batch = nK; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
+                if (f32) {
+                    g.A = (const double *)FJf;
+                    g.B = (const double *)Y3f;
+                    g.ftypes = kF32A | kF32B;
+                }
                 t_g = stage_begin(c);
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
                 // the accumulating launch also reads the lower half of Gamma

@@ -96,7 +96,11 @@ struct GemmArgs {
     long ldc, strideC;
     int batch, nred;
     bool lower;  // M == N: compute only the 128 x 128 tiles on or below the diagonal
+    // bits kF32A / kF32B / kF32C: that operand is stored as float (FP32 mode only;
+    // supported: A, B, C float with no transposes, or A, B float with B transposed)
+    int ftypes;
 };
+constexpr int kF32A = 1, kF32B = 2, kF32C = 4;
 hipError_t dgemm(const GemmArgs &g, hipStream_t st);
 // Same product with K cut into nsplit ranges (batch == 1, nred == 1): partials
 // go to ws (nsplit * M * N doubles) and are summed in a fixed order.

@@ -59,9 +59,11 @@ __device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool l
 }
 
 // element at a uniform base plus a 32-bit element offset (byte offset < 2^32)
-__device__ __forceinline__ double ld_off(const double *base, int off)
+template <typename E>
+__device__ __forceinline__ double ld_off(const E *base, int off)
 {
-    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + ((unsigned)off << 3));
+    return (double)*reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) +
+                                                ((unsigned)off * (unsigned)sizeof(E)));
 }
 
 // Matrix-core flavours of the one kernel below:
@@ -98,10 +100,13 @@ template <> struct MfmaCfg<1> {
 // alpha scales the A slabs on their way to LDS and, unless BETA, the
 // accumulators are stored as they are (arithmetic on them in the epilogue
 // makes the compiler stage all of them through registers at once).
-template <int MODE, bool TA, bool TB, bool BETA>
+//
+// EA, EB, EC: element types of A, B and C in memory (double, or float for the
+// FP32 flavour's intermediates, which it rounds to FP32 anyway).
+template <int MODE, bool TA, bool TB, bool BETA, typename EA = double, typename EB = double, typename EC = double>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm(
-    int M, int N, int K, double alpha, const double *__restrict__ A, long lda, long sA, long sAr,
-    const double *__restrict__ B, long ldb, long sB, long sBr, double beta, double *__restrict__ C, long ldc, long sC,
+    int M, int N, int K, double alpha, const EA *__restrict__ A, long lda, long sA, long sAr,
+    const EB *__restrict__ B, long ldb, long sB, long sBr, double beta, EC *__restrict__ C, long ldc, long sC,
     int nred, int tm, int tn, int total, int kc, bool lower)
 {
     typedef MfmaCfg<MODE> Cfg;
@@ -167,8 +172,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int r = it / ktiles;
         const int k0 = kbeg + (it % ktiles) * SK;
         // panel bases: k-fast operands start at row m0 / n0, the others at row k0
-        const double *pA = A + (long)r * sAr + (TA ? (long)k0 * lda + m0 : (long)m0 * lda);
-        const double *pB = B + (long)r * sBr + (TB ? (long)n0 * ldb : (long)k0 * ldb + n0);
+        const EA *pA = A + (long)r * sAr + (TA ? (long)k0 * lda + m0 : (long)m0 * lda);
+        const EB *pB = B + (long)r * sBr + (TB ? (long)n0 * ldb : (long)k0 * ldb + n0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             if (!TA) {
@@ -260,9 +265,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int e = 0; e < 4; ++e) {
                 const int row = m0 + wm * 64 + i * 16 + Cfg::row(lane, e);
                 if (row < M && col < N) {
-                    double *cp = C + (long)row * ldc + col;
-                    if constexpr (BETA) *cp = (double)acc[i][j][e] + beta * *cp;
-                    else *cp = (double)acc[i][j][e];
+                    EC *cp = C + (long)row * ldc + col;
+                    if constexpr (BETA) *cp = (EC)((double)acc[i][j][e] + beta * (double)*cp);
+                    else *cp = (EC)acc[i][j][e];
                 }
             }
         }
@@ -284,6 +289,30 @@ hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st)
     const long spanA = g.transA ? (SKm - 1) * g.lda + g.M : (BM - 1) * g.lda + g.K;
     const long spanB = g.transB ? (BN - 1) * g.ldb + g.K : (SKm - 1) * g.ldb + g.N;
     if (8 * std::max(spanA, spanB) >= (1L << 32)) return hipErrorInvalidValue;
+    if (g.ftypes != 0) {
+        // FP32-stored operands: the two products that build Gamma in the FP32 mode
+        const int nred0 = g.nred > 0 ? g.nred : 1;
+        dim3 grid0((unsigned)total);
+        if (mode != 1 || kc > 0) return hipErrorInvalidValue;
+        if (g.ftypes == (kF32A | kF32B | kF32C) && !g.transA && !g.transB && g.beta == 0.0)
+            hipLaunchKernelGGL((k_gemm<1, false, false, false, float, float, float>), grid0, dim3(256), 0, st, g.M, g.N,
+                               g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
+                               g.strideB, g.strideBr, g.beta, (float *)g.C, g.ldc, g.strideC, nred0, tm, tn, (int)total,
+                               kc, g.lower);
+        else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB && g.beta == 0.0)
+            hipLaunchKernelGGL((k_gemm<1, false, true, false, float, float, double>), grid0, dim3(256), 0, st, g.M, g.N,
+                               g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
+                               g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred0, tm, tn, (int)total, kc,
+                               g.lower);
+        else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB)
+            hipLaunchKernelGGL((k_gemm<1, false, true, true, float, float, double>), grid0, dim3(256), 0, st, g.M, g.N,
+                               g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
+                               g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred0, tm, tn, (int)total, kc,
+                               g.lower);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     dim3 grid((unsigned)total);
     const int nred = g.nred > 0 ? g.nred : 1;
 #define RIS_GEMM_LAUNCH1(MODE, TA, TB, BETA)                                                                     \

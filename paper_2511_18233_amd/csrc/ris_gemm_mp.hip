@@ -186,6 +186,7 @@ __global__ __launch_bounds__(256) void k_bgemm3(int M, int N, int K, double alph
 hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st)
 {
     if (mode == 0 || mode == 1) return gemm_kc(g, mode, 0, st);
+    if (g.ftypes) return hipErrorInvalidValue;  // FP32-stored operands: FP32 kernel only
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (g.lower) return hipErrorInvalidValue;  // lower-tile mode: FP64 / FP32 kernel only
     const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;

@@ -186,7 +186,7 @@ __global__ void k_axpby(const double *__restrict__ src, double *__restrict__ dst
 //   src[P][i][j] = base[P * sP + i * si + j * sj] * scale   (base null = 0).
 // grid: (3 column blocks x chunks of 256 columns, 3o rows, nP); the column
 // block, hence the source descriptors, is uniform per workgroup
-__global__ void k_assemble3(BlockGrid g, double *__restrict__ W, int o, int nP, int nchunk)
+__global__ void k_assemble3(BlockGrid g, double *__restrict__ W, float *__restrict__ Wf, int o, int nP, int nchunk)
 {
     const int n3 = 3 * o;
     const int bj = blockIdx.x / nchunk;
@@ -200,7 +200,15 @@ __global__ void k_assemble3(BlockGrid g, double *__restrict__ W, int o, int nP, 
         const BlockSrc b = g.b[bi][bj][t];
         if (b.base) v += b.scale * b.base[P * b.sP + (long)i * b.si + (long)j * b.sj];
     }
-    W[((long)P * n3 + row) * n3 + bj * o + j] = v;
+    const long at = ((long)P * n3 + row) * n3 + bj * o + j;
+    W[at] = v;
+    if (Wf) Wf[at] = (float)v;
+}
+
+__global__ void k_to_float(const double *__restrict__ x, float *__restrict__ y, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
 }
 
 // out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] (+ beta * out) over n0 x n1 x n2
@@ -366,11 +374,18 @@ hipError_t axpby(const double *src, double *dst, size_t n, double alpha, double 
     return hipGetLastError();
 }
 
-hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st)
+hipError_t to_float(const double *x, float *y, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_float, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st, float *Wf)
 {
     if (o <= 0 || nP <= 0) return hipSuccess;
     const int nchunk = (int)nblk((size_t)o, 256);
-    hipLaunchKernelGGL(k_assemble3, dim3(3 * nchunk, 3 * o, nP), dim3(256), 0, st, g, W, o, nP, nchunk);
+    hipLaunchKernelGGL(k_assemble3, dim3(3 * nchunk, 3 * o, nP), dim3(256), 0, st, g, W, Wf, o, nP, nchunk);
     return hipGetLastError();
 }
 

@@ -23,7 +23,10 @@ struct BlockSrc {
 struct BlockGrid {
     BlockSrc b[3][3][2];  // up to two summed sources per block; base == nullptr means none
 };
-hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st);
+// Wf (may be null) receives a float copy of W in the same pass.
+hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st, float *Wf = nullptr);
+// y = (float)x elementwise
+hipError_t to_float(const double *x, float *y, size_t n, hipStream_t st);
 // out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] + beta * out over n0 x n1 x n2
 hipError_t permute3(const double *in, double *out, int n0, int n1, int n2, long s0, long s1, long s2, long o0,
                     long o1, long o2, hipStream_t st, double alpha = 1.0, double beta = 0.0);
