@@ -126,6 +126,16 @@ size_t ris_ctx_bytes(const ris_ctx *ctx);
 size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int nocc, int nstate, int nvec,
                          int nout);
 
+/* The same sizing for the blocked path (ris_ctx_set_blocking): the peak
+ * device bytes when the auxiliary functions are taken in blocks of at most
+ * aux_block (at least one whole shell for the integrals) and the matvec
+ * exchange terms one vector at a time; aux_block = 0 gives the unblocked
+ * sizing of ris_request_bytes.  A context whose budget holds this many bytes
+ * completes the request: the calls fall back to blocks of this size or larger
+ * when the unblocked scratch does not fit.  Host-only; 0 for invalid input. */
+size_t ris_plan_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int nocc, int nstate, int nvec,
+                      int nout, int aux_block);
+
 /* Instrumented stages of the path (for ris_ctx_stage_stats). */
 enum ris_stage {
     RIS_STAGE_INT3C = 0,   /* (mu nu|P) integral kernels of ris_int3c */
@@ -205,6 +215,19 @@ int ris_tda_davidson(ris_ctx *ctx, int nroots, double tol, int maxit, int max_sp
  * kept_pairs (may be NULL) receives the number of ordered shell pairs kept,
  * or -1 before the first ris_aux_build.  RIS_E_INVALID unless 0 <= threshold < 1. */
 int ris_ctx_set_screening(ris_ctx *ctx, double threshold, long *kept_pairs);
+
+/* Memory blocking over the auxiliary index (the paper batches its
+ * density-fitting tensors along the AO or auxiliary dimension, Sec. 3; the
+ * block sizes here are an implementation choice).  aux_block > 0 caps the
+ * auxiliary functions per block: ris_int3c computes (mu nu|P) and its MO
+ * transforms one block of whole J shells at a time (at least one shell), and
+ * the gradient / NAC calls take the exchange (K) functions in blocks of at most
+ * aux_block, one output at a time.  0 (default): the unblocked path whenever
+ * its scratch fits the HBM budget, else the largest blocks that fit.  The
+ * results agree with the unblocked path to rounding (only the order of the
+ * metric-weight sums changes).  Takes effect from the next call.
+ * RIS_E_INVALID if aux_block < 0. */
+int ris_ctx_set_blocking(ris_ctx *ctx, int aux_block);
 
 /* Turn per-stage timing on (1) or off (0); either way the counters reset.
  * When on, each instrumented launch group is bracketed by HIP events on the

@@ -68,8 +68,8 @@ struct ris_ctx {
     double *coo = nullptr;   // [nK][o][o]  c^P_ij = sum_Q (M_K^-1)_PQ (ij|Q)
     double *cvo = nullptr;   // [v][nK][o]  c^P_aj
     double *cvv = nullptr;   // [v][nK][v]  c^P_ab
-    double *rvv = nullptr;   // [v][nK][v]  raw (ab|P), exchange set
-    double *rvo2 = nullptr;  // [v][o][nK]  raw (aj|P), exchange set
+    double *roo = nullptr;   // [nK][o][o]  raw (ij|P), exchange set
+    int ablock = 0;          // auxiliary functions per block (0: as many as fit)
 
     // ---- grow-only device regions; after warm-up a request of the same or a
     // smaller size allocates nothing (hipFree would synchronise the device)
@@ -186,7 +186,7 @@ struct Carve {
 void free_int3c(ris_ctx *c)
 {
     c->have_int3c = false;
-    c->C = c->eps = c->aiJ = c->coo = c->cvo = c->cvv = c->rvv = c->rvo2 = nullptr;
+    c->C = c->eps = c->aiJ = c->coo = c->cvo = c->cvv = c->roo = nullptr;
 }
 
 void free_aux(ris_ctx *c)
@@ -325,7 +325,7 @@ struct Dims {
 };
 
 struct MoLayout {
-    size_t oC, oE, oA, oOO, oVO, oVV, oRVV, oRVO, total;
+    size_t oC, oE, oA, oOO, oVO, oVV, oROO, total;
 };
 MoLayout mo_layout(const Dims &d)
 {
@@ -338,25 +338,23 @@ MoLayout mo_layout(const Dims &d)
     L.oOO = pv.take((size_t)d.nK * d.o * d.o);
     L.oVO = pv.take((size_t)d.nK * vo);
     L.oVV = pv.take((size_t)d.nK * d.v * d.v);
-    L.oRVV = pv.take((size_t)d.nK * d.v * d.v);
-    L.oRVO = pv.take((size_t)d.nK * vo);
+    L.oROO = pv.take((size_t)d.nK * d.o * d.o);
     L.total = pv.off;
     return L;
 }
 
+// (mu nu|P) of one block of nb auxiliary functions and its half-transformed
+// Z; after the blocks the same region serves the M_K^-1 fits by rows a.
 struct Int3cWs {
-    size_t oX, oZ, oOO, oVO, total;
+    size_t oX, oZ, total;
 };
-Int3cWs int3c_ws(const Dims &d)
+Int3cWs int3c_ws(const Dims &d, int nb)
 {
     Carve cv;
     Int3cWs L;
     const size_t NN = (size_t)d.N * d.N;
-    const size_t zel = std::max((size_t)d.nJ * d.N * d.o, (size_t)d.nK * d.N * d.v);
-    L.oX = cv.take((size_t)d.nJ * NN);
-    L.oZ = cv.take(zel);
-    L.oOO = cv.take((size_t)d.nK * d.o * d.o);
-    L.oVO = cv.take((size_t)d.nK * d.v * d.o);
+    L.oX = cv.take((size_t)nb * NN);
+    L.oZ = cv.take((size_t)nb * d.N * std::max(d.o, d.v));
     L.total = cv.off;
     return L;
 }
@@ -371,11 +369,11 @@ int matvec_u_splits(const Dims &d, int chunk)
     return balanced_splits((long)((d.v + 127) / 128) * ((chunk * d.o + 127) / 128), 8);
 }
 
-MatvecWs matvec_ws(const Dims &d, int nvec)
+MatvecWs matvec_ws(const Dims &d, int nvec, int chunk = kMatvecChunk)
 {
     Carve cv;
     MatvecWs L;
-    const int chunk = std::min(nvec, kMatvecChunk);
+    chunk = std::max(1, std::min(nvec, chunk));
     const long vo = (long)d.v * d.o, oo = (long)d.o * d.o;
     L.ot = cv.take((size_t)nvec * d.nJ * 2);
     L.oT = cv.take((size_t)chunk * d.nK * std::max(vo, oo));  // T (exchange A) or S (exchange B)
@@ -432,6 +430,50 @@ ContractWs contract_ws(const Dims &d, int ns)
     L.oshA = cv.take((size_t)d.nshAO * NO * 3);
     L.oshC = cv.take((size_t)d.nshJ * NO * 3);
     L.oshP = cv.take((size_t)d.nshJ * NO * 3);
+    L.total = cv.off;
+    return L;
+}
+
+// Scratch of the contraction blocked over the exchange (K) functions: the
+// per-state factors, per output the H_OU blocks of its two states for all P,
+// and per block of nb functions Tall, H_UU, W (+ float copy), Y and Gamma.
+struct ContractBlkWs {
+    size_t oR, oL, oRLT, oF, oFf, oD, otT, ocv, oHI0, oHI1, oHJ0, oHJ1, oTR, oG1, oV2, oSK, op3, op2, oshA, oshC, oshP,
+        oTall, oHUU, oW, oWf, oY, oG, total;
+};
+ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
+{
+    Carve cv;
+    ContractBlkWs L;
+    const long vo = (long)d.v * d.o, NN = (long)d.N * d.N, o3 = 3L * d.o, oo = (long)d.o * d.o;
+    const long w2 = 2L * ns * d.o;
+    L.oR = cv.take((size_t)ns * vo);
+    L.oL = cv.take((size_t)ns * vo);
+    L.oRLT = cv.take((size_t)d.v * w2);
+    L.oF = cv.take((size_t)ns * d.N * o3);
+    L.oFf = cv.take(((size_t)ns * d.N * o3 + 1) / 2);
+    L.oD = cv.take((size_t)ns * NN);
+    L.otT = cv.take((size_t)ns * d.nJ);
+    L.ocv = cv.take((size_t)ns * d.nJ);
+    L.oHI0 = cv.take((size_t)d.nK * oo);
+    L.oHI1 = cv.take((size_t)d.nK * oo);
+    L.oHJ0 = cv.take((size_t)d.nK * oo);
+    L.oHJ1 = cv.take((size_t)d.nK * oo);
+    L.oTR = cv.take((size_t)d.nK * oo);
+    L.oG1 = cv.take((size_t)d.nK * d.nK);
+    L.oV2 = cv.take((size_t)d.nJ * d.nJ);
+    L.oSK = cv.take(std::max((size_t)kSplitV * ns * d.nJ, (size_t)vpq_splits(d.nK) * d.nK * d.nK));
+    L.op3 = cv.take((size_t)d.nshAO * d.nshJ * 3 * kMaxOutChunk * 6);
+    L.op2 = cv.take((size_t)d.nshJ * 2 * kMaxOutChunk * 3);
+    L.oshA = cv.take((size_t)d.nshAO * kMaxOutChunk * 3);
+    L.oshC = cv.take((size_t)d.nshJ * kMaxOutChunk * 3);
+    L.oshP = cv.take((size_t)d.nshJ * kMaxOutChunk * 3);
+    L.oTall = cv.take((size_t)nb * d.v * 2 * d.o);
+    L.oHUU = cv.take((size_t)2 * nb * oo);
+    L.oW = cv.take((size_t)nb * o3 * o3);
+    L.oWf = cv.take(((size_t)nb * o3 * o3 + 1) / 2);
+    L.oY = cv.take((size_t)nb * d.N * o3);
+    L.oG = cv.take((size_t)nb * NN);
     L.total = cv.off;
     return L;
 }
@@ -510,10 +552,10 @@ void ris_ctx_destroy(ris_ctx *c)
     delete c;
 }
 
-size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int nocc, int nstate, int nvec,
-                         int nout)
+size_t ris_plan_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int nocc, int nstate, int nvec, int nout,
+                      int aux_block)
 {
-    if (!mol || !opts || mol->natm <= 0 || mol->nshell <= 0 || nocc <= 0 || nmo <= nocc) return 0;
+    if (!mol || !opts || mol->natm <= 0 || mol->nshell <= 0 || nocc <= 0 || nmo <= nocc || aux_block < 0) return 0;
     int nao = 0, nheavy = 0;
     for (int s = 0; s < mol->nshell; ++s) nao += ncart(mol->shell_l[s]);
     for (int a = 0; a < mol->natm; ++a) nheavy += (mol->Z[a] > 1);
@@ -521,12 +563,26 @@ size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, 
     const int nshJ = natm + (opts->j_p_on_heavy ? nheavy : 0);
     const int nJ = natm + (opts->j_p_on_heavy ? 3 * nheavy : 0);
     const Dims d{nao, nmo, nocc, nmo - nocc, nJ, natm, mol->shell_l ? mol->nshell : 0, nshJ, natm};
-    size_t ws = int3c_ws(d).total;
-    if (nvec > 0) ws = std::max(ws, matvec_ws(d, nvec).total);
-    if (nstate > 0) ws = std::max(ws, contract_ws(d, nstate).total);
+    size_t ws;
+    if (aux_block == 0) {
+        ws = int3c_ws(d, d.nJ).total;
+        if (nvec > 0) ws = std::max(ws, matvec_ws(d, nvec).total);
+        if (nstate > 0) ws = std::max(ws, contract_ws(d, nstate).total);
+    } else {
+        ws = int3c_ws(d, std::max(3, std::min(aux_block, d.nJ))).total;
+        if (nvec > 0) ws = std::max(ws, matvec_ws(d, nvec, 1).total);
+        if (nstate > 0) ws = std::max(ws, contract_blk_ws(d, nstate, std::min(aux_block, d.nK)).total);
+    }
+    ws = std::max(ws, sizeof(double) * (size_t)kTriBlock * nJ);  // metric inverse in ris_aux_build
     const size_t fixed = (size_t)8 * kBoysNGrid * kBoysCols + 64;
     return fixed + aux_layout(mol->nshell, nshJ, nao, nJ, natm).total + mo_layout(d).total + ws +
            (size_t)8 * std::max(nout, 0) * natm * 3;
+}
+
+size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int nocc, int nstate, int nvec,
+                         int nout)
+{
+    return ris_plan_bytes(mol, opts, nmo, nocc, nstate, nvec, nout, 0);
 }
 
 int ris_zvector_solve(ris_ctx *c, int nrhs, const double *rhs, double *Z, double tol, int maxit, int *iters,
@@ -869,6 +925,15 @@ int ris_ctx_set_screening(ris_ctx *c, double threshold, long *kept_pairs)
     return RIS_OK;
 }
 
+int ris_ctx_set_blocking(ris_ctx *c, int aux_block)
+{
+    if (!c) return RIS_E_INVALID;
+    c->err.clear();
+    if (aux_block < 0) return fail(c, RIS_E_INVALID, "aux_block must be >= 0");
+    c->ablock = aux_block;
+    return RIS_OK;
+}
+
 int ris_ctx_set_profiling(ris_ctx *c, int enable)
 {
     if (!c) return RIS_E_INVALID;
@@ -1088,8 +1153,15 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
 
     const Dims dm = ctx_dims(c);
     const MoLayout ML = mo_layout(dm);
-    const Int3cWs IW = int3c_ws(dm);
+    // auxiliary functions per block: all of them when they fit, else the most
+    // that fit beside the kept MO blocks (whole shells, at most 3 functions)
     const size_t other = c->held - c->mo_pool.bytes - c->ws_bytes;  // what stays allocated meanwhile
+    const size_t room = c->budget > other + ML.total ? c->budget - other - ML.total : 0;
+    const size_t wsroom = std::max(room, c->ws_bytes);
+    int nbf = nJ;
+    while (nbf > 3 && int3c_ws(dm, nbf).total > wsroom) nbf = std::max(3, (int)(nbf * 0.8));
+    if (c->ablock > 0) nbf = std::min(nbf, std::max(3, c->ablock));
+    const Int3cWs IW = int3c_ws(dm, nbf);
     if (other + ML.total + std::max(IW.total, c->ws_bytes) > c->budget)
         return fail(c, RIS_E_NOMEM, "int3c needs %.2f GB (persistent %.2f GB); budget %.2f GB, %.2f GB held",
                     (ML.total + IW.total) / 1e9, ML.total / 1e9, c->budget / 1e9, other / 1e9);
@@ -1103,61 +1175,88 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
         c->coo = (double *)(pb + ML.oOO);
         c->cvo = (double *)(pb + ML.oVO);
         c->cvv = (double *)(pb + ML.oVV);
-        c->rvv = (double *)(pb + ML.oRVV);
-        c->rvo2 = (double *)(pb + ML.oRVO);
+        c->roo = (double *)(pb + ML.oROO);
     }
     char *wsb = ws_get(c, IW.total, &st);
     if (!wsb) return st;
-    double *X = (double *)(wsb + IW.oX), *Z = (double *)(wsb + IW.oZ), *rawoo = (double *)(wsb + IW.oOO),
-           *rvoP = (double *)(wsb + IW.oVO);
+    double *X = (double *)(wsb + IW.oX), *Z = (double *)(wsb + IW.oZ);
+    const size_t tmp_el = IW.total / 8;  // the whole region as scratch for the fits
 
     // C rows into the internal (l-sorted) AO order
     HIPCHK(c, gather_rows(mo->C, c->C, c->d_ao_perm, N, nmo, nmo, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->eps, mo->eps, 8 * nmo, hipMemcpyDeviceToDevice, c->stream));
 
-    // (mu nu|P)
-    hipEvent_t t_int = stage_begin(c);
-    HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, X, c->stream));
-    stage_end(c, t_int, RIS_STAGE_INT3C, 0.0, 8.0 * (double)nJ * NN);
-    if (dbg) HIPCHK(c, scatter_sq(X, dbg, c->d_ao_perm, N, nJ, c->stream));
-    hipEvent_t t_mo = stage_begin(c);
-
     const double *CO = c->C, *CV = c->C + o;
-    // Z^P = X^P C_O  [nJ][N][o]
-    GemmArgs g = gm(N, o, N, false, false, 1.0, X, N, CO, nmo, 0.0, Z, o);
-    g.batch = nJ; g.strideA = NN; g.strideB = 0; g.strideC = (long)N * o;
-    HIPCHK(c, dgemm(g, c->stream));
-    // (ai|P) = C_V^T Z^P  [nJ][v][o]
-    g = gm(v, o, N, true, false, 1.0, CV, nmo, Z, o, 0.0, c->aiJ, o);
-    g.batch = nJ; g.strideA = 0; g.strideB = (long)N * o; g.strideC = vo;
-    HIPCHK(c, dgemm(g, c->stream));
-    // (ij|P) = C_O^T Z^P for the exchange set, then c_oo = M_K^-1 (ij|.)
-    g = gm(o, o, N, true, false, 1.0, CO, nmo, Z, o, 0.0, rawoo, o);
-    g.batch = nK; g.strideA = 0; g.strideB = (long)N * o; g.strideC = (long)o * o;
-    HIPCHK(c, dgemm(g, c->stream));
-    HIPCHK(c, dgemm(gm(nK, o * o, nK, false, false, 1.0, c->MinvK, nK, rawoo, (long)o * o, 0.0, c->coo, (long)o * o),
-                    c->stream));
-    // (ab|P) = C_V^T (X^P C_V) written as [a][P][b]; c_vv[a] = M_K^-1 (a.|.)
-    g = gm(N, v, N, false, false, 1.0, X, N, CV, nmo, 0.0, Z, v);
-    g.batch = nK; g.strideA = NN; g.strideB = 0; g.strideC = (long)N * v;
-    HIPCHK(c, dgemm(g, c->stream));
-    g = gm(v, v, N, true, false, 1.0, CV, nmo, Z, v, 0.0, c->rvv, (long)nK * v);
-    g.batch = nK; g.strideA = 0; g.strideB = (long)N * v; g.strideC = v;
-    HIPCHK(c, dgemm(g, c->stream));
-    g = gm(nK, v, nK, false, false, 1.0, c->MinvK, nK, c->rvv, v, 0.0, c->cvv, v);
-    g.batch = v; g.strideA = 0; g.strideB = (long)nK * v; g.strideC = (long)nK * v;
-    HIPCHK(c, dgemm(g, c->stream));
-    // (aj|P) of the exchange set as [a][P][j] -> c_vo ; and as [a][j][P]
-    HIPCHK(c, permute3(c->aiJ, rvoP, v, nK, o, o, vo, 1, (long)nK * o, o, 1, c->stream));
-    g = gm(nK, o, nK, false, false, 1.0, c->MinvK, nK, rvoP, o, 0.0, c->cvo, o);
-    g.batch = v; g.strideA = 0; g.strideB = (long)nK * o; g.strideC = (long)nK * o;
-    HIPCHK(c, dgemm(g, c->stream));
-    HIPCHK(c, permute3(c->aiJ, c->rvo2, v, o, nK, o, 1, vo, (long)o * nK, nK, 1, c->stream));
-    stage_end(c, t_mo, RIS_STAGE_MO,
-              2.0 * nJ * ((double)N * N * o + (double)N * v * o) +
-                  2.0 * nK * ((double)N * o * o + (double)N * N * v + (double)N * v * v) +
-                  2.0 * (double)nK * nK * ((double)o * o + (double)v * o + (double)v * v),
-              0.0);
+    const long oo = (long)o * o;
+    // blocks of whole J shells [cs0, cs1) = functions [f0, f1); the K set is
+    // the leading nK (s) functions, so a block holds K functions only below nK
+    std::vector<int> shf(c->nshJ + 1, 0);
+    for (int sh = 0; sh < c->nshJ; ++sh) shf[sh + 1] = shf[sh] + (sh < c->auxl_beg[1] ? 1 : 3);
+    for (int cs0 = 0; cs0 < c->nshJ;) {
+        int cs1 = cs0;
+        while (cs1 < c->nshJ && shf[cs1 + 1] - shf[cs0] <= nbf) ++cs1;
+        const int f0 = shf[cs0], nb = shf[cs1] - f0, nbk = std::max(0, std::min(f0 + nb, nK) - f0);
+        // (mu nu|P) for the block
+        hipEvent_t t_int = stage_begin(c);
+        HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, X, c->stream, cs0, cs1));
+        stage_end(c, t_int, RIS_STAGE_INT3C, 0.0, 8.0 * (double)nb * NN);
+        if (dbg) HIPCHK(c, scatter_sq(X, dbg + (size_t)f0 * NN, c->d_ao_perm, N, nb, c->stream));
+        hipEvent_t t_mo = stage_begin(c);
+        // Z^P = X^P C_O  [nb][N][o]
+        GemmArgs g = gm(N, o, N, false, false, 1.0, X, N, CO, nmo, 0.0, Z, o);
+        g.batch = nb; g.strideA = NN; g.strideB = 0; g.strideC = (long)N * o;
+        HIPCHK(c, dgemm(g, c->stream));
+        // (ai|P) = C_V^T Z^P  [nJ][v][o]
+        g = gm(v, o, N, true, false, 1.0, CV, nmo, Z, o, 0.0, c->aiJ + (size_t)f0 * vo, o);
+        g.batch = nb; g.strideA = 0; g.strideB = (long)N * o; g.strideC = vo;
+        HIPCHK(c, dgemm(g, c->stream));
+        if (nbk > 0) {
+            // raw (ij|P) = C_O^T Z^P of the exchange set  [nK][o][o]
+            g = gm(o, o, N, true, false, 1.0, CO, nmo, Z, o, 0.0, c->roo + (size_t)f0 * oo, o);
+            g.batch = nbk; g.strideA = 0; g.strideB = (long)N * o; g.strideC = oo;
+            HIPCHK(c, dgemm(g, c->stream));
+            // raw (ab|P) = C_V^T (X^P C_V) into the c_vv storage as [a][P][b]
+            g = gm(N, v, N, false, false, 1.0, X, N, CV, nmo, 0.0, Z, v);
+            g.batch = nbk; g.strideA = NN; g.strideB = 0; g.strideC = (long)N * v;
+            HIPCHK(c, dgemm(g, c->stream));
+            g = gm(v, v, N, true, false, 1.0, CV, nmo, Z, v, 0.0, c->cvv + (size_t)f0 * v, (long)nK * v);
+            g.batch = nbk; g.strideA = 0; g.strideB = (long)N * v; g.strideC = v;
+            HIPCHK(c, dgemm(g, c->stream));
+        }
+        stage_end(c, t_mo, RIS_STAGE_MO,
+                  2.0 * nb * ((double)N * N * o + (double)N * v * o) +
+                      2.0 * nbk * ((double)N * o * o + (double)N * N * v + (double)N * v * v),
+                  0.0);
+        cs0 = cs1;
+    }
+    hipEvent_t t_fit = stage_begin(c);
+    double *tmp = (double *)wsb;
+    // c_oo = M_K^-1 (ij|.)
+    HIPCHK(c, dgemm(gm(nK, (int)oo, nK, false, false, 1.0, c->MinvK, nK, c->roo, oo, 0.0, c->coo, oo), c->stream));
+    // c_vv[a] = M_K^-1 (a.|.) in place, rows a in chunks through the scratch
+    {
+        const int ac = (int)std::max<size_t>(1, std::min<size_t>(v, tmp_el / ((size_t)nK * v)));
+        for (int a0 = 0; a0 < v; a0 += ac) {
+            const int na = std::min(ac, v - a0);
+            double *blk = c->cvv + (size_t)a0 * nK * v;
+            GemmArgs g = gm(nK, v, nK, false, false, 1.0, c->MinvK, nK, blk, v, 0.0, tmp, v);
+            g.batch = na; g.strideA = 0; g.strideB = (long)nK * v; g.strideC = (long)nK * v;
+            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, hipMemcpyAsync(blk, tmp, (size_t)na * nK * v * 8, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    // c_vo[a] = M_K^-1 (a.|.) of the exchange set as [a][P][j], rows a in chunks
+    {
+        const int ac = (int)std::max<size_t>(1, std::min<size_t>(v, tmp_el / ((size_t)nK * o)));
+        for (int a0 = 0; a0 < v; a0 += ac) {
+            const int na = std::min(ac, v - a0);
+            HIPCHK(c, permute3(c->aiJ + (size_t)a0 * o, tmp, na, nK, o, o, vo, 1, (long)nK * o, o, 1, c->stream));
+            GemmArgs g = gm(nK, o, nK, false, false, 1.0, c->MinvK, nK, tmp, o, 0.0, c->cvo + (size_t)a0 * nK * o, o);
+            g.batch = na; g.strideA = 0; g.strideB = (long)nK * o; g.strideC = (long)nK * o;
+            HIPCHK(c, dgemm(g, c->stream));
+        }
+    }
+    stage_end(c, t_fit, RIS_STAGE_MO, 2.0 * (double)nK * nK * ((double)o * o + (double)v * o + (double)v * v), 0.0);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_int3c = true;
     return RIS_OK;
@@ -1178,8 +1277,12 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
     const long vo = (long)v * o, oo = (long)o * o;
     // coefficients of Delta, J, K_A, K_B for A, B, A+B, A-B
     static const double cDe[4] = {1, 0, 1, 1}, cJ[4] = {1, 1, 2, 0}, cKA[4] = {1, 0, 1, 1}, cKB[4] = {0, 1, 1, -1};
-    const int chunk = std::min(nvec, kMatvecChunk);
-    const MatvecWs MW = matvec_ws(ctx_dims(c), nvec);
+    // vectors per exchange chunk: as many (up to kMatvecChunk) as the budget allows
+    const size_t other = c->held - c->ws_bytes;
+    const size_t wsroom = std::max(c->budget > other ? c->budget - other : 0, c->ws_bytes);
+    int chunk = std::min(nvec, kMatvecChunk);
+    while (chunk > 1 && matvec_ws(ctx_dims(c), nvec, chunk).total > wsroom) --chunk;
+    const MatvecWs MW = matvec_ws(ctx_dims(c), nvec, chunk);
     int st;
     char *wsb = ws_get(c, MW.total, &st);
     if (!wsb) return st;
@@ -1201,28 +1304,29 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
         const double *Vk = V + (size_t)k0 * vo;
         double *ok = out + (size_t)k0 * vo;
         const long nvo = (long)nv * o;  // columns (k, i) of the chunk
+        // the exchange terms pair the fitted c^P of one index pair with the raw
+        // (pq|P) of the other: sum_PQ (pq|P) (M_K^-1)_PQ (rs|Q) = sum_P c^P_pq (rs|P)
         if (cKA[op] != 0.0) {
-            // T[P][b][k][i] = sum_j V_k[b][j] c_oo^P[i][j]
+            // T[P][b][k][i] = sum_j V_k[b][j] (ij|P)
             for (int k = 0; k < nv; ++k) {
-                GemmArgs g = gm(v, o, o, false, true, 1.0, Vk + k * vo, o, c->coo, o, 0.0, T + (size_t)k * o, nvo);
+                GemmArgs g = gm(v, o, o, false, true, 1.0, Vk + k * vo, o, c->roo, o, 0.0, T + (size_t)k * o, nvo);
                 g.batch = nK; g.strideA = 0; g.strideB = oo; g.strideC = (long)v * nvo;
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
-            // U[a][(k,i)] = sum_{(P,b)} (ab|P) T[(P,b)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
-            HIPCHK(c, gemm_splitk(gm(v, (int)nvo, nK * v, false, false, 1.0, c->rvv, (long)nK * v, T, nvo, 0.0, U, nvo),
+            // U[a][(k,i)] = sum_{(P,b)} c^P_ab T[(P,b)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
+            HIPCHK(c, gemm_splitk(gm(v, (int)nvo, nK * v, false, false, 1.0, c->cvv, (long)nK * v, T, nvo, 0.0, U, nvo),
                                   c->prec, usplit, SKm, c->stream));
             HIPCHK(c, permute3(U, ok, nv, v, o, o, nvo, 1, vo, o, 1, c->stream, -cKA[op] * c->cx, 1.0));
         }
         if (cKB[op] != 0.0) {
-            // S[j][P][k][i] = sum_b V_k[b][j] c_vo^P[b][i]
+            // S[P][j][k][i] = sum_b V_k[b][j] (bi|P)
             for (int k = 0; k < nv; ++k) {
-                GemmArgs g = gm(o, o, v, true, false, 1.0, Vk + k * vo, o, c->cvo, (long)nK * o, 0.0,
-                                T + (size_t)k * o, (long)nK * nvo);
-                g.batch = nK; g.strideA = 0; g.strideB = o; g.strideC = nvo;
+                GemmArgs g = gm(o, o, v, true, false, 1.0, Vk + k * vo, o, c->aiJ, o, 0.0, T + (size_t)k * o, nvo);
+                g.batch = nK; g.strideA = 0; g.strideB = vo; g.strideC = (long)o * nvo;
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
-            // U[a][(k,i)] = sum_{(j,P)} (aj|P) S[(j,P)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
-            HIPCHK(c, gemm_splitk(gm(v, (int)nvo, o * nK, false, false, 1.0, c->rvo2, (long)o * nK, T, nvo, 0.0, U, nvo),
+            // U[a][(k,i)] = sum_{(P,j)} c^P_aj S[(P,j)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
+            HIPCHK(c, gemm_splitk(gm(v, (int)nvo, nK * o, false, false, 1.0, c->cvo, (long)nK * o, T, nvo, 0.0, U, nvo),
                                   c->prec, usplit, SKm, c->stream));
             HIPCHK(c, permute3(U, ok, nv, v, o, o, nvo, 1, vo, o, 1, c->stream, -cKB[op] * c->cx, 1.0));
         }
@@ -1233,6 +1337,243 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
         const double fB = 4.0 * nK * (double)v * o * o;
         stage_end(c, t_mv, RIS_STAGE_MATVEC,
                   nvec * ((cJ[op] != 0 ? fJ : 0.0) + (cKA[op] != 0 ? fA : 0.0) + (cKB[op] != 0 ? fB : 0.0)), 0.0);
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RIS_OK;
+}
+
+// Y^P = F_I W^P and the exchange weights Gamma^P for nP auxiliary functions:
+// Gamma^P = -2 c_x Y^P F_I^T (same state) or -c_x (Y^P F_J^T + F_J Y^P^T);
+// only the lower triangle of each symmetric Gamma^P is formed (and read),
+// except in the split-BF16 mode (full tiles, symmetrised for NACs).  In the
+// FP32 mode the products take the float copies FfI / FfJ / Wf and Y is float.
+static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, const double *FJ, const float *FfI,
+                          const float *FfJ, const double *W, const float *Wf, double *Y3, double *Gk, bool same)
+{
+    const long o3 = 3L * o, NN = (long)N * N;
+    const bool f32 = c->prec == RIS_FP32;
+    float *Y3f = (float *)Y3;
+    GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, FI, o3, W, o3, 0.0, Y3, o3);
+    g.batch = nP; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
+    if (f32) {
+        g.A = (const double *)FfI;
+        g.B = (const double *)Wf;
+        g.C = (double *)Y3f;
+        g.ftypes = kF32A | kF32B | kF32C;
+    }
+    hipEvent_t t_y = stage_begin(c);
+    HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+    stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nP * N * o3 * o3, 0.0);
+    const bool lowt = c->prec != RIS_BF16X3;
+    // one timed group per GEMM launch; a lower-tile launch does
+    // nP N (N + 1) 3o flops and moves Y, F_J (float in the FP32 mode)
+    // and the lower half of Gamma (always double)
+    const double fl_low = (double)nP * N * (N + 1) * o3;
+    const double ein = f32 ? 4.0 : 8.0;
+    const double by_low = ein * ((double)nP * N * o3 + (double)N * o3) + 8.0 * (double)nP * N * (N + 1) / 2;
+    if (same || !lowt) {
+        g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
+        g.batch = nP; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = lowt;
+        if (f32) {
+            g.A = (const double *)Y3f;
+            g.B = (const double *)FfJ;
+            g.ftypes = kF32A | kF32B;
+        }
+        hipEvent_t t_g = stage_begin(c);
+        HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+        if (lowt) stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
+        else
+            stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nP * N * N * o3,
+                      8.0 * ((double)nP * N * N + (double)nP * N * o3 + (double)N * o3));
+    } else {
+        g = gm(N, N, (int)o3, false, true, -c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
+        g.batch = nP; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
+        if (f32) {
+            g.A = (const double *)Y3f;
+            g.B = (const double *)FfJ;
+            g.ftypes = kF32A | kF32B;
+        }
+        hipEvent_t t_g = stage_begin(c);
+        HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+        stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
+        g = gm(N, N, (int)o3, false, true, -c->cx, FJ, o3, Y3, o3, 1.0, Gk, N);
+        g.batch = nP; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
+        if (f32) {
+            g.A = (const double *)FfJ;
+            g.B = (const double *)Y3f;
+            g.ftypes = kF32A | kF32B;
+        }
+        t_g = stage_begin(c);
+        HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+        // the accumulating launch also reads the lower half of Gamma
+        stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low + 8.0 * (double)nP * N * (N + 1) / 2);
+    }
+    if (!same && !lowt) HIPCHK(c, symmetrize(Gk, N, nP, c->stream));
+    return RIS_OK;
+}
+
+// The same contraction with the exchange (K) functions taken in blocks of nb,
+// for problems whose all-P intermediates do not fit: one output at a time, and
+// for each block Tall^P = c_vv^P (R, L)_J, H_UU^P, W^P, Y^P and Gamma^P, then
+// the derivative contraction of the block's auxiliary shells.  The metric
+// weights need all P at once; with W^P and H^P written out in their blocks
+//   V_PQ = sum_kl H^P_kl W^Q_kl = (G + G^T)_PQ / 4,
+//   G_PQ = <H_RUU^P + H_LUU^P, c_oo^Q> + <H_RUO^P, H_ROU^Q> - <H_LUO^P, H_LOU^Q>
+// (<.,.> the elementwise inner product over (i, j)), which needs only the
+// H_OU blocks of the two states over all P and the block's H_UU.
+static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const double *Y, int npair,
+                                  const int *pI, const int *pJ, double *outg, int nb)
+{
+    const int N = c->nao, nmo = c->nmo, o = c->nocc, v = c->nvir, nJ = c->nJ, nK = c->nK, natm = c->natm;
+    const long vo = (long)v * o, NN = (long)N * N, o3 = 3L * o, oo = (long)o * o;
+    const int ns = nstate;
+    const long w2 = 2L * ns * o;
+    const int nsplit = vpq_splits(nK);
+    if (nK > c->auxl_beg[1]) return fail(c, RIS_E_UNSUPPORTED, "exchange set is not a run of leading s shells");
+    const ContractBlkWs CW = contract_blk_ws(ctx_dims(c), ns, nb);
+    int st;
+    char *wsb = ws_get(c, CW.total, &st);
+    if (!wsb) return st;
+    auto P_ = [&](size_t off) { return (double *)(wsb + off); };
+    double *R = P_(CW.oR), *L = P_(CW.oL), *RLT = P_(CW.oRLT), *F = P_(CW.oF), *D = P_(CW.oD), *tT = P_(CW.otT),
+           *cvec = P_(CW.ocv), *HI0 = P_(CW.oHI0), *HI1 = P_(CW.oHI1), *HJ0 = P_(CW.oHJ0), *HJ1 = P_(CW.oHJ1),
+           *TR = P_(CW.oTR), *G1 = P_(CW.oG1), *V2 = P_(CW.oV2), *SK = P_(CW.oSK), *p3 = P_(CW.op3),
+           *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP), *Tall = P_(CW.oTall),
+           *HUU = P_(CW.oHUU), *W = P_(CW.oW), *Y3 = P_(CW.oY), *G = P_(CW.oG);
+    const bool f32 = c->prec == RIS_FP32;
+    float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
+    const double *CO = c->C, *CV = c->C + o;
+
+    // ---- per-state factors (as in the unblocked contraction)
+    hipEvent_t t_h = stage_begin(c);
+    HIPCHK(c, make_rl(X, Y, R, L, (size_t)ns * vo, c->stream));
+    HIPCHK(c, permute3(R, RLT, v, ns, o, o, vo, 1, w2, o, 1, c->stream));
+    HIPCHK(c, permute3(L, RLT + (size_t)ns * o, v, ns, o, o, vo, 1, w2, o, 1, c->stream));
+    {
+        GemmArgs g = gm(N, o, v, false, false, 1.0, CV, nmo, R, o, 0.0, F, o3);
+        g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
+        HIPCHK(c, dgemm(g, c->stream));
+        g = gm(N, o, v, false, false, 1.0, CV, nmo, L, o, 0.0, F + o, o3);
+        g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
+        HIPCHK(c, dgemm(g, c->stream));
+        for (int s = 0; s < ns; ++s)
+            HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + 2 * o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
+                                       hipMemcpyDeviceToDevice, c->stream));
+        if (f32) HIPCHK(c, to_float(F, Ff, (size_t)ns * N * o3, c->stream));
+        g = gm(N, N, o, false, true, 1.0, F, o3, CO, nmo, 0.0, D, N);
+        g.batch = ns; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
+        HIPCHK(c, dgemm(g, c->stream));
+        HIPCHK(c, symmetrize(D, N, ns, c->stream));
+        HIPCHK(c, dgemm_splitk(gm(ns, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), kSplitV, SK,
+                               c->stream));
+        HIPCHK(c, dgemm(gm(ns, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
+    }
+    stage_end(c, t_h, RIS_STAGE_HBLK, 2.0 * ns * ((double)N * N * o) + 4.0 * ns * (double)N * v * o, 0.0);
+
+    auto blk = [](const double *b, long sP, long si, long sj, double sc) { return BlockSrc{b, sP, si, sj, sc}; };
+    auto sc = [](BlockSrc b, double f) { b.scale *= f; return b; };
+    const BlockSrc none{nullptr, 0, 0, 0, 0.0};
+    for (int k = 0; k < npair; ++k) {
+        const int I = pI[k], J = pJ[k];
+        // H_OU^P of a state s and t = R, L: [P][i][j] = sum_b c_vo^P[b][i] (R, L)_s[b][j]
+        hipEvent_t t_u = stage_begin(c);
+        double *HIt[2] = {HI0, HI1}, *HJt[2] = {I == J ? HI0 : HJ0, I == J ? HI1 : HJ1};
+        for (int t = 0; t < 2; ++t) {
+            HIPCHK(c, gemm_mp(gm(nK * o, o, v, true, false, 1.0, c->cvo, (long)nK * o, RLT + (size_t)(t * ns + I) * o,
+                                 w2, 0.0, HIt[t], o), c->prec, c->stream));
+            if (I != J)
+                HIPCHK(c, gemm_mp(gm(nK * o, o, v, true, false, 1.0, c->cvo, (long)nK * o,
+                                     RLT + (size_t)(t * ns + J) * o, w2, 0.0, HJt[t], o), c->prec, c->stream));
+        }
+        stage_end(c, t_u, RIS_STAGE_HBLK, (I == J ? 4.0 : 8.0) * (double)nK * o * v * o, 0.0);
+        HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * kMaxOutChunk * 6, 0.0, c->stream));
+        DerivJob job{};
+        job.nout = 1;
+        job.dens = D;
+        job.cvec = cvec;
+        job.nJ = nJ;
+        job.alphaJ = c->alphaJ;
+        job.partial = p3;
+        job.pair_ptr = c->screen > 0.0 ? c->d_pair_ptr : nullptr;
+        job.pair_idx = c->d_pair_idx;
+        for (int q = 0; q < kMaxOutChunk; ++q) {
+            job.stI[q] = I;
+            job.stJ[q] = J;
+        }
+        for (int p0 = 0; p0 < nK; p0 += nb) {
+            const int m = std::min(nb, nK - p0);
+            hipEvent_t t_b = stage_begin(c);
+            for (int t = 0; t < 2; ++t) {
+                // Tall^P[a][(t, j)] = sum_b c_vv^P[a][b] (R, L)_J[b][j] for P in the block
+                GemmArgs g = gm(v, o, v, false, false, 1.0, c->cvv + (size_t)p0 * v, (long)nK * v,
+                                RLT + (size_t)(t * ns + J) * o, w2, 0.0, Tall + (size_t)t * o, 2L * o);
+                g.batch = m; g.strideA = v; g.strideB = 0; g.strideC = (long)v * 2 * o;
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                // H_UU^P(t) = (R, L)_I^T Tall^P(t)
+                g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2, Tall + (size_t)t * o, 2L * o,
+                       0.0, HUU + (size_t)t * m * oo, o);
+                g.batch = m; g.strideA = 0; g.strideB = (long)v * 2 * o; g.strideC = oo;
+                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+            }
+            stage_end(c, t_b, RIS_STAGE_HBLK, 4.0 * (double)m * v * v * o + 4.0 * (double)m * oo * v, 0.0);
+            // exchange weights W^P of the block (rows / cols [U_R, U_L, C_O])
+            hipEvent_t t_yw = stage_begin(c);
+            const BlockSrc Hoo = blk(c->coo + (size_t)p0 * oo, oo, o, 1, 1.0);
+            const BlockSrc HRuo = blk(HIt[0] + (size_t)p0 * oo, oo, 1, o, 1.0);
+            const BlockSrc HLuo = blk(HIt[1] + (size_t)p0 * oo, oo, 1, o, 1.0);
+            const BlockSrc HRou = blk(HJt[0] + (size_t)p0 * oo, oo, o, 1, 1.0);
+            const BlockSrc HLou = blk(HJt[1] + (size_t)p0 * oo, oo, o, 1, 1.0);
+            const BlockSrc HRuu = blk(HUU, oo, o, 1, 1.0);
+            const BlockSrc HLuu = blk(HUU + (size_t)m * oo, oo, o, 1, 1.0);
+            BlockGrid gw{};
+            gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = none;             gw.b[0][2][0] = sc(HRou, 0.25);
+            gw.b[1][0][0] = none;           gw.b[1][1][0] = sc(Hoo, 0.25);   gw.b[1][2][0] = sc(HLou, -0.25);
+            gw.b[2][0][0] = sc(HRuo, 0.25); gw.b[2][1][0] = sc(HLuo, -0.25); gw.b[2][2][0] = sc(HRuu, 0.25);
+            gw.b[2][2][1] = sc(HLuu, 0.25);
+            HIPCHK(c, assemble3(gw, W, o, m, c->stream, f32 ? Wf : nullptr));
+            stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 9.0 * (double)oo * m);
+            // G rows of the block: <H_RUU^P + H_LUU^P, c_oo^Q>
+            hipEvent_t t_v = stage_begin(c);
+            for (int t = 0; t < 2; ++t)
+                HIPCHK(c, dgemm_splitk(gm(m, nK, (int)oo, false, true, 1.0, HUU + (size_t)t * m * oo, oo, c->coo, oo,
+                                          t ? 1.0 : 0.0, G1 + (size_t)p0 * nK, nK), nsplit, SK, c->stream));
+            stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)m * nK * oo, 0.0);
+            const int r = gamma_products(c, N, o, m, F + (size_t)I * N * o3, F + (size_t)J * N * o3,
+                                         Ff + (size_t)I * N * o3, Ff + (size_t)J * N * o3, W, Wf, Y3, G, I == J);
+            if (r != RIS_OK) return r;
+            // derivative contraction over the block's (s) shells, Coulomb part included
+            job.gammaK = G;
+            job.nK = m;
+            job.kbeg = p0;
+            hipEvent_t t_d = stage_begin(c);
+            HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, p0, p0 + m));
+            stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)m * NN);
+        }
+        // the remaining auxiliary shells carry the Coulomb part only
+        if (nK < c->nshJ) {
+            job.gammaK = nullptr;
+            job.nK = 0;
+            job.kbeg = 0;
+            hipEvent_t t_d = stage_begin(c);
+            HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, nK, c->nshJ));
+            stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 0.0);
+        }
+        // metric weights: W2 = -alpha_J c_I c_J^T + c_x (G + G^T) / 4
+        hipEvent_t t_v = stage_begin(c);
+        // G += <H_RUO^P, H_ROU^Q> - <H_LUO^P, H_LOU^Q>  (H_UO^P[i][j] = H_OU(I)^P[j][i])
+        for (int t = 0; t < 2; ++t) {
+            HIPCHK(c, permute3(HIt[t], TR, nK, o, o, oo, 1, o, oo, o, 1, c->stream));
+            HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)oo, false, true, t ? -1.0 : 1.0, TR, oo, HJt[t], oo, 1.0, G1, nK),
+                                   nsplit, SK, c->stream));
+        }
+        HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ, nJ,
+                           0.0, V2, nJ), c->stream));
+        HIPCHK(c, add_sym(G1, nK, V2, nJ, 0.25 * c->cx, c->stream));
+        stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)nK * nK * oo, 0.0);
+        HIPCHK(c, fill(p2, (size_t)c->nshJ * 2 * 1 * 3, 0.0, c->stream));
+        HIPCHK(c, launch_int2c_deriv(c->aux, c->boys, 1, V2, p2, c->stream));
+        HIPCHK(c, reduce_grad(p3, c->nshAO, c->nshJ, 1, kMaxOutChunk, p2, c->ao.sh.atom, c->aux.sh.atom, natm, shA,
+                              shC, shP, 1.0, 0, outg + (size_t)k * natm * 3, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RIS_OK;
@@ -1254,6 +1595,18 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
     const int NO = kMaxOutChunk;
     const int nsplit = vpq_splits(nK);
     const ContractWs CW = contract_ws(ctx_dims(c), ns);
+    {
+        // blocked over the exchange functions when forced or when the all-P
+        // intermediates do not fit; the largest block that fits otherwise
+        const size_t other = c->held - c->ws_bytes;
+        const size_t wsroom = std::max(c->budget > other ? c->budget - other : 0, c->ws_bytes);
+        if ((c->ablock > 0 && c->ablock < nK) || CW.total > wsroom) {
+            int nb = nK;
+            while (nb > 1 && contract_blk_ws(ctx_dims(c), ns, nb).total > wsroom) nb = std::max(1, (int)(nb * 0.8));
+            if (c->ablock > 0) nb = std::min(nb, c->ablock);
+            return contract_pairs_blocked(c, nstate, X, Y, npair, pI, pJ, outg, nb);
+        }
+    }
     int st;
     char *wsb = ws_get(c, CW.total, &st);
     if (!wsb) return st;
@@ -1265,7 +1618,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
     // FP32 mode: F, W and Y stored as float for the two products that build Gamma
     // (their FP32 kernel rounds the operands to FP32 anyway: same results)
     const bool f32 = c->prec == RIS_FP32;
-    float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf), *Y3f = (float *)Y3;
+    float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
     const double *CO = c->C, *CV = c->C + o;
 
     // ---- per-state intermediates
@@ -1372,69 +1725,13 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)(o3 * o3), false, true, c->cx, Hc, o3 * o3, W, o3 * o3, 1.0, V2k,
                                       nJ), nsplit, SK, c->stream));
             stage_end(c, t_v, RIS_STAGE_VPQ, 2.0 * (double)nK * nK * o3 * o3, 0.0);
-            // Y^P = F_I W^P ; Gamma^P = -2 c_x Y^P F_J^T
-            GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, F + (size_t)I * N * o3, o3, W, o3, 0.0, Y3, o3);
-            g.batch = nK; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
-            if (f32) {
-                g.A = (const double *)(Ff + (size_t)I * N * o3);
-                g.B = (const double *)Wf;
-                g.C = (double *)Y3f;
-                g.ftypes = kF32A | kF32B | kF32C;
-            }
-            hipEvent_t t_y = stage_begin(c);
-            HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-            stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nK * N * o3 * o3, 0.0);
+            // Y^P = F_I W^P ; Gamma^P from Y^P and F_J
             double *Gk = G + (size_t)k * nK * NN;
-            const double *FJ = F + (size_t)J * N * o3;
-            // only the lower triangle of the symmetric Gamma^P is formed (and read):
-            // gradients: -2 c_x Y F_I^T is symmetric; NACs: the symmetric part
-            // -c_x (Y F_J^T + F_J Y^T) as two lower-tile products
-            const bool lowt = c->prec != RIS_BF16X3;
-            // one timed group per GEMM launch; a lower-tile launch does
-            // nK N (N + 1) 3o flops and moves Y, F_J (float in the FP32 mode)
-            // and the lower half of Gamma (always double)
-            const double fl_low = (double)nK * N * (N + 1) * o3;
-            const double ein = f32 ? 4.0 : 8.0;
-            const double by_low = ein * ((double)nK * N * o3 + (double)N * o3) + 8.0 * (double)nK * N * (N + 1) / 2;
-            const float *FJf = Ff + (size_t)J * N * o3;
-            if (I == J || !lowt) {
-                g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
-                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = lowt;
-                if (f32) {
-                    g.A = (const double *)Y3f;
-                    g.B = (const double *)FJf;
-                    g.ftypes = kF32A | kF32B;
-                }
-                hipEvent_t t_g = stage_begin(c);
-                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-                if (lowt) stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
-                else
-                    stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nK * N * N * o3,
-                              8.0 * ((double)nK * N * N + (double)nK * N * o3 + (double)N * o3));
-            } else {
-                g = gm(N, N, (int)o3, false, true, -c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
-                g.batch = nK; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
-                if (f32) {
-                    g.A = (const double *)Y3f;
-                    g.B = (const double *)FJf;
-                    g.ftypes = kF32A | kF32B;
-                }
-                hipEvent_t t_g = stage_begin(c);
-                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-                stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
-                g = gm(N, N, (int)o3, false, true, -c->cx, FJ, o3, Y3, o3, 1.0, Gk, N);
-                g.batch = nK; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
-                if (f32) {
-                    g.A = (const double *)FJf;
-                    g.B = (const double *)Y3f;
-                    g.ftypes = kF32A | kF32B;
-                }
-                t_g = stage_begin(c);
-                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-                // the accumulating launch also reads the lower half of Gamma
-                stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low + 8.0 * (double)nK * N * (N + 1) / 2);
+            {
+                const int r = gamma_products(c, N, o, nK, F + (size_t)I * N * o3, F + (size_t)J * N * o3,
+                                             Ff + (size_t)I * N * o3, Ff + (size_t)J * N * o3, W, Wf, Y3, Gk, I == J);
+                if (r != RIS_OK) return r;
             }
-            if (I != J && !lowt) HIPCHK(c, symmetrize(Gk, N, nK, c->stream));
         }
         // three-centre derivative contraction + metric derivative, reduced into atoms
         HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * NO * 6, 0.0, c->stream));

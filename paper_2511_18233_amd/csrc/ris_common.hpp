@@ -54,14 +54,17 @@ struct AOGeom {
     int nao;
     int lbeg[kMaxAOL + 2];  // shells sorted by l: shells of l are [lbeg[l], lbeg[l+1])
 };
+// With an aux shell range [cs0, cs1) (cs1 < 0: to the last shell) only those
+// shells are computed and X row 0 is the first function of shell cs0.
 hipError_t launch_int3c(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],
-                        const double *boys, double *X, hipStream_t st);
+                        const double *boys, double *X, hipStream_t st, int cs0 = 0, int cs1 = -1);
 
 // Fused three-centre derivative contraction (see ris_ints.hip).
 struct DerivJob {
     int nout;                  // outputs in this launch (<= kMaxOutChunk)
     const double *gammaK;      // [nout][nK][nao][nao] symmetric K weights (lower triangle read), may be null
-    int nK;                    // K functions (first nK J functions)
+    int nK;                    // K functions held by gammaK: J functions [kbeg, kbeg + nK)
+    int kbeg;                  // (the K set is the leading s functions of the J set)
     const double *dens;        // [nstate][nao][nao] symmetric AO densities R^S
     const double *cvec;        // [nstate][nJ] c_I = M_J^-1 t_I
     int nJ;
@@ -74,8 +77,10 @@ struct DerivJob {
     const int *pair_idx;
 };
 constexpr int kMaxOutChunk = 4;
+// Only the aux shells in [cs0, cs1) (cs1 < 0: to the last shell); partial
+// slots of the other shells are left untouched.
 hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],
-                              const double *boys, const DerivJob &job, hipStream_t st);
+                              const double *boys, const DerivJob &job, hipStream_t st, int cs0 = 0, int cs1 = -1);
 
 // 2c metric derivative contraction: partial2[P shell][out][3] for d/dP.
 hipError_t launch_int2c_deriv(const AuxGeom &aux, const double *boys, int nout,

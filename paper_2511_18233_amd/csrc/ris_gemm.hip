@@ -284,11 +284,45 @@ hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st)
     if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
     const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
     if (total > 0x7fffffffL) return hipErrorInvalidValue;
-    // every operand byte offset from a panel base must fit 32 bits
+    // every operand byte offset from a panel base must fit 32 bits.  A k-fast
+    // operand (A untransposed, B transposed) spans the rows of its tile; when
+    // its rows are too long for a full tile, the product is issued in row
+    // (column) slices short enough for 32-bit offsets.
     const long SKm = mode == 0 ? 16 : 32;
-    const long spanA = g.transA ? (SKm - 1) * g.lda + g.M : (BM - 1) * g.lda + g.K;
-    const long spanB = g.transB ? (BN - 1) * g.ldb + g.K : (SKm - 1) * g.ldb + g.N;
-    if (8 * std::max(spanA, spanB) >= (1L << 32)) return hipErrorInvalidValue;
+    auto fits = [](long span) { return 8 * span < (1L << 32); };
+    if (!g.transA && !fits((std::min<long>(BM, g.M) - 1) * g.lda + g.K)) {
+        long r = BM - 1;
+        while (r > 1 && !fits((r - 1) * g.lda + g.K)) --r;
+        if (g.lower || !fits((r - 1) * g.lda + g.K)) return hipErrorInvalidValue;
+        const size_t szA = (g.ftypes & kF32A) ? 4 : 8, szC = (g.ftypes & kF32C) ? 4 : 8;
+        for (long m0 = 0; m0 < g.M; m0 += r) {
+            GemmArgs s = g;
+            s.M = (int)std::min<long>(r, g.M - m0);
+            s.A = (const double *)((const char *)g.A + (size_t)m0 * g.lda * szA);
+            s.C = (double *)((char *)g.C + (size_t)m0 * g.ldc * szC);
+            const hipError_t e = gemm_kc(s, mode, kc, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    if (g.transB && !fits((std::min<long>(BN, g.N) - 1) * g.ldb + g.K)) {
+        long r = BN - 1;
+        while (r > 1 && !fits((r - 1) * g.ldb + g.K)) --r;
+        if (g.lower || !fits((r - 1) * g.ldb + g.K)) return hipErrorInvalidValue;
+        const size_t szB = (g.ftypes & kF32B) ? 4 : 8, szC = (g.ftypes & kF32C) ? 4 : 8;
+        for (long n0 = 0; n0 < g.N; n0 += r) {
+            GemmArgs s = g;
+            s.N = (int)std::min<long>(r, g.N - n0);
+            s.B = (const double *)((const char *)g.B + (size_t)n0 * g.ldb * szB);
+            s.C = (double *)((char *)g.C + (size_t)n0 * szC);
+            const hipError_t e = gemm_kc(s, mode, kc, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const long spanA = g.transA ? (SKm - 1) * g.lda + g.M : (std::min<long>(BM, g.M) - 1) * g.lda + g.K;
+    const long spanB = g.transB ? (std::min<long>(BN, g.N) - 1) * g.ldb + g.K : (SKm - 1) * g.ldb + g.N;
+    if (!fits(spanA) || !fits(spanB)) return hipErrorInvalidValue;
     if (g.ftypes != 0) {
         // FP32-stored operands: the two products that build Gamma in the FP32 mode
         const int nred0 = g.nred > 0 ? g.nred : 1;

@@ -15,6 +15,7 @@
 //   d/dB = -d/dA - d/dC (translational invariance of the integral).
 // All angular loops are unrolled at compile time per (la, lb, lc) class so the
 // recurrence tables live in registers.
+#include <algorithm>
 #include <utility>
 
 #include "ris_boys.hpp"
@@ -190,7 +191,7 @@ constexpr double kTwoPi52 = 34.98683665524972497;  // 2 pi^{5/2}
 // (mu nu|P): one thread per ordered shell triplet of the class.
 template <int LA, int LB, int LC>
 __global__ __launch_bounds__(128) void k_int3c(ShellTab ao, int nao, int a0, int na, int b0, int nb,
-                                               ShellTab aux, int c0, int nc,
+                                               ShellTab aux, int c0, int nc, int pofs,
                                                const double *__restrict__ boys, double *__restrict__ X)
 {
     const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(128) void k_int3c(ShellTab ao, int nao, int a0, int
         constexpr int sx = cpow(LC, kc, 0), sy = cpow(LC, kc, 1), sz = cpow(LC, kc, 2);
         sfor<ncart(LA)>([&](auto ka) {
             constexpr int ix = cpow(LA, ka, 0), iy = cpow(LA, ka, 1), iz = cpow(LA, ka, 2);
-            double *row = X + ((size_t)(P0 + kc) * nao + (mu0 + ka)) * nao + nu0;
+            double *row = X + ((size_t)(P0 - pofs + kc) * nao + (mu0 + ka)) * nao + nu0;
             sfor<ncart(LB)>([&](auto kb) {
                 constexpr int jx = cpow(LB, kb, 0), jy = cpow(LB, kb, 1), jz = cpow(LB, kb, 2);
                 const double v = hsum<ix + jx + 1, iy + jy + 1, iz + jz + 1, sx, sy, sz>(
@@ -262,7 +263,8 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
     const double c = aux.exp[sc];
     const double Cx = aux.x[sc], Cy = aux.y[sc], Cz = aux.z[sc];
     const int mu0 = ao.off[sa], P0 = aux.off[sc];
-    const bool inK = P0 < job.nK;  // K functions are the leading (s) J functions
+    // K functions are the leading (s) J functions; gammaK holds [kbeg, kbeg + nK)
+    const bool inK = P0 >= job.kbeg && P0 < job.kbeg + job.nK;
     const size_t nao2 = (size_t)nao * nao;
 
     double acc[NO][6];
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
                         if (o < job.nout) {
                             double w = dI[o] * cJ[o][kc] + dJ[o] * cI[o][kc];
                             if (inK && job.gammaK)
-                                w += job.gammaK[((size_t)o * job.nK + P0 + kc) * nao2 + mnl];
+                                w += job.gammaK[((size_t)o * job.nK + (P0 - job.kbeg) + kc) * nao2 + mnl];
                             const double w2 = 2.0 * w;
                             acc[o][0] += w2 * dA[0];
                             acc[o][1] += w2 * dA[1];
@@ -523,77 +525,107 @@ hipError_t launch_int2c_deriv(const AuxGeom &aux, const double *boys, int nout, 
 }
 
 namespace {
-template <int LA, int LB, int LC>
-void int3c_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, const double *boys, double *X,
-               hipStream_t st)
+// aux shells of class LC inside [cs0, cs1)
+template <int LC>
+bool class_range(const int *auxl_beg, int cs0, int cs1, int *c0, int *nc)
 {
-    const int a0 = ao.lbeg[LA], na = ao.lbeg[LA + 1] - a0;
-    const int b0 = ao.lbeg[LB], nb = ao.lbeg[LB + 1] - b0;
-    const int c0 = auxl_beg[LC], nc = auxl_beg[LC + 1] - c0;
-    const long tot = (long)na * nb * nc;
-    if (tot == 0) return;
-    hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, st, ao.sh,
-                       ao.nao, a0, na, b0, nb, aux.sh, c0, nc, boys, X);
+    const int lo = std::max(auxl_beg[LC], cs0), hi = std::min(auxl_beg[LC + 1], cs1);
+    *c0 = lo;
+    *nc = hi - lo;
+    return hi > lo;
 }
 
 template <int LA, int LB, int LC>
-void deriv_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, const double *boys,
+void int3c_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, int cs0, int cs1, int pofs,
+               const double *boys, double *X, hipStream_t st)
+{
+    const int a0 = ao.lbeg[LA], na = ao.lbeg[LA + 1] - a0;
+    const int b0 = ao.lbeg[LB], nb = ao.lbeg[LB + 1] - b0;
+    int c0, nc;
+    if (!class_range<LC>(auxl_beg, cs0, cs1, &c0, &nc)) return;
+    const long tot = (long)na * nb * nc;
+    if (tot == 0) return;
+    hipLaunchKernelGGL((k_int3c<LA, LB, LC>), dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, st, ao.sh,
+                       ao.nao, a0, na, b0, nb, aux.sh, c0, nc, pofs, boys, X);
+}
+
+template <int LA, int LB, int LC>
+void deriv_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, int cs0, int cs1, const double *boys,
                const DerivJob &job, hipStream_t st)
 {
     const int a0 = ao.lbeg[LA], na = ao.lbeg[LA + 1] - a0;
     const int b0 = ao.lbeg[LB], nb = ao.lbeg[LB + 1] - b0;
-    const int c0 = auxl_beg[LC], nc = auxl_beg[LC + 1] - c0;
-    if (na == 0 || nb == 0 || nc == 0) return;
+    int c0, nc;
+    if (!class_range<LC>(auxl_beg, cs0, cs1, &c0, &nc)) return;
+    if (na == 0 || nb == 0) return;
     hipLaunchKernelGGL((k_int3c_deriv<LA, LB, LC, kMaxOutChunk>), dim3(na * nc), dim3(64), 0, st, ao.sh, ao.nao,
                        a0, na, b0, nb, aux.sh, c0, nc, aux.nshell, boys, job);
+}
+
+// first function of aux shell cs (shells sorted by l, ncart(l) functions each)
+int aux_func_off(const int *auxl_beg, int cs)
+{
+    int f = 0;
+    for (int l = 0; l <= kMaxAuxL; ++l) {
+        const int lo = auxl_beg[l], hi = auxl_beg[l + 1];
+        f += ncart(l) * (std::min(std::max(cs, lo), hi) - lo);
+    }
+    return f;
 }
 }  // namespace
 
 hipError_t launch_int3c(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2], const double *boys,
-                        double *X, hipStream_t st)
+                        double *X, hipStream_t st, int cs0, int cs1)
 {
-    int3c_one<0, 0, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<0, 1, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<0, 2, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<1, 0, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<1, 1, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<1, 2, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<2, 0, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<2, 1, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<2, 2, 0>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<0, 0, 1>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<0, 1, 1>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<0, 2, 1>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<1, 0, 1>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<1, 1, 1>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<1, 2, 1>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<2, 0, 1>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<2, 1, 1>(ao, aux, auxl_beg, boys, X, st);
-    int3c_one<2, 2, 1>(ao, aux, auxl_beg, boys, X, st);
+    if (cs1 < 0) cs1 = aux.nshell;
+    if (cs0 < 0 || cs0 > cs1 || cs1 > aux.nshell) return hipErrorInvalidValue;
+    if (cs0 == cs1) return hipSuccess;
+    // the block's first function is row 0 of X
+    const int pofs = aux_func_off(auxl_beg, cs0);
+    int3c_one<0, 0, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<0, 1, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<0, 2, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<1, 0, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<1, 1, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<1, 2, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<2, 0, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<2, 1, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<2, 2, 0>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<0, 0, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<0, 1, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<0, 2, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<1, 0, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<1, 1, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<1, 2, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<2, 0, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<2, 1, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
+    int3c_one<2, 2, 1>(ao, aux, auxl_beg, cs0, cs1, pofs, boys, X, st);
     return hipGetLastError();
 }
 
 hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],
-                              const double *boys, const DerivJob &job, hipStream_t st)
+                              const double *boys, const DerivJob &job, hipStream_t st, int cs0, int cs1)
 {
-    deriv_one<0, 0, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<0, 1, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<0, 2, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<1, 0, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<1, 1, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<1, 2, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<2, 0, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<2, 1, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<2, 2, 0>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<0, 0, 1>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<0, 1, 1>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<0, 2, 1>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<1, 0, 1>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<1, 1, 1>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<1, 2, 1>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<2, 0, 1>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<2, 1, 1>(ao, aux, auxl_beg, boys, job, st);
-    deriv_one<2, 2, 1>(ao, aux, auxl_beg, boys, job, st);
+    if (cs1 < 0) cs1 = aux.nshell;
+    if (cs0 < 0 || cs0 > cs1 || cs1 > aux.nshell) return hipErrorInvalidValue;
+    deriv_one<0, 0, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<0, 1, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<0, 2, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<1, 0, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<1, 1, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<1, 2, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<2, 0, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<2, 1, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<2, 2, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<0, 0, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<0, 1, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<0, 2, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<1, 0, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<1, 1, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<1, 2, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<2, 0, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<2, 1, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    deriv_one<2, 2, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
     return hipGetLastError();
 }
 

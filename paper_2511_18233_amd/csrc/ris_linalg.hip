@@ -161,6 +161,15 @@ __global__ void k_symmetrize(double *A, int n, int nb)
     M[(size_t)j * n + i] = v;
 }
 
+// V[P][Q] += s (G[P][Q] + G[Q][P]) over n x n (G dense n x n, V leading dim ldv)
+__global__ void k_add_sym(const double *__restrict__ G, int n, double *__restrict__ V, int ldv, double s)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n) return;
+    const int p = (int)(idx / n), q = (int)(idx % n);
+    V[(size_t)p * ldv + q] += s * (G[(size_t)p * n + q] + G[(size_t)q * n + p]);
+}
+
 // out[k][a][i] += s_de * (eps[nocc+a] - eps[i]) * V[k][a][i]
 __global__ void k_add_de(const double *__restrict__ eps, const double *__restrict__ V, double *__restrict__ out,
                          int nvir, int nocc, int nvec, double s_de)
@@ -357,6 +366,13 @@ hipError_t make_rl(const double *X, const double *Y, double *R, double *L, size_
 hipError_t symmetrize(double *A, int n, int nb, hipStream_t st)
 {
     hipLaunchKernelGGL(k_symmetrize, dim3(nblk((size_t)n * n * nb, 256)), dim3(256), 0, st, A, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t add_sym(const double *G, int n, double *V, int ldv, double s, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_sym, dim3(nblk((size_t)n * n, 256)), dim3(256), 0, st, G, n, V, ldv, s);
     return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@ hipError_t gather_rows(const double *src, double *dst, const int *perm, int nrow
 hipError_t scatter_sq(const double *in, double *out, const int *perm, int n, int nb, hipStream_t st);
 hipError_t make_rl(const double *X, const double *Y, double *R, double *L, size_t n, hipStream_t st);
 hipError_t symmetrize(double *A, int n, int nb, hipStream_t st);
+// V[P][Q] += s (G[P][Q] + G[Q][P]) for P, Q < n; G dense n x n, V with leading dimension ldv
+hipError_t add_sym(const double *G, int n, double *V, int ldv, double s, hipStream_t st);
 hipError_t add_de(const double *eps, const double *V, double *out, int nvir, int nocc, int nvec, double s,
                   hipStream_t st);
 hipError_t axpby(const double *src, double *dst, size_t n, double alpha, double beta, hipStream_t st);

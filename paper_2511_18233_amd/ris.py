@@ -23,8 +23,9 @@ OPS = {"A": 0, "B": 1, "A+B": 2, "A-B": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
            "ris_response_matvec", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
-           "ris_request_bytes",
-           "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_zvector_solve", "ris_tda_davidson",
+           "ris_request_bytes", "ris_plan_bytes",
+           "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_ctx_set_blocking", "ris_zvector_solve",
+           "ris_tda_davidson",
            "ris_zrhs_contract",
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
@@ -82,9 +83,13 @@ def load_library(path: str = LIB_PATH):
     lib.ris_request_bytes.argtypes = [ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.ris_request_bytes.restype = ctypes.c_size_t
+    lib.ris_plan_bytes.argtypes = [ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.ris_plan_bytes.restype = ctypes.c_size_t
     lib.ris_grad_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp, ctypes.c_int, ip, dp, vp]
     lib.ris_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.ris_ctx_set_screening.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_long)]
+    lib.ris_ctx_set_blocking.argtypes = [vp, ctypes.c_int]
     lib.ris_zvector_solve.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, ctypes.c_int, ip, dp]
     lib.ris_tda_davidson.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, vp, ip]
     lib.ris_zrhs_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp]
@@ -100,8 +105,9 @@ def load_library(path: str = LIB_PATH):
 
 
 def request_bytes(Z, shell_atom, shell_l, radius_bohr, nmo, nocc, nstate, nvec=0, nout=0, theta=0.2,
-                  j_p_on_heavy=True) -> int:
-    """Device bytes one request needs (host-only sizing from the library)."""
+                  j_p_on_heavy=True, aux_block=0) -> int:
+    """Device bytes one request needs (host-only sizing from the library);
+    aux_block > 0: the footprint of the path blocked over the auxiliary index."""
     lib = load_library()
     Z = np.ascontiguousarray(Z, dtype=np.int32)
     sa = np.ascontiguousarray(shell_atom, dtype=np.int32)
@@ -113,8 +119,8 @@ def request_bytes(Z, shell_atom, shell_l, radius_bohr, nmo, nocc, nstate, nvec=0
     mol = _Mol(Z.shape[0], Z.ctypes.data_as(ip), xyz.ctypes.data_as(dp), sl.shape[0], sa.ctypes.data_as(ip),
                sl.ctypes.data_as(ip), se.ctypes.data_as(dp))
     opts = _AuxOpts(float(theta), rad.ctypes.data_as(dp), int(bool(j_p_on_heavy)))
-    return int(lib.ris_request_bytes(ctypes.byref(mol), ctypes.byref(opts), int(nmo), int(nocc), int(nstate),
-                                     int(nvec), int(nout)))
+    return int(lib.ris_plan_bytes(ctypes.byref(mol), ctypes.byref(opts), int(nmo), int(nocc), int(nstate),
+                                  int(nvec), int(nout), int(aux_block)))
 
 
 def _ptr(t):
@@ -180,6 +186,11 @@ class RisContext:
         kept = ctypes.c_long(0)
         self._chk(self.lib.ris_ctx_set_screening(self.h, float(threshold), ctypes.byref(kept)))
         return int(kept.value)
+
+    def set_blocking(self, aux_block: int):
+        """Cap on auxiliary functions per block (0: unblocked when it fits,
+        else the largest blocks that fit the HBM budget)."""
+        self._chk(self.lib.ris_ctx_set_blocking(self.h, int(aux_block)))
 
     def set_profiling(self, on: bool):
         self._chk(self.lib.ris_ctx_set_profiling(self.h, int(bool(on))))

@@ -128,3 +128,39 @@ def test_reduced_precision_gemm(lib, mode, M, N, K, tA, tB, batch):
     bound = 8 * eps * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() * 1.3
     print("  err", err, "bound", bound, flush=True)
     assert err < bound
+
+
+@pytest.mark.parametrize("tB", [0, 1])
+def test_gemm_long_rows_sliced(lib, tB):
+    """A k-fast operand whose rows are too far apart for 32-bit offsets across
+    a 128-row tile (leading dimension 4.5e6 doubles, as (ai|P) at 500 atoms)
+    is issued in row slices: untransposed A (tB = 0) or transposed B (tB = 1)."""
+    import torch
+    ld = 4_500_000
+    rng = np.random.default_rng(77 + tB)
+    if tB == 0:
+        M, N, K = 140, 5, 24
+        a = rng.standard_normal((M, K))
+        b = rng.standard_normal((K, N))
+        buf = torch.zeros((M - 1) * ld + K, dtype=torch.float64, device="cuda")
+        buf.as_strided((M, K), (ld, 1)).copy_(torch.tensor(a))
+        dA, lda = buf, ld
+        dB, ldb = torch.tensor(b, device="cuda"), N
+    else:
+        M, N, K = 5, 140, 24
+        a = rng.standard_normal((M, K))
+        b = rng.standard_normal((N, K))
+        buf = torch.zeros((N - 1) * ld + K, dtype=torch.float64, device="cuda")
+        buf.as_strided((N, K), (ld, 1)).copy_(torch.tensor(b))
+        dA, lda = torch.tensor(a, device="cuda"), K
+        dB, ldb = buf, ld
+    dC = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    print(f"gemm long rows tB={tB} M={M} N={N} K={K} ld={ld}", flush=True)
+    st = lib.ris_test_gemm(0, M, N, K, 0, tB, 1.0, _p(dA), lda, 0, _p(dB), ldb, 0, 0.0, _p(dC), N, 0, 1)
+    assert st == 0
+    ref = a @ (b.T if tB else b)
+    err = np.abs(dC.cpu().numpy() - ref).max()
+    print("  err", err, flush=True)
+    assert err < 1e-12 * max(1.0, np.abs(ref).max())
+    del buf
+    torch.cuda.empty_cache()

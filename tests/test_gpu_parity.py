@@ -221,9 +221,12 @@ def test_error_paths(radii, torch_dev):
         c.aux_build(m.Z, m.xyz, m.shell_atom, bad_l, m.shell_exp, radii, 0.2, False)
     assert e.value.code == 2
     c.close()
-    # an HBM budget below the request is refused, not attempted
+    # an HBM budget below even the smallest blocks is refused, not attempted
+    # (chain30: its kept MO blocks alone exceed 1 MiB)
+    prob = molgen.make_chain_problem(30, seed=8, nstate=2, tda=False)
+    m = prob.mol
     small = RisContext(0, hbm_budget=1 << 20)
-    small.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, False)
+    small.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, True)
     with pytest.raises(RisError) as e:
         small.int3c(_to(prob.C, small.device), _to(prob.eps, small.device), prob.nocc)
     assert e.value.code == 3
