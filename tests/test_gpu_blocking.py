@@ -83,17 +83,23 @@ def test_blocked_fp64_vs_oracle_and_unblocked(ctx, radii, block):
     assert np.abs(got.sum(1)).max() <= 1e-10
 
 
-def test_blocked_fp32_vs_unblocked(ctx, radii):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_blocked_reduced_precision_vs_unblocked(ctx, radii, precision):
     prob = molgen.make_chain_problem(30, seed=8, nstate=3, tda=False)
     outs = _outs(prob.nstate)
-    say("[gpu] blocking chain30_tddft fp32: unblocked run")
-    _, nK, ref_gpu, _, _ = _run(ctx, prob, radii, 0, outs, precision="fp32")
+    say(f"[gpu] blocking chain30_tddft {precision}: unblocked run")
+    _, nK, ref_gpu, _, _ = _run(ctx, prob, radii, 0, outs, precision=precision)
     blk = max(2, nK // 3 + 1)
     say(f"[gpu]   blocked run (block {blk} of nK={nK})")
-    _, _, got, _, _ = _run(ctx, prob, radii, blk, outs, precision="fp32")
+    _, _, got, _, _ = _run(ctx, prob, radii, blk, outs, precision=precision)
     d = np.abs(got - ref_gpu).max()
-    say(f"[gpu]   fp32 blocked vs unblocked {d:.2e} (max {np.abs(ref_gpu).max():.2e})")
-    assert d <= 1e-10
+    say(f"[gpu]   {precision} blocked vs unblocked {d:.2e} (max {np.abs(ref_gpu).max():.2e})")
+    # FP32: the same roundings in both paths.  Split BF16: the blocked path
+    # forms H_UO as the transpose of H_OU, which swaps the operands of the
+    # hi*lo and lo*hi partial products and so their FP32 summation order; the
+    # two results differ at the mode's own rounding level (its error against
+    # FP64 is ~1e-7 Ha/Bohr here)
+    assert d <= (1e-10 if precision == "fp32" else 1e-7)
     assert np.abs(got.sum(1)).max() <= 1e-9
 
 
