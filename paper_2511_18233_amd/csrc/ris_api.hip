@@ -1344,9 +1344,8 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
 
 // Y^P = F_I W^P and the exchange weights Gamma^P for nP auxiliary functions:
 // Gamma^P = -2 c_x Y^P F_I^T (same state) or -c_x (Y^P F_J^T + F_J Y^P^T);
-// only the lower triangle of each symmetric Gamma^P is formed (and read),
-// except in the split-BF16 mode (full tiles, symmetrised for NACs).  In the
-// FP32 mode the products take the float copies FfI / FfJ / Wf and Y is float.
+// only the lower triangle of each symmetric Gamma^P is formed (and read).  In
+// the FP32 mode the products take the float copies FfI / FfJ / Wf and Y is float.
 static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, const double *FJ, const float *FfI,
                           const float *FfJ, const double *W, const float *Wf, double *Y3, double *Gk, bool same)
 {
@@ -1364,16 +1363,15 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
     hipEvent_t t_y = stage_begin(c);
     HIPCHK(c, gemm_mp(g, c->prec, c->stream));
     stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nP * N * o3 * o3, 0.0);
-    const bool lowt = c->prec != RIS_BF16X3;
     // one timed group per GEMM launch; a lower-tile launch does
     // nP N (N + 1) 3o flops and moves Y, F_J (float in the FP32 mode)
     // and the lower half of Gamma (always double)
     const double fl_low = (double)nP * N * (N + 1) * o3;
     const double ein = f32 ? 4.0 : 8.0;
     const double by_low = ein * ((double)nP * N * o3 + (double)N * o3) + 8.0 * (double)nP * N * (N + 1) / 2;
-    if (same || !lowt) {
+    if (same) {
         g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
-        g.batch = nP; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = lowt;
+        g.batch = nP; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
         if (f32) {
             g.A = (const double *)Y3f;
             g.B = (const double *)FfJ;
@@ -1381,10 +1379,7 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
         }
         hipEvent_t t_g = stage_begin(c);
         HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-        if (lowt) stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
-        else
-            stage_end(c, t_g, RIS_STAGE_GAMMA, 2.0 * (double)nP * N * N * o3,
-                      8.0 * ((double)nP * N * N + (double)nP * N * o3 + (double)N * o3));
+        stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
     } else {
         g = gm(N, N, (int)o3, false, true, -c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
         g.batch = nP; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
@@ -1408,7 +1403,6 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
         // the accumulating launch also reads the lower half of Gamma
         stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low + 8.0 * (double)nP * N * (N + 1) / 2);
     }
-    if (!same && !lowt) HIPCHK(c, symmetrize(Gk, N, nP, c->stream));
     return RIS_OK;
 }
 

@@ -119,6 +119,8 @@ int balanced_splits(long tiles, int smax);
 // and out, FP32 accumulation): mode 0 = FP64 (dgemm), 1 = FP32, 2 = split BF16
 // with three products (ris_gemm_mp.hip).
 hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st);
+// The split-BF16 product alone; kc > 0: split-K ranges of kc (a multiple of 32).
+hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st);
 // The matrix-core GEMM itself for mode 0 (FP64) or 1 (FP32); kc > 0 splits K
 // into ranges of kc indexed by the batch (ris_gemm.hip).
 hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st);

@@ -456,7 +456,7 @@ namespace ris {
 
 hipError_t gemm_splitk(const GemmArgs &g, int mode, int nsplit, double *ws, hipStream_t st)
 {
-    if (nsplit <= 1 || g.batch != 1 || g.nred > 1 || mode == 2) return gemm_mp(g, mode, st);
+    if (nsplit <= 1 || g.batch != 1 || g.nred > 1) return gemm_mp(g, mode, st);
     const int kc = ((g.K + nsplit - 1) / nsplit + 31) / 32 * 32;  // multiple of both k-slab depths
     const int used = (g.K + kc - 1) / kc;
     // one launch: batch index = k-range, partial products into ws[z][M][N]
@@ -468,7 +468,7 @@ hipError_t gemm_splitk(const GemmArgs &g, int mode, int nsplit, double *ws, hipS
     p.C = ws;
     p.ldc = g.N;
     p.strideC = (long)g.M * g.N;
-    hipError_t e = gemm_kc(p, mode, kc, st);
+    hipError_t e = mode == 2 ? bgemm_kc(p, kc, st) : gemm_kc(p, mode, kc, st);
     if (e != hipSuccess) return e;
     const long tot = (long)g.M * g.N;
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws, used, g.M, g.N,

@@ -27,12 +27,28 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 constexpr int BM = 128, BN = 128;
 constexpr int NXCD = 8;
 constexpr int GROUP_M = 2;
+constexpr int BK2 = 32;  // k-slab: one v_mfma_f32_16x16x32_bf16 step
+constexpr int PAD2 = 8;  // bf16 elements; keeps 16-byte alignment of each LDS row
 
-__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, int &z, int &mt, int &nt)
+// Linear workgroup id -> (batch, m-tile, n-tile): each XCD walks one
+// contiguous range; lower: the tiles mt >= nt of a square grid, row by row;
+// otherwise groups of GROUP_M m-tiles with the n-tile as the slower index.
+__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool lower, int &z, int &mt, int &nt)
 {
     const int q = total / NXCD, r = total % NXCD;
     const int xcd = b % NXCD, local = b / NXCD;
     const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+    if (lower) {
+        const int per = tm * (tm + 1) / 2;
+        z = lin / per;
+        const int t = lin % per;
+        int m = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (m * (m + 1) / 2 > t) --m;
+        while ((m + 1) * (m + 2) / 2 <= t) ++m;
+        mt = m;
+        nt = t - m * (m + 1) / 2;
+        return;
+    }
     const int per = tm * tn;
     z = lin / per;
     const int t = lin % per;
@@ -44,10 +60,13 @@ __device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, int &z
     nt = tg / gm;
 }
 
-// ----------------------------------------------------------- split BF16 --
-constexpr int BK2 = 32;
-constexpr int PAD2 = 8;  // bf16 elements; keeps 16-byte alignment of each row
+// double at a uniform base plus a 32-bit element offset (byte offset < 2^32)
+__device__ __forceinline__ double ldo(const double *base, int off)
+{
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + ((unsigned)off * 8u));
+}
 
+// x32 = fl32(x), hi = bf16(x32), lo = bf16(x32 - hi)
 __device__ __forceinline__ void split_bf16(double x, __bf16 &hi, __bf16 &lo)
 {
     const float f = (float)x;
@@ -55,13 +74,26 @@ __device__ __forceinline__ void split_bf16(double x, __bf16 &hi, __bf16 &lo)
     lo = (__bf16)(f - (float)hi);
 }
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_bgemm3(int M, int N, int K, double alpha, const double *__restrict__ A,
-                                                long lda, long sA, long sAr, const double *__restrict__ B, long ldb,
-                                                long sB, long sBr, double beta, double *__restrict__ C, long ldc,
-                                                long sC, int nred, int tm, int tn, int total)
+// ----------------------------------------------------------- split BF16 --
+// 128 x 128 tiles, 4 waves of 64 x 64, k-slabs of 32.  Every thread owns 8
+// pairs of consecutive k: along rows for a k-fast operand (16 lanes sweep 32
+// consecutive k of one row, so each load instruction reads whole rows) and
+// along the m- / n-index for the other (64 lanes sweep 64 consecutive
+// columns).  Loads are clamped into the operand and zeroed by a 0/1 factor
+// (one basic block per slab); each pair's hi and lo parts go to LDS as one
+// 32-bit word each, laid out [row][k] so a lane reads its MFMA fragment (8
+// consecutive k of one row) as one 16-byte vector.  The three products run
+// product-major over the 16 accumulators, so consecutive MFMAs never depend
+// on each other.  alpha scales A before the split; lower-tile, split-K
+// (batch index = k-range) and batch-reduce as in the FP64 kernel.
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+
+template <bool TA, bool TB, bool BETA>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_bgemm3(
+    int M, int N, int K, double alpha, const double *__restrict__ A, long lda, long sA, long sAr,
+    const double *__restrict__ B, long ldb, long sB, long sBr, double beta, double *__restrict__ C, long ldc, long sC,
+    int nred, int tm, int tn, int total, int kc, bool lower)
 {
-    // k-contiguous tiles: a lane's 8 consecutive k of one row are one 16-byte read
     __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][BK2 + PAD2];
     __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][BK2 + PAD2];
     __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][BK2 + PAD2];
@@ -69,68 +101,89 @@ __global__ __launch_bounds__(256) void k_bgemm3(int M, int N, int K, double alph
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     int bz, mt, nt;
-    tile_of(blockIdx.x, total, tm, tn, bz, mt, nt);
+    tile_of(blockIdx.x, total, tm, tn, lower, bz, mt, nt);
     const int m0 = mt * BM, n0 = nt * BN;
+    const int kbeg = kc > 0 ? bz * kc : 0;
+    const int kend = kc > 0 ? min(K, kbeg + kc) : K;
     A += (long)bz * sA;
     B += (long)bz * sB;
     C += (long)bz * sC;
+
     v4f acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    double ra[16], rb[16];
-    const int ktiles = (K + BK2 - 1) / BK2;
-    const int niter = ktiles * nred;
-    // element q of a thread's share: (row, k) of the 128 x 32 tile
-    auto load = [&](int it) {
-        const int r = it / ktiles, k0 = (it % ktiles) * BK2;
-        const double *Ar = A + (long)r * sAr;
-        const double *Br = B + (long)r * sBr;
+
+    // k-fast share: k-pair 2 (tid & 15), rows (tid >> 4) + 16 q;
+    // m-fast share: column tid & 127, k-pairs 2 (tid >> 7) + 4 q   (q < 8)
+    const int kp = 2 * (tid & 15), rk = tid >> 4;
+    const int cm = tid & 127, km = 2 * (tid >> 7);
+    int offA[8], offB[8];
+    unsigned vA = 0, vB = 0;  // bit q: row rk + 16 q inside the operand
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if (!TA) {  // 32 threads per row along k
-                const int k = tid & 31, m = (tid >> 5) + 8 * q, gm = m0 + m, gk = k0 + k;
-                ra[q] = (gm < M && gk < K) ? Ar[(long)gm * lda + gk] : 0.0;
-            } else {    // 128 threads per k along m
-                const int m = tid & 127, k = (tid >> 7) + 2 * q, gm = m0 + m, gk = k0 + k;
-                ra[q] = (gm < M && gk < K) ? Ar[(long)gk * lda + gm] : 0.0;
+    for (int q = 0; q < 8; ++q) {
+        const int ra = m0 + rk + 16 * q, rb = n0 + rk + 16 * q;
+        vA |= (ra < M ? 1u : 0u) << q;
+        vB |= (rb < N ? 1u : 0u) << q;
+        offA[q] = (min(ra, M - 1) - m0) * (int)lda;
+        offB[q] = (min(rb, N - 1) - n0) * (int)ldb;
+    }
+    const double mAc = m0 + cm < M ? 1.0 : 0.0, mBc = n0 + cm < N ? 1.0 : 0.0;
+    const int cA = min(m0 + cm, M - 1) - m0, cB = min(n0 + cm, N - 1) - n0;
+
+    double xa[8][2], xb[8][2];
+    const int ktiles = (kend - kbeg + BK2 - 1) / BK2;
+    const int niter = ktiles * nred;
+
+    auto load = [&](int it) {
+        const int r = it / ktiles;
+        const int k0 = kbeg + (it % ktiles) * BK2;
+        const double *pA = A + (long)r * sAr + (TA ? (long)k0 * lda + m0 : (long)m0 * lda);
+        const double *pB = B + (long)r * sBr + (TB ? (long)n0 * ldb : (long)k0 * ldb + n0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if (!TA) {
+                    const int gk = k0 + kp + s;
+                    xa[q][s] = ldo(pA, offA[q] + min(gk, kend - 1)) * ((gk < kend && (vA >> q & 1u)) ? 1.0 : 0.0);
+                } else {
+                    const int gk = k0 + km + 4 * q + s;
+                    xa[q][s] = ldo(pA, (min(gk, kend - 1) - k0) * (int)lda + cA) * (gk < kend ? mAc : 0.0);
+                }
+                if (TB) {
+                    const int gk = k0 + kp + s;
+                    xb[q][s] = ldo(pB, offB[q] + min(gk, kend - 1)) * ((gk < kend && (vB >> q & 1u)) ? 1.0 : 0.0);
+                } else {
+                    const int gk = k0 + km + 4 * q + s;
+                    xb[q][s] = ldo(pB, (min(gk, kend - 1) - k0) * (int)ldb + cB) * (gk < kend ? mBc : 0.0);
+                }
             }
-            if (!TB) {
-                const int n = tid & 127, k = (tid >> 7) + 2 * q, gn = n0 + n, gk = k0 + k;
-                rb[q] = (gn < N && gk < K) ? Br[(long)gk * ldb + gn] : 0.0;
-            } else {
-                const int k = tid & 31, n = (tid >> 5) + 8 * q, gn = n0 + n, gk = k0 + k;
-                rb[q] = (gn < N && gk < K) ? Br[(long)gn * ldb + gk] : 0.0;
-            }
-        }
     };
     auto store = [&](int stg) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            __bf16 h, l;
-            split_bf16(ra[q], h, l);
-            if (!TA) {
-                const int k = tid & 31, m = (tid >> 5) + 8 * q;
-                Ah[stg][m][k] = h;
-                Al[stg][m][k] = l;
-            } else {
-                const int m = tid & 127, k = (tid >> 7) + 2 * q;
-                Ah[stg][m][k] = h;
-                Al[stg][m][k] = l;
+        for (int q = 0; q < 8; ++q) {
+            v2bf ha, la, hb, lb;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                __bf16 h, l;
+                split_bf16(xa[q][s] * alpha, h, l);
+                ha[s] = h;
+                la[s] = l;
+                split_bf16(xb[q][s], h, l);
+                hb[s] = h;
+                lb[s] = l;
             }
-            split_bf16(rb[q], h, l);
-            if (!TB) {
-                const int n = tid & 127, k = (tid >> 7) + 2 * q;
-                Bh[stg][n][k] = h;
-                Bl[stg][n][k] = l;
-            } else {
-                const int k = tid & 31, n = (tid >> 5) + 8 * q;
-                Bh[stg][n][k] = h;
-                Bl[stg][n][k] = l;
-            }
+            const int arow = TA ? cm : rk + 16 * q, acol = TA ? km + 4 * q : kp;
+            const int brow = TB ? rk + 16 * q : cm, bcol = TB ? kp : km + 4 * q;
+            *(v2bf *)&Ah[stg][arow][acol] = ha;
+            *(v2bf *)&Al[stg][arow][acol] = la;
+            *(v2bf *)&Bh[stg][brow][bcol] = hb;
+            *(v2bf *)&Bl[stg][brow][bcol] = lb;
         }
     };
+
     if (niter > 0) {
         load(0);
         store(0);
@@ -139,31 +192,54 @@ __global__ __launch_bounds__(256) void k_bgemm3(int M, int N, int K, double alph
     const int kofs = 8 * (lane >> 4);
     for (int it = 0; it < niter; ++it) {
         const int cur = it & 1;
-        if (it + 1 < niter) load(it + 1);
+        // next slab (the last iteration reloads its own slab: in bounds, never read)
+        load(min(it + 1, niter - 1));
         v8bf ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int m = wm * 64 + i * 16 + (lane & 15);
-            ah[i] = *(const v8bf *)&Ah[cur][m][kofs];
-            al[i] = *(const v8bf *)&Al[cur][m][kofs];
-        }
+        for (int i = 0; i < 4; ++i) ah[i] = *(const v8bf *)&Ah[cur][wm * 64 + i * 16 + (lane & 15)][kofs];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = wn * 64 + j * 16 + (lane & 15);
-            bh[j] = *(const v8bf *)&Bh[cur][n][kofs];
-            bl[j] = *(const v8bf *)&Bl[cur][n][kofs];
-        }
+        for (int j = 0; j < 4; ++j) bl[j] = *(const v8bf *)&Bl[cur][wn * 64 + j * 16 + (lane & 15)][kofs];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) al[i] = *(const v8bf *)&Al[cur][wm * 64 + i * 16 + (lane & 15)][kofs];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bh[j] = *(const v8bf *)&Bh[cur][wn * 64 + j * 16 + (lane & 15)][kofs];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-            }
-        if (it + 1 < niter) store(cur ^ 1);
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        // the other buffer was last read in iteration it-1, before the barrier that ended it
+        store(cur ^ 1);
+        // schedule: the fragments of the first product, the other fragment
+        // reads and the 32 global loads one per MFMA, and the 32 LDS writes
+        // four per MFMA over the last eight MFMAs of the slab
+#pragma unroll
+        for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            __builtin_amdgcn_sched_group_barrier(0x200, 4, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
         __syncthreads();
     }
+
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -174,8 +250,8 @@ __global__ __launch_bounds__(256) void k_bgemm3(int M, int N, int K, double alph
                 const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
                 if (row < M && col < N) {
                     double *cp = C + (long)row * ldc + col;
-                    const double v = alpha * (double)acc[i][j][e];
-                    *cp = (beta == 0.0) ? v : v + beta * *cp;
+                    if constexpr (BETA) *cp = (double)acc[i][j][e] + beta * *cp;
+                    else *cp = (double)acc[i][j][e];
                 }
             }
         }
@@ -183,27 +259,71 @@ __global__ __launch_bounds__(256) void k_bgemm3(int M, int N, int K, double alph
 
 }  // namespace
 
+// Split-BF16 product (mode 2); kc > 0: split-K ranges (kc a multiple of 32).
+hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
+{
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.ftypes) return hipErrorInvalidValue;  // FP32-stored operands: FP32 kernel only
+    const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
+    const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
+    if (total > 0x7fffffffL) return hipErrorInvalidValue;
+    // 32-bit offsets from a panel base; k-fast operands with rows too long for
+    // a full tile are issued in row (column) slices
+    auto fits = [](long span) { return 8 * span < (1L << 32); };
+    if (!g.transA && !fits((std::min<long>(BM, g.M) - 1) * g.lda + g.K)) {
+        long r = BM - 1;
+        while (r > 1 && !fits((r - 1) * g.lda + g.K)) --r;
+        if (g.lower || !fits((r - 1) * g.lda + g.K)) return hipErrorInvalidValue;
+        for (long m0 = 0; m0 < g.M; m0 += r) {
+            GemmArgs s = g;
+            s.M = (int)std::min<long>(r, g.M - m0);
+            s.A = g.A + m0 * g.lda;
+            s.C = g.C + m0 * g.ldc;
+            const hipError_t e = bgemm_kc(s, kc, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    if (g.transB && !fits((std::min<long>(BN, g.N) - 1) * g.ldb + g.K)) {
+        long r = BN - 1;
+        while (r > 1 && !fits((r - 1) * g.ldb + g.K)) --r;
+        if (g.lower || !fits((r - 1) * g.ldb + g.K)) return hipErrorInvalidValue;
+        for (long n0 = 0; n0 < g.N; n0 += r) {
+            GemmArgs s = g;
+            s.N = (int)std::min<long>(r, g.N - n0);
+            s.B = g.B + n0 * g.ldb;
+            s.C = g.C + n0;
+            const hipError_t e = bgemm_kc(s, kc, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const long spanA = g.transA ? (BK2 - 1) * g.lda + g.M : (std::min<long>(BM, g.M) - 1) * g.lda + g.K;
+    const long spanB = g.transB ? (std::min<long>(BN, g.N) - 1) * g.ldb + g.K : (BK2 - 1) * g.ldb + g.N;
+    if (!fits(spanA) || !fits(spanB)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)total);
+    const int nred = g.nred > 0 ? g.nred : 1;
+#define RIS_B3_LAUNCH1(TA, TB, BETA)                                                                               \
+    hipLaunchKernelGGL((k_bgemm3<TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,        \
+                       g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC,     \
+                       nred, tm, tn, (int)total, kc, g.lower);
+#define RIS_B3_LAUNCH2(TA, TB)                                                                                     \
+    if (g.beta != 0.0) { RIS_B3_LAUNCH1(TA, TB, true) } else { RIS_B3_LAUNCH1(TA, TB, false) }
+    if (!g.transA && !g.transB) { RIS_B3_LAUNCH2(false, false) }
+    else if (g.transA && !g.transB) { RIS_B3_LAUNCH2(true, false) }
+    else if (!g.transA && g.transB) { RIS_B3_LAUNCH2(false, true) }
+    else { RIS_B3_LAUNCH2(true, true) }
+#undef RIS_B3_LAUNCH2
+#undef RIS_B3_LAUNCH1
+    return hipGetLastError();
+}
+
 hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st)
 {
     if (mode == 0 || mode == 1) return gemm_kc(g, mode, 0, st);
-    if (g.ftypes) return hipErrorInvalidValue;  // FP32-stored operands: FP32 kernel only
-    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    if (g.lower) return hipErrorInvalidValue;  // lower-tile mode: FP64 / FP32 kernel only
-    const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
-    const long total = (long)tm * tn * g.batch;
-    if (total > 0x7fffffffL) return hipErrorInvalidValue;
-    dim3 grid((unsigned)total);
-    const int nred = g.nred > 0 ? g.nred : 1;
-#define RIS_MP_LAUNCH(KERN, TA, TB)                                                                                \
-    hipLaunchKernelGGL((KERN<TA, TB>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda, g.strideA,      \
-                       g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, \
-                       (int)total)
-    if (!g.transA && !g.transB) RIS_MP_LAUNCH(k_bgemm3, false, false);
-    else if (g.transA && !g.transB) RIS_MP_LAUNCH(k_bgemm3, true, false);
-    else if (!g.transA && g.transB) RIS_MP_LAUNCH(k_bgemm3, false, true);
-    else RIS_MP_LAUNCH(k_bgemm3, true, true);
-#undef RIS_MP_LAUNCH
-    return hipGetLastError();
+    if (mode != 2) return hipErrorInvalidValue;
+    return bgemm_kc(g, 0, st);
 }
 
 }  // namespace ris
