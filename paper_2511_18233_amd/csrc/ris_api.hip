@@ -1350,7 +1350,8 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
                           const float *FfJ, const double *W, const float *Wf, double *Y3, double *Gk, bool same)
 {
     const long o3 = 3L * o, NN = (long)N * N;
-    const bool f32 = c->prec == RIS_FP32;
+    // FP32 and split-BF16 modes: F, W and Y as float (both round them to FP32 first)
+    const bool f32 = c->prec == RIS_FP32 || c->prec == RIS_BF16X3;
     float *Y3f = (float *)Y3;
     GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, FI, o3, W, o3, 0.0, Y3, o3);
     g.batch = nP; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
@@ -1434,7 +1435,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
            *TR = P_(CW.oTR), *G1 = P_(CW.oG1), *V2 = P_(CW.oV2), *SK = P_(CW.oSK), *p3 = P_(CW.op3),
            *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP), *Tall = P_(CW.oTall),
            *HUU = P_(CW.oHUU), *W = P_(CW.oW), *Y3 = P_(CW.oY), *G = P_(CW.oG);
-    const bool f32 = c->prec == RIS_FP32;
+    const bool f32 = c->prec == RIS_FP32 || c->prec == RIS_BF16X3;
     float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
     const double *CO = c->C, *CV = c->C + o;
 
@@ -1609,9 +1610,9 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
            *cvec = P_(CW.ocv), *Tall = P_(CW.oTall), *HUO = P_(CW.oHUO), *HOU = P_(CW.oHOU), *HUU = P_(CW.oHUU),
            *W = P_(CW.oW), *Hc = P_(CW.oHc), *Y3 = P_(CW.oY), *G = P_(CW.oG), *V2 = P_(CW.oV2), *SK = P_(CW.oSK),
            *p3 = P_(CW.op3), *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP);
-    // FP32 mode: F, W and Y stored as float for the two products that build Gamma
-    // (their FP32 kernel rounds the operands to FP32 anyway: same results)
-    const bool f32 = c->prec == RIS_FP32;
+    // FP32 and split-BF16 modes: F, W and Y stored as float for the two products
+    // that build Gamma (both kernels round the operands to FP32 first: same results)
+    const bool f32 = c->prec == RIS_FP32 || c->prec == RIS_BF16X3;
     float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
     const double *CO = c->C, *CV = c->C + o;
 

@@ -60,16 +60,18 @@ __device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool l
     nt = tg / gm;
 }
 
-// double at a uniform base plus a 32-bit element offset (byte offset < 2^32)
-__device__ __forceinline__ double ldo(const double *base, int off)
+// element at a uniform base plus a 32-bit element offset (byte offset < 2^32)
+template <typename E>
+__device__ __forceinline__ E ldo(const E *base, int off)
 {
-    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + ((unsigned)off * 8u));
+    return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) + ((unsigned)off * (unsigned)sizeof(E)));
 }
 
-// x32 = fl32(x), hi = bf16(x32), lo = bf16(x32 - hi)
-__device__ __forceinline__ void split_bf16(double x, __bf16 &hi, __bf16 &lo)
+// x32 = fl32(x) * s, hi = bf16(x32), lo = bf16(x32 - hi)  (s: a 0/1 mask, or alpha)
+template <typename E>
+__device__ __forceinline__ void split_bf16(E x, float s, __bf16 &hi, __bf16 &lo)
 {
-    const float f = (float)x;
+    const float f = (float)x * s;
     hi = (__bf16)f;
     lo = (__bf16)(f - (float)hi);
 }
@@ -88,10 +90,13 @@ __device__ __forceinline__ void split_bf16(double x, __bf16 &hi, __bf16 &lo)
 // (batch index = k-range) and batch-reduce as in the FP64 kernel.
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
-template <bool TA, bool TB, bool BETA>
+//
+// EA, EB, EC: element types in memory (double, or float for operands that are
+// already FP32, which the split rounds to first anyway: same result).
+template <bool TA, bool TB, bool BETA, typename EA = double, typename EB = double, typename EC = double>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_bgemm3(
-    int M, int N, int K, double alpha, const double *__restrict__ A, long lda, long sA, long sAr,
-    const double *__restrict__ B, long ldb, long sB, long sBr, double beta, double *__restrict__ C, long ldc, long sC,
+    int M, int N, int K, double alpha, const EA *__restrict__ A, long lda, long sA, long sAr,
+    const EB *__restrict__ B, long ldb, long sB, long sBr, double beta, EC *__restrict__ C, long ldc, long sC,
     int nred, int tm, int tn, int total, int kc, bool lower)
 {
     __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][BK2 + PAD2];
@@ -129,35 +134,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         offA[q] = (min(ra, M - 1) - m0) * (int)lda;
         offB[q] = (min(rb, N - 1) - n0) * (int)ldb;
     }
-    const double mAc = m0 + cm < M ? 1.0 : 0.0, mBc = n0 + cm < N ? 1.0 : 0.0;
+    const bool vAc = m0 + cm < M, vBc = n0 + cm < N;
     const int cA = min(m0 + cm, M - 1) - m0, cB = min(n0 + cm, N - 1) - n0;
+    const float falpha = (float)alpha;
 
-    double xa[8][2], xb[8][2];
+    EA xa[8][2];
+    EB xb[8][2];
+    float fa[8][2], fb[8][2];  // 0/1 validity (times alpha for A), applied in FP32 at the split
     const int ktiles = (kend - kbeg + BK2 - 1) / BK2;
     const int niter = ktiles * nred;
 
     auto load = [&](int it) {
         const int r = it / ktiles;
         const int k0 = kbeg + (it % ktiles) * BK2;
-        const double *pA = A + (long)r * sAr + (TA ? (long)k0 * lda + m0 : (long)m0 * lda);
-        const double *pB = B + (long)r * sBr + (TB ? (long)n0 * ldb : (long)k0 * ldb + n0);
+        const EA *pA = A + (long)r * sAr + (TA ? (long)k0 * lda + m0 : (long)m0 * lda);
+        const EB *pB = B + (long)r * sBr + (TB ? (long)n0 * ldb : (long)k0 * ldb + n0);
 #pragma unroll
         for (int q = 0; q < 8; ++q)
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 if (!TA) {
                     const int gk = k0 + kp + s;
-                    xa[q][s] = ldo(pA, offA[q] + min(gk, kend - 1)) * ((gk < kend && (vA >> q & 1u)) ? 1.0 : 0.0);
+                    xa[q][s] = ldo(pA, offA[q] + min(gk, kend - 1));
+                    fa[q][s] = (gk < kend && (vA >> q & 1u)) ? falpha : 0.0f;
                 } else {
                     const int gk = k0 + km + 4 * q + s;
-                    xa[q][s] = ldo(pA, (min(gk, kend - 1) - k0) * (int)lda + cA) * (gk < kend ? mAc : 0.0);
+                    xa[q][s] = ldo(pA, (min(gk, kend - 1) - k0) * (int)lda + cA);
+                    fa[q][s] = (gk < kend && vAc) ? falpha : 0.0f;
                 }
                 if (TB) {
                     const int gk = k0 + kp + s;
-                    xb[q][s] = ldo(pB, offB[q] + min(gk, kend - 1)) * ((gk < kend && (vB >> q & 1u)) ? 1.0 : 0.0);
+                    xb[q][s] = ldo(pB, offB[q] + min(gk, kend - 1));
+                    fb[q][s] = (gk < kend && (vB >> q & 1u)) ? 1.0f : 0.0f;
                 } else {
                     const int gk = k0 + km + 4 * q + s;
-                    xb[q][s] = ldo(pB, (min(gk, kend - 1) - k0) * (int)ldb + cB) * (gk < kend ? mBc : 0.0);
+                    xb[q][s] = ldo(pB, (min(gk, kend - 1) - k0) * (int)ldb + cB);
+                    fb[q][s] = (gk < kend && vBc) ? 1.0f : 0.0f;
                 }
             }
     };
@@ -168,10 +180,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 __bf16 h, l;
-                split_bf16(xa[q][s] * alpha, h, l);
+                split_bf16(xa[q][s], fa[q][s], h, l);
                 ha[s] = h;
                 la[s] = l;
-                split_bf16(xb[q][s], h, l);
+                split_bf16(xb[q][s], fb[q][s], h, l);
                 hb[s] = h;
                 lb[s] = l;
             }
@@ -249,9 +261,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int e = 0; e < 4; ++e) {
                 const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
                 if (row < M && col < N) {
-                    double *cp = C + (long)row * ldc + col;
-                    if constexpr (BETA) *cp = (double)acc[i][j][e] + beta * *cp;
-                    else *cp = (double)acc[i][j][e];
+                    EC *cp = C + (long)row * ldc + col;
+                    if constexpr (BETA) *cp = (EC)((double)acc[i][j][e] + beta * (double)*cp);
+                    else *cp = (EC)acc[i][j][e];
                 }
             }
         }
@@ -263,7 +275,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-    if (g.ftypes) return hipErrorInvalidValue;  // FP32-stored operands: FP32 kernel only
     const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
     if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
     const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
@@ -275,11 +286,12 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
         long r = BM - 1;
         while (r > 1 && !fits((r - 1) * g.lda + g.K)) --r;
         if (g.lower || !fits((r - 1) * g.lda + g.K)) return hipErrorInvalidValue;
+        const size_t szA = (g.ftypes & kF32A) ? 4 : 8, szC = (g.ftypes & kF32C) ? 4 : 8;
         for (long m0 = 0; m0 < g.M; m0 += r) {
             GemmArgs s = g;
             s.M = (int)std::min<long>(r, g.M - m0);
-            s.A = g.A + m0 * g.lda;
-            s.C = g.C + m0 * g.ldc;
+            s.A = (const double *)((const char *)g.A + (size_t)m0 * g.lda * szA);
+            s.C = (double *)((char *)g.C + (size_t)m0 * g.ldc * szC);
             const hipError_t e = bgemm_kc(s, kc, st);
             if (e != hipSuccess) return e;
         }
@@ -289,11 +301,12 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
         long r = BN - 1;
         while (r > 1 && !fits((r - 1) * g.ldb + g.K)) --r;
         if (g.lower || !fits((r - 1) * g.ldb + g.K)) return hipErrorInvalidValue;
+        const size_t szB = (g.ftypes & kF32B) ? 4 : 8, szC = (g.ftypes & kF32C) ? 4 : 8;
         for (long n0 = 0; n0 < g.N; n0 += r) {
             GemmArgs s = g;
             s.N = (int)std::min<long>(r, g.N - n0);
-            s.B = g.B + n0 * g.ldb;
-            s.C = g.C + n0;
+            s.B = (const double *)((const char *)g.B + (size_t)n0 * g.ldb * szB);
+            s.C = (double *)((char *)g.C + (size_t)n0 * szC);
             const hipError_t e = bgemm_kc(s, kc, st);
             if (e != hipSuccess) return e;
         }
@@ -304,6 +317,29 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
     if (!fits(spanA) || !fits(spanB)) return hipErrorInvalidValue;
     dim3 grid((unsigned)total);
     const int nred = g.nred > 0 ? g.nred : 1;
+    if (g.ftypes != 0) {
+        // FP32-stored operands: Y = F_I W (float in, float out) and Gamma
+        // from float Y and F_J (double out, BETA for the second NAC half)
+        if (kc > 0) return hipErrorInvalidValue;
+        if (g.ftypes == (kF32A | kF32B | kF32C) && !g.transA && !g.transB && g.beta == 0.0)
+            hipLaunchKernelGGL((k_bgemm3<false, false, false, float, float, float>), grid, dim3(256), 0, st, g.M, g.N,
+                               g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
+                               g.strideB, g.strideBr, g.beta, (float *)g.C, g.ldc, g.strideC, nred, tm, tn, (int)total,
+                               kc, g.lower);
+        else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB && g.beta == 0.0)
+            hipLaunchKernelGGL((k_bgemm3<false, true, false, float, float, double>), grid, dim3(256), 0, st, g.M, g.N,
+                               g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
+                               g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, (int)total, kc,
+                               g.lower);
+        else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB)
+            hipLaunchKernelGGL((k_bgemm3<false, true, true, float, float, double>), grid, dim3(256), 0, st, g.M, g.N,
+                               g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
+                               g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, (int)total, kc,
+                               g.lower);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
 #define RIS_B3_LAUNCH1(TA, TB, BETA)                                                                               \
     hipLaunchKernelGGL((k_bgemm3<TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,        \
                        g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC,     \
