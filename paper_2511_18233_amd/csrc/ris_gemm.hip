@@ -13,6 +13,7 @@
 // interleaved across the four lane groups; checked by the layout probe test).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "ris_common.hpp"
 
@@ -151,20 +152,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // a select, so the compiler keeps the loads unconditional).  The launcher
     // guarantees that every byte offset fits 32 bits (scalar base + 32-bit
     // vector offset addressing).
+    // staged values and their factors: FP32 for float operands (no FP64
+    // arithmetic on them), FP64 otherwise
+    typedef typename std::conditional<std::is_same<EA, float>::value, float, double>::type RA;
+    typedef typename std::conditional<std::is_same<EB, float>::value, float, double>::type RB;
     int offA[NQ], offB[NQ];
-    double mA[NQ], mB[NQ];
+    RA mA[NQ];
+    RB mB[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int gm = m0 + rf + RSTEP * q, gn = n0 + rf + RSTEP * q;
-        mA[q] = gm < M ? 1.0 : 0.0;
-        mB[q] = gn < N ? 1.0 : 0.0;
+        mA[q] = gm < M ? RA(1) : RA(0);
+        mB[q] = gn < N ? RB(1) : RB(0);
         offA[q] = (min(gm, M - 1) - m0) * (int)lda;
         offB[q] = (min(gn, N - 1) - n0) * (int)ldb;
     }
-    const double mAc = m0 + cf < M ? 1.0 : 0.0, mBc = n0 + cf < N ? 1.0 : 0.0;
+    const RA mAc = m0 + cf < M ? RA(1) : RA(0);
+    const RB mBc = n0 + cf < N ? RB(1) : RB(0);
     const int cA = min(m0 + cf, M - 1) - m0, cB = min(n0 + cf, N - 1) - n0;
+    const RA ralpha = (RA)alpha;
 
-    double ra[NQ], rb[NQ];
+    RA ra[NQ];
+    RB rb[NQ];
     const int ktiles = (kend - kbeg + SK - 1) / SK;
     const int niter = ktiles * nred;
 
@@ -178,28 +187,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int q = 0; q < NQ; ++q) {
             if (!TA) {
                 const int gk = k0 + kf;
-                const double x = ld_off(pA, offA[q] + min(gk, kend - 1));
-                ra[q] = x * (gk < kend ? mA[q] : 0.0);
+                const RA x = (RA)ld_off(pA, offA[q] + min(gk, kend - 1));
+                ra[q] = x * (gk < kend ? mA[q] : RA(0));
             } else {
                 const int gk = k0 + kr + 2 * q;
-                const double x = ld_off(pA, (min(gk, kend - 1) - k0) * (int)lda + cA);
-                ra[q] = x * (gk < kend ? mAc : 0.0);
+                const RA x = (RA)ld_off(pA, (min(gk, kend - 1) - k0) * (int)lda + cA);
+                ra[q] = x * (gk < kend ? mAc : RA(0));
             }
             if (!TB) {
                 const int gk = k0 + kr + 2 * q;
-                const double x = ld_off(pB, (min(gk, kend - 1) - k0) * (int)ldb + cB);
-                rb[q] = x * (gk < kend ? mBc : 0.0);
+                const RB x = (RB)ld_off(pB, (min(gk, kend - 1) - k0) * (int)ldb + cB);
+                rb[q] = x * (gk < kend ? mBc : RB(0));
             } else {
                 const int gk = k0 + kf;
-                const double x = ld_off(pB, offB[q] + min(gk, kend - 1));
-                rb[q] = x * (gk < kend ? mB[q] : 0.0);
+                const RB x = (RB)ld_off(pB, offB[q] + min(gk, kend - 1));
+                rb[q] = x * (gk < kend ? mB[q] : RB(0));
             }
         }
     };
     auto store = [&](int stg) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const T x = (T)(ra[q] * alpha), y = (T)rb[q];
+            const T x = (T)(ra[q] * ralpha), y = (T)rb[q];
             if (!TA) As[stg][kf][rf + RSTEP * q] = x;
             else As[stg][kr + 2 * q][cf] = x;
             if (!TB) Bs[stg][kr + 2 * q][cf] = y;
