@@ -43,3 +43,31 @@ def test_binding_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         RisContext(0)
+
+
+def _plan(name, block):
+    import numpy as np
+    import molgen
+    from paper_2511_18233_amd.ris import request_bytes
+    kind, natm, basis, ns, _ = molgen.WORKLOADS[name]
+    m = molgen.make_molecule(kind, natm, basis, np.random.default_rng(molgen.WORKLOAD_SEED[name]))
+    nocc = m.nelec // 2
+    return request_bytes(m.Z, m.shell_atom, m.shell_l, molgen.radii_bohr_table(), m.nao, nocc, ns, ns, 2 * ns - 1,
+                         aux_block=block)
+
+
+def test_hbm_planner_host_sizing():
+    """ris_plan_bytes (host-only): blocking over the auxiliary index shrinks
+    the footprint monotonically with the block size; the 500-atom request
+    does not fit one 288 GB GPU unblocked but does with 100-function blocks."""
+    from paper_2511_18233_amd import ris
+    if not os.path.exists(ris.LIB_PATH):
+        pytest.skip("libris_hip.so not built (run __graft_entry__.build())")
+    full = _plan("chain200", 0)
+    sizes = [_plan("chain200", b) for b in (8, 16, 32, 64, 128)]
+    assert all(a <= b for a, b in zip(sizes, sizes[1:]))
+    assert sizes[-1] < full
+    assert 70e9 < full < 90e9
+    assert _plan("chain500", 0) > 288e9
+    assert _plan("chain500", 100) < 0.9 * 288e9
+    assert _plan("chain500", -1) == 0
