@@ -1355,6 +1355,10 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
     float *Y3f = (float *)Y3;
     GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, FI, o3, W, o3, 0.0, Y3, o3);
     g.batch = nP; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
+    // W^P (rows / cols [U_R, C_O, U_L]) is zero in its (U_L, U_R) and (U_R, U_L)
+    // blocks: column tiles inside the U_R block need rows [0, 2o) of W, those
+    // inside the U_L block rows [o, 3o)
+    g.kband = o;
     if (f32) {
         g.A = (const double *)FfI;
         g.B = (const double *)Wf;
@@ -1448,11 +1452,11 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
         GemmArgs g = gm(N, o, v, false, false, 1.0, CV, nmo, R, o, 0.0, F, o3);
         g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
         HIPCHK(c, dgemm(g, c->stream));
-        g = gm(N, o, v, false, false, 1.0, CV, nmo, L, o, 0.0, F + o, o3);
+        g = gm(N, o, v, false, false, 1.0, CV, nmo, L, o, 0.0, F + 2 * o, o3);
         g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
         HIPCHK(c, dgemm(g, c->stream));
         for (int s = 0; s < ns; ++s)
-            HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + 2 * o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
+            HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
                                        hipMemcpyDeviceToDevice, c->stream));
         if (f32) HIPCHK(c, to_float(F, Ff, (size_t)ns * N * o3, c->stream));
         g = gm(N, N, o, false, true, 1.0, F, o3, CO, nmo, 0.0, D, N);
@@ -1511,7 +1515,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
             stage_end(c, t_b, RIS_STAGE_HBLK, 4.0 * (double)m * v * v * o + 4.0 * (double)m * oo * v, 0.0);
-            // exchange weights W^P of the block (rows / cols [U_R, U_L, C_O])
+            // exchange weights W^P of the block (rows / cols [U_R, C_O, U_L])
             hipEvent_t t_yw = stage_begin(c);
             const BlockSrc Hoo = blk(c->coo + (size_t)p0 * oo, oo, o, 1, 1.0);
             const BlockSrc HRuo = blk(HIt[0] + (size_t)p0 * oo, oo, 1, o, 1.0);
@@ -1521,10 +1525,10 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
             const BlockSrc HRuu = blk(HUU, oo, o, 1, 1.0);
             const BlockSrc HLuu = blk(HUU + (size_t)m * oo, oo, o, 1, 1.0);
             BlockGrid gw{};
-            gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = none;             gw.b[0][2][0] = sc(HRou, 0.25);
-            gw.b[1][0][0] = none;           gw.b[1][1][0] = sc(Hoo, 0.25);   gw.b[1][2][0] = sc(HLou, -0.25);
-            gw.b[2][0][0] = sc(HRuo, 0.25); gw.b[2][1][0] = sc(HLuo, -0.25); gw.b[2][2][0] = sc(HRuu, 0.25);
-            gw.b[2][2][1] = sc(HLuu, 0.25);
+            gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = sc(HRou, 0.25);  gw.b[0][2][0] = none;
+            gw.b[1][0][0] = sc(HRuo, 0.25); gw.b[1][1][0] = sc(HRuu, 0.25);  gw.b[1][2][0] = sc(HLuo, -0.25);
+            gw.b[1][1][1] = sc(HLuu, 0.25);
+            gw.b[2][0][0] = none;           gw.b[2][1][0] = sc(HLou, -0.25); gw.b[2][2][0] = sc(Hoo, 0.25);
             HIPCHK(c, assemble3(gw, W, o, m, c->stream, f32 ? Wf : nullptr));
             stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 9.0 * (double)oo * m);
             // G rows of the block: <H_RUU^P + H_LUU^P, c_oo^Q>
@@ -1578,7 +1582,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
 // Gradients / NAC numerators for a list of state pairs (I, J):
 //   out[k] = d/dR [ alpha_J sum (mn|ls)_J R^S_I R^S_J - c_x sum (ml|ns)_K (R^S_I R^S_J + L^A_I L^A_J) ]
 // with the exchange weights Gamma^P = D_I C^P D_J^T built from the rank-3o
-// factors F_s = [C_V R_s, C_V L_s, C_O]: Gamma^P = F_I W^P F_J^T.
+// factors F_s = [C_V R_s, C_O, C_V L_s]: Gamma^P = F_I W^P F_J^T.
 static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double *Y, int npair, const int *pI,
                           const int *pJ, double *outg)
 {
@@ -1623,15 +1627,15 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
     HIPCHK(c, permute3(R, RLT, v, ns, o, o, vo, 1, w2, o, 1, c->stream));
     HIPCHK(c, permute3(L, RLT + (size_t)ns * o, v, ns, o, o, vo, 1, w2, o, 1, c->stream));
     {
-        // F_s = [C_V R_s, C_V L_s, C_O]  (N x 3o)
+        // F_s = [C_V R_s, C_O, C_V L_s]  (N x 3o)
         GemmArgs g = gm(N, o, v, false, false, 1.0, CV, nmo, R, o, 0.0, F, o3);
         g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
         HIPCHK(c, dgemm(g, c->stream));
-        g = gm(N, o, v, false, false, 1.0, CV, nmo, L, o, 0.0, F + o, o3);
+        g = gm(N, o, v, false, false, 1.0, CV, nmo, L, o, 0.0, F + 2 * o, o3);
         g.batch = ns; g.strideA = 0; g.strideB = vo; g.strideC = (long)N * o3;
         HIPCHK(c, dgemm(g, c->stream));
         for (int s = 0; s < ns; ++s)
-            HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + 2 * o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
+            HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
                                        hipMemcpyDeviceToDevice, c->stream));
         if (f32) HIPCHK(c, to_float(F, Ff, (size_t)ns * N * o3, c->stream));
         // D_s = sym(U_Rs C_O^T) = R^S_s
@@ -1697,19 +1701,19 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             const BlockSrc HLuu = blk(HUU + (size_t)nK * oo, oo, o, 1, 1.0);
             const BlockSrc none{nullptr, 0, 0, 0, 0.0};
             auto sc = [](BlockSrc b, double f) { b.scale *= f; return b; };
-            // exchange weights W^P (rows/cols [U_R, U_L, C_O]) from D = (U C_O^T +- C_O U^T)/2
+            // exchange weights W^P (rows/cols [U_R, C_O, U_L]) from D = (U C_O^T +- C_O U^T)/2
             hipEvent_t t_yw = stage_begin(c);
             BlockGrid gw{};
-            gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = none;             gw.b[0][2][0] = sc(HRou, 0.25);
-            gw.b[1][0][0] = none;           gw.b[1][1][0] = sc(Hoo, 0.25);   gw.b[1][2][0] = sc(HLou, -0.25);
-            gw.b[2][0][0] = sc(HRuo, 0.25); gw.b[2][1][0] = sc(HLuo, -0.25); gw.b[2][2][0] = sc(HRuu, 0.25);
-            gw.b[2][2][1] = sc(HLuu, 0.25);
+            gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = sc(HRou, 0.25);  gw.b[0][2][0] = none;
+            gw.b[1][0][0] = sc(HRuo, 0.25); gw.b[1][1][0] = sc(HRuu, 0.25);  gw.b[1][2][0] = sc(HLuo, -0.25);
+            gw.b[1][1][1] = sc(HLuu, 0.25);
+            gw.b[2][0][0] = none;           gw.b[2][1][0] = sc(HLou, -0.25); gw.b[2][2][0] = sc(Hoo, 0.25);
             HIPCHK(c, assemble3(gw, W, o, nK, c->stream, f32 ? Wf : nullptr));
             // H^P = F_I^T C^P F_J over the blocks where W is nonzero
             BlockGrid gh{};
-            gh.b[0][0][0] = HRuu; gh.b[0][2][0] = HRuo;
-            gh.b[1][1][0] = HLuu; gh.b[1][2][0] = HLuo;
-            gh.b[2][0][0] = HRou; gh.b[2][1][0] = HLou; gh.b[2][2][0] = Hoo;
+            gh.b[0][0][0] = HRuu; gh.b[0][1][0] = HRuo;
+            gh.b[1][0][0] = HRou; gh.b[1][1][0] = Hoo; gh.b[1][2][0] = HLou;
+            gh.b[2][1][0] = HLuo; gh.b[2][2][0] = HLuu;
             HIPCHK(c, assemble3(gh, Hc, o, nK, c->stream));
             stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 2.0 * 9.0 * (double)oo * nK);
             hipEvent_t t_v = stage_begin(c);

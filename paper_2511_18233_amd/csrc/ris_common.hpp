@@ -104,6 +104,11 @@ struct GemmArgs {
     // bits kF32A / kF32B / kF32C: that operand is stored as float (FP32 mode only;
     // supported: A, B, C float with no transposes, or A, B float with B transposed)
     int ftypes;
+    // kband = w > 0 (K = 3w, B untransposed, no split-K): B's rows and columns
+    // are three blocks of w and B is zero in its (3rd row, 1st column) and
+    // (1st row, 3rd column) blocks, so a column tile inside the first block
+    // reads rows [0, 2w) and one inside the third block rows [w, 3w)
+    int kband;
 };
 constexpr int kF32A = 1, kF32B = 2, kF32C = 4;
 hipError_t dgemm(const GemmArgs &g, hipStream_t st);
