@@ -35,10 +35,10 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the lower-tile Gamma back-transform GEMM from the
 # FETCH_SIZE / WRITE_SIZE counter runs on the 199-atom workload (fetch scaled by
 # 2.0, write by 1.0 after a 1 GiB copy calibration), averaged over the 28
-# launches of a step (19 plain: 29.69 + 3.81 GB, 9 accumulating: 27.04 + 4.37 GB);
+# launches of a step (19 plain: 30.60 + 3.81 GB, 9 accumulating: 26.78 + 4.37 GB);
 # valid only for the GEMM source it was measured on (sha256 prefix; a later edit
 # that left the FP64 kernels' machine code identical keeps them valid); null otherwise.
-GAMMA_TRAFFIC = {"gemm_src_sha256": "b1a66269458a69e5", "workload": "chain200", "bytes_per_launch": 32.83e9}
+GAMMA_TRAFFIC = {"gemm_src_sha256": "d1a0acbb5fb92aeb", "workload": "chain200", "bytes_per_launch": 33.36e9}
 
 
 def log(*a):
