@@ -108,8 +108,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     int bz, mt, nt;
     tile_of(blockIdx.x, total, tm, tn, lower, bz, mt, nt);
     const int m0 = mt * BM, n0 = nt * BN;
-    const int kbeg = kc > 0 ? bz * kc : 0;
-    const int kend = kc > 0 ? min(K, kbeg + kc) : K;
+    // kc > 0: split-K range of the batch index; kc < 0: banded K of width -kc
+    int kbeg = 0, kend = K;
+    if (kc > 0) {
+        kbeg = bz * kc;
+        kend = min(K, kbeg + kc);
+    } else if (kc < 0) {
+        if (n0 >= -2 * kc) kbeg = -kc;
+        if (n0 + BN <= -kc) kend = min(K, -2 * kc);
+    }
     A += (long)bz * sA;
     B += (long)bz * sB;
     C += (long)bz * sC;
@@ -275,6 +282,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.kband > 0) {  // banded K (see GemmArgs), carried as kc = -kband
+        if (kc != 0 || g.transB || g.lower || g.K != 3 * g.kband) return hipErrorInvalidValue;
+        kc = -g.kband;
+    }
     const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
     if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
     const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
@@ -289,6 +300,7 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
         const size_t szA = (g.ftypes & kF32A) ? 4 : 8, szC = (g.ftypes & kF32C) ? 4 : 8;
         for (long m0 = 0; m0 < g.M; m0 += r) {
             GemmArgs s = g;
+            s.kband = 0;  // carried by kc from here on
             s.M = (int)std::min<long>(r, g.M - m0);
             s.A = (const double *)((const char *)g.A + (size_t)m0 * g.lda * szA);
             s.C = (double *)((char *)g.C + (size_t)m0 * g.ldc * szC);
@@ -304,6 +316,7 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
         const size_t szB = (g.ftypes & kF32B) ? 4 : 8, szC = (g.ftypes & kF32C) ? 4 : 8;
         for (long n0 = 0; n0 < g.N; n0 += r) {
             GemmArgs s = g;
+            s.kband = 0;
             s.N = (int)std::min<long>(r, g.N - n0);
             s.B = (const double *)((const char *)g.B + (size_t)n0 * g.ldb * szB);
             s.C = (double *)((char *)g.C + (size_t)n0 * szC);
