@@ -37,18 +37,19 @@ def _to(a, dev):
     return torch.as_tensor(np.ascontiguousarray(a), device=dev)
 
 
-def _run(ctx, prob, radii, block, outs, precision="fp64", dbg=False):
+def _run(ctx, prob, radii, block, outs, precision="fp64", dbg=False, jp=True):
     import torch
     m = prob.mol
     ctx.set_blocking(block)
-    nJ, nK = ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, True)
+    nJ, nK = ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
     dbg_t = torch.empty((nJ, m.nao, m.nao), dtype=torch.float64, device=ctx.device) if dbg else None
     ctx.int3c(_to(prob.C, ctx.device), _to(prob.eps, ctx.device), prob.nocc, 2.0, 0.25, precision=precision,
               dbg=dbg_t)
     rng = np.random.default_rng(11)
     V = rng.standard_normal((2,) + prob.X.shape[1:])
     mv = {op: ctx.response_matvec(op, _to(V, ctx.device)).cpu().numpy() for op in ("A+B", "A-B")}
-    X, Y = _to(prob.X, ctx.device), _to(prob.Y, ctx.device)
+    X = _to(prob.X, ctx.device)
+    Y = None if prob.Y is None else _to(prob.Y, ctx.device)
     g, n = ctx.grad_nac_contract(X, Y, [i for (i, j) in outs if i == j], [(i, j) for (i, j) in outs if i != j])
     got = np.concatenate([g.cpu().numpy(), n.cpu().numpy()])
     return nJ, nK, got, mv, (dbg_t.cpu().numpy() if dbg else None)
@@ -131,3 +132,25 @@ def test_budget_forces_blocks(ctx, radii):
     d = np.abs(got - ref_gpu).max()
     say(f"[gpu]   budget-blocked vs unblocked {d:.2e}")
     assert d <= 1e-12
+
+
+def test_blocked_tda_s_only_screen_off(ctx, radii):
+    """TDA amplitudes (Y = NULL), an s-only auxiliary set (J = K: no
+    Coulomb-only shells after the blocks) and the shell-pair screen off."""
+    from oracle import ris_oracle as O
+    prob = molgen.make_problem("ring12")
+    outs = _outs(prob.nstate)
+    try:
+        ctx.set_screening(0.0)
+        say("[gpu] blocking ring12 (TDA, s-only aux, screen off): unblocked run")
+        nJ, nK, ref_gpu, _, _ = _run(ctx, prob, radii, 0, outs, jp=False)
+        assert nJ == nK
+        say("[gpu]   blocked run (block 5)")
+        _, _, got, _, _ = _run(ctx, prob, radii, 5, outs, jp=False)
+    finally:
+        ctx.set_screening(1e-15)
+    ref = O.grad_nac(prob, radii, outs, j_p_on_heavy=False)
+    e_or, e_un = np.abs(got - ref).max(), np.abs(got - ref_gpu).max()
+    say(f"[gpu]   blocked vs oracle {e_or:.2e}, vs unblocked {e_un:.2e}")
+    assert e_or <= 1e-8
+    assert e_un <= 1e-12
