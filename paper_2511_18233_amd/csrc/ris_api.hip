@@ -56,6 +56,12 @@ struct ris_ctx {
     std::vector<double> h_sh_xyz, h_sh_exp;  // [nsh][3], [nsh]
     int *d_pair_ptr = nullptr, *d_pair_idx = nullptr;
     long npair_kept = 0;
+    // the 128 x 128 lower tiles of an AO-pair matrix that hold a kept shell
+    // pair (mt << 16 | nt): the exchange weights Gamma^P are formed only there
+    std::vector<int> h_sh_off;  // first AO function of each internal shell (+ total)
+    int *d_gtiles = nullptr;
+    int ngtiles = 0;
+    double gtile_lower = 0.0;  // elements on or below the diagonal inside those tiles
 
     // ---- int3c state
     bool have_int3c = false;
@@ -194,6 +200,8 @@ void free_aux(ris_ctx *c)
     free_int3c(c);
     c->d_ao_perm = nullptr;
     c->d_pair_ptr = c->d_pair_idx = nullptr;
+    c->d_gtiles = nullptr;
+    c->ngtiles = 0;
     c->MJ = c->LinvJ = c->MinvJ = c->MinvK = nullptr;
     c->ao = AOGeom{};
     c->aux = AuxGeom{};
@@ -310,9 +318,33 @@ int build_pairs(ris_ctx *c)
         }
     ptr[(size_t)ncls * nsh] = (int)idx.size();
     c->npair_kept = (long)idx.size();
+    // lower 128-tiles touched by a kept pair (the relation is symmetric)
+    const int N = c->nao, T = 128, tm = (N + T - 1) / T;
+    const std::vector<int> &off = c->h_sh_off;
+    std::vector<char> mark((size_t)tm * tm, 0);
+    for (int a = 0; a < nsh; ++a)
+        for (size_t q = ptr[(size_t)ncls * a]; q < (size_t)ptr[(size_t)ncls * (a + 1)]; ++q) {
+            const int b = idx[q];
+            for (int ta = off[a] / T; ta <= (off[a + 1] - 1) / T; ++ta)
+                for (int tb = off[b] / T; tb <= (off[b + 1] - 1) / T; ++tb)
+                    mark[(size_t)std::max(ta, tb) * tm + std::min(ta, tb)] = 1;
+        }
+    std::vector<int> tiles;
+    double lower = 0.0;
+    for (int mt = 0; mt < tm; ++mt)
+        for (int nt = 0; nt <= mt; ++nt)
+            if (mark[(size_t)mt * tm + nt]) {
+                tiles.push_back(mt << 16 | nt);
+                const double rows = std::min(N, mt * T + T) - mt * T, cols = std::min(N, nt * T + T) - nt * T;
+                lower += mt > nt ? rows * cols : rows * (rows + 1) / 2;
+            }
+    c->ngtiles = (int)tiles.size();
+    c->gtile_lower = lower;
     HIPCHK(c, hipMemcpyAsync(c->d_pair_ptr, ptr.data(), 4 * ptr.size(), hipMemcpyHostToDevice, c->stream));
     if (!idx.empty())
         HIPCHK(c, hipMemcpyAsync(c->d_pair_idx, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, c->stream));
+    if (!tiles.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_gtiles, tiles.data(), 4 * tiles.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RIS_OK;
 }
@@ -479,7 +511,7 @@ ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
 }
 
 struct AuxLayout {
-    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, oPP, oPI, total;
+    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, oPP, oPI, oGT, total;
 };
 AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
 {
@@ -495,6 +527,9 @@ AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
     // screened pair lists sized for the unscreened worst case (ints, 2 per slot)
     L.oPP = cv.take(((size_t)(kMaxAOL + 1) * nsh + 2) / 2);
     L.oPI = cv.take(((size_t)nsh * nsh + 1) / 2);
+    // lower-tile list of the AO-pair matrix (ints, 2 per slot)
+    const size_t tm = (size_t)(nao + 127) / 128;
+    L.oGT = cv.take((tm * (tm + 1) / 2 + 1) / 2);
     L.total = cv.off;
     return L;
 }
@@ -1026,6 +1061,7 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         f += ncart(l);
     }
     off[nsh] = f;
+    c->h_sh_off = off;
     c->h_sh_xyz.resize(3 * (size_t)nsh);
     for (int i = 0; i < nsh; ++i) {
         c->h_sh_xyz[3 * i] = x[i];
@@ -1077,6 +1113,7 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         c->MinvK = (double *)(base + AL.oIK);
         c->d_pair_ptr = (int *)(base + AL.oPP);
         c->d_pair_idx = (int *)(base + AL.oPI);
+        c->d_gtiles = (int *)(base + AL.oGT);
     }
     c->aux.nshell = nshJ;
     c->aux.nfunc = f;
@@ -1371,12 +1408,16 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
     // one timed group per GEMM launch; a lower-tile launch does
     // nP N (N + 1) 3o flops and moves Y, F_J (float in the FP32 mode)
     // and the lower half of Gamma (always double)
-    const double fl_low = (double)nP * N * (N + 1) * o3;
+    // only the lower tiles that hold a kept AO shell pair (the derivative
+    // contraction reads Gamma nowhere else); the flops and bytes counted are
+    // those of the lower-triangle elements inside them
+    const double fl_low = 2.0 * nP * c->gtile_lower * o3;
     const double ein = f32 ? 4.0 : 8.0;
-    const double by_low = ein * ((double)nP * N * o3 + (double)N * o3) + 8.0 * (double)nP * N * (N + 1) / 2;
+    const double by_low = ein * ((double)nP * N * o3 + (double)N * o3) + 8.0 * nP * c->gtile_lower;
     if (same) {
         g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
         g.batch = nP; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
+        g.tiles = c->d_gtiles; g.ntiles = c->ngtiles;
         if (f32) {
             g.A = (const double *)Y3f;
             g.B = (const double *)FfJ;
@@ -1388,6 +1429,7 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
     } else {
         g = gm(N, N, (int)o3, false, true, -c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
         g.batch = nP; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
+        g.tiles = c->d_gtiles; g.ntiles = c->ngtiles;
         if (f32) {
             g.A = (const double *)Y3f;
             g.B = (const double *)FfJ;
@@ -1398,6 +1440,7 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
         stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
         g = gm(N, N, (int)o3, false, true, -c->cx, FJ, o3, Y3, o3, 1.0, Gk, N);
         g.batch = nP; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
+        g.tiles = c->d_gtiles; g.ntiles = c->ngtiles;
         if (f32) {
             g.A = (const double *)FfJ;
             g.B = (const double *)Y3f;
@@ -1406,7 +1449,7 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
         t_g = stage_begin(c);
         HIPCHK(c, gemm_mp(g, c->prec, c->stream));
         // the accumulating launch also reads the lower half of Gamma
-        stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low + 8.0 * (double)nP * N * (N + 1) / 2);
+        stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low + 8.0 * nP * c->gtile_lower);
     }
     return RIS_OK;
 }

@@ -109,6 +109,10 @@ struct GemmArgs {
     // (1st row, 3rd column) blocks, so a column tile inside the first block
     // reads rows [0, 2w) and one inside the third block rows [w, 3w)
     int kband;
+    // lower mode only: compute just these tiles (mt << 16 | nt, mt >= nt; device
+    // array of ntiles) of every batch entry instead of all lower tiles
+    const int *tiles;
+    int ntiles;
 };
 constexpr int kF32A = 1, kF32B = 2, kF32C = 4;
 hipError_t dgemm(const GemmArgs &g, hipStream_t st);

@@ -32,11 +32,19 @@ constexpr int GROUP_M = 2;  // m-tiles swept together so their A panels stay in 
 // XCD one contiguous range of tiles.  Inside a batch the tiles are walked in
 // groups of GROUP_M m-tiles with the n-tile as the slower index, so one B
 // panel serves GROUP_M consecutive tiles and the group's A panels stay hot.
-__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool lower, int &z, int &mt, int &nt)
+__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool lower, const int *tiles, int &z,
+                                        int &mt, int &nt)
 {
     const int q = total / NXCD, r = total % NXCD;
     const int xcd = b % NXCD, local = b / NXCD;
     const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+    if (tiles) {  // an explicit list of tn tiles (mt << 16 | nt) per batch entry
+        z = lin / tn;
+        const int pk = tiles[lin - z * tn];
+        mt = pk >> 16;
+        nt = pk & 0xffff;
+        return;
+    }
     if (lower) {  // tiles (mt >= nt) of a square tm x tm grid, row by row
         const int per = tm * (tm + 1) / 2;
         z = lin / per;
@@ -108,7 +116,7 @@ template <int MODE, bool TA, bool TB, bool BETA, typename EA = double, typename 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm(
     int M, int N, int K, double alpha, const EA *__restrict__ A, long lda, long sA, long sAr,
     const EB *__restrict__ B, long ldb, long sB, long sBr, double beta, EC *__restrict__ C, long ldc, long sC,
-    int nred, int tm, int tn, int total, int kc, bool lower)
+    int nred, int tm, int tn, int total, int kc, bool lower, const int *__restrict__ tiles)
 {
     typedef MfmaCfg<MODE> Cfg;
     typedef typename Cfg::T T;
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     int bz, mt, nt;
-    tile_of(blockIdx.x, total, tm, tn, lower, bz, mt, nt);
+    tile_of(blockIdx.x, total, tm, tn, lower, tiles, bz, mt, nt);
     const int m0 = mt * BM, n0 = nt * BN;
     // kc > 0: split-K, the batch index selects the k-range [bz*kc, bz*kc + kc);
     // kc < 0: banded K of width w = -kc (column tiles inside the first or the
@@ -301,9 +309,15 @@ hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st)
         if (kc != 0 || g.transB || g.lower || g.K != 3 * g.kband) return hipErrorInvalidValue;
         kc = -g.kband;
     }
-    const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    const int tm = (g.M + BM - 1) / BM;
+    int tn = (g.N + BN - 1) / BN;
     if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
-    const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
+    long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
+    if (g.tiles) {  // an explicit list of lower tiles: tn carries its length
+        if (!g.lower || g.ntiles <= 0) return hipErrorInvalidValue;
+        tn = g.ntiles;
+        total = (long)g.ntiles * g.batch;
+    }
     if (total > 0x7fffffffL) return hipErrorInvalidValue;
     // every operand byte offset from a panel base must fit 32 bits.  A k-fast
     // operand (A untransposed, B transposed) spans the rows of its tile; when
@@ -355,17 +369,17 @@ hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st)
             hipLaunchKernelGGL((k_gemm<1, false, false, false, float, float, float>), grid0, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, (float *)g.C, g.ldc, g.strideC, nred0, tm, tn, (int)total,
-                               kc, g.lower);
+                               kc, g.lower, g.tiles);
         else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB && g.beta == 0.0)
             hipLaunchKernelGGL((k_gemm<1, false, true, false, float, float, double>), grid0, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred0, tm, tn, (int)total, kc,
-                               g.lower);
+                               g.lower, g.tiles);
         else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB)
             hipLaunchKernelGGL((k_gemm<1, false, true, true, float, float, double>), grid0, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred0, tm, tn, (int)total, kc,
-                               g.lower);
+                               g.lower, g.tiles);
         else
             return hipErrorInvalidValue;
         return hipGetLastError();
@@ -375,7 +389,7 @@ hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st)
 #define RIS_GEMM_LAUNCH1(MODE, TA, TB, BETA)                                                                     \
     hipLaunchKernelGGL((k_gemm<MODE, TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,  \
                        g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC,     \
-                       nred, tm, tn, (int)total, kc, g.lower);
+                       nred, tm, tn, (int)total, kc, g.lower, g.tiles);
 #define RIS_GEMM_LAUNCH2(MODE, TA, TB)                                                                           \
     if (g.beta != 0.0) { RIS_GEMM_LAUNCH1(MODE, TA, TB, true) } else { RIS_GEMM_LAUNCH1(MODE, TA, TB, false) }
 #define RIS_GEMM_LAUNCH(MODE)                                                                                    \

@@ -33,11 +33,19 @@ constexpr int PAD2 = 8;  // bf16 elements; keeps 16-byte alignment of each LDS r
 // Linear workgroup id -> (batch, m-tile, n-tile): each XCD walks one
 // contiguous range; lower: the tiles mt >= nt of a square grid, row by row;
 // otherwise groups of GROUP_M m-tiles with the n-tile as the slower index.
-__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool lower, int &z, int &mt, int &nt)
+__device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool lower, const int *tiles, int &z,
+                                        int &mt, int &nt)
 {
     const int q = total / NXCD, r = total % NXCD;
     const int xcd = b % NXCD, local = b / NXCD;
     const int lin = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+    if (tiles) {  // an explicit list of tn tiles (mt << 16 | nt) per batch entry
+        z = lin / tn;
+        const int pk = tiles[lin - z * tn];
+        mt = pk >> 16;
+        nt = pk & 0xffff;
+        return;
+    }
     if (lower) {
         const int per = tm * (tm + 1) / 2;
         z = lin / per;
@@ -97,7 +105,7 @@ template <bool TA, bool TB, bool BETA, typename EA = double, typename EB = doubl
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_bgemm3(
     int M, int N, int K, double alpha, const EA *__restrict__ A, long lda, long sA, long sAr,
     const EB *__restrict__ B, long ldb, long sB, long sBr, double beta, EC *__restrict__ C, long ldc, long sC,
-    int nred, int tm, int tn, int total, int kc, bool lower)
+    int nred, int tm, int tn, int total, int kc, bool lower, const int *__restrict__ tiles)
 {
     __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][BK2 + PAD2];
     __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][BK2 + PAD2];
@@ -106,7 +114,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     int bz, mt, nt;
-    tile_of(blockIdx.x, total, tm, tn, lower, bz, mt, nt);
+    tile_of(blockIdx.x, total, tm, tn, lower, tiles, bz, mt, nt);
     const int m0 = mt * BM, n0 = nt * BN;
     // kc > 0: split-K range of the batch index; kc < 0: banded K of width -kc
     int kbeg = 0, kend = K;
@@ -286,9 +294,15 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
         if (kc != 0 || g.transB || g.lower || g.K != 3 * g.kband) return hipErrorInvalidValue;
         kc = -g.kband;
     }
-    const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    const int tm = (g.M + BM - 1) / BM;
+    int tn = (g.N + BN - 1) / BN;
     if (g.lower && (g.M != g.N || kc > 0)) return hipErrorInvalidValue;
-    const long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
+    long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
+    if (g.tiles) {  // an explicit list of lower tiles: tn carries its length
+        if (!g.lower || g.ntiles <= 0) return hipErrorInvalidValue;
+        tn = g.ntiles;
+        total = (long)g.ntiles * g.batch;
+    }
     if (total > 0x7fffffffL) return hipErrorInvalidValue;
     // 32-bit offsets from a panel base; k-fast operands with rows too long for
     // a full tile are issued in row (column) slices
@@ -338,17 +352,17 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
             hipLaunchKernelGGL((k_bgemm3<false, false, false, float, float, float>), grid, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, (float *)g.C, g.ldc, g.strideC, nred, tm, tn, (int)total,
-                               kc, g.lower);
+                               kc, g.lower, g.tiles);
         else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB && g.beta == 0.0)
             hipLaunchKernelGGL((k_bgemm3<false, true, false, float, float, double>), grid, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, (int)total, kc,
-                               g.lower);
+                               g.lower, g.tiles);
         else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB)
             hipLaunchKernelGGL((k_bgemm3<false, true, true, float, float, double>), grid, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, (int)total, kc,
-                               g.lower);
+                               g.lower, g.tiles);
         else
             return hipErrorInvalidValue;
         return hipGetLastError();
@@ -356,7 +370,7 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
 #define RIS_B3_LAUNCH1(TA, TB, BETA)                                                                               \
     hipLaunchKernelGGL((k_bgemm3<TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,        \
                        g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC,     \
-                       nred, tm, tn, (int)total, kc, g.lower);
+                       nred, tm, tn, (int)total, kc, g.lower, g.tiles);
 #define RIS_B3_LAUNCH2(TA, TB)                                                                                     \
     if (g.beta != 0.0) { RIS_B3_LAUNCH1(TA, TB, true) } else { RIS_B3_LAUNCH1(TA, TB, false) }
     if (!g.transA && !g.transB) { RIS_B3_LAUNCH2(false, false) }
