@@ -32,13 +32,13 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 (matrix)
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 (matrix)
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of the lower-tile Gamma back-transform GEMM from the
+# HBM bytes per launch of the Gamma back-transform GEMM (listed lower tiles) from the
 # FETCH_SIZE / WRITE_SIZE counter runs on the 199-atom workload (fetch scaled by
 # 2.0, write by 1.0 after a 1 GiB copy calibration), averaged over the 28
-# launches of a step (19 plain: 30.60 + 3.81 GB, 9 accumulating: 26.78 + 4.37 GB);
+# launches of a step (19 plain: 21.57 + 3.20 GB, 9 accumulating: 23.97 + 3.70 GB);
 # valid only for the GEMM source it was measured on (sha256 prefix; a later edit
 # that left the FP64 kernels' machine code identical keeps them valid); null otherwise.
-GAMMA_TRAFFIC = {"gemm_src_sha256": "d1a0acbb5fb92aeb", "workload": "chain200", "bytes_per_launch": 33.36e9}
+GAMMA_TRAFFIC = {"gemm_src_sha256": "3d476486cedb2d55", "workload": "chain200", "bytes_per_launch": 25.70e9}
 
 
 def log(*a):
@@ -358,7 +358,7 @@ def main():
         # multiplies in; the split-BF16 product runs three BF16 GEMMs per
         # useful product, so its achieved rate counts all three
         kern, peak = {
-            "fp64": ("k_gemm<0,false,true,*> lower tiles, f64 (Gamma^P = (F_I W^P) F_J^T, batched over P)",
+            "fp64": ("k_gemm<0,false,true,*> listed lower tiles, f64 (Gamma^P = (F_I W^P) F_J^T, batched over P)",
                      PEAK_FP64_TFLOPS),
             "fp32": ("k_gemm<1,false,true,*,float,float,double> lower tiles, f32 inputs "
                      "(Gamma^P = (F_I W^P) F_J^T, batched over P)", PEAK_FP32_TFLOPS),
