@@ -239,7 +239,12 @@ __global__ __launch_bounds__(128) void k_int3c(ShellTab ao, int nao, int a0, int
 // (weights symmetric in mu nu, so the bra-2 derivative folds into the factor
 // 2 on bra 1 over ordered pairs).  The wave sum is written to
 // partial[sa][sc][LB][o][6] for a deterministic reduction afterwards.
-template <int LA, int LB, int LC, int NO>
+//
+// G > 1: a wave takes G consecutive C shells of the class, lane l working on
+// C shell l % G and every G-th partner (short screened partner lists, as for
+// d shells, would otherwise leave most lanes idle); the sums are reduced
+// over the lanes of each C shell.
+template <int LA, int LB, int LC, int NO, int G>
 __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0, int na, int b0, int nb,
                                                     ShellTab aux, int c0, int nc, int nshAux,
                                                     const double *__restrict__ boys, DerivJob job)
@@ -247,16 +252,19 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
     // Waves are dispatched round-robin over the 8 XCDs; remap so each XCD walks
     // a contiguous range with the C shell fastest: waves resident together on
     // one XCD share the A shell and reuse its density rows from that XCD's L2.
-    const int total = na * nc;
+    const int ncg = (nc + G - 1) / G;
+    const int total = na * ncg;
     if ((int)blockIdx.x >= total) return;
     int lin;
     {
         const int q = total / 8, r = total % 8, x = blockIdx.x % 8, local = blockIdx.x / 8;
         lin = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + local;
     }
-    const int sa = a0 + lin / nc;
-    const int sc = c0 + lin % nc;
     const int lane = threadIdx.x;
+    const int sa = a0 + lin / ncg;
+    const int cl = lane % G, csh = (lin % ncg) * G + cl;
+    const bool cvalid = csh < nc;
+    const int sc = c0 + min(csh, nc - 1);
 
     constexpr int L = LA + LB + LC + 1;
     const double Ax = ao.x[sa], Ay = ao.y[sa], Az = ao.z[sa];
@@ -290,7 +298,8 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
         cnt = job.pair_ptr[(kMaxAOL + 1) * sa + LB + 1] - q0;
         lst = job.pair_idx + q0;
     }
-    for (int ib = lane; ib < cnt; ib += 64) {
+    if (!cvalid) cnt = 0;  // lanes past the last C shell of the class
+    for (int ib = lane / G; ib < cnt; ib += 64 / G) {
         const int sb = lst ? lst[ib] : b0 + ib;
         const double a = ao.exp[sa], b = ao.exp[sb];
         const double p = a + b, ip = 1.0 / p;
@@ -375,17 +384,17 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
             });
         });
     }
-    // wave reduction (fixed order, deterministic)
+    // reduction over the lanes of each C shell (fixed order, deterministic)
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             double v = acc[o][k];
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            for (int off = 32; off >= G; off >>= 1) v += __shfl_xor(v, off, 64);
             acc[o][k] = v;
         }
-    if (lane == 0) {
+    if (lane < G && cvalid) {
         double *dst = job.partial + (((size_t)sa * nshAux + sc) * (kMaxAOL + 1) + LB) * NO * 6;
 #pragma unroll
         for (int o = 0; o < NO; ++o)
@@ -558,8 +567,10 @@ void deriv_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, int cs
     int c0, nc;
     if (!class_range<LC>(auxl_beg, cs0, cs1, &c0, &nc)) return;
     if (na == 0 || nb == 0) return;
-    hipLaunchKernelGGL((k_int3c_deriv<LA, LB, LC, kMaxOutChunk>), dim3(na * nc), dim3(64), 0, st, ao.sh, ao.nao,
-                       a0, na, b0, nb, aux.sh, c0, nc, aux.nshell, boys, job);
+    // d-shell partner lists are short: four C shells per wave there
+    constexpr int G = LB == 2 ? 4 : 1;
+    hipLaunchKernelGGL((k_int3c_deriv<LA, LB, LC, kMaxOutChunk, G>), dim3(na * ((nc + G - 1) / G)), dim3(64), 0, st,
+                       ao.sh, ao.nao, a0, na, b0, nb, aux.sh, c0, nc, aux.nshell, boys, job);
 }
 
 // first function of aux shell cs (shells sorted by l, ncart(l) functions each)
