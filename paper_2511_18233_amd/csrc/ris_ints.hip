@@ -568,7 +568,7 @@ void deriv_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, int cs
     if (!class_range<LC>(auxl_beg, cs0, cs1, &c0, &nc)) return;
     if (na == 0 || nb == 0) return;
     // d-shell partner lists are short: four C shells per wave there
-    constexpr int G = LB == 2 ? 4 : 1;
+    constexpr int G = LB == 2 ? 4 : (LB == 1 ? 2 : 1);
     hipLaunchKernelGGL((k_int3c_deriv<LA, LB, LC, kMaxOutChunk, G>), dim3(na * ((nc + G - 1) / G)), dim3(64), 0, st,
                        ao.sh, ao.nao, a0, na, b0, nb, aux.sh, c0, nc, aux.nshell, boys, job);
 }
