@@ -307,14 +307,15 @@ def main():
             return
         torch.cuda.synchronize()
         log("[bench]   matvecs done")
-        for k0 in range(0, len(grads), 4):
-            ctx.grad_nac_contract(X, Y, grads[k0:k0 + 4], [], None, g_out[k0:k0 + 4], n_out[:0])
+        # gradient J together with the NAC (J-1, J): in one call they share
+        # the exchange products of state J
+        for k, J in enumerate(grads):
+            pk = [q for q, (a, b) in enumerate(pairs) if b == J]
+            assert len(pk) <= 1  # adjacent-pair NACs: at most one ends in state J
+            ctx.grad_nac_contract(X, Y, [J], [pairs[q] for q in pk], None, g_out[k:k + 1],
+                                  n_out[pk[0]:pk[0] + 1] if pk else n_out[:0])
             torch.cuda.synchronize()
-            log(f"[bench]   gradients {k0}..{min(k0 + 4, len(grads)) - 1} done")
-        for k0 in range(0, len(pairs), 4):
-            ctx.grad_nac_contract(X, Y, [], pairs[k0:k0 + 4], None, g_out[:0], n_out[k0:k0 + 4])
-            torch.cuda.synchronize()
-            log(f"[bench]   NACs {k0}..{min(k0 + 4, len(pairs)) - 1} done")
+            log(f"[bench]   gradient {J}" + (f" + NAC {pairs[pk[0]]}" if pk else "") + " done")
 
     log(f"[bench] natm={m.natm} nao={m.nao} nocc={prob.nocc} states={ns} outputs/step={len(outs)}")
     for w in range(args.warmup):

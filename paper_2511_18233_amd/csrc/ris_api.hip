@@ -471,7 +471,7 @@ ContractWs contract_ws(const Dims &d, int ns)
 // and per block of nb functions Tall, H_UU, W (+ float copy), Y and Gamma.
 struct ContractBlkWs {
     size_t oR, oL, oRLT, oF, oFf, oD, otT, ocv, oHI0, oHI1, oHJ0, oHJ1, oTR, oG1, oV2, oSK, op3, op2, oshA, oshC, oshP,
-        oTall, oHUU, oW, oWf, oY, oG, total;
+        oTall, oHUU, oW, oWf, oY, oG, oOut, total;
 };
 ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
 {
@@ -492,8 +492,9 @@ ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
     L.oHJ0 = cv.take((size_t)d.nK * oo);
     L.oHJ1 = cv.take((size_t)d.nK * oo);
     L.oTR = cv.take((size_t)d.nK * oo);
-    L.oG1 = cv.take((size_t)d.nK * d.nK);
-    L.oV2 = cv.take((size_t)d.nJ * d.nJ);
+    L.oG1 = cv.take((size_t)kMaxOutChunk * d.nK * d.nK);
+    L.oV2 = cv.take((size_t)kMaxOutChunk * d.nJ * d.nJ);
+    L.oOut = cv.take((size_t)kMaxOutChunk * d.natm * 3);
     L.oSK = cv.take(std::max((size_t)kSplitV * ns * d.nJ, (size_t)vpq_splits(d.nK) * d.nK * d.nK));
     L.op3 = cv.take((size_t)d.nshAO * d.nshJ * 3 * kMaxOutChunk * 6);
     L.op2 = cv.take((size_t)d.nshJ * 2 * kMaxOutChunk * 3);
@@ -1515,19 +1516,47 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
     auto blk = [](const double *b, long sP, long si, long sj, double sc) { return BlockSrc{b, sP, si, sj, sc}; };
     auto sc = [](BlockSrc b, double f) { b.scale *= f; return b; };
     const BlockSrc none{nullptr, 0, 0, 0, 0.0};
-    for (int k = 0; k < npair; ++k) {
-        const int I = pI[k], J = pJ[k];
+    // Outputs that share the state J share the per-block Tall^P = c_vv^P (R, L)_J
+    // and the H_OU blocks of J: a group holds outputs with one J and at most one
+    // other state I (a gradient J with the NAC (I, J), say), up to kMaxOutChunk.
+    std::vector<std::vector<int>> groups;
+    {
+        std::vector<char> done(npair, 0);
+        for (int k = 0; k < npair; ++k) {
+            if (done[k]) continue;
+            const int J = pJ[k];
+            int other = pI[k] != J ? pI[k] : -1;
+            std::vector<int> gq;
+            for (int k2 = k; k2 < npair && (int)gq.size() < kMaxOutChunk; ++k2) {
+                if (done[k2] || pJ[k2] != J) continue;
+                const int I2 = pI[k2];
+                if (I2 != J) {
+                    if (other < 0) other = I2;
+                    if (I2 != other) continue;
+                }
+                gq.push_back(k2);
+                done[k2] = 1;
+            }
+            groups.push_back(gq);
+        }
+    }
+    double *Gout = P_(CW.oOut);
+    for (const std::vector<int> &gq : groups) {
+        const int r = (int)gq.size(), J = pJ[gq[0]];
+        int Io = -1;  // the group's state other than J, if any
+        for (int q = 0; q < r; ++q)
+            if (pI[gq[q]] != J) Io = pI[gq[q]];
         // H_OU^P of a state s and t = R, L: [P][i][j] = sum_b c_vo^P[b][i] (R, L)_s[b][j]
         hipEvent_t t_u = stage_begin(c);
-        double *HIt[2] = {HI0, HI1}, *HJt[2] = {I == J ? HI0 : HJ0, I == J ? HI1 : HJ1};
+        double *HJt[2] = {HJ0, HJ1}, *HOt[2] = {HI0, HI1};
         for (int t = 0; t < 2; ++t) {
-            HIPCHK(c, gemm_mp(gm(nK * o, o, v, true, false, 1.0, c->cvo, (long)nK * o, RLT + (size_t)(t * ns + I) * o,
-                                 w2, 0.0, HIt[t], o), c->prec, c->stream));
-            if (I != J)
+            HIPCHK(c, gemm_mp(gm(nK * o, o, v, true, false, 1.0, c->cvo, (long)nK * o, RLT + (size_t)(t * ns + J) * o,
+                                 w2, 0.0, HJt[t], o), c->prec, c->stream));
+            if (Io >= 0)
                 HIPCHK(c, gemm_mp(gm(nK * o, o, v, true, false, 1.0, c->cvo, (long)nK * o,
-                                     RLT + (size_t)(t * ns + J) * o, w2, 0.0, HJt[t], o), c->prec, c->stream));
+                                     RLT + (size_t)(t * ns + Io) * o, w2, 0.0, HOt[t], o), c->prec, c->stream));
         }
-        stage_end(c, t_u, RIS_STAGE_HBLK, (I == J ? 4.0 : 8.0) * (double)nK * o * v * o, 0.0);
+        stage_end(c, t_u, RIS_STAGE_HBLK, (Io >= 0 ? 8.0 : 4.0) * (double)nK * o * v * o, 0.0);
         HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * kMaxOutChunk * 6, 0.0, c->stream));
         DerivJob job{};
         job.nout = 1;
@@ -1535,13 +1564,8 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
         job.cvec = cvec;
         job.nJ = nJ;
         job.alphaJ = c->alphaJ;
-        job.partial = p3;
         job.pair_ptr = c->screen > 0.0 ? c->d_pair_ptr : nullptr;
         job.pair_idx = c->d_pair_idx;
-        for (int q = 0; q < kMaxOutChunk; ++q) {
-            job.stI[q] = I;
-            job.stJ[q] = J;
-        }
         for (int p0 = 0; p0 < nK; p0 += nb) {
             const int m = std::min(nb, nK - p0);
             hipEvent_t t_b = stage_begin(c);
@@ -1551,71 +1575,99 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                                 RLT + (size_t)(t * ns + J) * o, w2, 0.0, Tall + (size_t)t * o, 2L * o);
                 g.batch = m; g.strideA = v; g.strideB = 0; g.strideC = (long)v * 2 * o;
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
-                // H_UU^P(t) = (R, L)_I^T Tall^P(t)
-                g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2, Tall + (size_t)t * o, 2L * o,
-                       0.0, HUU + (size_t)t * m * oo, o);
-                g.batch = m; g.strideA = 0; g.strideB = (long)v * 2 * o; g.strideC = oo;
-                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
             }
-            stage_end(c, t_b, RIS_STAGE_HBLK, 4.0 * (double)m * v * v * o + 4.0 * (double)m * oo * v, 0.0);
-            // exchange weights W^P of the block (rows / cols [U_R, C_O, U_L])
-            hipEvent_t t_yw = stage_begin(c);
-            const BlockSrc Hoo = blk(c->coo + (size_t)p0 * oo, oo, o, 1, 1.0);
-            const BlockSrc HRuo = blk(HIt[0] + (size_t)p0 * oo, oo, 1, o, 1.0);
-            const BlockSrc HLuo = blk(HIt[1] + (size_t)p0 * oo, oo, 1, o, 1.0);
-            const BlockSrc HRou = blk(HJt[0] + (size_t)p0 * oo, oo, o, 1, 1.0);
-            const BlockSrc HLou = blk(HJt[1] + (size_t)p0 * oo, oo, o, 1, 1.0);
-            const BlockSrc HRuu = blk(HUU, oo, o, 1, 1.0);
-            const BlockSrc HLuu = blk(HUU + (size_t)m * oo, oo, o, 1, 1.0);
-            BlockGrid gw{};
-            gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = sc(HRou, 0.25);  gw.b[0][2][0] = none;
-            gw.b[1][0][0] = sc(HRuo, 0.25); gw.b[1][1][0] = sc(HRuu, 0.25);  gw.b[1][2][0] = sc(HLuo, -0.25);
-            gw.b[1][1][1] = sc(HLuu, 0.25);
-            gw.b[2][0][0] = none;           gw.b[2][1][0] = sc(HLou, -0.25); gw.b[2][2][0] = sc(Hoo, 0.25);
-            HIPCHK(c, assemble3(gw, W, o, m, c->stream, f32 ? Wf : nullptr));
-            stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 9.0 * (double)oo * m);
-            // G rows of the block: <H_RUU^P + H_LUU^P, c_oo^Q>
+            stage_end(c, t_b, RIS_STAGE_HBLK, 4.0 * (double)m * v * v * o, 0.0);
+            for (int q = 0; q < r; ++q) {
+                const int I = pI[gq[q]];
+                double *const *HIt = I == J ? HJt : HOt;
+                hipEvent_t t_q = stage_begin(c);
+                for (int t = 0; t < 2; ++t) {
+                    // H_UU^P(t) = (R, L)_I^T Tall^P(t)
+                    GemmArgs g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2, Tall + (size_t)t * o,
+                                    2L * o, 0.0, HUU + (size_t)t * m * oo, o);
+                    g.batch = m; g.strideA = 0; g.strideB = (long)v * 2 * o; g.strideC = oo;
+                    HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                }
+                stage_end(c, t_q, RIS_STAGE_HBLK, 4.0 * (double)m * oo * v, 0.0);
+                // exchange weights W^P of the block (rows / cols [U_R, C_O, U_L])
+                hipEvent_t t_yw = stage_begin(c);
+                const BlockSrc Hoo = blk(c->coo + (size_t)p0 * oo, oo, o, 1, 1.0);
+                const BlockSrc HRuo = blk(HIt[0] + (size_t)p0 * oo, oo, 1, o, 1.0);
+                const BlockSrc HLuo = blk(HIt[1] + (size_t)p0 * oo, oo, 1, o, 1.0);
+                const BlockSrc HRou = blk(HJt[0] + (size_t)p0 * oo, oo, o, 1, 1.0);
+                const BlockSrc HLou = blk(HJt[1] + (size_t)p0 * oo, oo, o, 1, 1.0);
+                const BlockSrc HRuu = blk(HUU, oo, o, 1, 1.0);
+                const BlockSrc HLuu = blk(HUU + (size_t)m * oo, oo, o, 1, 1.0);
+                BlockGrid gw{};
+                gw.b[0][0][0] = sc(Hoo, 0.25);  gw.b[0][1][0] = sc(HRou, 0.25);  gw.b[0][2][0] = none;
+                gw.b[1][0][0] = sc(HRuo, 0.25); gw.b[1][1][0] = sc(HRuu, 0.25);  gw.b[1][2][0] = sc(HLuo, -0.25);
+                gw.b[1][1][1] = sc(HLuu, 0.25);
+                gw.b[2][0][0] = none;           gw.b[2][1][0] = sc(HLou, -0.25); gw.b[2][2][0] = sc(Hoo, 0.25);
+                HIPCHK(c, assemble3(gw, W, o, m, c->stream, f32 ? Wf : nullptr));
+                stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 9.0 * (double)oo * m);
+                // G rows of the block: <H_RUU^P + H_LUU^P, c_oo^Q>
+                double *G1q = G1 + (size_t)q * nK * nK;
+                hipEvent_t t_v = stage_begin(c);
+                for (int t = 0; t < 2; ++t)
+                    HIPCHK(c, dgemm_splitk(gm(m, nK, (int)oo, false, true, 1.0, HUU + (size_t)t * m * oo, oo, c->coo,
+                                              oo, t ? 1.0 : 0.0, G1q + (size_t)p0 * nK, nK), nsplit, SK, c->stream));
+                stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)m * nK * oo, 0.0);
+                const int rr = gamma_products(c, N, o, m, F + (size_t)I * N * o3, F + (size_t)J * N * o3,
+                                              Ff + (size_t)I * N * o3, Ff + (size_t)J * N * o3, W, Wf, Y3, G, I == J);
+                if (rr != RIS_OK) return rr;
+                // derivative contraction over the block's (s) shells, Coulomb part
+                // included, into the partial slot q of the group
+                job.gammaK = G;
+                job.nK = m;
+                job.kbeg = p0;
+                job.partial = p3 + 6 * q;
+                for (int u = 0; u < kMaxOutChunk; ++u) {
+                    job.stI[u] = I;
+                    job.stJ[u] = J;
+                }
+                hipEvent_t t_d = stage_begin(c);
+                HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, p0, p0 + m));
+                stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)m * NN);
+            }
+        }
+        for (int q = 0; q < r; ++q) {
+            const int I = pI[gq[q]];
+            double *const *HIt = I == J ? HJt : HOt;
+            job.partial = p3 + 6 * q;
+            for (int u = 0; u < kMaxOutChunk; ++u) {
+                job.stI[u] = I;
+                job.stJ[u] = J;
+            }
+            // the remaining auxiliary shells carry the Coulomb part only
+            if (nK < c->nshJ) {
+                job.gammaK = nullptr;
+                job.nK = 0;
+                job.kbeg = 0;
+                hipEvent_t t_d = stage_begin(c);
+                HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, nK, c->nshJ));
+                stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 0.0);
+            }
+            // metric weights: W2 = -alpha_J c_I c_J^T + c_x (G + G^T) / 4
+            double *G1q = G1 + (size_t)q * nK * nK, *V2q = V2 + (size_t)q * nJ * nJ;
             hipEvent_t t_v = stage_begin(c);
-            for (int t = 0; t < 2; ++t)
-                HIPCHK(c, dgemm_splitk(gm(m, nK, (int)oo, false, true, 1.0, HUU + (size_t)t * m * oo, oo, c->coo, oo,
-                                          t ? 1.0 : 0.0, G1 + (size_t)p0 * nK, nK), nsplit, SK, c->stream));
-            stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)m * nK * oo, 0.0);
-            const int r = gamma_products(c, N, o, m, F + (size_t)I * N * o3, F + (size_t)J * N * o3,
-                                         Ff + (size_t)I * N * o3, Ff + (size_t)J * N * o3, W, Wf, Y3, G, I == J);
-            if (r != RIS_OK) return r;
-            // derivative contraction over the block's (s) shells, Coulomb part included
-            job.gammaK = G;
-            job.nK = m;
-            job.kbeg = p0;
-            hipEvent_t t_d = stage_begin(c);
-            HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, p0, p0 + m));
-            stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)m * NN);
+            // G += <H_RUO^P, H_ROU^Q> - <H_LUO^P, H_LOU^Q>  (H_UO^P[i][j] = H_OU(I)^P[j][i])
+            for (int t = 0; t < 2; ++t) {
+                HIPCHK(c, permute3(HIt[t], TR, nK, o, o, oo, 1, o, oo, o, 1, c->stream));
+                HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)oo, false, true, t ? -1.0 : 1.0, TR, oo, HJt[t], oo, 1.0, G1q,
+                                          nK), nsplit, SK, c->stream));
+            }
+            HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ,
+                               nJ, 0.0, V2q, nJ), c->stream));
+            HIPCHK(c, add_sym(G1q, nK, V2q, nJ, 0.25 * c->cx, c->stream));
+            stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)nK * nK * oo, 0.0);
         }
-        // the remaining auxiliary shells carry the Coulomb part only
-        if (nK < c->nshJ) {
-            job.gammaK = nullptr;
-            job.nK = 0;
-            job.kbeg = 0;
-            hipEvent_t t_d = stage_begin(c);
-            HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, nK, c->nshJ));
-            stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 0.0);
-        }
-        // metric weights: W2 = -alpha_J c_I c_J^T + c_x (G + G^T) / 4
-        hipEvent_t t_v = stage_begin(c);
-        // G += <H_RUO^P, H_ROU^Q> - <H_LUO^P, H_LOU^Q>  (H_UO^P[i][j] = H_OU(I)^P[j][i])
-        for (int t = 0; t < 2; ++t) {
-            HIPCHK(c, permute3(HIt[t], TR, nK, o, o, oo, 1, o, oo, o, 1, c->stream));
-            HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)oo, false, true, t ? -1.0 : 1.0, TR, oo, HJt[t], oo, 1.0, G1, nK),
-                                   nsplit, SK, c->stream));
-        }
-        HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ, nJ,
-                           0.0, V2, nJ), c->stream));
-        HIPCHK(c, add_sym(G1, nK, V2, nJ, 0.25 * c->cx, c->stream));
-        stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)nK * nK * oo, 0.0);
-        HIPCHK(c, fill(p2, (size_t)c->nshJ * 2 * 1 * 3, 0.0, c->stream));
-        HIPCHK(c, launch_int2c_deriv(c->aux, c->boys, 1, V2, p2, c->stream));
-        HIPCHK(c, reduce_grad(p3, c->nshAO, c->nshJ, 1, kMaxOutChunk, p2, c->ao.sh.atom, c->aux.sh.atom, natm, shA,
-                              shC, shP, 1.0, 0, outg + (size_t)k * natm * 3, c->stream));
+        HIPCHK(c, fill(p2, (size_t)c->nshJ * 2 * r * 3, 0.0, c->stream));
+        HIPCHK(c, launch_int2c_deriv(c->aux, c->boys, r, V2, p2, c->stream));
+        HIPCHK(c, reduce_grad(p3, c->nshAO, c->nshJ, r, kMaxOutChunk, p2, c->ao.sh.atom, c->aux.sh.atom, natm, shA,
+                              shC, shP, 1.0, 0, Gout, c->stream));
+        for (int q = 0; q < r; ++q)
+            HIPCHK(c, hipMemcpyAsync(outg + (size_t)gq[q] * natm * 3, Gout + (size_t)q * natm * 3, 8 * (size_t)natm * 3,
+                                     hipMemcpyDeviceToDevice, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RIS_OK;

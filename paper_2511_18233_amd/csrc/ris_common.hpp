@@ -70,7 +70,7 @@ struct DerivJob {
     int nJ;
     int stI[8], stJ[8];        // state pair of each output
     double alphaJ;
-    double *partial;           // [nshellAO][nshellAux][nout][6] (dA xyz, dC xyz)
+    double *partial;           // [nshellAO][nshellAux][3][kMaxOutChunk][6] (dA xyz, dC xyz); slots o < nout written
     // AO shell-pair screen (null: every pair): the partners of internal shell sa
     // in class l are pair_idx[pair_ptr[(kMaxAOL+1) sa + l] .. pair_ptr[(kMaxAOL+1) sa + l + 1])
     const int *pair_ptr;

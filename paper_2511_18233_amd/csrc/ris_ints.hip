@@ -395,11 +395,14 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
             acc[o][k] = v;
         }
     if (lane < G && cvalid) {
+        // only the job's outputs: the partial slots of other outputs are left as they are
         double *dst = job.partial + (((size_t)sa * nshAux + sc) * (kMaxAOL + 1) + LB) * NO * 6;
 #pragma unroll
         for (int o = 0; o < NO; ++o)
+            if (o < job.nout) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) dst[o * 6 + k] = acc[o][k];
+                for (int k = 0; k < 6; ++k) dst[o * 6 + k] = acc[o][k];
+            }
     }
 }
 
