@@ -1259,7 +1259,9 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
             HIPCHK(c, dgemm(g, c->stream));
             g = gm(v, v, N, true, false, 1.0, CV, nmo, Z, v, 0.0, c->cvv + (size_t)f0 * v, (long)nK * v);
             g.batch = nbk; g.strideA = 0; g.strideB = (long)N * v; g.strideC = v;
+            g.lower = true;  // (ab|P) is symmetric in a, b: lower tiles, then mirrored
             HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, mirror_lower(c->cvv + (size_t)f0 * v, v, (long)nK * v, v, nbk, c->stream));
         }
         stage_end(c, t_mo, RIS_STAGE_MO,
                   2.0 * nb * ((double)N * N * o + (double)N * v * o) +
@@ -1582,11 +1584,13 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                 double *const *HIt = I == J ? HJt : HOt;
                 hipEvent_t t_q = stage_begin(c);
                 for (int t = 0; t < 2; ++t) {
-                    // H_UU^P(t) = (R, L)_I^T Tall^P(t)
+                    // H_UU^P(t) = (R, L)_I^T Tall^P(t)  (symmetric for a gradient: lower tiles + mirror)
                     GemmArgs g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2, Tall + (size_t)t * o,
                                     2L * o, 0.0, HUU + (size_t)t * m * oo, o);
                     g.batch = m; g.strideA = 0; g.strideB = (long)v * 2 * o; g.strideC = oo;
+                    g.lower = I == J;
                     HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                    if (I == J) HIPCHK(c, mirror_lower(HUU + (size_t)t * m * oo, o, o, oo, m, c->stream));
                 }
                 stage_end(c, t_q, RIS_STAGE_HBLK, 4.0 * (double)m * oo * v, 0.0);
                 // exchange weights W^P of the block (rows / cols [U_R, C_O, U_L])
@@ -1779,12 +1783,14 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         for (int k = 0; k < nb; ++k) {
             const int I = pI[k0 + k], J = pJ[k0 + k];
             hipEvent_t t_u = stage_begin(c);
-            // H_UU^P = (R,L)_I^T Tall^P_{(R,L) J}
+            // H_UU^P = (R,L)_I^T Tall^P_{(R,L) J}  (symmetric for a gradient: lower tiles + mirror)
             for (int t = 0; t < 2; ++t) {
                 GemmArgs g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2,
                                 Tall + (size_t)(t * ns + J) * o, (long)nK * w2, 0.0, HUU + (size_t)t * nK * oo, o);
                 g.batch = nK; g.strideA = 0; g.strideB = w2; g.strideC = oo;
+                g.lower = I == J;
                 HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                if (I == J) HIPCHK(c, mirror_lower(HUU + (size_t)t * nK * oo, o, o, oo, nK, c->stream));
             }
             stage_end(c, t_u, RIS_STAGE_HBLK, 4.0 * (double)nK * oo * v, 0.0);
             const BlockSrc Hoo = blk(c->coo, oo, o, 1, 1.0);

@@ -161,6 +161,29 @@ __global__ void k_symmetrize(double *A, int n, int nb)
     M[(size_t)j * n + i] = v;
 }
 
+// C_b[i][j] = C_b[j][i] for j > i: the strict upper triangle copied from the
+// lower one, 32 x 32 tiles through LDS (block (tj, ti, b) writes upper tile
+// (ti, tj) from lower tile (tj, ti); 32 x 8 threads)
+__global__ void k_mirror_lower(double *__restrict__ C, int n, long ldc, long sC)
+{
+    __shared__ double t[32][33];
+    const int tj = blockIdx.x, ti = blockIdx.y;
+    if (tj < ti) return;
+    double *M = C + (long)blockIdx.z * sC;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int r = tj * 32 + ty + k, col = ti * 32 + tx;
+        if (r < n && col < n) t[ty + k][tx] = M[(long)r * ldc + col];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int r = ti * 32 + ty + k, col = tj * 32 + tx;
+        if (r < n && col < n && col > r) M[(long)r * ldc + col] = t[tx][ty + k];
+    }
+}
+
 // V[P][Q] += s (G[P][Q] + G[Q][P]) over n x n (G dense n x n, V leading dim ldv)
 __global__ void k_add_sym(const double *__restrict__ G, int n, double *__restrict__ V, int ldv, double s)
 {
@@ -366,6 +389,15 @@ hipError_t make_rl(const double *X, const double *Y, double *R, double *L, size_
 hipError_t symmetrize(double *A, int n, int nb, hipStream_t st)
 {
     hipLaunchKernelGGL(k_symmetrize, dim3(nblk((size_t)n * n * nb, 256)), dim3(256), 0, st, A, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t mirror_lower(double *C, int n, long ldc, long sC, int batch, hipStream_t st)
+{
+    if (n <= 1 || batch <= 0) return hipSuccess;
+    if (batch > 65535) return hipErrorInvalidValue;
+    const int nt = (n + 31) / 32;
+    hipLaunchKernelGGL(k_mirror_lower, dim3(nt, nt, batch), dim3(32, 8), 0, st, C, n, ldc, sC);
     return hipGetLastError();
 }
 

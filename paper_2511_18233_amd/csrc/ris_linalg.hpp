@@ -11,6 +11,9 @@ hipError_t gather_rows(const double *src, double *dst, const int *perm, int nrow
 hipError_t scatter_sq(const double *in, double *out, const int *perm, int n, int nb, hipStream_t st);
 hipError_t make_rl(const double *X, const double *Y, double *R, double *L, size_t n, hipStream_t st);
 hipError_t symmetrize(double *A, int n, int nb, hipStream_t st);
+// C_b[i][j] = C_b[j][i] for j > i, b < batch (n x n blocks, leading dimension ldc, batch stride sC):
+// completes a symmetric result of which only the lower triangle was formed
+hipError_t mirror_lower(double *C, int n, long ldc, long sC, int batch, hipStream_t st);
 // V[P][Q] += s (G[P][Q] + G[Q][P]) for P, Q < n; G dense n x n, V with leading dimension ldv
 hipError_t add_sym(const double *G, int n, double *V, int ldv, double s, hipStream_t st);
 hipError_t add_de(const double *eps, const double *V, double *out, int nvir, int nocc, int nvec, double s,
