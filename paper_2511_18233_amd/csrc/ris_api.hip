@@ -449,7 +449,8 @@ ContractWs contract_ws(const Dims &d, int ns)
     L.oHOU = cv.take((size_t)d.nK * d.o * w2);
     L.oHUU = cv.take((size_t)2 * d.nK * oo);
     L.oW = cv.take((size_t)d.nK * o3 * o3);
-    L.oHc = cv.take((size_t)d.nK * o3 * o3);
+    // gathered H_UO / H_OU blocks ([P][i][j], four of them) and G of the metric weights
+    L.oHc = cv.take((size_t)4 * d.nK * oo + (size_t)d.nK * d.nK);
     L.oY = cv.take((size_t)d.nK * d.N * o3);
     // FP32 copies of F_s and W^P for the FP32 mode (float elements, two per slot)
     L.oFf = cv.take(((size_t)ns * d.N * o3 + 1) / 2);
@@ -1810,21 +1811,28 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             gw.b[1][1][1] = sc(HLuu, 0.25);
             gw.b[2][0][0] = none;           gw.b[2][1][0] = sc(HLou, -0.25); gw.b[2][2][0] = sc(Hoo, 0.25);
             HIPCHK(c, assemble3(gw, W, o, nK, c->stream, f32 ? Wf : nullptr));
-            // H^P = F_I^T C^P F_J over the blocks where W is nonzero
-            BlockGrid gh{};
-            gh.b[0][0][0] = HRuu; gh.b[0][1][0] = HRuo;
-            gh.b[1][0][0] = HRou; gh.b[1][1][0] = Hoo; gh.b[1][2][0] = HLou;
-            gh.b[2][1][0] = HLuo; gh.b[2][2][0] = HLuu;
-            HIPCHK(c, assemble3(gh, Hc, o, nK, c->stream));
-            stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 2.0 * 9.0 * (double)oo * nK);
+            stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 9.0 * (double)oo * nK);
             hipEvent_t t_v = stage_begin(c);
-            // metric weights: W2 = -alpha_J c_I c_J^T + c_x V, V_PQ = sum_kl H^P_kl W^Q_kl
+            // metric weights: W2 = -alpha_J c_I c_J^T + c_x V with V_PQ = sum_kl H^P_kl W^Q_kl
+            // = (G + G^T)_PQ / 4, G_PQ = <H_RUU^P + H_LUU^P, c_oo^Q> + <H_RUO^P, H_ROU^Q>
+            // - <H_LUO^P, H_LOU^Q> (elementwise inner products over (i, j); the
+            // H blocks gathered into [P][i][j] order in the H region)
             double *V2k = V2 + (size_t)k * nJ * nJ;
+            double *Ru = Hc, *Rc = Hc + (size_t)nK * oo, *Lu = Hc + 2 * (size_t)nK * oo, *Lc = Hc + 3 * (size_t)nK * oo,
+                   *Gm = Hc + 4 * (size_t)nK * oo;
+            HIPCHK(c, permute3(HUO + (size_t)I * o * nK * o, Ru, nK, o, o, o, (long)nK * o, 1, oo, o, 1, c->stream));
+            HIPCHK(c, permute3(HUO + (size_t)(ns + I) * o * nK * o, Lu, nK, o, o, o, (long)nK * o, 1, oo, o, 1,
+                               c->stream));
+            HIPCHK(c, permute3(HOU + (size_t)J * o, Rc, nK, o, o, (long)o * w2, w2, 1, oo, o, 1, c->stream));
+            HIPCHK(c, permute3(HOU + (size_t)(ns + J) * o, Lc, nK, o, o, (long)o * w2, w2, 1, oo, o, 1, c->stream));
+            const double *gA[4] = {HUU, HUU + (size_t)nK * oo, Ru, Lu}, *gB[4] = {c->coo, c->coo, Rc, Lc};
+            for (int u = 0; u < 4; ++u)
+                HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)oo, false, true, u == 3 ? -1.0 : 1.0, gA[u], oo, gB[u], oo,
+                                          u ? 1.0 : 0.0, Gm, nK), nsplit, SK, c->stream));
             HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ,
                                nJ, 0.0, V2k, nJ), c->stream));
-            HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)(o3 * o3), false, true, c->cx, Hc, o3 * o3, W, o3 * o3, 1.0, V2k,
-                                      nJ), nsplit, SK, c->stream));
-            stage_end(c, t_v, RIS_STAGE_VPQ, 2.0 * (double)nK * nK * o3 * o3, 0.0);
+            HIPCHK(c, add_sym(Gm, nK, V2k, nJ, 0.25 * c->cx, c->stream));
+            stage_end(c, t_v, RIS_STAGE_VPQ, 8.0 * (double)nK * nK * oo, 0.0);
             // Y^P = F_I W^P ; Gamma^P from Y^P and F_J
             double *Gk = G + (size_t)k * nK * NN;
             {
