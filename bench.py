@@ -55,10 +55,11 @@ def make_workload(name):
 
 
 def oracle_sample(prob, jp, outs, radii):
-    """Time the CPU oracle on bounded samples of the same workload and scale
-    each stage linearly to one full step: (mu nu|P) for a few auxiliary
-    shells, the exchange weights of two K functions for one output pair, and
-    the derivative contraction over those functions for one output."""
+    """Time the CPU oracle on bounded samples of the same workload (about 10 s
+    of host work) and scale each stage linearly to one full step: (mu nu|P)
+    for 24 s and 8 p auxiliary shells, the exchange weights of 24 K functions
+    for one output pair, and the derivative contraction over the sampled
+    functions for one output."""
     from oracle import ris_oracle as O
     import threadpoolctl  # noqa: F401  (BLAS threads stay at the default: all cores)
     mol = prob.mol
@@ -66,21 +67,23 @@ def oracle_sample(prob, jp, outs, radii):
     aux = O.aux_build(mol, radii, 0.2, jp)
     nJs, nKs = aux.J.n, aux.K.n
     nJ, nK = aux.J.nfunc, aux.K.nfunc
-    # (1) three-centre integrals on 2 s + 1 p auxiliary shells
-    pick = [0, 1] + ([nKs] if nJs > nKs else [])
+    # (1) three-centre integrals on 24 s + 8 p auxiliary shells
+    ks, kp = min(24, nKs), (min(8, nJs - nKs) if nJs > nKs else 0)
+    pick = list(range(ks)) + list(range(nKs, nKs + kp))
     sub = O.Shells(aux.J.xyz[pick], aux.J.l[pick], aux.J.exp[pick], aux.J.atom[pick])
     t = time.perf_counter()
     t3 = O.int3c(ao, sub)
     t_int = time.perf_counter() - t
     nf = sub.nfunc
     full_int = t_int * (nJ + nK) / nf
-    # (2) exchange weights (Gamma^P, V) for 2 K functions of one output pair
+    # (2) exchange weights (Gamma^P, V) for the ks sampled K (s) functions of one output pair
     RS, LA = O.ao_densities(prob.C, prob.nocc, prob.X[:2], None if prob.Y is None else prob.Y[:2])
-    Ssub = O.Setup(ao, aux, t3[:1], t3[:2], O.int2c(sub)[:1, :1], O.int2c(sub)[:2, :2])
+    M2 = O.int2c(sub)
+    Ssub = O.Setup(ao, aux, t3[:1], t3[:ks], M2[:1, :1], M2[:ks, :ks])
     t = time.perf_counter()
     O.pair_weights(Ssub, RS[0], RS[1], False, 2.0, 0.25)
     t_pw = time.perf_counter() - t
-    full_pw = t_pw * nK / 2 * 2 * len(outs)          # per K function, two pairs per output
+    full_pw = t_pw * nK / ks * 2 * len(outs)         # per K function, two pairs per output
     # (3) derivative contraction over the sampled aux shells, one output
     W = np.random.default_rng(0).standard_normal((1, nf, mol.nao, mol.nao))
     t = time.perf_counter()
@@ -92,7 +95,7 @@ def oracle_sample(prob, jp, outs, radii):
     return {
         "value": len(outs) / total, "unit": "grads+NACs/s", "cores": nthreads, "kind": "oracle",
         "sample": (f"{mol.natm}-atom workload: int3c on {nf} of {nJ}+{nK} aux functions ({t_int:.1f} s), "
-                   f"exchange weights for 2 of {nK} K functions x 1 pair ({t_pw:.1f} s), derivative "
+                   f"exchange weights for {ks} of {nK} K functions x 1 pair ({t_pw:.1f} s), derivative "
                    f"contraction on {nf} aux functions x 1 output ({t_dr:.1f} s); each scaled linearly to "
                    f"{len(outs)} outputs: est. {total:.0f} s per step"),
     }
