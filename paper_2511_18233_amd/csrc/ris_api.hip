@@ -391,6 +391,10 @@ Int3cWs int3c_ws(const Dims &d, int nb)
     return L;
 }
 
+// K-split of the long-K Coulomb products t = V (ai|P)^T (K = nvir nocc, a few
+// output rows): 512 ranges fill the 256 CUs twice over, also when (ai|P) rows
+// are long enough that the product goes out in column slices of one tile each
+constexpr int kSplitV = 512;
 struct MatvecWs {
     size_t ot, oT, oU, oSK, total;
 };
@@ -411,13 +415,12 @@ MatvecWs matvec_ws(const Dims &d, int nvec, int chunk = kMatvecChunk)
     L.oT = cv.take((size_t)chunk * d.nK * std::max(vo, oo));  // T (exchange A) or S (exchange B)
     L.oU = cv.take((size_t)chunk * vo);                        // [a][k][i] product before the permuted add
     // split-K partials of t = V (ai|P)^T and of the exchange products U
-    L.oSK = cv.take(std::max((size_t)64 * nvec * d.nJ,
+    L.oSK = cv.take(std::max((size_t)kSplitV * nvec * d.nJ,
                              (size_t)matvec_u_splits(d, chunk) * d.v * chunk * d.o));
     L.total = cv.off;
     return L;
 }
 
-constexpr int kSplitV = 64;  // K-split of the long-K Coulomb products
 constexpr int kDavMaxSpace = 256;  // largest Davidson subspace (the Jacobi eigensolver's size)
 // K-split of the V_PQ product (nK x nK output, K = 9 o^2): about 1024
 // workgroups over its 128 x 128 tiles
@@ -1331,14 +1334,14 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
            *U = (double *)(wsb + MW.oU), *SKm = (double *)(wsb + MW.oSK);
     hipEvent_t t_mv = stage_begin(c);
     // Coulomb: t = V (ai|P)^T (tiny output, K = nvir*nocc: split-K) ; cc = t M_J^-1 ; out = cJ alpha_J cc (ai|P)
-    HIPCHK(c, dgemm_splitk(gm(nvec, nJ, (int)vo, false, true, 1.0, V, vo, c->aiJ, vo, 0.0, t, nJ), 64, SKm,
+    HIPCHK(c, dgemm_splitk(gm(nvec, nJ, (int)vo, false, true, 1.0, V, vo, c->aiJ, vo, 0.0, t, nJ), kSplitV, SKm,
                            c->stream));
     HIPCHK(c, dgemm(gm(nvec, nJ, nJ, false, false, 1.0, t, nJ, c->MinvJ, nJ, 0.0, cc, nJ), c->stream));
     HIPCHK(c, dgemm(gm(nvec, (int)vo, nJ, false, false, cJ[op] * c->alphaJ, cc, nJ, c->aiJ, vo, 0.0, out, vo),
                     c->stream));
     if (cDe[op] != 0.0) HIPCHK(c, add_de(c->eps, V, out, v, o, nvec, cDe[op], c->stream));
     // K-split of U within the partials region (sized in matvec_ws for full chunks)
-    const size_t skcap = std::max((size_t)64 * nvec * nJ, (size_t)matvec_u_splits(ctx_dims(c), chunk) * v * chunk * o);
+    const size_t skcap = std::max((size_t)kSplitV * nvec * nJ, (size_t)matvec_u_splits(ctx_dims(c), chunk) * v * chunk * o);
     for (int k0 = 0; k0 < nvec; k0 += chunk) {
         const int nv = std::min(chunk, nvec - k0);
         const int usplit = (int)std::min((size_t)matvec_u_splits(ctx_dims(c), nv), skcap / ((size_t)v * nv * o));
