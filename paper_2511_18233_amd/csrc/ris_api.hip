@@ -1478,6 +1478,8 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
     const int ns = nstate;
     const long w2 = 2L * ns * o;
     const int nsplit = vpq_splits(nK);
+    // doubles in the split-K partials region (the SK region of contract_blk_ws)
+    const size_t skcap = std::max((size_t)kSplitV * ns * nJ, (size_t)nsplit * nK * nK);
     if (nK > c->auxl_beg[1]) return fail(c, RIS_E_UNSUPPORTED, "exchange set is not a run of leading s shells");
     const ContractBlkWs CW = contract_blk_ws(ctx_dims(c), ns, nb);
     int st;
@@ -1616,9 +1618,12 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                 // G rows of the block: <H_RUU^P + H_LUU^P, c_oo^Q>
                 double *G1q = G1 + (size_t)q * nK * nK;
                 hipEvent_t t_v = stage_begin(c);
+                // K-split for about 1024 workgroups over the block's m x nK tiles, within the partials region
+                const long tmn = (long)((m + 127) / 128) * ((nK + 127) / 128);
+                const int bsplit = (int)std::max(1L, std::min({256L, 1024L / tmn, (long)(skcap / ((size_t)m * nK))}));
                 for (int t = 0; t < 2; ++t)
                     HIPCHK(c, dgemm_splitk(gm(m, nK, (int)oo, false, true, 1.0, HUU + (size_t)t * m * oo, oo, c->coo,
-                                              oo, t ? 1.0 : 0.0, G1q + (size_t)p0 * nK, nK), nsplit, SK, c->stream));
+                                              oo, t ? 1.0 : 0.0, G1q + (size_t)p0 * nK, nK), bsplit, SK, c->stream));
                 stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)m * nK * oo, 0.0);
                 const int rr = gamma_products(c, N, o, m, F + (size_t)I * N * o3, F + (size_t)J * N * o3,
                                               Ff + (size_t)I * N * o3, Ff + (size_t)J * N * o3, W, Wf, Y3, G, I == J);
@@ -1705,6 +1710,8 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         if ((c->ablock > 0 && c->ablock < nK) || CW.total > wsroom) {
             int nb = nK;
             while (nb > 1 && contract_blk_ws(ctx_dims(c), ns, nb).total > wsroom) nb = std::max(1, (int)(nb * 0.8));
+            // whole 128-row tiles for the block's rows of the Gram matrix
+            if (nb > 128) nb = nb / 128 * 128;
             if (c->ablock > 0) nb = std::min(nb, c->ablock);
             return contract_pairs_blocked(c, nstate, X, Y, npair, pI, pJ, outg, nb);
         }
