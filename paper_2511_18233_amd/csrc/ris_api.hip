@@ -1760,15 +1760,14 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         // Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j]
         HIPCHK(c, gemm_mp(gm(v * nK, (int)w2, v, false, false, 1.0, c->cvv, v, RLT, w2, 0.0, Tall, w2), c->prec,
                           c->stream));
-        // HUO[(t,s,i)][(P,j)] = sum_a (R,L)_s[a][i] c_vo^P[a][j]  (= H_UO blocks)
-        HIPCHK(c, gemm_mp(gm((int)w2, nK * o, v, true, false, 1.0, RLT, w2, c->cvo, (long)nK * o, 0.0, HUO,
-                             (long)nK * o), c->prec, c->stream));
         // HOU[(P,i)][(t,s,j)] = sum_b c_vo^P[b][i] (R,L)_s[b][j]  (= H_OU blocks)
         HIPCHK(c, gemm_mp(gm(nK * o, (int)w2, v, true, false, 1.0, c->cvo, (long)nK * o, RLT, w2, 0.0, HOU, w2),
                           c->prec, c->stream));
+        // HUO[(t,s,i)][(P,j)] = HOU[(P,j)][(t,s,i)]  (H_UO^P of a state is the transpose of its H_OU^P)
+        HIPCHK(c, transpose(HOU, w2, HUO, (long)nK * o, nK * o, (int)w2, c->stream));
     }
     stage_end(c, t_h, RIS_STAGE_HBLK,
-              2.0 * (double)v * nK * w2 * v + 4.0 * (double)w2 * nK * o * v + 2.0 * ns * ((double)N * N * o) +
+              2.0 * (double)v * nK * w2 * v + 2.0 * (double)w2 * nK * o * v + 2.0 * ns * ((double)N * N * o) +
                   4.0 * ns * (double)N * v * o,
               0.0);
 

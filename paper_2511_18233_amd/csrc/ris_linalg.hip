@@ -184,6 +184,30 @@ __global__ void k_mirror_lower(double *__restrict__ C, int n, long ldc, long sC)
     }
 }
 
+// out[c][r] = in[r][c] for r < R, c < C through a 32 x 32 LDS tile (both
+// sides coalesced); row tiles strided over the y grid
+__global__ void k_transpose(const double *__restrict__ in, long ldi, double *__restrict__ out, long ldo, int R, int C)
+{
+    __shared__ double t[32][33];
+    const int tx = threadIdx.x, ty = threadIdx.y, c0 = blockIdx.x * 32;
+    const int nrt = (R + 31) / 32;
+    for (int rt = blockIdx.y; rt < nrt; rt += gridDim.y) {
+        const int r0 = rt * 32;
+#pragma unroll
+        for (int k = 0; k < 32; k += 8) {
+            const int r = r0 + ty + k, col = c0 + tx;
+            if (r < R && col < C) t[ty + k][tx] = in[(long)r * ldi + col];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 32; k += 8) {
+            const int col = c0 + ty + k, r = r0 + tx;
+            if (r < R && col < C) out[(long)col * ldo + r] = t[tx][ty + k];
+        }
+        __syncthreads();
+    }
+}
+
 // V[P][Q] += s (G[P][Q] + G[Q][P]) over n x n (G dense n x n, V leading dim ldv)
 __global__ void k_add_sym(const double *__restrict__ G, int n, double *__restrict__ V, int ldv, double s)
 {
@@ -398,6 +422,14 @@ hipError_t mirror_lower(double *C, int n, long ldc, long sC, int batch, hipStrea
     if (batch > 65535) return hipErrorInvalidValue;
     const int nt = (n + 31) / 32;
     hipLaunchKernelGGL(k_mirror_lower, dim3(nt, nt, batch), dim3(32, 8), 0, st, C, n, ldc, sC);
+    return hipGetLastError();
+}
+
+hipError_t transpose(const double *in, long ldi, double *out, long ldo, int R, int C, hipStream_t st)
+{
+    if (R <= 0 || C <= 0) return hipSuccess;
+    const int nct = (C + 31) / 32, nrt = (R + 31) / 32;
+    hipLaunchKernelGGL(k_transpose, dim3(nct, std::min(nrt, 65535)), dim3(32, 8), 0, st, in, ldi, out, ldo, R, C);
     return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@ hipError_t symmetrize(double *A, int n, int nb, hipStream_t st);
 // C_b[i][j] = C_b[j][i] for j > i, b < batch (n x n blocks, leading dimension ldc, batch stride sC):
 // completes a symmetric result of which only the lower triangle was formed
 hipError_t mirror_lower(double *C, int n, long ldc, long sC, int batch, hipStream_t st);
+// out[c][r] = in[r][c] for r < R, c < C (leading dimensions ldi, ldo; not in place)
+hipError_t transpose(const double *in, long ldi, double *out, long ldo, int R, int C, hipStream_t st);
 // V[P][Q] += s (G[P][Q] + G[Q][P]) for P, Q < n; G dense n x n, V with leading dimension ldv
 hipError_t add_sym(const double *G, int n, double *V, int ldv, double s, hipStream_t st);
 hipError_t add_de(const double *eps, const double *V, double *out, int nvir, int nocc, int nvec, double s,
