@@ -39,6 +39,13 @@ int ris_test_gemm(int mode, int M, int N, int K, int transA, int transB, double 
  * receives the eigenvalues ascending.  Synchronous; allocates its own work. */
 int ris_test_sym_eig(int m, double *A, double *w);
 
+/* out[c][r] = in[r][c] for r < R, c < C by the path's LDS-tiled transpose
+ * (it forms the H_UO blocks from the H_OU blocks): in (device, leading
+ * dimension ldi >= C), out (device, leading dimension ldo >= R, not
+ * overlapping in).  Returns 1 on invalid arguments, 7 on a HIP error.
+ * Synchronous. */
+int ris_test_transpose(const double *in, long ldi, double *out, long ldo, int R, int C);
+
 #ifdef __cplusplus
 }
 #endif

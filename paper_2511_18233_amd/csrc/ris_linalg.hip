@@ -496,3 +496,10 @@ hipError_t reduce_grad(const double *p3, int nshAO, int nshAux, int nout, int NO
 }
 
 }  // namespace ris
+
+extern "C" int ris_test_transpose(const double *in, long ldi, double *out, long ldo, int R, int C)
+{
+    if (R < 0 || C < 0 || !in || !out || in == out || ldi < C || ldo < R) return 1;
+    if (ris::transpose(in, ldi, out, ldo, R, C, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return 7;
+    return 0;
+}

@@ -29,7 +29,8 @@ EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes
            "ris_zrhs_contract",
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
-           "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm", "ris_test_sym_eig")
+           "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm", "ris_test_sym_eig",
+           "ris_test_transpose")
 
 
 class RisError(RuntimeError):
@@ -100,6 +101,7 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.c_double, vp, L, L, vp, L, L, ctypes.c_double, vp, L, L, ctypes.c_int]
     lib.ris_test_gemm.argtypes = [ctypes.c_int] + lib.ris_test_dgemm.argtypes
     lib.ris_test_sym_eig.argtypes = [ctypes.c_int, vp, vp]
+    lib.ris_test_transpose.argtypes = [vp, L, vp, L, ctypes.c_int, ctypes.c_int]
     _lib = lib
     return lib
 
