@@ -422,7 +422,7 @@ MatvecWs matvec_ws(const Dims &d, int nvec, int chunk = kMatvecChunk)
 }
 
 constexpr int kDavMaxSpace = 256;  // largest Davidson subspace (the Jacobi eigensolver's size)
-// K-split of the V_PQ product (nK x nK output, K = 9 o^2): about 1024
+// K-split of the Gram products of V_PQ (nK x nK output, K = o^2): about 1024
 // workgroups over its 128 x 128 tiles
 int vpq_splits(int nK)
 {
