@@ -81,7 +81,7 @@ def oracle_sample(prob, jp, outs, radii):
     M2 = O.int2c(sub)
     Ssub = O.Setup(ao, aux, t3[:1], t3[:ks], M2[:1, :1], M2[:ks, :ks])
     t = time.perf_counter()
-    O.pair_weights(Ssub, RS[0], RS[1], False, 2.0, 0.25)
+    O.pair_weights(Ssub, RS[0], RS[1], 0.0, 0.25)
     t_pw = time.perf_counter() - t
     full_pw = t_pw * nK / ks * 2 * len(outs)         # per K function, two pairs per output
     # (3) derivative contraction over the sampled aux shells, one output

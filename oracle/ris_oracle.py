@@ -216,12 +216,22 @@ class Setup:
     int3K: np.ndarray   # [nK][nao][nao]
     MJ: np.ndarray
     MK: np.ndarray
+    scale: np.ndarray | None = None   # [nJ] factors multiplying the auxiliary functions (None: 1)
 
 
-def setup(mol, radius_bohr, theta=DEFAULT_THETA, j_p_on_heavy=True) -> Setup:
+def setup(mol, radius_bohr, theta=DEFAULT_THETA, j_p_on_heavy=True, aux_scale=None) -> Setup:
+    """Integrals of the problem.  aux_scale (optional, [nJ]) multiplies each J
+    auxiliary function (and the K functions, the leading s functions of the J
+    set, by the same factors): an RI result must not depend on it."""
     ao = ao_shells(mol)
     aux = aux_build(mol, radius_bohr, theta, j_p_on_heavy)
-    return Setup(ao, aux, int3c(ao, aux.J), int3c(ao, aux.K), int2c(aux.J), int2c(aux.K))
+    S = Setup(ao, aux, int3c(ao, aux.J), int3c(ao, aux.K), int2c(aux.J), int2c(aux.K))
+    if aux_scale is not None:
+        sJ = np.asarray(aux_scale, dtype=np.float64)
+        sK = sJ[:S.MK.shape[0]]
+        S = Setup(ao, aux, S.int3J * sJ[:, None, None], S.int3K * sK[:, None, None], S.MJ * np.outer(sJ, sJ),
+                  S.MK * np.outer(sK, sK), sJ)
+    return S
 
 
 def metric_solve(M: np.ndarray, t: np.ndarray) -> np.ndarray:
@@ -390,15 +400,16 @@ def energy_at(mol, xyz, radius_bohr, RS1, RS2, LA1, LA2, alpha_J=DEFAULT_ALPHA_J
     return energy_functional(S2, RS1, RS2, LA1, LA2, alpha_J, c_x)
 
 
-def pair_weights(S: Setup, D1, D2, with_J: bool, alpha_J, c_x):
-    """Weights of the derivative integrals for one density pair (D1, D2):
+def pair_weights(S: Setup, D1, D2, alpha_J, c_x):
+    """Weights of the derivative integrals for one density pair (D1, D2) of the
+    bilinear functional a_J sum (mn|ls)_J D1_mn D2_ls - c_x sum (ml|ns)_K D1_mn D2_ls:
     W3J[P] = a_J (D1 c2_P + D2 c1_P), W2J = -a_J c1 c2^T           (Coulomb)
     W3K[P] = -c_x (D1 C^P D2^T + D1^T C^P D2), W2K[P,Q] = c_x V_PQ  (exchange)
     with c = M_J^-1 t, t_P = sum (mn|P) D_mn, C^P = sum_Q (M_K^-1)_PQ (Q|..),
-    V_PQ = sum C^P_ml (D1 C^Q D2^T)_ml."""
+    V_PQ = sum C^P_ml (D1 C^Q D2^T)_ml.  a_J = 0 skips the Coulomb part."""
     nJ = S.MJ.shape[0]
     nK = S.MK.shape[0]
-    if with_J:
+    if alpha_J != 0.0:
         t1 = np.einsum("Pmn,mn->P", S.int3J, D1)
         t2 = np.einsum("Pmn,mn->P", S.int3J, D2)
         c1 = metric_solve(S.MJ, t1)
@@ -418,10 +429,11 @@ def pair_weights(S: Setup, D1, D2, with_J: bool, alpha_J, c_x):
     return W3J, W2J, W3K, W2K
 
 
-def ris_derivative(S: Setup, natm: int, pairs, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX,
-                   atom_mask=None) -> np.ndarray:
-    """Nuclear derivative of E_IJ for a list of outputs.  Each output is a list
-    of (D1, D2, with_J) density pairs; returns [nout][natm][3] (Ha/Bohr)."""
+def ris_derivative(S: Setup, natm: int, pairs, atom_mask=None) -> np.ndarray:
+    """Nuclear derivative of a sum of bilinear ris functionals for a list of
+    outputs.  Each output is a list of (D1, D2, a_J, c_x) terms, each the
+    functional a_J sum (mn|ls)_J D1_mn D2_ls - c_x sum (ml|ns)_K D1_mn D2_ls;
+    returns [nout][natm][3] (Ha/Bohr)."""
     nout = len(pairs)
     nJ = S.MJ.shape[0]
     nK = S.MK.shape[0]
@@ -437,8 +449,12 @@ def ris_derivative(S: Setup, natm: int, pairs, alpha_J=DEFAULT_ALPHA_J, c_x=DEFA
         W2J = np.zeros((len(ob), nJ, nJ))
         W2K = np.zeros((len(ob), nK, nK))
         for k, o in enumerate(ob):
-            for (D1, D2, with_J) in pairs[o]:
-                a, b, c, d = pair_weights(S, D1, D2, with_J, alpha_J, c_x)
+            for (D1, D2, aJ, cx) in pairs[o]:
+                a, b, c, d = pair_weights(S, D1, D2, aJ, cx)
+                if S.scale is not None:   # scaled auxiliary functions (P7): (mn|P)^x scales with P
+                    sJ, sK = S.scale, S.scale[:nK]
+                    a, b = a * sJ[:, None, None], b * np.outer(sJ, sJ)
+                    c, d = c * sK[:, None, None], d * np.outer(sK, sK)
                 W3J[k] += a
                 W2J[k] += b
                 W3K[k] += c
@@ -450,27 +466,69 @@ def ris_derivative(S: Setup, natm: int, pairs, alpha_J=DEFAULT_ALPHA_J, c_x=DEFA
     return g
 
 
-def output_pairs(RS, LA, I: int, J: int):
+def output_pairs(RS, LA, I: int, J: int, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX):
     """Density pairs of E_IJ: the Coulomb + exchange pair {R^S_I, R^S_J} and the
     exchange-only pair {L^A_I, L^A_J} (the Coulomb contraction of an
     antisymmetric density vanishes)."""
-    return [(RS[I], RS[J], True), (LA[I], LA[J], False)]
+    return [(RS[I], RS[J], alpha_J, c_x), (LA[I], LA[J], 0.0, c_x)]
 
 
 def grad_nac(prob, radius_bohr, outputs, alpha_J=DEFAULT_ALPHA_J, c_x=DEFAULT_CX,
              theta=DEFAULT_THETA, j_p_on_heavy=True, extra=None, S: Setup | None = None):
     """ris gradient (I == J) / NAC numerator (I != J) for each (I, J) in outputs,
-    [nout][natm][3] in Ha/Bohr.  `extra` optionally adds generic density pairs
-    (D1, D2, cJ, cK) to every output."""
+    [nout][natm][3] in Ha/Bohr.
+
+    `extra` optionally adds density pairs to single outputs: a list of
+    (k, D1, D2, cJ, cK), each adding to output k the nuclear derivative of
+    cJ sum (mn|ls)_J D1_mn D2_ls - cK sum (ml|ns)_K D1_mn D2_ls at fixed AO
+    matrices D1, D2 over the same ris auxiliary sets.  This is how the
+    ground-state density D and the relaxed density P_I = T_II + Z^S (or the
+    difference density T_IJ) enter the <g^(xi); {D, P}> terms of the
+    gradient and NAC expressions (Sec. 2.2, eqs. gI_xi_ris and gIJ_xi_ris;
+    Appendix A.1 eq. T and A.2), taken here over the ris auxiliary basis
+    because the full density-fitting basis is not part of the path."""
     mol = prob.mol
     if S is None:
         S = setup(mol, radius_bohr, theta, j_p_on_heavy)
     RS, LA = ao_densities(prob.C, prob.nocc, prob.X, prob.Y)
-    pairs = [output_pairs(RS, LA, I, J) for (I, J) in outputs]
-    g = ris_derivative(S, mol.natm, pairs, alpha_J, c_x)
-    if extra:
-        for (D1, D2, cJ, cK) in extra:
-            gj = ris_derivative(S, mol.natm, [[(D1, D2, True)]], alpha_J, 0.0)[0]
-            gk = ris_derivative(S, mol.natm, [[(D1, D2, False)]], 0.0, 1.0)[0]
-            g += cJ * gj + cK * gk
-    return g
+    pairs = [output_pairs(RS, LA, I, J, alpha_J, c_x) for (I, J) in outputs]
+    for (k, D1, D2, cJ, cK) in (extra or ()):
+        pairs[k].append((D1, D2, cJ, cK))
+    return ris_derivative(S, mol.natm, pairs)
+
+
+# ------------------------------------------- densities of Appendix A.1-A.2 --
+def ground_density(C, nocc):
+    """D = C [[1, 0], [0, 0]] C^T: the occupied projector in the AO basis
+    (the matrix D of Appendix A.3 carried to the AO basis)."""
+    CO = C[:, :nocc]
+    return CO @ CO.T
+
+
+def difference_density(C, nocc, X, Y, I: int, J: int):
+    """T_IJ = (gamma + gamma^T) / 2 in the AO basis with the MO matrix
+    gamma^IJ = [[-(X_J^T X_I + Y_I^T Y_J)_ij, 0], [0, (X_I X_J^T + Y_J Y_I^T)_ab]]
+    (Appendix A.1, eq. T); amplitudes X[a][i] (Y = None: TDA)."""
+    o = nocc
+    nmo = C.shape[1]
+    XI, XJ = X[I], X[J]
+    YI = np.zeros_like(XI) if Y is None else Y[I]
+    YJ = np.zeros_like(XJ) if Y is None else Y[J]
+    g = np.zeros((nmo, nmo))
+    g[:o, :o] = -(XJ.T @ XI + YI.T @ YJ)
+    g[o:, o:] = XI @ XJ.T + YJ @ YI.T
+    Tm = 0.5 * (g + g.T)
+    return C @ Tm @ C.T
+
+
+def z_symmetric(C, nocc, Z):
+    """Z^S = (Z + Z^T) / 2 with Z = C_V Z C_O^T (Appendix A.2); Z[a][i]."""
+    Zm = C[:, nocc:] @ Z @ C[:, :nocc].T
+    return 0.5 * (Zm + Zm.T)
+
+
+def relaxed_density(C, nocc, X, Y, I: int, Z, J: int | None = None):
+    """P_I = T_II + Z^S (gradient), or P_IJ = T_IJ + Z~^S when J is given and Z
+    is the scaled multiplier of the coupling (Appendix A.2)."""
+    J = I if J is None else J
+    return difference_density(C, nocc, X, Y, I, J) + z_symmetric(C, nocc, Z)

@@ -463,3 +463,132 @@ def test_planted_mistakes_are_caught(ring, monkeypatch):
     monkeypatch.setattr(O, "pair_weights", flip)
     g = O.grad_nac(p, rad, [(0, 0)], j_p_on_heavy=False, S=S)[0]
     assert abs(g[0, 0] - fd) > 1e-7
+
+
+# ------------------------------------------------- auxiliary basis values --
+def test_aux_exponent_values():
+    """alpha_A = theta / R_A^2 with theta = 0.2 and R_A in Bohr: H (0.37 A)
+    0.409099, C (0.77 A) 0.094461, N (0.75 A) 0.099566, O (0.73 A) 0.105096
+    Bohr^-2 (values worked out by hand from the radii, 1 Bohr = 0.529177210903 A)."""
+    p = molgen.make_problem("ring12")
+    rad = molgen.radii_bohr_table()
+    aux = O.aux_build(p.mol, rad, 0.2, True)
+    exp_by_z = {int(z): float(e) for z, e in zip(p.mol.Z[aux.J.atom], aux.J.exp)}
+    assert abs(exp_by_z[1] - 0.409099) < 5e-7
+    assert abs(exp_by_z[6] - 0.094461) < 5e-7
+    assert abs(0.2 / rad[7] ** 2 - 0.099566) < 5e-7
+    assert abs(0.2 / rad[8] ** 2 - 0.105096) < 5e-7
+    # J = s on every atom then p on heavy atoms, one exponent per atom; K = the s set
+    assert list(aux.J.l) == [0] * 12 + [1] * 6
+    assert np.array_equal(aux.J.exp[12:], aux.J.exp[:6])
+    assert np.array_equal(aux.K.exp, aux.J.exp[:12])
+
+
+# --------------------------------------------- aux normalisation (P7) --
+def test_aux_normalisation_invariance(radii):
+    """Multiplying each auxiliary function by a constant changes (mn|P) and
+    (P|Q) but no RI result.  With powers of two as the constants every scaled
+    quantity is exact in floating point, so energies, matvecs and gradients
+    must agree to 1e-14 relative (gradients: 1e-14 Ha/Bohr absolute, the
+    noise of the oracle's threaded sums; mixed-l AOs, p auxiliary functions,
+    TDDFT amplitudes).  With general constants (0.3..3) the results differ by the
+    rounding of the metric solves, about cond(M_J) u = 3e-12 of their largest
+    terms: bar 1e-10.  A result that dropped or doubled a metric factor moves
+    by O(1) (planted below)."""
+    p = molgen.make_tiny_problem(31, natm=3, lmax=2, nstate=2, tda=False)
+    S0 = O.setup(p.mol, radii, j_p_on_heavy=True)
+    nJ = S0.MJ.shape[0]
+    rng = np.random.default_rng(5)
+    RS, LA = O.ao_densities(p.C, p.nocc, p.X, p.Y)
+    V = np.random.default_rng(6).standard_normal((2,) + p.X.shape[1:])
+    g0 = O.grad_nac(p, radii, [(0, 0), (0, 1)], S=S0)
+    for scale, bar, gbar in ((2.0 ** rng.integers(-3, 4, nJ), 1e-14, 1e-14),
+                             (rng.uniform(0.3, 3.0, nJ), 1e-10, 1e-10 * np.abs(g0).max())):
+        S1 = O.setup(p.mol, radii, j_p_on_heavy=True, aux_scale=scale)
+        assert np.abs(S1.MJ - S0.MJ).max() > 1e-3          # the integrals did change
+        for aJ, cx in ((2.0, 0.0), (0.0, 0.25)):            # Coulomb and exchange parts
+            e0 = O.energy_functional(S0, RS[0], RS[1], LA[0], LA[1], alpha_J=aJ, c_x=cx)
+            e1 = O.energy_functional(S1, RS[0], RS[1], LA[0], LA[1], alpha_J=aJ, c_x=cx)
+            assert abs(e1 - e0) <= bar * abs(e0), (aJ, cx, e0, e1)
+        for op in ("A", "B"):
+            m0 = O.response_matvec(S0, p.C, p.eps, p.nocc, V, op)
+            m1 = O.response_matvec(S1, p.C, p.eps, p.nocc, V, op)
+            assert np.abs(m1 - m0).max() <= bar * np.abs(m0).max()
+        g1 = O.grad_nac(p, radii, [(0, 0), (0, 1)], S=S1)
+        assert np.abs(g1 - g0).max() <= gbar
+    # planted mistake: the scaled integrals without the scale in the derivative weights
+    S_bad = O.Setup(S1.ao, S1.aux, S1.int3J, S1.int3K, S1.MJ, S1.MK, None)
+    g_bad = O.grad_nac(p, radii, [(0, 0)], S=S_bad)
+    assert np.abs(g_bad[0] - g0[0]).max() > 1e-3 * np.abs(g0[0]).max()
+
+
+# ------------------------------- densities of Appendix A.1-A.2, extra pairs --
+def test_difference_density_forms(radii):
+    """T_IJ of eq. T (from X, Y) against the R, L form the ris right-hand side
+    uses for I = J (Appendix A.3: T_II = [[-(R^T R + L^T L)/2, 0], [0, (R R^T +
+    L L^T)/2]]); T_II conserves the electron count (tr S T = 0); T_IJ is
+    symmetric and T_IJ = T_JI."""
+    p = molgen.make_tiny_problem(32, natm=3, lmax=2, nstate=2, tda=False)
+    C, o = p.C, p.nocc
+    Smat = molgen.overlap_matrix(p.mol)
+    R, L = p.X + p.Y, p.X - p.Y
+    for I in range(2):
+        T = O.difference_density(C, o, p.X, p.Y, I, I)
+        nmo = C.shape[1]
+        Tm = np.zeros((nmo, nmo))
+        Tm[:o, :o] = -0.5 * (R[I].T @ R[I] + L[I].T @ L[I])
+        Tm[o:, o:] = 0.5 * (R[I] @ R[I].T + L[I] @ L[I].T)
+        assert np.abs(T - C @ Tm @ C.T).max() < 1e-13 * np.abs(T).max()
+        assert abs(np.sum(Smat * T)) < 1e-12
+    T01 = O.difference_density(C, o, p.X, p.Y, 0, 1)
+    assert np.abs(T01 - T01.T).max() < 1e-14 * np.abs(T01).max()
+    assert np.abs(T01 - O.difference_density(C, o, p.X, p.Y, 1, 0)).max() < 1e-14 * np.abs(T01).max()
+    # the ground density is the occupied projector: D S D = D, tr S D = nocc
+    D = O.ground_density(C, o)
+    assert np.abs(D @ Smat @ D - D).max() < 1e-12 * np.abs(D).max()
+    assert abs(np.sum(Smat * D) - o) < 1e-11
+
+
+def _extra_case(seed, natm, lmax, radii, jp):
+    p = molgen.make_tiny_problem(seed, natm=natm, lmax=lmax, nstate=2, tda=False)
+    Z = np.random.default_rng(seed + 100).standard_normal(p.X.shape[1:])
+    Z *= 0.1 / np.linalg.norm(Z)
+    D = O.ground_density(p.C, p.nocc)
+    P = O.relaxed_density(p.C, p.nocc, p.X, p.Y, 1, Z)
+    return p, D, P
+
+
+@pytest.mark.parametrize("seed,natm,lmax,jp", [(41, 3, 2, True), (42, 4, 1, False)])
+def test_extra_pair_vs_finite_differences(radii, seed, natm, lmax, jp):
+    """The extra-pair branch: the derivative it adds to an output equals the
+    5-point finite difference of cJ sum (mn|ls)_J D1 D2 - cK sum (ml|ns)_K D1 D2
+    at fixed D1 = D (ground density), D2 = P_1 = T_11 + Z^S (seeded Z,
+    |Z| = 0.1), within 1e-9 Ha/Bohr; cJ and cK enter as given (0.7, 0.3 are
+    chosen unlike a_J and c_x so a mixed-up coefficient shows)."""
+    p, D, P = _extra_case(seed, natm, lmax, radii, jp)
+    S = O.setup(p.mol, radii, j_p_on_heavy=jp)
+    cJ, cK = 0.7, 0.3
+    base = O.grad_nac(p, radii, [(1, 1), (0, 1)], j_p_on_heavy=jp, S=S)
+    g = O.grad_nac(p, radii, [(1, 1), (0, 1)], j_p_on_heavy=jp, S=S, extra=[(1, D, P, cJ, cK)])
+    assert np.abs(g[0] - base[0]).max() < 1e-14       # only output 1 gets the pair
+    add = g[1] - base[1]
+    zero = np.zeros_like(D)
+    fun = lambda x: O.energy_at(p.mol, x, radii, D, P, zero, zero, alpha_J=cJ, c_x=cK, j_p_on_heavy=jp)
+    for A in range(natm):
+        for d in range(3):
+            fd = _fd5(fun, p.mol.xyz, A, d)
+            assert abs(fd - add[A, d]) < 1e-9, (A, d, fd, add[A, d])
+    assert np.abs(add.sum(0)).max() < 1e-10
+
+
+def test_extra_pair_planted_mistakes(radii, monkeypatch):
+    """cJ and cK swapped, or the exchange part's sign flipped, in the
+    extra-pair branch must fail the finite-difference pin."""
+    p, D, P = _extra_case(41, 3, 2, radii, True)
+    S = O.setup(p.mol, radii, j_p_on_heavy=True)
+    zero = np.zeros_like(D)
+    fd = _fd5(lambda x: O.energy_at(p.mol, x, radii, D, P, zero, zero, alpha_J=0.7, c_x=0.3), p.mol.xyz, 0, 0)
+    base = O.grad_nac(p, radii, [(1, 1)], S=S)[0]
+    for bad in ((D, P, 0.3, 0.7), (D, P, 0.7, -0.3)):
+        g = O.grad_nac(p, radii, [(1, 1)], S=S, extra=[(0,) + bad])[0]
+        assert abs((g - base)[0, 0] - fd) > 1e-7
