@@ -266,6 +266,24 @@ int ris_int3c(ris_ctx *ctx, const ris_mo *mo, double *dbg_int3c);
  * op selects A, B, A+B or A-B; out has V's shape (device, may not alias V). */
 int ris_response_matvec(ris_ctx *ctx, int op, int nvec, const double *V, double *out);
 
+/* Allocation-free ris_response_matvec, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving or solver loops,
+ * harnesses that forbid hipMalloc.  Same operators, arguments, layouts and
+ * results as ris_response_matvec (the same kernels), but its intermediates
+ * live in a fixed 128 MiB device array that the library holds on every device
+ * it runs on until the process ends; the call makes no hipMalloc / hipFree and
+ * no other allocation, and records no profiling events.  Returns RIS_E_NOMEM,
+ * with the bytes needed in ris_last_error, when even one vector per exchange
+ * chunk needs more scratch than that (the intermediates grow as
+ * nK nvir nocc, so roughly molecules above 70 atoms of the chain workloads);
+ * the context's own state (MO blocks, metric) must already exist (ris_int3c).
+ * Returns once the work is enqueued on the context's stream (no
+ * synchronisation).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other contexts, other host threads) race
+ * and must be serialised by the caller.  Nothing in the array needs to start
+ * at zero; it keeps the last call's contents. */
+int ris_response_matvec_noalloc(ris_ctx *ctx, int op, int nvec, const double *V, double *out);
+
 /* ris part of excited-state gradients (Sec. 2.2, eq. gI_xi_ris): for each
  * selected state I = sel[k], grad[k][A][x] = d/dA_x <g^ris; Gamma_II> at fixed
  * AO transition densities R^S_I, L^A_I built from R_I = X_I + Y_I and

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstdarg>
 #include <cstring>
@@ -20,7 +21,34 @@
 
 using namespace ris;
 
+// Fixed device scratch of ris_response_matvec_noalloc (128 MiB).  Each device
+// that loads the library holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (the array's name on the host is a stand-in, not a device address).
+static __device__ __align__(256) char scratch[(size_t)128 << 20];
+
 namespace {
+
+constexpr size_t kNoAllocScratchBytes = sizeof(scratch);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved once per device).
+hipError_t scratch_address(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 struct DevBuf {
     void *p = nullptr;
@@ -39,6 +67,7 @@ struct ris_ctx {
 
     double *boys = nullptr;  // Boys table
     int *info = nullptr;     // Cholesky status (device)
+    void *scratch_dev = nullptr;  // this device's fixed scratch (ris_response_matvec_noalloc)
 
     // ---- aux_build state
     bool have_aux = false;
@@ -564,6 +593,11 @@ int ris_ctx_create(ris_ctx **out, int device, void *hip_stream, size_t hbm_budge
         return RIS_E_DEVICE;
     }
     c->budget = hbm_budget ? hbm_budget : (size_t)(0.9 * (double)fr);
+    // the fixed scratch of the allocation-free matvec, resolved with the device current
+    if (scratch_address(device, &c->scratch_dev) != hipSuccess) {
+        delete c;
+        return RIS_E_DEVICE;
+    }
     int st;
     c->boys = (double *)dalloc(c, sizeof(double) * kBoysNGrid * kBoysCols, &st);
     c->info = (int *)dalloc(c, 64, &st);
@@ -1307,7 +1341,8 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
 }
 
 // ------------------------------------------------------------------------
-int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *out)
+// Argument checks shared by both matvec entry points.
+static int matvec_check(ris_ctx *c, int op, int nvec, const double *V, double *out)
 {
     if (!c) return RIS_E_INVALID;
     c->err.clear();
@@ -1316,23 +1351,22 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
     if (nvec < 0) return fail(c, RIS_E_INVALID, "nvec < 0");
     if (nvec == 0) return RIS_OK;
     if (!V || !out || V == out) return fail(c, RIS_E_INVALID, "null or aliased vector pointer");
-    HIPCHK(c, hipSetDevice(c->device));
+    return RIS_OK;
+}
+
+// The matvec itself on the scratch wsb (laid out by matvec_ws(nvec, chunk)).
+// timed: bracket it with the stage events (the allocation-free entry point
+// records none, so it creates no events either).
+static int matvec_run(ris_ctx *c, int op, int nvec, const double *V, double *out, char *wsb, int chunk, bool timed)
+{
     const int o = c->nocc, v = c->nvir, nJ = c->nJ, nK = c->nK;
     const long vo = (long)v * o, oo = (long)o * o;
     // coefficients of Delta, J, K_A, K_B for A, B, A+B, A-B
     static const double cDe[4] = {1, 0, 1, 1}, cJ[4] = {1, 1, 2, 0}, cKA[4] = {1, 0, 1, 1}, cKB[4] = {0, 1, 1, -1};
-    // vectors per exchange chunk: as many (up to kMatvecChunk) as the budget allows
-    const size_t other = c->held - c->ws_bytes;
-    const size_t wsroom = std::max(c->budget > other ? c->budget - other : 0, c->ws_bytes);
-    int chunk = std::min(nvec, kMatvecChunk);
-    while (chunk > 1 && matvec_ws(ctx_dims(c), nvec, chunk).total > wsroom) --chunk;
     const MatvecWs MW = matvec_ws(ctx_dims(c), nvec, chunk);
-    int st;
-    char *wsb = ws_get(c, MW.total, &st);
-    if (!wsb) return st;
     double *t = (double *)(wsb + MW.ot), *cc = t + (size_t)nvec * nJ, *T = (double *)(wsb + MW.oT),
            *U = (double *)(wsb + MW.oU), *SKm = (double *)(wsb + MW.oSK);
-    hipEvent_t t_mv = stage_begin(c);
+    hipEvent_t t_mv = timed ? stage_begin(c) : nullptr;
     // Coulomb: t = V (ai|P)^T (tiny output, K = nvir*nocc: split-K) ; cc = t M_J^-1 ; out = cJ alpha_J cc (ai|P)
     HIPCHK(c, dgemm_splitk(gm(nvec, nJ, (int)vo, false, true, 1.0, V, vo, c->aiJ, vo, 0.0, t, nJ), kSplitV, SKm,
                            c->stream));
@@ -1382,8 +1416,44 @@ int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *o
         stage_end(c, t_mv, RIS_STAGE_MATVEC,
                   nvec * ((cJ[op] != 0 ? fJ : 0.0) + (cKA[op] != 0 ? fA : 0.0) + (cKB[op] != 0 ? fB : 0.0)), 0.0);
     }
+    return RIS_OK;
+}
+
+int ris_response_matvec(ris_ctx *c, int op, int nvec, const double *V, double *out)
+{
+    int st = matvec_check(c, op, nvec, V, out);
+    if (st != RIS_OK || nvec == 0) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    // vectors per exchange chunk: as many (up to kMatvecChunk) as the budget allows
+    const size_t other = c->held - c->ws_bytes;
+    const size_t wsroom = std::max(c->budget > other ? c->budget - other : 0, c->ws_bytes);
+    int chunk = std::min(nvec, kMatvecChunk);
+    while (chunk > 1 && matvec_ws(ctx_dims(c), nvec, chunk).total > wsroom) --chunk;
+    char *wsb = ws_get(c, matvec_ws(ctx_dims(c), nvec, chunk).total, &st);
+    if (!wsb) return st;
+    st = matvec_run(c, op, nvec, V, out, wsb, chunk, true);
+    if (st != RIS_OK) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RIS_OK;
+}
+
+int ris_response_matvec_noalloc(ris_ctx *c, int op, int nvec, const double *V, double *out)
+{
+    int st = matvec_check(c, op, nvec, V, out);
+    if (st != RIS_OK || nvec == 0) return st;
+    if (!c->scratch_dev) return fail(c, RIS_E_DEVICE, "fixed scratch of the device was not resolved");
+    HIPCHK(c, hipSetDevice(c->device));
+    // the largest exchange chunk whose scratch fits the fixed array
+    int chunk = std::min(nvec, kMatvecChunk);
+    while (chunk > 1 && matvec_ws(ctx_dims(c), nvec, chunk).total > kNoAllocScratchBytes) --chunk;
+    const size_t need = matvec_ws(ctx_dims(c), nvec, chunk).total;
+    if (need > kNoAllocScratchBytes)
+        return fail(c, RIS_E_NOMEM,
+                    "ris_response_matvec_noalloc: %d vectors need %zu bytes of scratch; the fixed scratch holds %zu "
+                    "(use fewer vectors or ris_response_matvec)",
+                    nvec, need, kNoAllocScratchBytes);
+    // every buffer of the matvec is written before it is read: nothing to clear
+    return matvec_run(c, op, nvec, V, out, (char *)c->scratch_dev, chunk, false);
 }
 
 // Y^P = F_I W^P and the exchange weights Gamma^P for nP auxiliary functions:

@@ -22,7 +22,7 @@ STATUS = {0: "RIS_OK", 1: "RIS_E_INVALID", 2: "RIS_E_UNSUPPORTED", 3: "RIS_E_NOM
 OPS = {"A": 0, "B": 1, "A+B": 2, "A-B": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
-           "ris_response_matvec", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
+           "ris_response_matvec", "ris_response_matvec_noalloc", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
            "ris_request_bytes", "ris_plan_bytes",
            "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_ctx_set_blocking", "ris_zvector_solve",
            "ris_tda_davidson",
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
     lib.ris_aux_build.argtypes = [vp, ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ip, ip]
     lib.ris_int3c.argtypes = [vp, ctypes.POINTER(_MO), vp]
     lib.ris_response_matvec.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.ris_response_matvec_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.ris_grad_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp]
     lib.ris_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, dp, vp]
     lib.ris_request_bytes.argtypes = [ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ctypes.c_int, ctypes.c_int,
@@ -248,6 +249,16 @@ class RisContext:
         nvec = V.shape[0] if V.dim() == 3 else 1
         self._chk(self.lib.ris_response_matvec(self.h, OPS[op] if isinstance(op, str) else int(op), nvec, _ptr(V),
                                                _ptr(out)))
+        return out
+
+    def response_matvec_noalloc(self, op, V, out):
+        """ris_response_matvec_noalloc: the same product with the library's fixed
+        device scratch (no allocation; enqueued only).  `out` must be given."""
+        _check_dev(V, self.device, "V")
+        _check_dev(out, self.device, "out")
+        nvec = V.shape[0] if V.dim() == 3 else 1
+        self._chk(self.lib.ris_response_matvec_noalloc(self.h, OPS[op] if isinstance(op, str) else int(op), nvec,
+                                                       _ptr(V), _ptr(out)))
         return out
 
     def zvector_solve(self, rhs, tol=1e-10, maxit=200, out=None, allow_noconv=False):
