@@ -284,32 +284,79 @@ int ris_response_matvec(ris_ctx *ctx, int op, int nvec, const double *V, double 
  * at zero; it keeps the last call's contents. */
 int ris_response_matvec_noalloc(ris_ctx *ctx, int op, int nvec, const double *V, double *out);
 
+/* One extra density pair of a gradient / NAC output: the <g^(xi); {D, P}>
+ * terms of Sec. 2.2 (eqs. gI_xi_ris and gIJ_xi_ris), in which the ground-state
+ * density D meets the relaxed density P_I = T_II + Z^S of a gradient or
+ * P_IJ = T_IJ + Z~^S of a coupling (Appendix A.1 eq. T, Appendix A.2), taken
+ * here over the same ris auxiliary sets as the transition densities (the
+ * full density-fitting basis is not part of this path).  The pair adds to
+ * output `out` the nuclear derivative, at fixed D1 and D2, of
+ *     cJ sum (mn|ls)_J D1_mn D2_ls - cK sum (ml|ns)_K D1_mn D2_ls
+ * with (pq|rs)_X = sum_PQ (pq|P)(M_X^-1)_PQ(Q|rs), the three-term RI
+ * derivative included.  D1 and D2 are device [nao][nao] arrays in the
+ * caller's AO order, read only; they are taken as symmetric (the call uses
+ * (D + D^T)/2, which is the matrix itself for the densities above).  The
+ * extra pairs run in FP64 in every precision mode.  ris_density_ao builds D,
+ * T_IJ and P_IJ on the device. */
+typedef struct {
+    int out;            /* output index: into sel (gradients) or pairs (NACs);
+                           ris_grad_nac_contract counts the nsel gradients first */
+    const double *D1;   /* [nao][nao] device */
+    const double *D2;   /* [nao][nao] device */
+    double cJ;          /* Coulomb coefficient */
+    double cK;          /* exchange coefficient */
+} ris_extra_pair;
+
 /* ris part of excited-state gradients (Sec. 2.2, eq. gI_xi_ris): for each
  * selected state I = sel[k], grad[k][A][x] = d/dA_x <g^ris; Gamma_II> at fixed
  * AO transition densities R^S_I, L^A_I built from R_I = X_I + Y_I and
- * L_I = X_I - Y_I (Appendix A.1), including the (P|Q) metric derivative.
+ * L_I = X_I - Y_I (Appendix A.1), including the (P|Q) metric derivative,
+ * plus the derivatives of the extra pairs that name output k (nextra may be
+ * 0 and extra NULL).
  * X, Y: [nstate][nvir][nocc] device; Y = NULL means TDA (Y = 0, Sec. 3).
- * grad: [nsel][natm][3] device, Ha/Bohr (dE/dR, not a force). */
+ * grad: [nsel][natm][3] device, Ha/Bohr (dE/dR, not a force).
+ * Synchronises the context's stream before returning. */
 int ris_grad_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y,
-                      int nsel, const int *sel, double *grad);
+                      int nsel, const int *sel, int nextra, const ris_extra_pair *extra, double *grad);
 
 /* ris part of NACs between excited states (Sec. 2.2, eq. gIJ_xi_ris): for
  * each pair (I, J) = (pairs[2k], pairs[2k+1]) writes the numerator
- * d/dA_x <g^ris; Gamma_IJ> to nac[k][A][x] (device, Ha/Bohr); if omega
- * (host, [nstate]) is given the result is divided by (omega_J - omega_I)
- * (1/Bohr).  Returns RIS_E_DEGENERATE (after writing the numerator) if any
- * gap is below 1e-12. */
+ * d/dA_x <g^ris; Gamma_IJ> (plus the extra pairs that name output k) to
+ * nac[k][A][x] (device, Ha/Bohr); if omega (host, [nstate]) is given the
+ * whole numerator is divided by (omega_J - omega_I) (1/Bohr).  Returns
+ * RIS_E_DEGENERATE (after writing the numerator) if any gap is below 1e-12.
+ * Synchronises the context's stream before returning. */
 int ris_nac_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y,
-                     int npair, const int *pairs, const double *omega, double *nac);
+                     int npair, const int *pairs, int nextra, const ris_extra_pair *extra,
+                     const double *omega, double *nac);
 
 /* Gradients and NAC numerators in one call (Sec. 2.2, eqs. gI_xi_ris and
  * gIJ_xi_ris): same outputs and errors as ris_grad_contract followed by
  * ris_nac_contract on the same amplitudes, but the per-state intermediates
  * (AO transition-density factors and their exchange blocks) are built once
- * for all outputs.  Either list may be empty (its pointers may then be NULL). */
+ * for all outputs.  Either list may be empty (its pointers may then be NULL).
+ * extra[e].out counts the nsel gradients first, then the npair couplings.
+ * Synchronises the context's stream before returning. */
 int ris_grad_nac_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y,
                           int nsel, const int *sel, double *grad,
-                          int npair, const int *pairs, const double *omega, double *nac);
+                          int npair, const int *pairs, const double *omega, double *nac,
+                          int nextra, const ris_extra_pair *extra);
+
+/* AO densities for the extra pairs (device, FP64, every precision mode):
+ *   RIS_DENS_GROUND     : D = C_O C_O^T, the occupied projector (the MO
+ *                         matrix diag(1_occ, 0) of Appendix A.3 in the AO basis);
+ *   RIS_DENS_DIFFERENCE : T_IJ = C (gamma + gamma^T)/2 C^T with
+ *                         gamma_oo = -(X_J^T X_I + Y_I^T Y_J),
+ *                         gamma_vv = X_I X_J^T + Y_J Y_I^T (Appendix A.1, eq. T);
+ *   RIS_DENS_RELAXED    : T_IJ + Z^S, Z^S = (C_V Z C_O^T + C_O Z^T C_V^T)/2
+ *                         (Appendix A.2: P_I = T_II + Z^S, P_IJ = T_IJ + Z~^S).
+ * X, Y: [nstate][nvir][nocc] device (Y = NULL: TDA), I, J < nstate (ignored
+ * for the ground density, as are X, Y and Z); Z: [nvir][nocc] device (the
+ * relaxed density only); D: [nao][nao] device, caller AO order, overwritten.
+ * Uses the orbitals given to ris_int3c (RIS_E_ORDER before it). */
+enum ris_density { RIS_DENS_GROUND = 0, RIS_DENS_DIFFERENCE = 1, RIS_DENS_RELAXED = 2 };
+int ris_density_ao(ris_ctx *ctx, int kind, int nstate, const double *X, const double *Y, int I, int J,
+                   const double *Z, double *D);
 
 #ifdef __cplusplus
 }

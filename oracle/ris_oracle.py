@@ -47,6 +47,14 @@ What it computes, and where the paper defines it:
   definition: the dense (A+B)^ris assembled column by column from the matvec
   and a direct solve.
 
+* extra density pairs: the <g^(xi); {D, P}> terms of the gradient and NAC
+  (Sec. 2.2, eqs. gI_xi_ris / gIJ_xi_ris) with the ground density D, the
+  difference density T_IJ (Appendix A.1 eq. T) and the relaxed density
+  P = T + Z^S (Appendix A.2), each pair (D1, D2, cJ, cK) contributing the
+  derivative of cJ sum (mn|ls)_J D1 D2 - cK sum (ml|ns)_K D1 D2 over the same
+  ris auxiliary sets (the paper's full density-fitting basis is not part of
+  the path).  Pinned by 5-point finite differences of that functional.
+
 Readings where the paper is silent or ambiguous (each one a parameter here):
 a_J (closed-shell Coulomb factor, default 2), c_x (default 0.25, PBE0),
 the exchange index order for antisymmetric L^A (chosen so that E_II equals

@@ -75,6 +75,7 @@ struct ris_ctx {
     int nJ = 0, nK = 0, nshJ = 0, nsJ = 0;  // J functions, K functions, J shells, J s-shells
     std::vector<int> h_ao_perm;             // internal AO function -> caller AO function
     std::vector<int> h_ao_atom, h_aux_atom;
+    std::vector<int> h_aux_off;             // first J function of each J shell (+ total)
     AOGeom ao{};
     AuxGeom aux{};
     int auxl_beg[kMaxAuxL + 2] = {0, 0, 0};
@@ -1160,6 +1161,7 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
     c->auxl_beg[1] = natm;
     c->auxl_beg[2] = nshJ;
     c->h_aux_atom = aat;
+    c->h_aux_off = aoff;
     c->natm = natm;
     c->nao = nao;
     c->nshAO = nsh;
@@ -1934,17 +1936,218 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
     return RIS_OK;
 }
 
+// ------------------------------------------------------------------------
+// Extra density pairs (ris_extra_pair): pair e adds to its output the nuclear
+// derivative, at fixed symmetric D1, D2 (internal AO order), of
+//   cJ sum (mn|ls)_J D1_mn D2_ls - cK sum (ml|ns)_K D1_mn D2_ls.
+// Coulomb: t_x[P] = sum (mn|P) D_x,mn, c_x = M_J^-1 t_x; weights cJ (D1 c2_P + D2 c1_P)
+// on (mn|P)^xi and -cJ c1 c2^T on M_J^xi.  Exchange: with C^P = sum_Q (M_K^-1)_PQ (Q|..)
+// and X^P = D1 C^P D2, weights -cK (X^P + X^P^T) on (mn|P)^xi and cK V on M_K^xi,
+// V_PQ = <X^P, C^Q> = sum_R <X^P, (R|..)> (M_K^-1)_RQ.  The AO integrals are
+// recomputed in blocks of whole shells of at most nb functions: once over the
+// J shells for t and, per block of exchange functions, once for C^P of the
+// block and once per pair for its rows of V (a block already in place is not
+// recomputed, so a single block costs one evaluation).
+struct ExtraWs {
+    size_t oD, ot, oc, ocs, oSK, oV2, oV, oVr, op3, op2, oshA, oshC, oshP, oG, oCb, oUb, oXb, oBq, total;
+};
+// K-split of the Gram-type products V = X B^T (m x nq output, K = nao^2): about
+// 1024 workgroups over the output tiles
+static int extra_vsplit(int m, int n)
+{
+    const long t = (long)((m + 127) / 128) * ((n + 127) / 128);
+    return (int)std::max(1L, std::min(256L, 1024L / t));
+}
+static ExtraWs extra_ws(const Dims &d, int ne, int nb)
+{
+    Carve cv;
+    ExtraWs L;
+    const size_t NN = (size_t)d.N * d.N, NO = kMaxOutChunk;
+    L.oD = cv.take((size_t)2 * ne * NN);
+    L.ot = cv.take((size_t)2 * ne * d.nJ);
+    L.oc = cv.take((size_t)2 * ne * d.nJ);
+    L.ocs = cv.take((size_t)2 * ne * d.nJ);
+    // split-K partials: t (2ne x nb per range) and V (at most 1024 x 128^2 over all ranges, or nb^2 unsplit)
+    L.oSK = cv.take(std::max({(size_t)kSplitV * 2 * ne * nb, (size_t)1024 * 128 * 128, (size_t)nb * nb}));
+    L.oV2 = cv.take(NO * d.nJ * d.nJ);
+    L.oV = cv.take(NO * d.nK * d.nK);
+    L.oVr = cv.take((size_t)nb * d.nK);
+    L.op3 = cv.take((size_t)d.nshAO * d.nshJ * 3 * NO * 6);
+    L.op2 = cv.take((size_t)d.nshJ * 2 * NO * 3);
+    L.oshA = cv.take((size_t)d.nshAO * NO * 3);
+    L.oshC = cv.take((size_t)d.nshJ * NO * 3);
+    L.oshP = cv.take((size_t)d.nshJ * NO * 3);
+    L.oG = cv.take(NO * d.natm * 3);
+    L.oCb = cv.take((size_t)nb * NN);
+    L.oUb = cv.take((size_t)nb * NN);
+    L.oXb = cv.take((size_t)nb * NN);
+    L.oBq = cv.take((size_t)nb * NN);
+    L.total = cv.off;
+    return L;
+}
+
+static int contract_extra(ris_ctx *c, int ne, const ris_extra_pair *ex, const int *eout, double *outg)
+{
+    const int N = c->nao, nJ = c->nJ, nK = c->nK, natm = c->natm, NO = kMaxOutChunk;
+    const long NN = (long)N * N;
+    if (nK > c->auxl_beg[1]) return fail(c, RIS_E_UNSUPPORTED, "exchange set is not a run of leading s shells");
+    const Dims dm = ctx_dims(c);
+    // the largest block of auxiliary functions (at least one p shell) that fits
+    const size_t other = c->held - c->ws_bytes;
+    const size_t wsroom = std::max(c->budget > other ? c->budget - other : 0, c->ws_bytes);
+    int nb = std::max(nK, 3);
+    if (c->ablock > 0) nb = std::min(nb, c->ablock);
+    nb = std::max(nb, 3);
+    while (nb > 3 && extra_ws(dm, ne, nb).total > wsroom) nb = std::max(3, (int)(nb * 0.8));
+    const ExtraWs EW = extra_ws(dm, ne, nb);
+    int st;
+    char *wsb = ws_get(c, EW.total, &st);
+    if (!wsb) return st;
+    auto P_ = [&](size_t off) { return (double *)(wsb + off); };
+    double *Dx = P_(EW.oD), *t = P_(EW.ot), *cr = P_(EW.oc), *cs = P_(EW.ocs), *SK = P_(EW.oSK), *V2 = P_(EW.oV2),
+           *Vk = P_(EW.oV), *Vr = P_(EW.oVr), *p3 = P_(EW.op3), *p2 = P_(EW.op2), *shA = P_(EW.oshA),
+           *shC = P_(EW.oshC), *shP = P_(EW.oshP), *Gt = P_(EW.oG), *Cb = P_(EW.oCb), *Ub = P_(EW.oUb),
+           *Xb = P_(EW.oXb), *Bq = P_(EW.oBq);
+    const std::vector<int> &aoff = c->h_aux_off;
+
+    // densities in the internal AO order, symmetrised: Dx[2e] = D1 of pair e, Dx[2e+1] = D2
+    for (int e = 0; e < ne; ++e)
+        for (int x = 0; x < 2; ++x) {
+            double *Dd = Dx + (size_t)(2 * e + x) * NN;
+            HIPCHK(c, gather_sq(x ? ex[e].D2 : ex[e].D1, Dd, c->d_ao_perm, N, c->stream));
+            HIPCHK(c, symmetrize(Dd, N, 1, c->stream));
+        }
+    // blocks of whole J shells [a, b) holding at most nb functions
+    auto shell_blocks = [&](int s0, int s1) {
+        std::vector<std::pair<int, int>> bl;
+        for (int a = s0; a < s1;) {
+            int b = a + 1;
+            while (b < s1 && aoff[b + 1] - aoff[a] <= nb) ++b;
+            bl.push_back({a, b});
+            a = b;
+        }
+        return bl;
+    };
+    // (mn|P) of the J shells [a, b) in Bq (row 0 = first function of shell a)
+    int bq_a = -1, bq_b = -1;
+    auto int3c_block = [&](int a, int b) -> hipError_t {
+        if (a == bq_a && b == bq_b) return hipSuccess;
+        bq_a = a;
+        bq_b = b;
+        return launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, Bq, c->stream, a, b);
+    };
+
+    // Coulomb vectors of every extra density: t = D (mn|P)^T over the J set, c = t M_J^-1
+    for (auto [a, b] : shell_blocks(0, c->nshJ)) {
+        const int f0 = aoff[a], nf = aoff[b] - aoff[a];
+        HIPCHK(c, int3c_block(a, b));
+        HIPCHK(c, dgemm_splitk(gm(2 * ne, nf, (int)NN, false, true, 1.0, Dx, NN, Bq, NN, 0.0, t + f0, nJ), kSplitV,
+                               SK, c->stream));
+    }
+    HIPCHK(c, dgemm(gm(2 * ne, nJ, nJ, false, false, 1.0, t, nJ, c->MinvJ, nJ, 0.0, cr, nJ), c->stream));
+
+    DerivJob job{};
+    job.dens = Dx;
+    job.cvec = cs;
+    job.nJ = nJ;
+    job.alphaJ = 1.0;  // cJ is carried by the scaled Coulomb vectors cs
+    job.pair_ptr = c->screen > 0.0 ? c->d_pair_ptr : nullptr;
+    job.pair_idx = c->d_pair_idx;
+    const auto kblocks = shell_blocks(0, nK);  // the K functions: the leading s shells, one function each
+    for (int e0 = 0; e0 < ne; e0 += NO) {
+        const int r = std::min(NO, ne - e0);
+        for (int q = 0; q < r; ++q) {
+            const int e = e0 + q;
+            HIPCHK(c, axpby(cr + (size_t)2 * e * nJ, cs + (size_t)2 * e * nJ, (size_t)2 * nJ, ex[e].cJ, 0.0,
+                            c->stream));
+        }
+        HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * NO * 6, 0.0, c->stream));
+        for (auto [k0, k1] : kblocks) {
+            const int m = k1 - k0;
+            // C^P = sum_Q (M_K^-1)_PQ (Q|..) for P in the block
+            for (auto [q0, q1] : kblocks) {
+                HIPCHK(c, int3c_block(q0, q1));
+                HIPCHK(c, dgemm(gm(m, (int)NN, q1 - q0, false, false, 1.0, c->MinvK + (size_t)k0 * nK + q0, nK, Bq,
+                                   NN, q0 ? 1.0 : 0.0, Cb, NN), c->stream));
+            }
+            for (int q = 0; q < r; ++q) {
+                const int e = e0 + q;
+                const double *D1 = Dx + (size_t)2 * e * NN, *D2 = D1 + NN;
+                // X^P = D1 C^P D2
+                GemmArgs g = gm(N, N, N, false, false, 1.0, D1, N, Cb, N, 0.0, Ub, N);
+                g.batch = m; g.strideA = 0; g.strideB = NN; g.strideC = NN;
+                HIPCHK(c, dgemm(g, c->stream));
+                g = gm(N, N, N, false, false, 1.0, Ub, N, D2, N, 0.0, Xb, N);
+                g.batch = m; g.strideA = NN; g.strideB = 0; g.strideC = NN;
+                HIPCHK(c, dgemm(g, c->stream));
+                // the block's rows of V: Vr[P][R] = <X^P, (R|..)>, V[P][Q] = sum_R Vr[P][R] (M_K^-1)_RQ
+                for (auto [q0, q1] : kblocks) {
+                    HIPCHK(c, int3c_block(q0, q1));
+                    HIPCHK(c, dgemm_splitk(gm(m, q1 - q0, (int)NN, false, true, 1.0, Xb, NN, Bq, NN, 0.0, Vr + q0, nK),
+                                           extra_vsplit(m, q1 - q0), SK, c->stream));
+                }
+                HIPCHK(c, dgemm(gm(m, nK, nK, false, false, 1.0, Vr, nK, c->MinvK, nK, 0.0,
+                                   Vk + ((size_t)q * nK + k0) * nK, nK), c->stream));
+                // exchange weights of the block on the lower triangle: -cK (X^P + X^P^T)
+                HIPCHK(c, sym_sum_lower(Xb, Ub, N, m, -ex[e].cK, c->stream));
+                // derivative contraction over the block's shells, Coulomb part included, into slot q
+                job.nout = 1;
+                job.gammaK = Ub;
+                job.nK = m;
+                job.kbeg = k0;
+                job.partial = p3 + 6 * q;
+                for (int u = 0; u < NO; ++u) {
+                    job.stI[u] = 2 * e;
+                    job.stJ[u] = 2 * e + 1;
+                }
+                HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, k0, k1));
+            }
+        }
+        // the remaining (p) shells carry the Coulomb part only
+        if (nK < c->nshJ) {
+            job.nout = r;
+            job.gammaK = nullptr;
+            job.nK = 0;
+            job.kbeg = 0;
+            job.partial = p3;
+            for (int u = 0; u < NO; ++u) {
+                const int e = e0 + std::min(u, r - 1);
+                job.stI[u] = 2 * e;
+                job.stJ[u] = 2 * e + 1;
+            }
+            HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, nK, c->nshJ));
+        }
+        // metric weights: W2 = -cJ c1 c2^T + cK V (V on the leading K block)
+        for (int q = 0; q < r; ++q) {
+            const int e = e0 + q;
+            double *V2q = V2 + (size_t)q * nJ * nJ;
+            HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -ex[e].cJ, cr + (size_t)2 * e * nJ, nJ,
+                               cr + (size_t)(2 * e + 1) * nJ, nJ, 0.0, V2q, nJ), c->stream));
+            HIPCHK(c, add_sym(Vk + (size_t)q * nK * nK, nK, V2q, nJ, 0.5 * ex[e].cK, c->stream));
+        }
+        HIPCHK(c, fill(p2, (size_t)c->nshJ * 2 * r * 3, 0.0, c->stream));
+        HIPCHK(c, launch_int2c_deriv(c->aux, c->boys, r, V2, p2, c->stream));
+        HIPCHK(c, reduce_grad(p3, c->nshAO, c->nshJ, r, NO, p2, c->ao.sh.atom, c->aux.sh.atom, natm, shA, shC, shP,
+                              1.0, 0, Gt, c->stream));
+        // added into the outputs in pair order (deterministic)
+        for (int q = 0; q < r; ++q)
+            HIPCHK(c, axpby(Gt + (size_t)q * natm * 3, outg + (size_t)eout[e0 + q] * natm * 3, (size_t)natm * 3, 1.0,
+                            1.0, c->stream));
+    }
+    return RIS_OK;
+}
+
 int ris_grad_nac_contract(ris_ctx *c, int nstate, const double *X, const double *Y, int nsel, const int *sel,
-                          double *grad, int npair, const int *pairs, const double *omega, double *nac)
+                          double *grad, int npair, const int *pairs, const double *omega, double *nac, int nextra,
+                          const ris_extra_pair *extra)
 {
     if (!c) return RIS_E_INVALID;
     c->err.clear();
     if (!c->have_int3c) return fail(c, RIS_E_ORDER, "gradient/NAC call before ris_int3c");
-    if (nstate <= 0 || nsel < 0 || npair < 0 || !X || (nsel > 0 && (!sel || !grad)) ||
-        (npair > 0 && (!pairs || !nac)))
+    if (nstate <= 0 || nsel < 0 || npair < 0 || nextra < 0 || !X || (nsel > 0 && (!sel || !grad)) ||
+        (npair > 0 && (!pairs || !nac)) || (nextra > 0 && !extra))
         return fail(c, RIS_E_INVALID, "bad gradient/NAC arguments");
     const int nout = nsel + npair;
-    if (nout == 0) return RIS_OK;
     std::vector<int> pI(nout), pJ(nout);
     for (int k = 0; k < nsel; ++k) {
         if (sel[k] < 0 || sel[k] >= nstate) return fail(c, RIS_E_INVALID, "sel[%d]=%d out of range", k, sel[k]);
@@ -1956,6 +2159,16 @@ int ris_grad_nac_contract(ris_ctx *c, int nstate, const double *X, const double 
         if (pI[nsel + k] < 0 || pI[nsel + k] >= nstate || pJ[nsel + k] < 0 || pJ[nsel + k] >= nstate)
             return fail(c, RIS_E_INVALID, "pair %d out of range", k);
     }
+    std::vector<int> eout(nextra);
+    for (int e = 0; e < nextra; ++e) {
+        if (extra[e].out < 0 || extra[e].out >= nout)
+            return fail(c, RIS_E_INVALID, "extra pair %d names output %d of %d", e, extra[e].out, nout);
+        if (!extra[e].D1 || !extra[e].D2) return fail(c, RIS_E_INVALID, "extra pair %d: null density", e);
+        if (!std::isfinite(extra[e].cJ) || !std::isfinite(extra[e].cK))
+            return fail(c, RIS_E_INVALID, "extra pair %d: coefficient not finite", e);
+        eout[e] = extra[e].out;
+    }
+    if (nout == 0) return RIS_OK;
     int st;
     double *out = nullptr;
     const size_t per = (size_t)c->natm * 3;
@@ -1966,38 +2179,94 @@ int ris_grad_nac_contract(ris_ctx *c, int nstate, const double *X, const double 
         out = nsel > 0 ? grad : nac;
     }
     st = contract_pairs(c, nstate, X, Y, nout, pI.data(), pJ.data(), out);
+    if (st == RIS_OK && nextra > 0) st = contract_extra(c, nextra, extra, eout.data(), out);
     if (st == RIS_OK && nsel > 0 && npair > 0) {
         HIPCHK(c, hipMemcpyAsync(grad, out, 8 * per * nsel, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(nac, out + per * nsel, 8 * per * npair, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    if (st || !omega || npair == 0) return st;
+    if (st) return st;
     bool degenerate = false;
-    for (int k = 0; k < npair; ++k) {
-        const double gap = omega[pJ[nsel + k]] - omega[pI[nsel + k]];
-        if (std::fabs(gap) < 1e-12) {
-            degenerate = true;
-            continue;
+    if (omega) {
+        for (int k = 0; k < npair; ++k) {
+            const double gap = omega[pJ[nsel + k]] - omega[pI[nsel + k]];
+            if (std::fabs(gap) < 1e-12) {
+                degenerate = true;
+                continue;
+            }
+            HIPCHK(c, axpby(nac + (size_t)k * per, nac + (size_t)k * per, per, 1.0 / gap, 0.0, c->stream));
         }
-        HIPCHK(c, axpby(nac + (size_t)k * per, nac + (size_t)k * per, per, 1.0 / gap, 0.0, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (degenerate) return fail(c, RIS_E_DEGENERATE, "degenerate state pair: numerator left undivided");
     return RIS_OK;
 }
 
-int ris_grad_contract(ris_ctx *c, int nstate, const double *X, const double *Y, int nsel, const int *sel, double *grad)
+int ris_grad_contract(ris_ctx *c, int nstate, const double *X, const double *Y, int nsel, const int *sel, int nextra,
+                      const ris_extra_pair *extra, double *grad)
 {
     if (!c) return RIS_E_INVALID;
     if (nsel > 0 && !sel) return fail(c, RIS_E_INVALID, "null selection");
-    return ris_grad_nac_contract(c, nstate, X, Y, nsel, sel, grad, 0, nullptr, nullptr, nullptr);
+    return ris_grad_nac_contract(c, nstate, X, Y, nsel, sel, grad, 0, nullptr, nullptr, nullptr, nextra, extra);
 }
 
 int ris_nac_contract(ris_ctx *c, int nstate, const double *X, const double *Y, int npair, const int *pairs,
-                     const double *omega, double *nac)
+                     int nextra, const ris_extra_pair *extra, const double *omega, double *nac)
 {
     if (!c) return RIS_E_INVALID;
-    return ris_grad_nac_contract(c, nstate, X, Y, 0, nullptr, nullptr, npair, pairs, omega, nac);
+    return ris_grad_nac_contract(c, nstate, X, Y, 0, nullptr, nullptr, npair, pairs, omega, nac, nextra, extra);
+}
+
+int ris_density_ao(ris_ctx *c, int kind, int nstate, const double *X, const double *Y, int I, int J, const double *Z,
+                   double *D)
+{
+    if (!c) return RIS_E_INVALID;
+    c->err.clear();
+    if (!c->have_int3c) return fail(c, RIS_E_ORDER, "ris_density_ao before ris_int3c");
+    if (kind < RIS_DENS_GROUND || kind > RIS_DENS_RELAXED) return fail(c, RIS_E_INVALID, "unknown density %d", kind);
+    if (!D) return fail(c, RIS_E_INVALID, "null output");
+    if (kind != RIS_DENS_GROUND) {
+        if (!X || nstate <= 0 || I < 0 || J < 0 || I >= nstate || J >= nstate)
+            return fail(c, RIS_E_INVALID, "bad amplitudes or state index (I=%d, J=%d, nstate=%d)", I, J, nstate);
+        if (kind == RIS_DENS_RELAXED && !Z) return fail(c, RIS_E_INVALID, "relaxed density without Z");
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    const int N = c->nao, nmo = c->nmo, o = c->nocc, v = c->nvir;
+    const long vo = (long)v * o, NN = (long)N * N;
+    Carve cv;
+    const size_t oM = cv.take(NN), o1 = cv.take((size_t)N * std::max(v, o)), o2 = cv.take((size_t)N * std::max(v, o));
+    int st;
+    char *wsb = ws_get(c, cv.off, &st);
+    if (!wsb) return st;
+    double *M = (double *)(wsb + oM), *T1 = (double *)(wsb + o1), *T2 = (double *)(wsb + o2);
+    const double *CO = c->C, *CV = c->C + o;
+    if (kind == RIS_DENS_GROUND) {
+        HIPCHK(c, dgemm(gm(N, N, o, false, true, 1.0, CO, nmo, CO, nmo, 0.0, M, N), c->stream));
+    } else {
+        const double *XI = X + (size_t)I * vo, *XJ = X + (size_t)J * vo;
+        // occupied block: -C_O (X_J^T X_I + Y_I^T Y_J) C_O^T = -(X_J C_O^T)^T (X_I C_O^T) - (Y_I C_O^T)^T (Y_J C_O^T)
+        for (int y = 0; y < (Y ? 2 : 1); ++y) {
+            const double *A = y ? Y + (size_t)I * vo : XJ, *B = y ? Y + (size_t)J * vo : XI;
+            HIPCHK(c, dgemm(gm(v, N, o, false, true, 1.0, A, o, CO, nmo, 0.0, T1, N), c->stream));
+            HIPCHK(c, dgemm(gm(v, N, o, false, true, 1.0, B, o, CO, nmo, 0.0, T2, N), c->stream));
+            HIPCHK(c, dgemm(gm(N, N, v, true, false, -1.0, T1, N, T2, N, y ? 1.0 : 0.0, M, N), c->stream));
+        }
+        // virtual block: C_V (X_I X_J^T + Y_J Y_I^T) C_V^T = (C_V X_I)(C_V X_J)^T + (C_V Y_J)(C_V Y_I)^T
+        for (int y = 0; y < (Y ? 2 : 1); ++y) {
+            const double *A = y ? Y + (size_t)J * vo : XI, *B = y ? Y + (size_t)I * vo : XJ;
+            HIPCHK(c, dgemm(gm(N, o, v, false, false, 1.0, CV, nmo, A, o, 0.0, T1, o), c->stream));
+            HIPCHK(c, dgemm(gm(N, o, v, false, false, 1.0, CV, nmo, B, o, 0.0, T2, o), c->stream));
+            HIPCHK(c, dgemm(gm(N, N, o, false, true, 1.0, T1, o, T2, o, 1.0, M, N), c->stream));
+        }
+        if (kind == RIS_DENS_RELAXED) {
+            // + C_V Z C_O^T (symmetrised below with the rest)
+            HIPCHK(c, dgemm(gm(N, o, v, false, false, 1.0, CV, nmo, Z, o, 0.0, T1, o), c->stream));
+            HIPCHK(c, dgemm(gm(N, N, o, false, true, 1.0, T1, o, CO, nmo, 1.0, M, N), c->stream));
+        }
+    }
+    HIPCHK(c, symmetrize(M, N, 1, c->stream));
+    HIPCHK(c, scatter_sq(M, D, c->d_ao_perm, N, 1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RIS_OK;
 }
 
 }  // extern "C"

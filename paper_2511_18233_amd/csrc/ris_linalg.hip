@@ -135,6 +135,16 @@ __global__ void k_scatter_sq(const double *__restrict__ in, double *__restrict__
     out[b * nn + (long)perm[i] * n + perm[j]] = in[idx];
 }
 
+// out[i][j] = in[perm[i]][perm[j]]  (one n x n matrix into the permuted order)
+__global__ void k_gather_sq(const double *__restrict__ in, double *__restrict__ out, const int *__restrict__ perm,
+                            int n)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    out[idx] = in[(long)perm[i] * n + perm[j]];
+}
+
 // R = X + s Y, L = X - s Y  (s = 0 when Y is absent)
 __global__ void k_rl(const double *__restrict__ X, const double *__restrict__ Y, double *__restrict__ R,
                      double *__restrict__ L, size_t n)
@@ -205,6 +215,32 @@ __global__ void k_transpose(const double *__restrict__ in, long ldi, double *__r
             if (r < R && col < C) out[(long)col * ldo + r] = t[tx][ty + k];
         }
         __syncthreads();
+    }
+}
+
+// G_b[r][c] = s (X_b[r][c] + X_b[c][r]) on the lower triangle (c <= r) of n x n
+// blocks b (batch stride sB): 32 x 32 tiles on or below the diagonal, the
+// mirrored tile staged through LDS so that both reads are coalesced.  Only
+// lower tiles are written and only the block's own and its mirrored tile are
+// read, so G may alias X.
+__global__ void k_sym_sum_lower(const double *__restrict__ X, double *__restrict__ G, int n, long sB, double s)
+{
+    __shared__ double t[32][33];
+    const int tj = blockIdx.x, ti = blockIdx.y;
+    if (tj > ti) return;
+    const double *Xb = X + (long)blockIdx.z * sB;
+    double *Gb = G + (long)blockIdx.z * sB;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int r = tj * 32 + ty + k, col = ti * 32 + tx;
+        if (r < n && col < n) t[ty + k][tx] = Xb[(long)r * n + col];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        const int r = ti * 32 + ty + k, col = tj * 32 + tx;
+        if (r < n && col < n && col <= r) Gb[(long)r * n + col] = s * (Xb[(long)r * n + col] + t[tx][ty + k]);
     }
 }
 
@@ -404,6 +440,12 @@ hipError_t scatter_sq(const double *in, double *out, const int *perm, int n, int
     return hipGetLastError();
 }
 
+hipError_t gather_sq(const double *in, double *out, const int *perm, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_sq, dim3(nblk((size_t)n * n, 256)), dim3(256), 0, st, in, out, perm, n);
+    return hipGetLastError();
+}
+
 hipError_t make_rl(const double *X, const double *Y, double *R, double *L, size_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_rl, dim3(nblk(n, 256)), dim3(256), 0, st, X, Y, R, L, n);
@@ -430,6 +472,15 @@ hipError_t transpose(const double *in, long ldi, double *out, long ldo, int R, i
     if (R <= 0 || C <= 0) return hipSuccess;
     const int nct = (C + 31) / 32, nrt = (R + 31) / 32;
     hipLaunchKernelGGL(k_transpose, dim3(nct, std::min(nrt, 65535)), dim3(32, 8), 0, st, in, ldi, out, ldo, R, C);
+    return hipGetLastError();
+}
+
+hipError_t sym_sum_lower(const double *X, double *G, int n, int batch, double s, hipStream_t st)
+{
+    if (n <= 0 || batch <= 0) return hipSuccess;
+    if (batch > 65535) return hipErrorInvalidValue;
+    const int nt = (n + 31) / 32;
+    hipLaunchKernelGGL(k_sym_sum_lower, dim3(nt, nt, batch), dim3(32, 8), 0, st, X, G, n, (long)n * n, s);
     return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@ hipError_t fill(double *p, size_t n, double v, hipStream_t st);
 hipError_t gather_rows(const double *src, double *dst, const int *perm, int nrow, int ncol, int ld_src,
                        hipStream_t st);
 hipError_t scatter_sq(const double *in, double *out, const int *perm, int n, int nb, hipStream_t st);
+// out[i][j] = in[perm[i]][perm[j]] for one n x n matrix
+hipError_t gather_sq(const double *in, double *out, const int *perm, int n, hipStream_t st);
 hipError_t make_rl(const double *X, const double *Y, double *R, double *L, size_t n, hipStream_t st);
 hipError_t symmetrize(double *A, int n, int nb, hipStream_t st);
 // C_b[i][j] = C_b[j][i] for j > i, b < batch (n x n blocks, leading dimension ldc, batch stride sC):
@@ -16,6 +18,8 @@ hipError_t symmetrize(double *A, int n, int nb, hipStream_t st);
 hipError_t mirror_lower(double *C, int n, long ldc, long sC, int batch, hipStream_t st);
 // out[c][r] = in[r][c] for r < R, c < C (leading dimensions ldi, ldo; not in place)
 hipError_t transpose(const double *in, long ldi, double *out, long ldo, int R, int C, hipStream_t st);
+// G_b = s (X_b + X_b^T) on the lower triangle of batch n x n blocks (G may alias X)
+hipError_t sym_sum_lower(const double *X, double *G, int n, int batch, double s, hipStream_t st);
 // V[P][Q] += s (G[P][Q] + G[Q][P]) for P, Q < n; G dense n x n, V with leading dimension ldv
 hipError_t add_sym(const double *G, int n, double *V, int ldv, double s, hipStream_t st);
 hipError_t add_de(const double *eps, const double *V, double *out, int nvir, int nocc, int nvec, double s,

@@ -21,12 +21,13 @@ STATUS = {0: "RIS_OK", 1: "RIS_E_INVALID", 2: "RIS_E_UNSUPPORTED", 3: "RIS_E_NOM
           5: "RIS_E_DEGENERATE", 6: "RIS_E_ORDER", 7: "RIS_E_DEVICE", 8: "RIS_E_NOCONV"}
 OPS = {"A": 0, "B": 1, "A+B": 2, "A-B": 3}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+DENSITY = {"ground": 0, "difference": 1, "relaxed": 2}
 EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
            "ris_response_matvec", "ris_response_matvec_noalloc", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
            "ris_request_bytes", "ris_plan_bytes",
            "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_ctx_set_blocking", "ris_zvector_solve",
            "ris_tda_davidson",
-           "ris_zrhs_contract",
+           "ris_zrhs_contract", "ris_density_ao",
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
            "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm", "ris_test_sym_eig",
@@ -57,6 +58,11 @@ class _MO(ctypes.Structure):
                 ("c_x", ctypes.c_double), ("precision", ctypes.c_int)]
 
 
+class _Extra(ctypes.Structure):
+    _fields_ = [("out", ctypes.c_int), ("D1", ctypes.c_void_p), ("D2", ctypes.c_void_p), ("cJ", ctypes.c_double),
+                ("cK", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -80,15 +86,18 @@ def load_library(path: str = LIB_PATH):
     lib.ris_int3c.argtypes = [vp, ctypes.POINTER(_MO), vp]
     lib.ris_response_matvec.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.ris_response_matvec_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
-    lib.ris_grad_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp]
-    lib.ris_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, dp, vp]
+    ep = ctypes.POINTER(_Extra)
+    lib.ris_grad_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, ctypes.c_int, ep, vp]
+    lib.ris_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, ctypes.c_int, ep, dp, vp]
+    lib.ris_density_ao.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.ris_request_bytes.argtypes = [ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.ris_request_bytes.restype = ctypes.c_size_t
     lib.ris_plan_bytes.argtypes = [ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.ris_plan_bytes.restype = ctypes.c_size_t
-    lib.ris_grad_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp, ctypes.c_int, ip, dp, vp]
+    lib.ris_grad_nac_contract.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, ip, vp, ctypes.c_int, ip, dp, vp,
+                                          ctypes.c_int, ep]
     lib.ris_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.ris_ctx_set_screening.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_long)]
     lib.ris_ctx_set_blocking.argtypes = [vp, ctypes.c_int]
@@ -130,6 +139,21 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _extra_array(extra, dev, nao):
+    """(count, ctypes array) of ris_extra_pair from [(out, D1, D2, cJ, cK)]
+    with D1, D2 device float64 [nao][nao] tensors."""
+    if not extra:
+        return 0, None
+    arr = (_Extra * len(extra))()
+    for k, (out, D1, D2, cJ, cK) in enumerate(extra):
+        for nm, D in (("D1", D1), ("D2", D2)):
+            _check_dev(D, dev, f"extra[{k}].{nm}")
+            if tuple(D.shape) != (nao, nao):
+                raise ValueError(f"extra[{k}].{nm} must be [{nao}][{nao}]")
+        arr[k] = _Extra(int(out), D1.data_ptr(), D2.data_ptr(), float(cJ), float(cK))
+    return len(extra), arr
+
+
 def _check_dev(t, dev, name):
     import torch
     if t is None:
@@ -158,7 +182,7 @@ class RisContext:
         if st != RIS_OK:
             raise RisError(st, "ris_ctx_create failed")
         self.h = h
-        self.natm = 0
+        self.natm = self.nao = 0
         self.nJ = self.nK = 0
         self.nocc = self.nvir = 0
 
@@ -309,7 +333,24 @@ class RisContext:
             self._chk(st)
         return w, out, int(it.value)
 
-    def grad_contract(self, X, Y, sel, out=None):
+    def density_ao(self, kind, X=None, Y=None, I=0, J=0, Z=None, out=None):
+        """AO density [nao][nao] on the device: "ground" (C_O C_O^T), "difference"
+        (T_IJ) or "relaxed" (T_IJ + Z^S, Z device [nvir][nocc])."""
+        import torch
+        _check_dev(X, self.device, "X")
+        _check_dev(Y, self.device, "Y")
+        _check_dev(Z, self.device, "Z")
+        if out is None:
+            out = torch.empty((self.nao, self.nao), dtype=torch.float64, device=self.device)
+        _check_dev(out, self.device, "D")
+        ns = X.shape[0] if X is not None else 0
+        self._chk(self.lib.ris_density_ao(self.h, DENSITY[kind] if isinstance(kind, str) else int(kind), ns, _ptr(X),
+                                          _ptr(Y), int(I), int(J), _ptr(Z), _ptr(out)))
+        return out
+
+    def grad_contract(self, X, Y, sel, out=None, extra=None):
+        """Gradients of states sel; extra: [(k, D1, D2, cJ, cK)] density pairs
+        added to output k (D1, D2 device [nao][nao])."""
         import torch
         _check_dev(X, self.device, "X")
         _check_dev(Y, self.device, "Y")
@@ -317,11 +358,12 @@ class RisContext:
         if out is None:
             out = torch.empty((sel.size, self.natm, 3), dtype=torch.float64, device=self.device)
         _check_dev(out, self.device, "grad")
+        ne, ea = _extra_array(extra, self.device, self.nao)
         self._chk(self.lib.ris_grad_contract(self.h, X.shape[0], _ptr(X), _ptr(Y), sel.size,
-                                             sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(out)))
+                                             sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ne, ea, _ptr(out)))
         return out
 
-    def nac_contract(self, X, Y, pairs, omega=None, out=None, allow_degenerate=False):
+    def nac_contract(self, X, Y, pairs, omega=None, out=None, allow_degenerate=False, extra=None):
         import torch
         _check_dev(X, self.device, "X")
         _check_dev(Y, self.device, "Y")
@@ -332,8 +374,9 @@ class RisContext:
         om = None
         if omega is not None:
             om = np.ascontiguousarray(omega, dtype=np.float64)
+        ne, ea = _extra_array(extra, self.device, self.nao)
         st = self.lib.ris_nac_contract(self.h, X.shape[0], _ptr(X), _ptr(Y), pairs.shape[0],
-                                       pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                       pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ne, ea,
                                        om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if om is not None else None,
                                        _ptr(out))
         if st == 5 and allow_degenerate:
@@ -342,7 +385,7 @@ class RisContext:
         return out
 
 
-def _grad_nac_impl(self, X, Y, sel, pairs, omega=None, grad=None, nac=None, allow_degenerate=False):
+def _grad_nac_impl(self, X, Y, sel, pairs, omega=None, grad=None, nac=None, allow_degenerate=False, extra=None):
     import torch
     _check_dev(X, self.device, "X")
     _check_dev(Y, self.device, "Y")
@@ -356,10 +399,11 @@ def _grad_nac_impl(self, X, Y, sel, pairs, omega=None, grad=None, nac=None, allo
     _check_dev(nac, self.device, "nac")
     om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
     ip = ctypes.POINTER(ctypes.c_int)
+    ne, ea = _extra_array(extra, self.device, self.nao)
     st = self.lib.ris_grad_nac_contract(
         self.h, X.shape[0], _ptr(X), _ptr(Y), sel.size, sel.ctypes.data_as(ip), _ptr(grad), pairs.shape[0],
         pairs.ctypes.data_as(ip), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if om is not None else None,
-        _ptr(nac))
+        _ptr(nac), ne, ea)
     if not (st == 5 and allow_degenerate):
         self._chk(st)
     return grad, nac
