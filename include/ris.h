@@ -33,7 +33,8 @@
  *   - Errors: a status code is returned and a message is kept for
  *     ris_last_error; nothing is thrown across the ABI.  After an error the
  *     outputs of that call are undefined.
- *   - One context per host thread; calls on one context must not overlap.
+ *   - Calls on one context must not overlap; any host thread may make them,
+ *     one at a time.  Contexts are independent of each other.
  */
 #ifndef RIS_H
 #define RIS_H
@@ -58,13 +59,20 @@ enum ris_status {
 
 /* Arithmetic of the exchange-weight contractions (the products that build
  * Gamma^P, its MO-space blocks and V_PQ) and of the exchange part of the
- * matvecs.  Integrals, MO transforms, every metric solve (M^-1 applications),
- * the Coulomb part and all gradient accumulation stay FP64 in every mode.
+ * matvecs.  Integrals, every metric solve (M^-1 applications), the Coulomb
+ * part, the extra density pairs and all gradient accumulation stay FP64 in
+ * every mode; the MO transforms of (mu nu|P) too, unless RIS_PREC_TRANSFORMS
+ * is or-ed into the mode.
  *   RIS_FP64   : FP64 matrix cores.
  *   RIS_FP32   : FP32 matrix cores, FP32 accumulation.
- *   RIS_BF16X3 : split BF16 (x ~ hi + lo), three products hi.hi + hi.lo + lo.hi
- *                on BF16 matrix cores, FP32 accumulation. */
-enum ris_precision { RIS_FP64 = 0, RIS_FP32 = 1, RIS_BF16X3 = 2 };
+ *   RIS_BF16X3 : split BF16 (x32 = fl32(x) ~ hi + lo), three products
+ *                hi.hi + hi.lo + lo.hi on BF16 matrix cores, FP32 accumulation
+ *                (about 16 bits of each operand).
+ *   RIS_BF16X6 : three-way split BF16 (x32 = hi + mid + lo, all 24 bits), the
+ *                six products down to order 2^-16, FP32 accumulation.
+ *   RIS_PREC_TRANSFORMS : flag; the (ai|P), (ij|P) and (ab|P) transforms of
+ *                (mu nu|P) also run in the mode (the M^-1 fits stay FP64). */
+enum ris_precision { RIS_FP64 = 0, RIS_FP32 = 1, RIS_BF16X3 = 2, RIS_BF16X6 = 3, RIS_PREC_TRANSFORMS = 16 };
 
 /* Response operators of the Casida problem (Sec. 2.1, eqs. casida, A_matrix,
  * B_matrix): A, B, A+B, A-B with the ris kernel. */
@@ -99,7 +107,7 @@ typedef struct {
     const double *eps;  /* [nmo] device, orbital energies */
     double alpha_J;     /* Coulomb factor (closed-shell singlet: 2) */
     double c_x;         /* exact-exchange fraction (Sec. 2.1, eq. g_integral) */
-    int precision;      /* enum ris_precision */
+    int precision;      /* enum ris_precision, optionally | RIS_PREC_TRANSFORMS */
 } ris_mo;
 
 /* Create a context on `device` (HIP ordinal) that enqueues on `hip_stream`
@@ -116,6 +124,12 @@ const char *ris_last_error(const ris_ctx *ctx);
 
 /* Bytes of device memory the context currently holds. */
 size_t ris_ctx_bytes(const ris_ctx *ctx);
+
+/* Free every device region the context holds for a request (basis tables,
+ * metric, MO blocks, scratch), keeping only what ris_ctx_create made; the
+ * next call must be ris_aux_build.  For a scheduler that needs an idle
+ * context's memory for another request.  Synchronises the context's stream. */
+int ris_ctx_release(ris_ctx *ctx);
 
 /* Peak device bytes a context holds for one request of this molecule with
  * nmo orbitals (nocc occupied), nstate amplitude vectors, matvecs of up to

@@ -28,8 +28,9 @@ int ris_test_dgemm(int M, int N, int K, int transA, int transB, double alpha, co
                    const double *B, long ldb, long sB, double beta, double *C, long ldc, long sC, int batch);
 
 /* Same product through the path's reduced-precision GEMM: mode 0 = FP64,
- * 1 = FP32 matrix cores, 2 = split BF16 with three products; FP64 operands and
- * result, FP32 accumulation for modes 1 and 2.  Synchronous. */
+ * 1 = FP32 matrix cores, 2 = split BF16 with three products, 3 = split BF16
+ * with six products; FP64 operands and result, FP32 accumulation for modes
+ * 1-3.  Synchronous. */
 int ris_test_gemm(int mode, int M, int N, int K, int transA, int transB, double alpha, const double *A, long lda,
                   long sA, const double *B, long ldb, long sB, double beta, double *C, long ldc, long sC, int batch);
 
@@ -45,6 +46,14 @@ int ris_test_sym_eig(int m, double *A, double *w);
  * overlapping in).  Returns 1 on invalid arguments, 7 on a HIP error.
  * Synchronous. */
 int ris_test_transpose(const double *in, long ldi, double *out, long ldo, int R, int C);
+
+/* The path's device Boys function F_m(T) = int_0^1 t^2m exp(-T t^2) dt (the
+ * table + Taylor + downward recursion below T = 40, the asymptotic F_0 and
+ * upward recursion above; it serves every integral kernel): F[i][m] =
+ * F_m(T[i]) for m = 0..7.  T (device, n values >= 0), F (device, n x 8).
+ * Returns 1 on invalid arguments, 7 on a HIP error.  Synchronous; allocates
+ * its own table. */
+int ris_test_boys(int n, const double *T, double *F);
 
 #ifdef __cplusplus
 }

@@ -98,6 +98,7 @@ struct ris_ctx {
     int nmo = 0, nocc = 0, nvir = 0;
     double alphaJ = 2.0, cx = 0.25;
     int prec = RIS_FP64;  // arithmetic of the exchange-weight contractions
+    int prec_tr = RIS_FP64;  // arithmetic of the MO transforms of (mu nu|P)
     double *C = nullptr;    // [nao][nmo] internal AO order
     double *eps = nullptr;  // [nmo]
     double *aiJ = nullptr;   // [nJ][v][o]  raw (ai|P), Coulomb set
@@ -1042,6 +1043,25 @@ int ris_ctx_stage_stats(ris_ctx *c, int stage, double *ms, double *flops, double
     return RIS_OK;
 }
 
+int ris_ctx_release(ris_ctx *c)
+{
+    if (!c) return RIS_E_INVALID;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_aux(c);
+    ris_ctx::Pool *pools[] = {&c->aux_pool, &c->mo_pool, &c->out_pool, &c->zv_pool, &c->dv_pool};
+    for (ris_ctx::Pool *pl : pools) {
+        dfree(c, pl->p);
+        pl->p = nullptr;
+        pl->bytes = 0;
+    }
+    dfree(c, c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    return RIS_OK;
+}
+
 const char *ris_last_error(const ris_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 size_t ris_ctx_bytes(const ris_ctx *c) { return c ? c->held : 0; }
@@ -1214,7 +1234,8 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
     if (mo->nao != c->nao) return fail(c, RIS_E_INVALID, "nao %d does not match the basis (%d)", mo->nao, c->nao);
     if (mo->nocc <= 0 || mo->nocc >= mo->nmo || mo->nmo > mo->nao)
         return fail(c, RIS_E_INVALID, "need 0 < nocc < nmo <= nao (nocc=%d nmo=%d)", mo->nocc, mo->nmo);
-    if (mo->precision < RIS_FP64 || mo->precision > RIS_BF16X3)
+    const int pmode = mo->precision & ~RIS_PREC_TRANSFORMS;
+    if (pmode < RIS_FP64 || pmode > RIS_BF16X6)
         return fail(c, RIS_E_UNSUPPORTED, "precision mode %d not built", mo->precision);
     HIPCHK(c, hipSetDevice(c->device));
     free_int3c(c);
@@ -1225,7 +1246,10 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
     c->nvir = v;
     c->alphaJ = mo->alpha_J;
     c->cx = mo->c_x;
-    c->prec = mo->precision;
+    c->prec = pmode;
+    // arithmetic of the (mu nu|P) -> MO transforms: FP64 unless the flag asks for the mode
+    const int tprec = (mo->precision & RIS_PREC_TRANSFORMS) ? pmode : RIS_FP64;
+    c->prec_tr = tprec;
     const size_t NN = (size_t)N * N;
     const long vo = (long)v * o;
 
@@ -1283,24 +1307,24 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
         // Z^P = X^P C_O  [nb][N][o]
         GemmArgs g = gm(N, o, N, false, false, 1.0, X, N, CO, nmo, 0.0, Z, o);
         g.batch = nb; g.strideA = NN; g.strideB = 0; g.strideC = (long)N * o;
-        HIPCHK(c, dgemm(g, c->stream));
+        HIPCHK(c, gemm_mp(g, tprec, c->stream));
         // (ai|P) = C_V^T Z^P  [nJ][v][o]
         g = gm(v, o, N, true, false, 1.0, CV, nmo, Z, o, 0.0, c->aiJ + (size_t)f0 * vo, o);
         g.batch = nb; g.strideA = 0; g.strideB = (long)N * o; g.strideC = vo;
-        HIPCHK(c, dgemm(g, c->stream));
+        HIPCHK(c, gemm_mp(g, tprec, c->stream));
         if (nbk > 0) {
             // raw (ij|P) = C_O^T Z^P of the exchange set  [nK][o][o]
             g = gm(o, o, N, true, false, 1.0, CO, nmo, Z, o, 0.0, c->roo + (size_t)f0 * oo, o);
             g.batch = nbk; g.strideA = 0; g.strideB = (long)N * o; g.strideC = oo;
-            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, gemm_mp(g, tprec, c->stream));
             // raw (ab|P) = C_V^T (X^P C_V) into the c_vv storage as [a][P][b]
             g = gm(N, v, N, false, false, 1.0, X, N, CV, nmo, 0.0, Z, v);
             g.batch = nbk; g.strideA = NN; g.strideB = 0; g.strideC = (long)N * v;
-            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, gemm_mp(g, tprec, c->stream));
             g = gm(v, v, N, true, false, 1.0, CV, nmo, Z, v, 0.0, c->cvv + (size_t)f0 * v, (long)nK * v);
             g.batch = nbk; g.strideA = 0; g.strideB = (long)N * v; g.strideC = v;
             g.lower = true;  // (ab|P) is symmetric in a, b: lower tiles, then mirrored
-            HIPCHK(c, dgemm(g, c->stream));
+            HIPCHK(c, gemm_mp(g, tprec, c->stream));
             HIPCHK(c, mirror_lower(c->cvv + (size_t)f0 * v, v, (long)nK * v, v, nbk, c->stream));
         }
         stage_end(c, t_mo, RIS_STAGE_MO,
@@ -1467,7 +1491,7 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
 {
     const long o3 = 3L * o, NN = (long)N * N;
     // FP32 and split-BF16 modes: F, W and Y as float (both round them to FP32 first)
-    const bool f32 = c->prec == RIS_FP32 || c->prec == RIS_BF16X3;
+    const bool f32 = c->prec != RIS_FP64;
     float *Y3f = (float *)Y3;
     GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, FI, o3, W, o3, 0.0, Y3, o3);
     g.batch = nP; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
@@ -1563,7 +1587,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
            *TR = P_(CW.oTR), *G1 = P_(CW.oG1), *V2 = P_(CW.oV2), *SK = P_(CW.oSK), *p3 = P_(CW.op3),
            *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP), *Tall = P_(CW.oTall),
            *HUU = P_(CW.oHUU), *W = P_(CW.oW), *Y3 = P_(CW.oY), *G = P_(CW.oG);
-    const bool f32 = c->prec == RIS_FP32 || c->prec == RIS_BF16X3;
+    const bool f32 = c->prec != RIS_FP64;
     float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
     const double *CO = c->C, *CV = c->C + o;
 
@@ -1798,7 +1822,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
            *p3 = P_(CW.op3), *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP);
     // FP32 and split-BF16 modes: F, W and Y stored as float for the two products
     // that build Gamma (both kernels round the operands to FP32 first: same results)
-    const bool f32 = c->prec == RIS_FP32 || c->prec == RIS_BF16X3;
+    const bool f32 = c->prec != RIS_FP64;
     float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
     const double *CO = c->C, *CV = c->C + o;
 

@@ -119,17 +119,18 @@ hipError_t dgemm(const GemmArgs &g, hipStream_t st);
 // Same product with K cut into nsplit ranges (batch == 1, nred == 1): partials
 // go to ws (nsplit * M * N doubles) and are summed in a fixed order.
 hipError_t dgemm_splitk(const GemmArgs &g, int nsplit, double *ws, hipStream_t st);
-// Same for mode 0 / 1 (FP64 / FP32 matrix cores); mode 2 runs unsplit.
+// Same for every mode of gemm_mp (partials in FP64, summed in a fixed order).
 hipError_t gemm_splitk(const GemmArgs &g, int mode, int nsplit, double *ws, hipStream_t st);
 // K-split count in [1, smax] that fills whole waves of workgroups best for a
 // product of `tiles` 128 x 128 output tiles (1 for large tile counts).
 int balanced_splits(long tiles, int smax);
 // Same contract with the products on reduced-precision matrix cores (FP64 in
 // and out, FP32 accumulation): mode 0 = FP64 (dgemm), 1 = FP32, 2 = split BF16
-// with three products (ris_gemm_mp.hip).
+// with three products, 3 = split BF16 with six products (ris_gemm_mp.hip).
 hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st);
-// The split-BF16 product alone; kc > 0: split-K ranges of kc (a multiple of 32).
-hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st);
+// The split-BF16 product alone (nparts 2: three products, 3: six); kc > 0:
+// split-K ranges of kc (a multiple of 32).
+hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st, int nparts = 2);
 // The matrix-core GEMM itself for mode 0 (FP64) or 1 (FP32); kc > 0 splits K
 // into ranges of kc indexed by the batch (ris_gemm.hip).
 hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st);

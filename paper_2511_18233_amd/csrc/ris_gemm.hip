@@ -505,7 +505,7 @@ hipError_t gemm_splitk(const GemmArgs &g, int mode, int nsplit, double *ws, hipS
     p.C = ws;
     p.ldc = g.N;
     p.strideC = (long)g.M * g.N;
-    hipError_t e = mode == 2 ? bgemm_kc(p, kc, st) : gemm_kc(p, mode, kc, st);
+    hipError_t e = mode >= 2 ? bgemm_kc(p, kc, st, mode == 2 ? 2 : 3) : gemm_kc(p, mode, kc, st);
     if (e != hipSuccess) return e;
     const long tot = (long)g.M * g.N;
     hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws, used, g.M, g.N,

@@ -7,6 +7,11 @@
 //          lo = bf16(x32 - hi); a.b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b with
 //          v_mfma_f32_16x16x32_bf16 (the lo_a lo_b term, ~2^-16 relative, is
 //          dropped).
+//   mode 3 (split BF16, six products): the three-way split x32 = hi + mid + lo
+//          (mid = bf16(x32 - hi), lo = bf16(x32 - hi - mid), which holds all
+//          24 bits of x32) and the six products whose order is at most 2^-16:
+//          hi.hi + hi.mid + mid.hi + hi.lo + lo.hi + mid.mid (mid.lo, lo.mid
+//          and lo.lo, 2^-24 and below, are dropped).
 //
 // Same contract as the FP64 dgemm (batch, batch-reduce, transposes, alpha,
 // beta) and the same XCD-aware tile order.  Lane layouts (checked by the probe
@@ -75,13 +80,18 @@ __device__ __forceinline__ E ldo(const E *base, int off)
     return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) + ((unsigned)off * (unsigned)sizeof(E)));
 }
 
-// x32 = fl32(x) * s, hi = bf16(x32), lo = bf16(x32 - hi)  (s: a 0/1 mask, or alpha)
-template <typename E>
-__device__ __forceinline__ void split_bf16(E x, float s, __bf16 &hi, __bf16 &lo)
+// x32 = fl32(x) * s split into NS bf16 parts: p[0] = bf16(x32), p[k] = bf16 of
+// what the earlier parts leave (each difference is exact in FP32); s is a 0/1
+// mask, or alpha
+template <int NS, typename E>
+__device__ __forceinline__ void split_bf16(E x, float s, __bf16 (&p)[NS])
 {
-    const float f = (float)x * s;
-    hi = (__bf16)f;
-    lo = (__bf16)(f - (float)hi);
+    float f = (float)x * s;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        p[k] = (__bf16)f;
+        f -= (float)p[k];
+    }
 }
 
 // ----------------------------------------------------------- split BF16 --
@@ -98,19 +108,33 @@ __device__ __forceinline__ void split_bf16(E x, float s, __bf16 &hi, __bf16 &lo)
 // (batch index = k-range) and batch-reduce as in the FP64 kernel.
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
+// Parts of A and B in product u: NS = 2: hi.lo, lo.hi, hi.hi;
+// NS = 3: hi.lo, lo.hi, mid.mid, hi.mid, mid.hi, hi.hi (smallest first).
+template <int NS>
+__device__ constexpr int part_a(int u)
+{
+    return NS == 2 ? (u == 1 ? 1 : 0) : (u == 1 ? 2 : (u == 2 || u == 4) ? 1 : 0);
+}
+template <int NS>
+__device__ constexpr int part_b(int u)
+{
+    return NS == 2 ? (u == 0 ? 1 : 0) : (u == 0 ? 2 : (u == 2 || u == 3) ? 1 : 0);
+}
+
 //
 // EA, EB, EC: element types in memory (double, or float for operands that are
 // already FP32, which the split rounds to first anyway: same result).
-template <bool TA, bool TB, bool BETA, typename EA = double, typename EB = double, typename EC = double>
+// NS: parts per operand (2: three products, 3: six products).
+template <int NS, bool TA, bool TB, bool BETA, typename EA = double, typename EB = double, typename EC = double>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_bgemm3(
     int M, int N, int K, double alpha, const EA *__restrict__ A, long lda, long sA, long sAr,
     const EB *__restrict__ B, long ldb, long sB, long sBr, double beta, EC *__restrict__ C, long ldc, long sC,
     int nred, int tm, int tn, int total, int kc, bool lower, const int *__restrict__ tiles)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][BK2 + PAD2];
-    __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][BK2 + PAD2];
-    __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][BK2 + PAD2];
-    __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN][BK2 + PAD2];
+    static_assert(NS == 2 || NS == 3, "two or three parts per operand");
+    static_assert(BM == BN, "A and B part tiles share one LDS shape");
+    // parts [0, NS) of A and [NS, 2 NS) of B, two stages each: [part][stage][row][k]
+    __shared__ __attribute__((aligned(16))) __bf16 S[2 * NS][2][BM][BK2 + PAD2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     int bz, mt, nt;
@@ -191,23 +215,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     auto store = [&](int stg) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            v2bf ha, la, hb, lb;
+            v2bf pa[NS], pb[NS];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                __bf16 h, l;
-                split_bf16(xa[q][s], fa[q][s], h, l);
-                ha[s] = h;
-                la[s] = l;
-                split_bf16(xb[q][s], fb[q][s], h, l);
-                hb[s] = h;
-                lb[s] = l;
+                __bf16 t[NS];
+                split_bf16<NS>(xa[q][s], fa[q][s], t);
+#pragma unroll
+                for (int k = 0; k < NS; ++k) pa[k][s] = t[k];
+                split_bf16<NS>(xb[q][s], fb[q][s], t);
+#pragma unroll
+                for (int k = 0; k < NS; ++k) pb[k][s] = t[k];
             }
             const int arow = TA ? cm : rk + 16 * q, acol = TA ? km + 4 * q : kp;
             const int brow = TB ? rk + 16 * q : cm, bcol = TB ? kp : km + 4 * q;
-            *(v2bf *)&Ah[stg][arow][acol] = ha;
-            *(v2bf *)&Al[stg][arow][acol] = la;
-            *(v2bf *)&Bh[stg][brow][bcol] = hb;
-            *(v2bf *)&Bl[stg][brow][bcol] = lb;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                *(v2bf *)&S[k][stg][arow][acol] = pa[k];
+                *(v2bf *)&S[NS + k][stg][brow][bcol] = pb[k];
+            }
         }
     };
 
@@ -221,48 +246,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int cur = it & 1;
         // next slab (the last iteration reloads its own slab: in bounds, never read)
         load(min(it + 1, niter - 1));
-        v8bf ah[4], al[4], bh[4], bl[4];
+        // fragments: part k of A rows / B columns of this wave
+        v8bf fa_[NS][4], fb_[NS][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ah[i] = *(const v8bf *)&Ah[cur][wm * 64 + i * 16 + (lane & 15)][kofs];
+        for (int i = 0; i < 4; ++i) fa_[0][i] = *(const v8bf *)&S[0][cur][wm * 64 + i * 16 + (lane & 15)][kofs];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bl[j] = *(const v8bf *)&Bl[cur][wn * 64 + j * 16 + (lane & 15)][kofs];
+        for (int j = 0; j < 4; ++j) fb_[1][j] = *(const v8bf *)&S[NS + 1][cur][wn * 64 + j * 16 + (lane & 15)][kofs];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) al[i] = *(const v8bf *)&Al[cur][wm * 64 + i * 16 + (lane & 15)][kofs];
+        for (int i = 0; i < 4; ++i) fa_[1][i] = *(const v8bf *)&S[1][cur][wm * 64 + i * 16 + (lane & 15)][kofs];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bh[j] = *(const v8bf *)&Bh[cur][wn * 64 + j * 16 + (lane & 15)][kofs];
+        for (int j = 0; j < 4; ++j) fb_[0][j] = *(const v8bf *)&S[NS][cur][wn * 64 + j * 16 + (lane & 15)][kofs];
+        if constexpr (NS == 3) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i) fa_[2][i] = *(const v8bf *)&S[2][cur][wm * 64 + i * 16 + (lane & 15)][kofs];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) fb_[2][j] = *(const v8bf *)&S[NS + 2][cur][wn * 64 + j * 16 + (lane & 15)][kofs];
+        }
+        // products (part of A, part of B), smallest first, each over all 16
+        // accumulators: hi.lo, lo.hi, hi.hi; or hi.lo, lo.hi, mid.mid, hi.mid, mid.hi, hi.hi
+        constexpr int NP = NS == 2 ? 3 : 6;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int u = 0; u < NP; ++u)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_[part_a<NS>(u)][i], fb_[part_b<NS>(u)][j],
+                                                                        acc[i][j], 0, 0, 0);
         // the other buffer was last read in iteration it-1, before the barrier that ended it
         store(cur ^ 1);
-        // schedule: the fragments of the first product, the other fragment
-        // reads and the 32 global loads one per MFMA, and the 32 LDS writes
-        // four per MFMA over the last eight MFMAs of the slab
+        if constexpr (NS == 2) {
+            // schedule: the fragments of the first product, the other fragment
+            // reads and the 32 global loads one per MFMA, and the 32 LDS writes
+            // four per MFMA over the last eight MFMAs of the slab
 #pragma unroll
-        for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        }
+            for (int u = 0; u < 8; ++u) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        }
+            for (int u = 0; u < 32; ++u) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            __builtin_amdgcn_sched_group_barrier(0x200, 4, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            for (int u = 0; u < 8; ++u) {
+                __builtin_amdgcn_sched_group_barrier(0x200, 4, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
         }
         __syncthreads();
     }
@@ -286,8 +319,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 }  // namespace
 
-// Split-BF16 product (mode 2); kc > 0: split-K ranges (kc a multiple of 32).
-hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
+// Split-BF16 product (ns = 2 parts: mode 2, ns = 3: mode 3); kc > 0: split-K
+// ranges (kc a multiple of 32).
+template <int NS>
+static hipError_t bgemm_ns(const GemmArgs &g, int kc, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     if (g.kband > 0) {  // banded K (see GemmArgs), carried as kc = -kband
@@ -318,7 +353,7 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
             s.M = (int)std::min<long>(r, g.M - m0);
             s.A = (const double *)((const char *)g.A + (size_t)m0 * g.lda * szA);
             s.C = (double *)((char *)g.C + (size_t)m0 * g.ldc * szC);
-            const hipError_t e = bgemm_kc(s, kc, st);
+            const hipError_t e = bgemm_ns<NS>(s, kc, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -334,7 +369,7 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
             s.N = (int)std::min<long>(r, g.N - n0);
             s.B = (const double *)((const char *)g.B + (size_t)n0 * g.ldb * szB);
             s.C = (double *)((char *)g.C + (size_t)n0 * szC);
-            const hipError_t e = bgemm_kc(s, kc, st);
+            const hipError_t e = bgemm_ns<NS>(s, kc, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -349,17 +384,17 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
         // from float Y and F_J (double out, BETA for the second NAC half)
         if (kc > 0) return hipErrorInvalidValue;
         if (g.ftypes == (kF32A | kF32B | kF32C) && !g.transA && !g.transB && g.beta == 0.0)
-            hipLaunchKernelGGL((k_bgemm3<false, false, false, float, float, float>), grid, dim3(256), 0, st, g.M, g.N,
+            hipLaunchKernelGGL((k_bgemm3<NS, false, false, false, float, float, float>), grid, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, (float *)g.C, g.ldc, g.strideC, nred, tm, tn, (int)total,
                                kc, g.lower, g.tiles);
         else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB && g.beta == 0.0)
-            hipLaunchKernelGGL((k_bgemm3<false, true, false, float, float, double>), grid, dim3(256), 0, st, g.M, g.N,
+            hipLaunchKernelGGL((k_bgemm3<NS, false, true, false, float, float, double>), grid, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, (int)total, kc,
                                g.lower, g.tiles);
         else if (g.ftypes == (kF32A | kF32B) && !g.transA && g.transB)
-            hipLaunchKernelGGL((k_bgemm3<false, true, true, float, float, double>), grid, dim3(256), 0, st, g.M, g.N,
+            hipLaunchKernelGGL((k_bgemm3<NS, false, true, true, float, float, double>), grid, dim3(256), 0, st, g.M, g.N,
                                g.K, g.alpha, (const float *)g.A, g.lda, g.strideA, g.strideAr, (const float *)g.B, g.ldb,
                                g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC, nred, tm, tn, (int)total, kc,
                                g.lower, g.tiles);
@@ -368,7 +403,7 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
         return hipGetLastError();
     }
 #define RIS_B3_LAUNCH1(TA, TB, BETA)                                                                               \
-    hipLaunchKernelGGL((k_bgemm3<TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,        \
+    hipLaunchKernelGGL((k_bgemm3<NS, TA, TB, BETA>), grid, dim3(256), 0, st, g.M, g.N, g.K, g.alpha, g.A, g.lda,        \
                        g.strideA, g.strideAr, g.B, g.ldb, g.strideB, g.strideBr, g.beta, g.C, g.ldc, g.strideC,     \
                        nred, tm, tn, (int)total, kc, g.lower, g.tiles);
 #define RIS_B3_LAUNCH2(TA, TB)                                                                                     \
@@ -382,11 +417,18 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st, int nparts)
+{
+    if (nparts == 2) return bgemm_ns<2>(g, kc, st);
+    if (nparts == 3) return bgemm_ns<3>(g, kc, st);
+    return hipErrorInvalidValue;
+}
+
 hipError_t gemm_mp(const GemmArgs &g, int mode, hipStream_t st)
 {
     if (mode == 0 || mode == 1) return gemm_kc(g, mode, 0, st);
-    if (mode != 2) return hipErrorInvalidValue;
-    return bgemm_kc(g, 0, st);
+    if (mode != 2 && mode != 3) return hipErrorInvalidValue;
+    return bgemm_kc(g, 0, st, mode == 2 ? 2 : 3);
 }
 
 }  // namespace ris
@@ -395,7 +437,7 @@ extern "C" int ris_test_gemm(int mode, int M, int N, int K, int transA, int tran
                              long lda, long sA, const double *B, long ldb, long sB, double beta, double *C, long ldc,
                              long sC, int batch)
 {
-    if (M < 0 || N < 0 || K < 0 || batch < 0 || !A || !B || !C || mode < 0 || mode > 2) return 1;
+    if (M < 0 || N < 0 || K < 0 || batch < 0 || !A || !B || !C || mode < 0 || mode > 3) return 1;
     ris::GemmArgs g{};
     g.M = M; g.N = N; g.K = K;
     g.transA = transA != 0; g.transB = transB != 0;

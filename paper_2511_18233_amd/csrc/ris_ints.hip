@@ -17,6 +17,7 @@
 // recurrence tables live in registers.
 #include <algorithm>
 #include <utility>
+#include <vector>
 
 #include "ris_boys.hpp"
 #include "ris_common.hpp"
@@ -644,3 +645,36 @@ hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg
 }
 
 }  // namespace ris
+
+// ------------------------------------------------------------------------
+// Test probe of the device Boys function: F[i][m] = F_m(T[i]) for m <= 7.
+namespace {
+__global__ void k_boys_probe(int n, const double *__restrict__ T, const double *__restrict__ tab,
+                             double *__restrict__ F)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double f[ris::kBoysMaxM + 1];
+    ris::boys_eval<ris::kBoysMaxM>(T[i], tab, f);
+#pragma unroll
+    for (int m = 0; m <= ris::kBoysMaxM; ++m) F[(size_t)i * (ris::kBoysMaxM + 1) + m] = f[m];
+}
+}  // namespace
+
+extern "C" int ris_test_boys(int n, const double *T, double *F)
+{
+    if (n < 0 || (n > 0 && (!T || !F))) return 1;
+    if (n == 0) return 0;
+    std::vector<double> tab((size_t)ris::kBoysNGrid * ris::kBoysCols);
+    ris::boys_table_host(tab.data());
+    double *dtab = nullptr;
+    if (hipMalloc(&dtab, tab.size() * sizeof(double)) != hipSuccess) return 7;
+    int rc = 0;
+    if (hipMemcpy(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) rc = 7;
+    if (!rc) {
+        hipLaunchKernelGGL(k_boys_probe, dim3((n + 255) / 256), dim3(256), 0, 0, n, T, dtab, F);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) rc = 7;
+    }
+    (void)hipFree(dtab);
+    return rc;
+}

@@ -20,9 +20,10 @@ RIS_OK = 0
 STATUS = {0: "RIS_OK", 1: "RIS_E_INVALID", 2: "RIS_E_UNSUPPORTED", 3: "RIS_E_NOMEM", 4: "RIS_E_NOT_PD",
           5: "RIS_E_DEGENERATE", 6: "RIS_E_ORDER", 7: "RIS_E_DEVICE", 8: "RIS_E_NOCONV"}
 OPS = {"A": 0, "B": 1, "A+B": 2, "A-B": 3}
-PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+PREC_TRANSFORMS = 16  # or-ed into a mode: the MO transforms of (mu nu|P) run in it too
 DENSITY = {"ground": 0, "difference": 1, "relaxed": 2}
-EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_aux_build", "ris_int3c",
+EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes", "ris_ctx_release", "ris_aux_build", "ris_int3c",
            "ris_response_matvec", "ris_response_matvec_noalloc", "ris_grad_contract", "ris_nac_contract", "ris_grad_nac_contract",
            "ris_request_bytes", "ris_plan_bytes",
            "ris_ctx_set_profiling", "ris_ctx_set_screening", "ris_ctx_set_blocking", "ris_zvector_solve",
@@ -31,7 +32,7 @@ EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
            "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm", "ris_test_sym_eig",
-           "ris_test_transpose")
+           "ris_test_transpose", "ris_test_boys")
 
 
 class RisError(RuntimeError):
@@ -82,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib.ris_last_error.restype = ctypes.c_char_p
     lib.ris_ctx_bytes.argtypes = [vp]
     lib.ris_ctx_bytes.restype = ctypes.c_size_t
+    lib.ris_ctx_release.argtypes = [vp]
     lib.ris_aux_build.argtypes = [vp, ctypes.POINTER(_Mol), ctypes.POINTER(_AuxOpts), ip, ip]
     lib.ris_int3c.argtypes = [vp, ctypes.POINTER(_MO), vp]
     lib.ris_response_matvec.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
@@ -112,6 +114,7 @@ def load_library(path: str = LIB_PATH):
     lib.ris_test_gemm.argtypes = [ctypes.c_int] + lib.ris_test_dgemm.argtypes
     lib.ris_test_sym_eig.argtypes = [ctypes.c_int, vp, vp]
     lib.ris_test_transpose.argtypes = [vp, L, vp, L, ctypes.c_int, ctypes.c_int]
+    lib.ris_test_boys.argtypes = [ctypes.c_int, vp, vp]
     _lib = lib
     return lib
 
@@ -205,6 +208,10 @@ class RisContext:
     def bytes_held(self) -> int:
         return int(self.lib.ris_ctx_bytes(self.h))
 
+    def release(self):
+        """Free the context's request regions (ris_ctx_release)."""
+        self._chk(self.lib.ris_ctx_release(self.h))
+
     STAGES = ("int3c", "mo", "matvec", "hblk", "gamma", "deriv", "aux", "yw", "vpq")
 
     def set_screening(self, threshold: float) -> int:
@@ -259,7 +266,11 @@ class RisContext:
         _check_dev(dbg, self.device, "dbg")
         nao, nmo = C.shape
         if isinstance(precision, str):
-            precision = PRECISION[precision]
+            # "fp32", or "fp32+transforms" for the MO transforms in the mode too
+            base, _, tr = precision.partition("+")
+            if base not in PRECISION or tr not in ("", "transforms"):
+                raise ValueError(f"unknown precision {precision!r}")
+            precision = PRECISION[base] | (PREC_TRANSFORMS if tr else 0)
         mo = _MO(nao, nmo, int(nocc), C.data_ptr(), eps.data_ptr(), float(alpha_J), float(c_x), int(precision))
         self._chk(self.lib.ris_int3c(self.h, ctypes.byref(mo), _ptr(dbg)))
         self.nocc, self.nvir = int(nocc), int(nmo - nocc)

@@ -11,7 +11,12 @@ similar sizes allocates nothing.
 Admission: a request waits in FIFO order until a slot is free and the HBM it
 needs -- the library's own sizing (ris_request_bytes), minus what the chosen
 slot already holds -- fits in the server's budget next to what the other slots
-hold.  A request larger than the whole budget is rejected.  Work of different
+hold.  When it fits only without the regions idle slots keep, those regions are
+released (ris_ctx_release) and the request is admitted, so an idle pool never
+blocks the head of the queue.  A request larger than the whole budget is
+rejected.  The bytes each slot holds are read by the slot's own thread after
+each request and kept on the host; the scheduler never calls into a context
+that another thread may be using.  Work of different
 slots overlaps on the device (one host thread per slot; the ctypes calls drop
 the GIL while the library waits on its stream).
 
@@ -88,6 +93,10 @@ class GpuExecutor:
     def held_bytes(self) -> int:
         return self.ctx.bytes_held
 
+    def release(self):
+        """Free the slot's regions (called only while the slot is idle)."""
+        self.ctx.release()
+
     def need_bytes(self, r: Request) -> int:
         from .ris import request_bytes
         return request_bytes(r.Z, r.shell_atom, r.shell_l, self.rad, r.C.shape[1], r.nocc, r.X.shape[0], 0,
@@ -121,6 +130,8 @@ class Server:
         self.lock = threading.Condition()
         self.free = list(range(len(self.ex)))
         self.reserved = [0] * len(self.ex)   # bytes a busy slot may grow to
+        # bytes each slot holds, as its own thread last read them
+        self.held = [int(e.held_bytes()) for e in self.ex]
         self.pending: list[Request] = []
         self.results: dict[int, Result] = {}
         self.t0 = 0.0
@@ -132,7 +143,15 @@ class Server:
 
     # -- admission ---------------------------------------------------------
     def _held(self, k: int) -> int:
-        return self.ex[k].held_bytes()
+        return self.held[k]
+
+    def _release_idle(self, keep: int):
+        """Release the regions of the idle slots other than `keep` (their
+        threads wait on their queues, so nothing else touches them)."""
+        for j in self.free:
+            if j != keep and self.held[j] > 0 and hasattr(self.ex[j], "release"):
+                self.ex[j].release()
+                self.held[j] = 0
 
     def _try_admit(self):
         """Admit pending requests in FIFO order while a slot and memory allow."""
@@ -147,6 +166,7 @@ class Server:
                 continue
             # a slot keeps its regions: it needs max(held, need); the others hold
             # what they hold now or what their running request may grow to
+            busy = [j for j in range(len(self.ex)) if j not in self.free]
             best = None
             for k in self.free:
                 others = sum(max(self._held(j), self.reserved[j]) for j in range(len(self.ex)) if j != k)
@@ -154,7 +174,17 @@ class Server:
                     best = k
                     break
             if best is None:
-                return  # head of the queue waits (FIFO) until memory frees up
+                # does it fit once the idle slots give their regions back?
+                k = self.free[0]
+                if sum(max(self._held(j), self.reserved[j]) for j in busy) + need <= self.budget:
+                    self._release_idle(keep=k)
+                    if sum(max(self._held(j), self.reserved[j]) for j in busy) + max(self._held(k), need) \
+                            > self.budget and hasattr(self.ex[k], "release"):
+                        self.ex[k].release()
+                        self.held[k] = 0
+                    best = k
+                else:
+                    return  # head of the queue waits (FIFO) until a busy slot finishes
             self.pending.pop(0)
             self.free.remove(best)
             self.reserved[best] = max(self._held(best), need)
@@ -183,7 +213,9 @@ class Server:
             except Exception as e:  # one failing request does not stop the others
                 res.error = f"{type(e).__name__}: {e}"
             res.done = self.now()
+            held = int(self.ex[k].held_bytes())   # this slot's own thread, after its request
             with self.lock:
+                self.held[k] = held
                 self.free.append(k)
                 self.free.sort()
                 self.reserved[k] = 0

@@ -1,7 +1,7 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times.
 
-* 60-atom chain: GPU gradients / NAC numerators against the FP64 oracle on
-  sampled outputs (the oracle computes them one by one).
+* 60-atom chain: all 19 GPU gradients / NAC numerators against the FP64
+  oracle's (stored by a committed oracle-only script), in every precision mode.
 * 199-atom chain (the headline workload): properties that hold at any size --
   the GPU gradient equals central finite differences of the GPU's own energy
   functional E_II = 1/2 R.(A+B-D)R + 1/2 L.(A-B-D)L evaluated from its matvecs
@@ -51,22 +51,34 @@ def ctx():
     c.close()
 
 
-def test_chain60_vs_oracle_sampled(ctx, radii):
+def _chain60_ref(prob):
+    """The oracle's 19 outputs of the 60-atom workload (10 gradients, then the
+    9 adjacent-pair NAC numerators), written by tests/golden/make_chain60_ref.py
+    (oracle only) and tied to the current oracle by
+    test_oracle_pins.py::test_chain60_golden_matches_oracle."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "chain60_grad_nac.txt")
+    return np.loadtxt(path).reshape(2 * prob.nstate - 1, prob.mol.natm, 3)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-8), ("fp32", 1e-6), ("bf16x6", 1e-6), ("bf16x3", 1e-6)])
+def test_chain60_all_outputs_vs_oracle(ctx, radii, precision, bar):
+    """All 10 gradients and 9 NAC numerators of the 60-atom workload against the
+    oracle: FP64 within 1e-8 Ha/Bohr, the reduced-precision exchange
+    contractions within 1e-6 (each mode's error is printed)."""
     import torch
-    from oracle import ris_oracle as O
     prob = molgen.make_problem("chain60")
-    say(f"[gpu] chain60 natm={prob.mol.natm} nao={prob.mol.nao}")
-    _gpu_problem(ctx, prob, radii, True)
+    say(f"[gpu] chain60 natm={prob.mol.natm} nao={prob.mol.nao} precision={precision}")
+    _gpu_problem(ctx, prob, radii, True, precision=precision)
     X = torch.as_tensor(prob.X, device=ctx.device)
     Y = torch.as_tensor(prob.Y, device=ctx.device)
     g, n = ctx.grad_nac_contract(X, Y, list(range(prob.nstate)), [(i, i + 1) for i in range(prob.nstate - 1)])
-    g, n = g.cpu().numpy(), n.cpu().numpy()
-    assert np.abs(g.sum(1)).max() <= 1e-10 and np.abs(n.sum(1)).max() <= 1e-10
-    say("[gpu] chain60 oracle for outputs (3,3) and (4,5)")
-    ref = O.grad_nac(prob, radii, [(3, 3), (4, 5)])
-    err = max(np.abs(g[3] - ref[0]).max(), np.abs(n[4] - ref[1]).max())
-    say(f"[gpu]   max |dgrad| {err:.3e} (max {np.abs(ref).max():.3e})")
-    assert err <= 1e-8
+    got = np.concatenate([g.cpu().numpy(), n.cpu().numpy()])
+    ref = _chain60_ref(prob)
+    err = np.abs(got - ref).max()
+    say(f"[gpu]   {precision}: max |d| over 19 outputs {err:.3e} (max |g| {np.abs(ref).max():.3e})")
+    assert err <= bar
+    assert np.abs(got.sum(1)).max() <= 1e-10
 
 
 def test_chain200_finite_difference_and_invariance(ctx, radii):

@@ -121,23 +121,33 @@ def test_grad_nac_parity(ctx, radii, case):
 
 
 MIXED_CASES = {
-    "chain12_tddft": (CASES["chain12_tddft"][0], True, 1e-6),
-    "chain30_tddft": (lambda: molgen.make_chain_problem(30, seed=8, nstate=3, tda=False), True, 1e-6),
-    # 4 atoms at random positions 1.6 Bohr apart: the diffuse minimal auxiliary
-    # set is nearly linearly dependent, M^-1 amplifies operand rounding; the
-    # error is reported and only bounded loosely (a wrong product would be O(1))
-    "tiny_cluster_illcond": (CASES["tiny_mixed_tddft"][0], True, None),
+    "ring12": (CASES["ring12"][0], False),
+    "chain12_tddft": (CASES["chain12_tddft"][0], True),
+    "chain30_tddft": (lambda: molgen.make_chain_problem(30, seed=8, nstate=3, tda=False), True),
+    # 4 atoms 1.7-3.5 Bohr apart (a compressed cluster, far from the chain
+    # workloads): gradients up to 0.16 Ha/Bohr, ten times the chains'
+    "tiny_cluster": (CASES["tiny_mixed_tddft"][0], True),
 }
+# What each mode claims (reading A18): FP32 and the six-product split BF16 hold
+# 1e-6 Ha/Bohr on every case; the three-product split keeps about 16 bits of
+# each operand and claims 1e-6 on the workload-shaped molecules (ring, chains)
+# and 5e-4 max|g| on any input (measured 4.4e-4 max|g| on the compressed cluster).
+MIXED_BAR = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1e-6}
+MIXED_REL_BAR = {"bf16x3": ("tiny_cluster", 5e-4)}
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6", "bf16x3", "fp32+transforms"])
 @pytest.mark.parametrize("case", list(MIXED_CASES))
 def test_mixed_precision_error(ctx, radii, case, precision):
-    """Reduced-precision exchange contractions: gradients and NAC numerators
-    within 1e-6 Ha/Bohr of the FP64 oracle on chain molecules; the error is
-    printed per case."""
+    """Reduced-precision exchange contractions against the FP64 oracle, the
+    error of each case and mode printed.  "+transforms" also runs the MO
+    transforms of (mu nu|P) in the mode: FP32 holds 1e-6 there on the ring and
+    the chains only (the compressed cluster loses three digits), so the flag
+    is opt-in and checked on those."""
     import torch
-    make, jp, bar = MIXED_CASES[case]
+    make, jp = MIXED_CASES[case]
+    if precision == "fp32+transforms" and case == "tiny_cluster":
+        pytest.skip("the transforms flag makes no claim for the compressed cluster (error 1e-3 Ha/Bohr)")
     prob = make()
     m = prob.mol
     ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
@@ -150,11 +160,13 @@ def test_mixed_precision_error(ctx, radii, case, precision):
     got = np.concatenate([g.cpu().numpy(), n.cpu().numpy()])
     ref = O.grad_nac(prob, radii, outs, j_p_on_heavy=jp)
     err = np.abs(got - ref).max()
-    say(f"[gpu]   {case} {precision}: max |dgrad| {err:.3e} Ha/Bohr (max |grad| {np.abs(ref).max():.3e})")
-    if bar is not None:
-        assert err <= bar
+    gmax = np.abs(ref).max()
+    say(f"[gpu]   {case} {precision}: max |dgrad| {err:.3e} Ha/Bohr (max |grad| {gmax:.3e}, rel {err / gmax:.2e})")
+    rel = MIXED_REL_BAR.get(precision)
+    if rel is not None and rel[0] == case:
+        assert err <= rel[1] * gmax
     else:
-        assert err <= 1e-3 * np.abs(ref).max()
+        assert err <= MIXED_BAR.get(precision.split("+")[0], 1e-6)
     torch.cuda.synchronize()
 
 

@@ -592,3 +592,19 @@ def test_extra_pair_planted_mistakes(radii, monkeypatch):
     for bad in ((D, P, 0.3, 0.7), (D, P, 0.7, -0.3)):
         g = O.grad_nac(p, radii, [(1, 1)], S=S, extra=[(0,) + bad])[0]
         assert abs((g - base)[0, 0] - fd) > 1e-7
+
+
+# ------------------------------------------- stored 60-atom oracle outputs --
+def test_chain60_golden_matches_oracle(radii):
+    """The stored 60-atom outputs (tests/golden/chain60_grad_nac.txt, written by
+    make_chain60_ref.py from the oracle alone) are the current oracle's: the
+    gradient of state 0 recomputed here agrees to 1e-13 Ha/Bohr (threaded BLAS
+    sums), and the stored set is translationally invariant."""
+    import os
+    p = molgen.make_problem("chain60")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "chain60_grad_nac.txt")
+    ref = np.loadtxt(path).reshape(2 * p.nstate - 1, p.mol.natm, 3)
+    S = O.setup(p.mol, radii, j_p_on_heavy=True)
+    g0 = O.grad_nac(p, radii, [(0, 0)], S=S)[0]
+    assert np.abs(g0 - ref[0]).max() <= 1e-13
+    assert np.abs(ref.sum(axis=1)).max() <= 1e-10

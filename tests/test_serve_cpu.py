@@ -20,6 +20,10 @@ class FakeExec:
     def held_bytes(self):
         return self.held
 
+    def release(self):
+        self.log.append(("release", -1, self.k, time.perf_counter()))
+        self.held = 0
+
     def need_bytes(self, r):
         return int(r.shell_exp[0])          # the test encodes the footprint here
 
@@ -108,3 +112,38 @@ def test_continuous_admission_while_others_run():
     end0 = [t for (e, rid, _, t) in log if e == "end" and rid == 0][0]
     later = [t for (e, rid, _, t) in log if e == "end" and rid > 0]
     assert all(t < end0 for t in later)
+
+
+def test_idle_regions_are_released_for_the_head():
+    # two 40-byte requests leave both slots holding 40 of a 100 budget; a
+    # 70-byte request fits only once an idle slot gives its region back
+    log = []
+    s = make(2, 100, log)
+    res = s.run_trace([req(0, 0.0, 40, 0.01), req(1, 0.0, 40, 0.01), req(2, 0.05, 70, 0.01)], timeout=10.0)
+    s.close()
+    assert all(r.error is None for r in res.values())
+    assert any(e == "release" for (e, _, _, _) in log)
+    assert res[2].grad[0, 0, 0] == 2
+
+
+def test_scheduler_reads_no_context_of_a_busy_slot():
+    # held bytes come from each slot's own thread: the executor records the
+    # threads that asked, and only its worker (or the constructor) may ask
+    log = []
+
+    class Strict(FakeExec):
+        def __init__(self, k, log):
+            super().__init__(k, log)
+            self.askers = set()
+
+        def held_bytes(self):
+            self.askers.add(threading.get_ident())
+            return self.held
+
+    ex = [Strict(k, log) for k in range(2)]
+    main = threading.get_ident()
+    s = Server(ex, 100)
+    s.run_trace([req(k, 0.0, 10, 0.01) for k in range(6)])
+    s.close()
+    for e, w in zip(ex, s.workers):
+        assert e.askers <= {main, w.ident}
