@@ -267,6 +267,8 @@ def overlap_matrix(mol: Molecule) -> np.ndarray:
     nao = int(off[-1])
     S = np.zeros((nao, nao))
     A_all = mol.xyz[mol.shell_atom]
+    # component normalisations per shell (the same scalar formula, once per shell)
+    cnorm = [np.array([[cart_norm(float(e), *c) for c in CART[l]] for e in mol.shell_exp]) for l in range(3)]
     for la in range(3):
         for lb in range(3):
             ia = np.nonzero(mol.shell_l == la)[0]
@@ -308,9 +310,9 @@ def overlap_matrix(mol: Molecule) -> np.ndarray:
                         t[i, j] = v
                 oneD.append(t)
             for ca, (ax, ay, az) in enumerate(CART[la]):
-                na = np.array([cart_norm(e, ax, ay, az) for e in a])
+                na = cnorm[la][I, ca]
                 for cb, (bx, by, bz) in enumerate(CART[lb]):
-                    nb = np.array([cart_norm(e, bx, by, bz) for e in b])
+                    nb = cnorm[lb][J, cb]
                     val = s00 * na * nb * oneD[0][ax, bx] * oneD[1][ay, by] * oneD[2][az, bz]
                     S[off[I] + ca, off[J] + cb] = val
     return S
