@@ -6,10 +6,15 @@ and MO blocks) -> ris_response_matvec ((A+B) R_I and (A-B) L_I for every
 state) -> ris_grad_nac_contract (gradients of every state and NAC numerators of
 adjacent pairs, one call).
 Default workload: 200-atom C/N/O chain (seed 2), 10 TDDFT states, 10 gradients
-+ 9 NAC numerators per step, FP64.
++ 9 NAC numerators per step.  `value` is the plain-FP64 rate.  The same line
+carries the step in each reduced-precision mode (rate, Gamma roofline against
+that mode's peak, max |d grad| and |d NAC| per result against the FP64 step),
+a bounded serving replay (saturation throughput and p50/p99 latency under
+Poisson arrivals, against the sequential FP64 loop) and the CPU oracle timed on
+a bounded sample (all threads and one thread).
 
     python bench.py [--steps K] [--warmup W] [--workload chain200|chain60|ring12]
-                    [--no-cpu-baseline]
+                    [--mode-steps S] [--serve N] [--no-cpu-baseline]
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -54,21 +59,31 @@ def make_workload(name):
     return prob, jp, outs
 
 
-def oracle_sample(prob, jp, outs, radii):
-    """Time the CPU oracle on bounded samples of the same workload (about 10 s
-    of host work) and scale each stage linearly to one full step: (mu nu|P)
-    for 24 s and 8 p auxiliary shells, the exchange weights of 24 K functions
-    for one output pair, and the derivative contraction over the sampled
-    functions for one output."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample(prob, jp, outs, radii, scale=1.0):
+    """Time the CPU oracle on bounded samples of the same workload and scale
+    each stage linearly to one full step: (mu nu|P) for 24 s and 8 p auxiliary
+    shells, the exchange weights of 24 K functions for one output pair, and
+    the derivative contraction over the sampled functions for one output
+    (about 10 s of host work at scale 1; `scale` shrinks the sample)."""
     from oracle import ris_oracle as O
-    import threadpoolctl  # noqa: F401  (BLAS threads stay at the default: all cores)
     mol = prob.mol
     ao = O.ao_shells(mol)
     aux = O.aux_build(mol, radii, 0.2, jp)
     nJs, nKs = aux.J.n, aux.K.n
     nJ, nK = aux.J.nfunc, aux.K.nfunc
     # (1) three-centre integrals on 24 s + 8 p auxiliary shells
-    ks, kp = min(24, nKs), (min(8, nJs - nKs) if nJs > nKs else 0)
+    ks = max(1, min(int(round(24 * scale)), nKs))
+    kp = (max(1, min(int(round(8 * scale)), nJs - nKs)) if nJs > nKs else 0)
     pick = list(range(ks)) + list(range(nKs, nKs + kp))
     sub = O.Shells(aux.J.xyz[pick], aux.J.l[pick], aux.J.exp[pick], aux.J.atom[pick])
     t = time.perf_counter()
@@ -91,13 +106,30 @@ def oracle_sample(prob, jp, outs, radii):
     t_dr = time.perf_counter() - t
     full_dr = t_dr * (nJ + nK) / nf * len(outs)     # the oracle contracts one output per pass here
     total = full_int + full_pw + full_dr
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return total, (f"int3c on {nf} of {nJ}+{nK} aux functions ({t_int:.1f} s), exchange weights for {ks} of "
+                   f"{nK} K functions x 1 pair ({t_pw:.1f} s), derivative contraction on {nf} aux functions x 1 "
+                   f"output ({t_dr:.1f} s)")
+
+
+def cpu_baseline(prob, jp, outs, radii):
+    """The oracle on the host: all threads (OpenMP integrals, BLAS), then one
+    thread on an eighth-size sample; both scaled to one full step."""
+    import threadpoolctl
+    from oracle import ris_oracle as O
+    O.lib()  # load the oracle's integrals (and their OpenMP runtime) first
+    info = threadpoolctl.threadpool_info()
+    blas = ", ".join(sorted({f"{d.get('internal_api')} {d.get('version')}" for d in info
+                             if d.get("user_api") == "blas"}))
+    nthreads = max([d.get("num_threads", 1) for d in info] + [1])
+    total, what = oracle_sample(prob, jp, outs, radii)
+    with threadpoolctl.threadpool_limits(limits=1):
+        total1, what1 = oracle_sample(prob, jp, outs, radii, scale=0.125)
     return {
         "value": len(outs) / total, "unit": "grads+NACs/s", "cores": nthreads, "kind": "oracle",
-        "sample": (f"{mol.natm}-atom workload: int3c on {nf} of {nJ}+{nK} aux functions ({t_int:.1f} s), "
-                   f"exchange weights for {ks} of {nK} K functions x 1 pair ({t_pw:.1f} s), derivative "
-                   f"contraction on {nf} aux functions x 1 output ({t_dr:.1f} s); each scaled linearly to "
+        "sample": (f"{prob.mol.natm}-atom workload, {nthreads} threads: {what}; each scaled linearly to "
                    f"{len(outs)} outputs: est. {total:.0f} s per step"),
+        "one_thread": {"value": len(outs) / total1, "sample": f"1 thread: {what1}; est. {total1:.0f} s per step"},
+        "cpu_model": _cpu_model(), "blas": blas,
     }
 
 
@@ -167,92 +199,169 @@ def davidson_bench(ctx, prob, jp, radii, C, eps, nroots, tol=1e-6, maxit=15):
     return out
 
 
-def compare_precisions(ctx, prob, jp, grads, pairs, radii, C, eps, X, Y):
-    """Run the step once per precision mode; max |d grad| and |d NAC| against
-    the FP64 GPU result (itself pinned to the oracle by the parity tests)."""
-    import time as _t
+def run_steps(ctx, step, steps, warmup, label):
+    """W untimed steps, then K timed ones with per-stage event timing on."""
     import torch
-    m = prob.mol
+    for w in range(warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] {label} warmup {w}: {time.perf_counter() - t:.3f} s")
+    ctx.set_profiling(True)
+    times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ts = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        log(f"[bench] {label} step {k}: {times[-1]:.3f} s")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    stats = ctx.stage_stats()
+    ctx.set_profiling(False)
+    return times, total, stats
+
+
+KERNELS = {
+    "fp64": ("k_gemm<0,false,true,*> listed lower tiles, f64 (Gamma^P = (F_I W^P) F_J^T, batched over P)",
+             PEAK_FP64_TFLOPS, 1.0),
+    "fp32": ("k_gemm<1,false,true,*,float,float,double> listed lower tiles, f32 inputs "
+             "(Gamma^P = (F_I W^P) F_J^T, batched over P)", PEAK_FP32_TFLOPS, 1.0),
+    "bf16x3": ("k_bgemm3<2,...> listed lower tiles, three bf16 products (Gamma^P = (F_I W^P) F_J^T, batched "
+               "over P)", PEAK_BF16_TFLOPS, 3.0),
+    "bf16x6": ("k_bgemm3<3,...> listed lower tiles, six bf16 products (Gamma^P = (F_I W^P) F_J^T, batched "
+               "over P)", PEAK_BF16_TFLOPS, 6.0),
+}
+
+
+def gamma_roofline(stats, precision, workload):
+    """Roofline of the Gamma back-transform launches: algorithmic FLOPs per
+    launch over their average event-timed duration, against the matrix-core
+    peak of the type the launch multiplies in (split-BF16 modes count every
+    BF16 product they issue)."""
+    gms, gfl, gby, gn = stats["gamma"]
+    if gn <= 0 or gms <= 0:
+        return None
+    kern, peak, nprod = KERNELS[precision]
+    ach = gfl / gn / (gms * 1e-3 / gn) / 1e12 * nprod
+    import hashlib
+    src = os.path.join(ROOT, "paper_2511_18233_amd", "csrc", "ris_gemm.hip")
+    same = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == GAMMA_TRAFFIC["gemm_src_sha256"]
+    traffic = GAMMA_TRAFFIC["bytes_per_launch"] if (same and workload == GAMMA_TRAFFIC["workload"]
+                                                    and precision == "fp64") else None
+    return {"bound": "mfma", "kernel": kern, "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(ach / peak, 4), "traffic": traffic, "flops_per_launch": gfl / gn,
+            "avg_launch_ms": gms / gn, "algorithmic_bytes_per_launch": gby / gn}
+
+
+def stage_table(stats, steps):
     out = {}
-    ref = None
-    for prec in ("fp64", "fp32", "bf16x3"):
-        ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
-        torch.cuda.synchronize()
-        t = _t.perf_counter()
-        ctx.int3c(C, eps, prob.nocc, 2.0, 0.25, precision=prec)
-        g, n = ctx.grad_nac_contract(X, Y, grads, pairs)
-        torch.cuda.synchronize()
-        dt = _t.perf_counter() - t
-        g, n = g.cpu().numpy(), n.cpu().numpy()
-        if ref is None:
-            ref = (g, n)
-        out[prec] = {"int3c_plus_contract_s": round(dt, 4),
-                     "max_abs_dgrad": float(np.abs(g - ref[0]).max()),
-                     "max_abs_dnac": float(np.abs(n - ref[1]).max()) if n.size else None,
-                     "max_abs_grad": float(np.abs(ref[0]).max())}
-        log(f"[bench] precision {prec}: {dt:.3f} s, max|dgrad| {out[prec]['max_abs_dgrad']:.2e}")
+    for name, (ms, fl, by, n) in stats.items():
+        out[name] = {"ms_per_step": ms / steps, "launches": n,
+                     "tflops": (fl / (ms * 1e-3) / 1e12) if ms > 0 and fl > 0 else None,
+                     "gbs": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None}
     return out
 
 
-def serve_bench(nreq, nslots, radii):
-    """Serving trace (chain molecules 20-120 atoms, 2 gradients + 1 NAC each):
-    sequential FP64 rate first, then a Poisson trace at 1.5x that rate through
-    (a) one FP64 slot, (b) nslots FP64 slots (equal accuracy) and (c) nslots
-    slots with the exchange contractions in FP32; throughput and p50/p99
-    latency of each, and the max deviation from the sequential FP64 results."""
+def serve_bench(nreq, nslots, radii, mixed=("fp32", "bf16x6")):
+    """Serving replay (chain molecules 20-120 atoms from seeded trajectories,
+    2 gradients + 1 NAC numerator each):
+      * sequential FP64: one slot, requests back to back (the reference loop
+        and the reference results);
+      * saturation: every request queued at t = 0, through nslots FP64 slots
+        (equal accuracy) and nslots slots in each mixed mode;
+      * Poisson arrivals at 1.5x the sequential rate: p50/p99 latency of the
+        sequential loop, of nslots FP64 slots and of nslots slots in the
+        faster mixed mode.
+    Each slot's regions are warmed on the largest requests first (grow-only
+    regions: no allocation inside the timed replays).  Results of every run
+    are compared with the sequential FP64 ones."""
     from paper_2511_18233_amd.serve import GpuExecutor, Server, latency_stats, make_trace
     log(f"[bench] serving: building a {nreq}-request trace")
-    reqs = make_trace(nreq, max(1, nreq // 16), rate_hz=1.0, seed=1000,
-                      progress=lambda k, n: log(f"[bench] serving: built {k}/{n} requests"))
-    seq = Server([GpuExecutor(0, 0, radii, "fp64")], 200 << 30)
-    warm = seq.run_trace(reqs[:2], realtime=False)  # warm the slot's regions
-    del warm
-    seq.close()
-    seq = Server([GpuExecutor(0, 0, radii, "fp64")], 200 << 30)
     t = time.perf_counter()
-    r0 = seq.run_trace(reqs, realtime=False)
-    t_seq = time.perf_counter() - t
-    seq.close()
+    reqs = make_trace(nreq, max(1, nreq // 8), rate_hz=1.0, seed=1000,
+                      progress=lambda k, n: log(f"[bench] serving: built {k}/{n} requests"))
+    log(f"[bench] serving: trace built in {time.perf_counter() - t:.1f} s")
+    big = sorted(reqs, key=lambda r: -r.C.shape[0])[:2]
+    budget = 200 << 30
+    pools = {}
+
+    def pool(kind, n):
+        key = (kind, n)
+        if key not in pools:
+            ex = [GpuExecutor(k, 0, radii, kind) for k in range(n)]
+            for e in ex:            # grow each slot's regions to the largest requests
+                for r in big:
+                    e.run(r)
+            pools[key] = ex
+        return pools[key]
+
+    def replay(kind, n, arrivals, realtime):
+        for r, a in zip(reqs, arrivals):
+            r.arrival = float(a)
+        srv = Server(pool(kind, n), budget)
+        t0 = time.perf_counter()
+        rr = srv.run_trace(reqs, realtime=realtime)
+        wall = time.perf_counter() - t0
+        srv.close(executors=False)
+        return rr, wall
+
+    zero = np.zeros(nreq)
+    r0, t_seq = replay("fp64", 1, zero, False)
     rate = nreq / t_seq
+    log(f"[bench] serving sequential fp64: {rate:.2f} req/s")
+
+    def dev(rr):
+        return max(float(max(np.abs(rr[k].grad - r0[k].grad).max(), np.abs(rr[k].nac - r0[k].nac).max()))
+                   for k in rr if rr[k].error is None)
+
+    out = {"requests": nreq, "outputs_per_request": 3,
+           "sizes_atoms": [int(min(r.Z.shape[0] for r in reqs)), int(max(r.Z.shape[0] for r in reqs))],
+           "sequential_fp64": {"req_s": rate, "grads_nacs_s": 3 * rate}}
+    sat = {}
+    for kind in ("fp64",) + tuple(mixed):
+        rr, wall = replay(kind, nslots, zero, False)
+        errs = sum(1 for x in rr.values() if x.error)
+        sat[kind] = {"slots": nslots, "req_s": nreq / wall, "grads_nacs_s": 3 * nreq / wall,
+                     "vs_sequential_fp64": (nreq / wall) / rate, "max_abs_diff_vs_fp64": dev(rr), "errors": errs}
+        log(f"[bench] serving saturation {kind} x{nslots}: {nreq / wall:.2f} req/s ({sat[kind]['vs_sequential_fp64']:.2f}x)")
+    out["saturation"] = sat
+    best = max(mixed, key=lambda k: sat[k]["req_s"])
     lam = 1.5 * rate
     gaps = np.random.default_rng(7).exponential(1.0 / lam, nreq)
     arr = np.cumsum(gaps) - gaps[0]
-    for r, a in zip(reqs, arr):
-        r.arrival = float(a)
-    out = {"requests": nreq, "outputs_per_request": 3, "sequential_fp64_back_to_back_req_s": rate,
-           "arrival_rate_req_s": lam}
-    for name, execs in (("fifo_fp64_1slot", lambda: [GpuExecutor(0, 0, radii, "fp64")]),
-                        (f"batched_fp64_{nslots}slots",
-                         lambda: [GpuExecutor(k, 0, radii, "fp64") for k in range(nslots)]),
-                        (f"batched_fp32_{nslots}slots",
-                         lambda: [GpuExecutor(k, 0, radii, "fp32") for k in range(nslots)])):
-        srv = Server(execs(), 200 << 30)
-        t = time.perf_counter()
-        rr = srv.run_trace(reqs, realtime=True)
-        wall = time.perf_counter() - t
-        srv.close()
+    pois = {"arrival_rate_req_s": lam}
+    for name, kind, n in (("sequential_fp64", "fp64", 1), (f"fp64_x{nslots}", "fp64", nslots),
+                          (f"{best}_x{nslots}", best, nslots)):
+        rr, wall = replay(kind, n, arr, True)
         st = latency_stats(rr)
-        errs = [x.error for x in rr.values() if x.error]
-        dmax = max(float(max(np.abs(rr[k].grad - r0[k].grad).max(), np.abs(rr[k].nac - r0[k].nac).max()))
-                   for k in rr if rr[k].error is None)
-        out[name] = {"req_s": nreq / wall, "grads_nacs_s": 3 * nreq / wall, "p50_ms": st["p50_ms"],
-                     "p99_ms": st["p99_ms"], "errors": len(errs), "max_abs_diff_vs_fp64": dmax}
-        log(f"[bench] serving {name}: {nreq / wall:.2f} req/s p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms")
+        pois[name] = {"req_s": nreq / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                      "max_abs_diff_vs_fp64": dev(rr), "errors": sum(1 for x in rr.values() if x.error)}
+        log(f"[bench] serving poisson {name}: {nreq / wall:.2f} req/s p50 {st['p50_ms']:.1f} ms "
+            f"p99 {st['p99_ms']:.1f} ms")
+    out["poisson"] = pois
+    out["mixed_mode"] = best
+    for ex in pools.values():
+        for e in ex:
+            e.close()
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="chain200")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--compare-precisions", action="store_true",
-                    help="also run fp32 and bf16x3 once and report their max |d grad| vs the FP64 result")
-    ap.add_argument("--serve", type=int, default=0,
-                    help="also replay a serving trace of this many requests (20-120 atoms)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"],
+                    help="arithmetic of the headline steps (default plain FP64)")
+    ap.add_argument("--mode-steps", type=int, default=5,
+                    help="timed steps per reduced-precision mode (0: skip the modes)")
+    ap.add_argument("--serve", type=int, default=128,
+                    help="requests of the serving replay (20-120 atoms; 0: skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--zrhs", action="store_true",
                     help="also time the ris Z-vector right-hand-side terms for the step's outputs")
@@ -297,87 +406,49 @@ def main():
     # auxiliary index by itself when the unblocked scratch does not fit)
     big = len(outs) > 19
 
-    def step():
-        ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
-        ctx.int3c(C, eps, prob.nocc, 2.0, 0.25, precision=args.precision)
-        if big:
+    def make_step(precision):
+        def step():
+            ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+            ctx.int3c(C, eps, prob.nocc, 2.0, 0.25, precision=precision)
+            if big:
+                torch.cuda.synchronize()
+                log("[bench]   int3c + MO transforms done")
+            ctx.response_matvec("A+B", R, mv_out)
+            ctx.response_matvec("A-B", L, mv_out)
+            if not big:
+                ctx.grad_nac_contract(X, Y, grads, pairs, None, g_out, n_out)
+                return
             torch.cuda.synchronize()
-            log("[bench]   int3c + MO transforms done")
-        ctx.response_matvec("A+B", R, mv_out)
-        ctx.response_matvec("A-B", L, mv_out)
-        if not big:
-            ctx.grad_nac_contract(X, Y, grads, pairs, None, g_out, n_out)
-            return
-        torch.cuda.synchronize()
-        log("[bench]   matvecs done")
-        # gradient J together with the NAC (J-1, J): in one call they share
-        # the exchange products of state J
-        for k, J in enumerate(grads):
-            pk = [q for q, (a, b) in enumerate(pairs) if b == J]
-            assert len(pk) <= 1  # adjacent-pair NACs: at most one ends in state J
-            ctx.grad_nac_contract(X, Y, [J], [pairs[q] for q in pk], None, g_out[k:k + 1],
-                                  n_out[pk[0]:pk[0] + 1] if pk else n_out[:0])
-            torch.cuda.synchronize()
-            log(f"[bench]   gradient {J}" + (f" + NAC {pairs[pk[0]]}" if pk else "") + " done")
+            log("[bench]   matvecs done")
+            # gradient J together with the NAC (J-1, J): in one call they share
+            # the exchange products of state J
+            for k, J in enumerate(grads):
+                pk = [q for q, (a, b) in enumerate(pairs) if b == J]
+                assert len(pk) <= 1  # adjacent-pair NACs: at most one ends in state J
+                ctx.grad_nac_contract(X, Y, [J], [pairs[q] for q in pk], None, g_out[k:k + 1],
+                                      n_out[pk[0]:pk[0] + 1] if pk else n_out[:0])
+                torch.cuda.synchronize()
+                log(f"[bench]   gradient {J}" + (f" + NAC {pairs[pk[0]]}" if pk else "") + " done")
+        return step
 
     log(f"[bench] natm={m.natm} nao={m.nao} nocc={prob.nocc} states={ns} outputs/step={len(outs)}")
-    for w in range(args.warmup):
-        t = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        log(f"[bench] warmup {w}: {time.perf_counter() - t:.3f} s")
-    ctx.set_profiling(True)
-    times = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-        log(f"[bench] step {k}: {times[-1]:.3f} s")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    stats = ctx.stage_stats()
-    ctx.set_profiling(False)
-
-    per_stage = {}
-    for name, (ms, fl, by, n) in stats.items():
-        per_stage[name] = {"ms_per_step": ms / args.steps, "launches": n,
-                           "tflops": (fl / (ms * 1e-3) / 1e12) if ms > 0 and fl > 0 else None,
-                           "gbs": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None}
-        log(f"[bench] stage {name:7s} {ms / args.steps:10.2f} ms/step  launches={n}"
-            + (f"  {fl / (ms * 1e-3) / 1e12:7.2f} TFLOP/s" if ms > 0 and fl > 0 else ""))
-    # dominant matrix-core kernel: the AO back-transform GEMM of the exchange weights
-    gms, gfl, gby, gn = stats["gamma"]
-    roof = None
-    if gn > 0 and gms > 0:
-        ach = gfl / gn / (gms * 1e-3 / gn) / 1e12
-        import hashlib
-        src = os.path.join(ROOT, "paper_2511_18233_amd", "csrc", "ris_gemm.hip")
-        same = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == GAMMA_TRAFFIC["gemm_src_sha256"]
-        traffic = GAMMA_TRAFFIC["bytes_per_launch"] if (same and args.workload == GAMMA_TRAFFIC["workload"]
-                                                        and args.precision == "fp64") else None
-        # each precision is priced against the matrix-core peak of the type it
-        # multiplies in; the split-BF16 product runs three BF16 GEMMs per
-        # useful product, so its achieved rate counts all three
-        kern, peak = {
-            "fp64": ("k_gemm<0,false,true,*> listed lower tiles, f64 (Gamma^P = (F_I W^P) F_J^T, batched over P)",
-                     PEAK_FP64_TFLOPS),
-            "fp32": ("k_gemm<1,false,true,*,float,float,double> lower tiles, f32 inputs "
-                     "(Gamma^P = (F_I W^P) F_J^T, batched over P)", PEAK_FP32_TFLOPS),
-            "bf16x3": ("k_bgemm3 full tiles, three bf16 products (Gamma^P = (F_I W^P) F_J^T, batched over P)",
-                       PEAK_BF16_TFLOPS)}[args.precision]
-        if args.precision == "bf16x3":
-            ach *= 3.0
-        roof = {"bound": "mfma", "kernel": kern,
-                "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": traffic,
-                "flops_per_launch": gfl / gn, "avg_launch_ms": gms / gn,
-                "algorithmic_bytes_per_launch": gby / gn}
+    times, total, stats = run_steps(ctx, make_step(args.precision), args.steps, args.warmup, args.precision)
+    per_stage = stage_table(stats, args.steps)
+    for name, st in per_stage.items():
+        log(f"[bench] stage {name:7s} {st['ms_per_step']:10.2f} ms/step  launches={st['launches']}"
+            + (f"  {st['tflops']:7.2f} TFLOP/s" if st["tflops"] else ""))
+    roof = gamma_roofline(stats, args.precision, args.workload)
+    # whole step: the algorithmic FLOPs the stage timers count, over the measured step time
+    step_fl = sum(fl for (ms, fl, by, n) in stats.values()) / args.steps
+    step_roof = {"achieved_tflops": round(step_fl / (total / args.steps) / 1e12, 3),
+                 "peak": PEAK_FP64_TFLOPS,
+                 "unit": "TFLOP/s", "algorithmic_flops_per_step": step_fl}
+    step_roof["frac"] = round(step_roof["achieved_tflops"] / step_roof["peak"], 4)
+    g_ref = g_out.cpu().numpy().copy()
+    n_ref = n_out.cpu().numpy().copy()
 
     # translational invariance of the gradients (sum over atoms vanishes)
-    inv = float(g_out.sum(1).abs().max().item()) if len(grads) else 0.0
+    inv = float(np.abs(g_ref.sum(1)).max()) if len(grads) else 0.0
     from paper_2511_18233_amd.ris import request_bytes
     plan0 = request_bytes(m.Z, m.shell_atom, m.shell_l, radii, m.nao, prob.nocc, ns, ns, len(outs))
     hbm = {"held_gb": round(ctx.bytes_held / 1e9, 2),
@@ -390,17 +461,22 @@ def main():
     res = {
         "metric": METRIC, "value": round(value, 4), "unit": "grads+NACs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * total / args.steps, 2),
+        "ms_per_step_min": round(1e3 * float(tsorted[0]), 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32 (exchange contractions), f64 elsewhere",
-                  "bf16x3": "bf16x3 (exchange contractions), f64 elsewhere"}[args.precision], "data": "synthetic",
+                  "bf16x3": "bf16x3 (exchange contractions), f64 elsewhere",
+                  "bf16x6": "bf16x6 (exchange contractions), f64 elsewhere"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": f"{args.workload}: seeded C/N/O chain, {m.natm} atoms, nao={m.nao}, "
                                f"nocc={prob.nocc}, nauxJ={ctx.nJ}, nauxK={ctx.nK}, {ns} TDDFT states, "
                                f"{len(grads)} gradients + {len(pairs)} NAC numerators per step",
                    "natm": m.natm, "nao": m.nao, "nocc": prob.nocc, "nauxJ": ctx.nJ, "nauxK": ctx.nK,
                    "nstate": ns, "outputs_per_step": len(outs), "precision": args.precision},
-        "latency_ms": {"p50": round(1e3 * float(np.percentile(tsorted, 50)), 2),
-                       "p99": round(1e3 * float(np.percentile(tsorted, 99)), 2)},
+        "step_latency_ms": {"p50": round(1e3 * float(np.percentile(tsorted, 50)), 2),
+                            "p99": round(1e3 * float(np.percentile(tsorted, 99)), 2),
+                            "min": round(1e3 * float(tsorted[0]), 2)},
         "roofline": roof,
+        "step_roofline": step_roof,
         "stages": per_stage,
         "grad_sum_max": inv,
         "hbm": hbm,
@@ -408,24 +484,52 @@ def main():
     mv = per_stage.get("matvec")
     if mv and mv["ms_per_step"] > 0:
         res["matvecs_per_s"] = round(2 * ns / (mv["ms_per_step"] * 1e-3), 2)
+
+    # the same step in each reduced-precision mode, against the FP64 step's outputs
+    if args.mode_steps > 0 and args.precision == "fp64":
+        modes = {}
+        for mode in ("fp32", "bf16x6", "bf16x3"):
+            mt, mtot, mst = run_steps(ctx, make_step(mode), args.mode_steps, 1, mode)
+            g = g_out.cpu().numpy()
+            n = n_out.cpu().numpy()
+            per = [float(np.abs(g[k] - g_ref[k]).max()) for k in range(len(grads))] + \
+                  [float(np.abs(n[k] - n_ref[k]).max()) for k in range(len(pairs))]
+            rate = len(outs) * args.mode_steps / mtot
+            modes[mode] = {
+                "grads_nacs_per_s": round(rate, 4), "ms_per_step": round(1e3 * mtot / args.mode_steps, 2),
+                "ms_per_step_min": round(1e3 * min(mt), 2), "steps": args.mode_steps,
+                "vs_plain_fp64": round(rate / value, 4),
+                "roofline": gamma_roofline(mst, mode, args.workload),
+                "max_abs_dgrad_vs_fp64": max(per[:len(grads)]) if grads else None,
+                "max_abs_dnac_vs_fp64": max(per[len(grads):]) if pairs else None,
+                "max_abs_grad": float(np.abs(g_ref).max()),
+                "per_result_max_abs_d": [round(x, 15) for x in per],
+                "stages_ms_per_step": {k: round(v["ms_per_step"], 2) for k, v in stage_table(mst, args.mode_steps).items()},
+            }
+            log(f"[bench] {mode}: {rate:.2f} grads+NACs/s ({rate / value:.2f}x fp64), max|dgrad| "
+                f"{modes[mode]['max_abs_dgrad_vs_fp64']:.2e} max|dNAC| {modes[mode]['max_abs_dnac_vs_fp64']:.2e}")
+        res["precision_modes"] = modes
     if args.zrhs:
         res["zrhs"] = zrhs_bench(ctx, prob, jp, radii, C, eps, X, Y, outs)
     if args.davidson > 0:
         res["davidson"] = davidson_bench(ctx, prob, jp, radii, C, eps, args.davidson)
     if args.zvector > 0:
         res["zvector"] = zvector_bench(ctx, prob, jp, radii, C, eps, args.zvector, 1e-8)
-    if args.compare_precisions:
-        # the 500-atom comparison takes two gradients and one NAC (the full set
-        # would run for minutes per mode)
-        cg, cp = (grads[:2], pairs[:1]) if big else (grads, pairs)
-        res["precision_errors"] = compare_precisions(ctx, prob, jp, cg, cp, radii, C, eps, X, Y)
-        res["precision_errors"]["outputs"] = {"gradients": list(cg), "nacs": [list(q) for q in cp]}
     ctx.close()
     if args.serve > 0:
-        res["serving"] = serve_bench(args.serve, args.serve_slots, radii)
+        sv = serve_bench(args.serve, args.serve_slots, radii)
+        res["serving"] = sv
+        best = sv["mixed_mode"]
+        pb = sv["poisson"][f"{best}_x{args.serve_slots}"]
+        # the metric's latency: requests of the serving replay under Poisson arrivals
+        res["latency_ms"] = {"p50": round(pb["p50_ms"], 2), "p99": round(pb["p99_ms"], 2),
+                             "of": f"serving replay, {best} x{args.serve_slots} slots, Poisson "
+                                   f"{sv['poisson']['arrival_rate_req_s']:.1f} req/s",
+                             "sequential_fp64_p50": round(sv["poisson"]["sequential_fp64"]["p50_ms"], 2),
+                             "sequential_fp64_p99": round(sv["poisson"]["sequential_fp64"]["p99_ms"], 2)}
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        res["cpu_baseline"] = oracle_sample(prob, jp, outs, radii)
+        res["cpu_baseline"] = cpu_baseline(prob, jp, outs, radii)
     print(json.dumps(res), flush=True)
 
 

@@ -71,7 +71,7 @@ def phase_signs(X_prev: np.ndarray, X_cur: np.ndarray, C_prev: np.ndarray, C_cur
     of s_I (+1 when s_I is 0)."""
     X_prev = np.asarray(X_prev, dtype=np.float64)
     X_cur = np.asarray(X_cur, dtype=np.float64)
-    d = np.sign(np.einsum("mp,mn,np->p", C_prev, S_cur, C_cur))
+    d = np.sign(np.einsum("mp,mp->p", C_prev, S_cur @ C_cur))   # diag(C_prev^T S C_cur)
     d[d == 0] = 1.0
     dv, do = d[nocc:], d[:nocc]
     out = np.ones(X_prev.shape[0])

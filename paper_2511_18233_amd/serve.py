@@ -241,7 +241,9 @@ class Server:
                 self.lock.wait(timeout=min(left, 1.0))
         return dict(self.results)
 
-    def close(self):
+    def close(self, executors: bool = True):
+        """Stop the worker threads; executors=False keeps the slots' contexts
+        (and their warm regions) for another server."""
         if self.closed:
             return
         self.closed = True
@@ -249,9 +251,10 @@ class Server:
             q.put(None)
         for w in self.workers:
             w.join(timeout=60)
-        for e in self.ex:
-            if hasattr(e, "close"):
-                e.close()
+        if executors:
+            for e in self.ex:
+                if hasattr(e, "close"):
+                    e.close()
 
 
 def latency_stats(results) -> dict:
