@@ -28,8 +28,11 @@
  *     on the context's device; small tables (ris_mol, ris_aux_opts, sel,
  *     pairs, omega) are HOST pointers.  The caller owns every buffer it
  *     passes; the context owns all of its internal device state.
- *   - All device work is enqueued on the stream given at ris_ctx_create;
- *     calls return once the work is enqueued except where noted.
+ *   - All device work is enqueued on the stream given at ris_ctx_create.
+ *     Each declaration states whether the call synchronises that stream
+ *     before returning: the calls that read a device result on the host
+ *     (Cholesky status, convergence tests) or hand back buffers the caller
+ *     may free at once do; ris_response_matvec_noalloc does not.
  *   - Errors: a status code is returned and a message is kept for
  *     ris_last_error; nothing is thrown across the ABI.  After an error the
  *     outputs of that call are undefined.
@@ -180,7 +183,8 @@ enum ris_stage {
  * run; rel_resid (may be NULL) the largest true relative residual
  * ||rhs_k - (A+B) Z_k|| / ||rhs_k|| after the solve (one extra matvec).
  * Returns RIS_E_NOCONV if maxit iterations end before every right-hand side
- * has stopped (Z holds the last iterate), RIS_E_ORDER before ris_int3c. */
+ * has stopped (Z holds the last iterate), RIS_E_ORDER before ris_int3c.
+ * Synchronous (the convergence test reads the residuals on the host). */
 int ris_zvector_solve(ris_ctx *ctx, int nrhs, const double *rhs, double *Z, double tol, int maxit, int *iters,
                       double *rel_resid);
 
@@ -198,7 +202,8 @@ int ris_zvector_solve(ris_ctx *ctx, int nrhs, const double *rhs, double *Z, doub
  * precision mode.  X, Y: [nstate][nvir][nocc] device (Y = NULL: TDA);
  * pairs: host [npair][2]; G: device [npair][nmo][nmo], rows and columns in
  * the MO order of ris_int3c's C.  Recomputes (mu nu|P) into the context's
- * scratch (nJ nao^2 doubles).  RIS_E_ORDER before ris_int3c. */
+ * scratch (nJ nao^2 doubles).  RIS_E_ORDER before ris_int3c.  Synchronises the
+ * context's stream before returning. */
 int ris_zrhs_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y, int npair, const int *pairs,
                       double *G);
 
@@ -214,7 +219,8 @@ int ris_zrhs_contract(ris_ctx *ctx, int nstate, const double *X, const double *Y
  * omega: host [nroots], ascending; X: device [nroots][nvir][nocc], unit
  * vectors (sign arbitrary but reproducible).  iters (may be NULL): iterations
  * run.  RIS_E_NOCONV after maxit iterations or when no new direction is left
- * (omega and X hold the last Ritz pairs), RIS_E_ORDER before ris_int3c. */
+ * (omega and X hold the last Ritz pairs), RIS_E_ORDER before ris_int3c.
+ * Synchronous (omega is a host array). */
 int ris_tda_davidson(ris_ctx *ctx, int nroots, double tol, int maxit, int max_space, double *omega, double *X,
                      int *iters);
 
@@ -270,14 +276,16 @@ int ris_aux_build(ris_ctx *ctx, const ris_mol *mol, const ris_aux_opts *opts,
  * blocks sum_Q (M_K^-1)_PQ (pq|Q).  mo->C and mo->eps are copied.  If
  * dbg_int3c is not NULL it receives (mu nu|P) as [nauxJ][nao][nao] in the
  * caller's AO order (device pointer).  RIS_E_ORDER before ris_aux_build,
- * RIS_E_NOMEM if the tensors exceed the budget. */
+ * RIS_E_NOMEM if the tensors exceed the budget.  Synchronises the context's
+ * stream before returning. */
 int ris_int3c(ris_ctx *ctx, const ris_mo *mo, double *dbg_int3c);
 
 /* ris response matrix-vector products (Sec. 2.1, eqs. A_matrix, B_matrix
  * with K = g^ris): for each of nvec vectors V[v][o] (device, [nvec][nvir][nocc])
  *   (A V)_ai = (e_a - e_i) V_ai + alpha_J sum_bj (ai|bj)_J V_bj - c_x sum_bj (ab|ij)_K V_bj
  *   (B V)_ai =                     alpha_J sum_bj (ai|bj)_J V_bj - c_x sum_bj (aj|bi)_K V_bj
- * op selects A, B, A+B or A-B; out has V's shape (device, may not alias V). */
+ * op selects A, B, A+B or A-B; out has V's shape (device, may not alias V).
+ * Synchronises the context's stream before returning. */
 int ris_response_matvec(ris_ctx *ctx, int op, int nvec, const double *V, double *out);
 
 /* Allocation-free ris_response_matvec, for callers that cannot allocate
@@ -367,7 +375,8 @@ int ris_grad_nac_contract(ris_ctx *ctx, int nstate, const double *X, const doubl
  * X, Y: [nstate][nvir][nocc] device (Y = NULL: TDA), I, J < nstate (ignored
  * for the ground density, as are X, Y and Z); Z: [nvir][nocc] device (the
  * relaxed density only); D: [nao][nao] device, caller AO order, overwritten.
- * Uses the orbitals given to ris_int3c (RIS_E_ORDER before it). */
+ * Uses the orbitals given to ris_int3c (RIS_E_ORDER before it).
+ * Synchronises the context's stream before returning. */
 enum ris_density { RIS_DENS_GROUND = 0, RIS_DENS_DIFFERENCE = 1, RIS_DENS_RELAXED = 2 };
 int ris_density_ao(ris_ctx *ctx, int kind, int nstate, const double *X, const double *Y, int I, int J,
                    const double *Z, double *D);

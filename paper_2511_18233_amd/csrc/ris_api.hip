@@ -894,30 +894,48 @@ int ris_zrhs_contract(ris_ctx *c, int nstate, const double *X, const double *Y, 
         if (I < 0 || J < 0 || I >= nstate || J >= nstate) return fail(c, RIS_E_INVALID, "pair %d out of range", k);
         used[I] = used[J] = 1;
     }
+    if (c->nK > c->auxl_beg[1]) return fail(c, RIS_E_UNSUPPORTED, "exchange set is not a run of leading s shells");
     HIPCHK(c, hipSetDevice(c->device));
     const int N = c->nao, nmo = c->nmo, o = c->nocc, v = c->nvir, nJ = c->nJ, nK = c->nK, ns = nstate;
-    const long vo = (long)v * o, NN = (long)N * N, MM = (long)nmo * nmo, Ko = (long)nK * o;
+    const long vo = (long)v * o, NN = (long)N * N, MM = (long)nmo * nmo;
+    // ---- common part: R, L, U = C_V R, U' = C_V L, Coulomb vectors, the AO
+    // matrices g[D] of every used state (t = 0: R^S, t = 1: L^A) and their MO forms
     Carve cv;
     const size_t oR = cv.take((size_t)ns * vo), oL = cv.take((size_t)ns * vo), oUR = cv.take((size_t)ns * N * o),
                  oUL = cv.take((size_t)ns * N * o), otT = cv.take((size_t)ns * nJ), ocv = cv.take((size_t)ns * nJ),
-                 oSK = cv.take((size_t)kSplitV * ns * nJ), oX3 = cv.take((size_t)nJ * NN),
-                 oBk = cv.take((size_t)nK * NN), oZ1 = cv.take((size_t)N * Ko), oZ2 = cv.take((size_t)N * Ko),
-                 oY1 = cv.take((size_t)N * Ko), oY2 = cv.take((size_t)N * Ko), oJ = cv.take((size_t)ns * NN),
-                 ogA = cv.take(NN), oT1 = cv.take((size_t)N * nmo), ogM = cv.take((size_t)ns * 2 * MM),
-                 oEm = cv.take((size_t)4 * MM);
-    // K-split of the two exchange products (N x N output, K = nK o)
+                 oSK = cv.take((size_t)kSplitV * ns * nJ), ogA = cv.take((size_t)ns * 2 * NN),
+                 oT1 = cv.take((size_t)N * nmo), ogM = cv.take((size_t)ns * 2 * MM), oEm = cv.take((size_t)4 * MM);
+    const size_t common = cv.off;
+    // K-split of the exchange products (N x N output, K = (block functions) x nocc)
     const int ksp = balanced_splits((long)((N + 127) / 128) * ((N + 127) / 128), 8);
-    const size_t oSK2 = cv.take((size_t)ksp * NN);
+    // the integral part: all J functions at once, or blocks of nb functions (whole shells)
+    auto path_bytes = [&](int nb, bool all) {
+        Carve q;
+        const long Ko = (long)(all ? nK : nb) * o;
+        q.take((size_t)(all ? nJ : nb) * NN);  // raw (mu nu|P) of the J set / of the block
+        q.take((size_t)(all ? nK : nb) * NN);  // metric-applied exchange functions C^P
+        if (!all) q.take((size_t)nb * NN);     // streamed K blocks
+        for (int k = 0; k < 4; ++k) q.take((size_t)N * Ko);
+        q.take((size_t)ksp * NN);
+        return q.off;
+    };
+    const size_t other = c->held - c->ws_bytes;
+    const size_t wsroom = std::max(c->budget > other ? c->budget - other : 0, c->ws_bytes);
+    const bool blocked = (c->ablock > 0 && c->ablock < nK) || common + path_bytes(nK, true) > wsroom;
+    int nb = nK;
+    if (blocked) {
+        nb = std::max(3, c->ablock > 0 ? std::min(c->ablock, nK) : nK);
+        while (nb > 3 && common + path_bytes(nb, false) > wsroom) nb = std::max(3, (int)(nb * 0.8));
+    }
+    const size_t total = common + path_bytes(nb, !blocked);
     int st;
-    char *wsb = ws_get(c, cv.off, &st);
+    char *wsb = ws_get(c, total, &st);
     if (!wsb) return st;
     auto P_ = [&](size_t off) { return (double *)(wsb + off); };
     double *R = P_(oR), *L = P_(oL), *UR = P_(oUR), *UL = P_(oUL), *tT = P_(otT), *cvec = P_(ocv), *SK = P_(oSK),
-           *X3 = P_(oX3), *Bk = P_(oBk), *Z1 = P_(oZ1), *Z2 = P_(oZ2), *Y1 = P_(oY1), *Y2 = P_(oY2), *Jao = P_(oJ),
-           *gA = P_(ogA), *T1 = P_(oT1), *gM = P_(ogM), *Em = P_(oEm), *SK2 = P_(oSK2);
+           *gAll = P_(ogA), *T1 = P_(oT1), *gM = P_(ogM), *Em = P_(oEm);
     const double *CO = c->C, *CV = c->C + o;
 
-    // R, L, the AO factors U = C_V R, U' = C_V L and the Coulomb vectors c = M_J^-1 t
     HIPCHK(c, make_rl(X, Y, R, L, (size_t)ns * vo, c->stream));
     for (int t = 0; t < 2; ++t) {
         GemmArgs g = gm(N, o, v, false, false, 1.0, CV, nmo, t ? L : R, o, 0.0, t ? UL : UR, o);
@@ -927,37 +945,93 @@ int ris_zrhs_contract(ris_ctx *c, int nstate, const double *X, const double *Y, 
     HIPCHK(c, dgemm_splitk(gm(ns, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), kSplitV, SK,
                            c->stream));
     HIPCHK(c, dgemm(gm(ns, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
-    // AO three-centre integrals again, the metric-applied exchange set, the Coulomb matrices
-    HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, X3, c->stream));
-    HIPCHK(c, dgemm(gm(nK, (int)NN, nK, false, false, 1.0, c->MinvK, nK, X3, NN, 0.0, Bk, NN), c->stream));
-    HIPCHK(c, dgemm(gm(ns, (int)NN, nJ, false, false, c->alphaJ, cvec, nJ, X3, NN, 0.0, Jao, NN), c->stream));
-    // Z1^P = B^P C_O, Z2^P = (mu nu|P) C_O as [mu][P][i]
-    for (int t = 0; t < 2; ++t) {
-        GemmArgs g = gm(N, o, N, false, false, 1.0, t ? X3 : Bk, N, CO, nmo, 0.0, t ? Z2 : Z1, Ko);
-        g.batch = nK; g.strideA = NN; g.strideB = 0; g.strideC = o;
+    HIPCHK(c, fill(gAll, (size_t)ns * 2 * NN, 0.0, c->stream));
+
+    // the exchange part of g[D] for the functions [p0, p0 + m) of the K set:
+    //   K[D] = sum_P C^P D (mu nu|P) = (Y1 Z2^T +- Z1 Y2^T) / 2,
+    //   Z1^P = C^P C_O, Z2^P = (.|P) C_O, Y1^P = C^P U, Y2^P = (.|P) U  ([mu][P][i])
+    auto exchange = [&](const double *Cb, const double *Xb, int m, double *Z1, double *Z2, double *Y1, double *Y2,
+                        double *SK2) -> int {
+        const long Ko = (long)m * o;
+        for (int t = 0; t < 2; ++t) {
+            GemmArgs g = gm(N, o, N, false, false, 1.0, t ? Xb : Cb, N, CO, nmo, 0.0, t ? Z2 : Z1, Ko);
+            g.batch = m; g.strideA = NN; g.strideB = 0; g.strideC = o;
+            HIPCHK(c, dgemm(g, c->stream));
+        }
+        for (int s = 0; s < ns; ++s) {
+            if (!used[s]) continue;
+            for (int t = 0; t < 2; ++t) {
+                const double *U = (t ? UL : UR) + (size_t)s * N * o;
+                for (int q = 0; q < 2; ++q) {
+                    GemmArgs g = gm(N, o, N, false, false, 1.0, q ? Xb : Cb, N, U, o, 0.0, q ? Y2 : Y1, Ko);
+                    g.batch = m; g.strideA = NN; g.strideB = 0; g.strideC = o;
+                    HIPCHK(c, dgemm(g, c->stream));
+                }
+                double *gA = gAll + ((size_t)s * 2 + t) * NN;
+                const double sgn = t ? -1.0 : 1.0;
+                HIPCHK(c, dgemm_splitk(gm(N, N, (int)Ko, false, true, -0.5 * c->cx, Y1, Ko, Z2, Ko, 1.0, gA, N), ksp,
+                                       SK2, c->stream));
+                HIPCHK(c, dgemm_splitk(gm(N, N, (int)Ko, false, true, -0.5 * c->cx * sgn, Z1, Ko, Y2, Ko, 1.0, gA,
+                                          N), ksp, SK2, c->stream));
+            }
+        }
+        return RIS_OK;
+    };
+    // Coulomb part alpha_J sum_P c_s,P (mu nu|P) of the J functions [f0, f0 + nf), into gAll[s][0]
+    auto coulomb = [&](const double *Xb, int f0, int nf) -> int {
+        GemmArgs g = gm(ns, (int)NN, nf, false, false, c->alphaJ, cvec + f0, nJ, Xb, NN, 1.0, gAll, 2 * NN);
         HIPCHK(c, dgemm(g, c->stream));
+        return RIS_OK;
+    };
+
+    Carve q;
+    q.off = common;
+    if (!blocked) {
+        const long Ko = (long)nK * o;
+        double *X3 = P_(q.take((size_t)nJ * NN)), *Bk = P_(q.take((size_t)nK * NN));
+        double *Z1 = P_(q.take((size_t)N * Ko)), *Z2 = P_(q.take((size_t)N * Ko)), *Y1 = P_(q.take((size_t)N * Ko)),
+               *Y2 = P_(q.take((size_t)N * Ko)), *SK2 = P_(q.take((size_t)ksp * NN));
+        HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, X3, c->stream));
+        HIPCHK(c, dgemm(gm(nK, (int)NN, nK, false, false, 1.0, c->MinvK, nK, X3, NN, 0.0, Bk, NN), c->stream));
+        if ((st = coulomb(X3, 0, nJ)) != RIS_OK) return st;
+        if ((st = exchange(Bk, X3, nK, Z1, Z2, Y1, Y2, SK2)) != RIS_OK) return st;
+    } else {
+        const long Ko = (long)nb * o;
+        double *Xb = P_(q.take((size_t)nb * NN)), *Cb = P_(q.take((size_t)nb * NN)), *Bq = P_(q.take((size_t)nb * NN));
+        double *Z1 = P_(q.take((size_t)N * Ko)), *Z2 = P_(q.take((size_t)N * Ko)), *Y1 = P_(q.take((size_t)N * Ko)),
+               *Y2 = P_(q.take((size_t)N * Ko)), *SK2 = P_(q.take((size_t)ksp * NN));
+        const std::vector<int> &aoff = c->h_aux_off;
+        // J shells in blocks of at most nb functions: the Coulomb part
+        for (int a = 0; a < c->nshJ;) {
+            int b = a + 1;
+            while (b < c->nshJ && aoff[b + 1] - aoff[a] <= nb) ++b;
+            HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, Xb, c->stream, a, b));
+            if ((st = coulomb(Xb, aoff[a], aoff[b] - aoff[a])) != RIS_OK) return st;
+            a = b;
+        }
+        // K functions (the leading s shells) in blocks of nb: C^P of the block
+        // from every K block streamed through Bq, the raw block itself in Xb
+        for (int k0 = 0; k0 < nK; k0 += nb) {
+            const int m = std::min(nb, nK - k0);
+            HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, Xb, c->stream, k0, k0 + m));
+            for (int q0 = 0; q0 < nK; q0 += nb) {
+                const int mq = std::min(nb, nK - q0);
+                const double *src = Xb;
+                if (q0 != k0) {
+                    HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, Bq, c->stream, q0, q0 + mq));
+                    src = Bq;
+                }
+                HIPCHK(c, dgemm(gm(m, (int)NN, mq, false, false, 1.0, c->MinvK + (size_t)k0 * nK + q0, nK, src, NN,
+                                   q0 ? 1.0 : 0.0, Cb, NN), c->stream));
+            }
+            if ((st = exchange(Cb, Xb, m, Z1, Z2, Y1, Y2, SK2)) != RIS_OK) return st;
+        }
     }
-    // g^ris[D] in the MO basis for D = R^S_s (t = 0) and L^A_s (t = 1) of every state used:
-    //   K[D] = sum_P B^P D (mu nu|P) = (Y1 Z2^T +- Z1 Y2^T) / 2, Y1 = B^P U, Y2 = (.|P) U
+    // MO forms C^T g[D] C of every used (state, density)
     for (int s = 0; s < ns; ++s) {
         if (!used[s]) continue;
         for (int t = 0; t < 2; ++t) {
-            const double *U = (t ? UL : UR) + (size_t)s * N * o;
-            for (int q = 0; q < 2; ++q) {
-                GemmArgs g = gm(N, o, N, false, false, 1.0, q ? X3 : Bk, N, U, o, 0.0, q ? Y2 : Y1, Ko);
-                g.batch = nK; g.strideA = NN; g.strideB = 0; g.strideC = o;
-                HIPCHK(c, dgemm(g, c->stream));
-            }
-            if (t == 0)
-                HIPCHK(c, hipMemcpyAsync(gA, Jao + (size_t)s * NN, sizeof(double) * NN, hipMemcpyDeviceToDevice,
-                                         c->stream));
-            else
-                HIPCHK(c, fill(gA, NN, 0.0, c->stream));
-            const double sgn = t ? -1.0 : 1.0;
-            HIPCHK(c, dgemm_splitk(gm(N, N, (int)Ko, false, true, -0.5 * c->cx, Y1, Ko, Z2, Ko, 1.0, gA, N), ksp,
-                                   SK2, c->stream));
-            HIPCHK(c, dgemm_splitk(gm(N, N, (int)Ko, false, true, -0.5 * c->cx * sgn, Z1, Ko, Y2, Ko, 1.0, gA, N),
-                                   ksp, SK2, c->stream));
+            const double *gA = gAll + ((size_t)s * 2 + t) * NN;
             HIPCHK(c, dgemm(gm(N, nmo, N, false, false, 1.0, gA, N, c->C, nmo, 0.0, T1, nmo), c->stream));
             HIPCHK(c, dgemm(gm(nmo, nmo, N, true, false, 1.0, c->C, nmo, T1, nmo, 0.0, gM + ((size_t)s * 2 + t) * MM,
                                nmo), c->stream));

@@ -171,3 +171,23 @@ def test_chain200_blocked_equals_unblocked(ctx, radii):
     assert dmv <= 1e-12
     assert dg <= 1e-12
     assert np.abs(res[64][1][:2].sum(1)).max() <= 1e-10
+
+
+def test_chain200_zrhs_blocked_equals_unblocked(ctx, radii):
+    """The ris Z-vector right-hand side at the headline size with the
+    integrals recomputed in blocks of 64 auxiliary functions agrees with the
+    unblocked path to rounding (only the order of the sums over P changes)."""
+    import torch
+    prob = molgen.make_problem("chain200")
+    X = torch.as_tensor(prob.X, device=ctx.device)
+    Y = torch.as_tensor(prob.Y, device=ctx.device)
+    out = {}
+    for block in (0, 64):
+        ctx.set_blocking(block)
+        say(f"[gpu] chain200 zrhs, aux block {block}")
+        _gpu_problem(ctx, prob, radii, True)
+        out[block] = ctx.zrhs_contract(X, Y, [(0, 0), (2, 3)]).cpu().numpy()
+    ctx.set_blocking(0)
+    rel = np.abs(out[64] - out[0]).max() / np.abs(out[0]).max()
+    say(f"[gpu]   blocked vs unblocked rel {rel:.2e}")
+    assert rel <= 1e-12

@@ -1,6 +1,7 @@
 """Serving loop on the GPU: requests that overlap on the device give the same
 results as the same requests run alone (bitwise: each slot's work is the same
-kernels with ordered reductions), and every result matches the FP64 oracle."""
+kernels with ordered reductions), the results match the FP64 oracle, and so
+does the time-derivative coupling T_IJ = g_IJ . v the server returns."""
 import numpy as np
 import pytest
 
@@ -37,3 +38,8 @@ def test_alone_equals_mixed_and_oracle(radii):
     ref = O.grad_nac(prob, radii, [(0, 0), (1, 1), (0, 1)])
     got = np.concatenate([rm[0].grad, rm[0].nac])
     assert np.abs(got - ref).max() <= 1e-8
+    # the time-derivative coupling the server returns, T_01 = g_01 . v (Sec. 5.4),
+    # against the oracle's NAC numerator dotted with the request's velocities
+    t_ref = float(np.sum(ref[2] * r.velocity))
+    assert rm[0].tdc is not None and rm[0].tdc.shape == (1,)
+    assert abs(rm[0].tdc[0] - t_ref) <= 1e-8 * np.abs(r.velocity).sum()

@@ -36,14 +36,18 @@ CASES = [("ring12", lambda: molgen.make_problem("ring12"), False, [(0, 0), (1, 1
          ("chain12_tddft", lambda: molgen.make_chain_problem(12, 5, 3, tda=False), True, [(0, 0), (2, 2), (0, 1)])]
 
 
+@pytest.mark.parametrize("block", [0, 5])
 @pytest.mark.parametrize("name,make,jp,pairs", CASES, ids=[c[0] for c in CASES])
-def test_zrhs_vs_oracle_and_zvector(ctx, radii, name, make, jp, pairs):
+def test_zrhs_vs_oracle_and_zvector(ctx, radii, name, make, jp, pairs, block):
+    """block > 0: the integrals recomputed in blocks of at most 5 auxiliary
+    functions (whole shells), as at sizes whose (mu nu|P) does not fit."""
     import torch
     from oracle import ris_oracle as O
     prob = make()
     m = prob.mol
     dev = ctx.device
-    say(f"[gpu] zrhs {name}: aux_build + int3c")
+    ctx.set_blocking(block)
+    say(f"[gpu] zrhs {name}: aux_build + int3c (block {block})")
     ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
     ctx.int3c(torch.as_tensor(prob.C, device=dev), torch.as_tensor(prob.eps, device=dev), prob.nocc, 2.0, 0.25)
     X = torch.as_tensor(prob.X, device=dev)
@@ -64,6 +68,7 @@ def test_zrhs_vs_oracle_and_zvector(ctx, radii, name, make, jp, pairs):
     zerr = np.abs(Z.cpu().numpy() - Zref).max()
     say(f"[gpu]   {name}: Z-vector {it} iterations, max|dZ| {zerr:.2e} (max|Z| {np.abs(Zref).max():.2e})")
     assert zerr <= 1e-8 * np.abs(Zref).max()
+    ctx.set_blocking(0)
 
 
 def test_zrhs_errors(ctx, radii):
