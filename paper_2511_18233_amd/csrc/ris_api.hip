@@ -80,6 +80,12 @@ struct ris_ctx {
     AuxGeom aux{};
     int auxl_beg[kMaxAuxL + 2] = {0, 0, 0};
     int *d_ao_perm = nullptr;
+    // the forward integrals of ris_int3c and their MO transforms use a second
+    // AO order, the kernels' shell order (by l), so (mu nu|P) rows are written
+    // in whole runs; the result is in the MO basis, so only C's rows follow it
+    AOGeom ao_int{};
+    std::vector<int> h_ao_perm_int;  // integral-order function -> caller function
+    int *d_ao_perm_int = nullptr;
     double *MJ = nullptr, *LinvJ = nullptr, *MinvJ = nullptr, *MinvK = nullptr;
     // AO shell-pair screen of the derivative contraction (internal shell order)
     double screen = kDefaultScreen;
@@ -230,6 +236,8 @@ void free_aux(ris_ctx *c)
 {
     free_int3c(c);
     c->d_ao_perm = nullptr;
+    c->d_ao_perm_int = nullptr;
+    c->ao_int = AOGeom{};
     c->d_pair_ptr = c->d_pair_idx = nullptr;
     c->d_gtiles = nullptr;
     c->ngtiles = 0;
@@ -352,12 +360,18 @@ int build_pairs(ris_ctx *c)
     // lower 128-tiles touched by a kept pair (the relation is symmetric)
     const int N = c->nao, T = 128, tm = (N + T - 1) / T;
     const std::vector<int> &off = c->h_sh_off;
+    // functions of internal shell i: shells are sorted by l
+    auto shell_nf = [&](int i) {
+        int l = 0;
+        while (i >= c->ao.lbeg[l + 1]) ++l;
+        return ncart(l);
+    };
     std::vector<char> mark((size_t)tm * tm, 0);
     for (int a = 0; a < nsh; ++a)
         for (size_t q = ptr[(size_t)ncls * a]; q < (size_t)ptr[(size_t)ncls * (a + 1)]; ++q) {
             const int b = idx[q];
-            for (int ta = off[a] / T; ta <= (off[a + 1] - 1) / T; ++ta)
-                for (int tb = off[b] / T; tb <= (off[b + 1] - 1) / T; ++tb)
+            for (int ta = off[a] / T; ta <= (off[a] + shell_nf(a) - 1) / T; ++ta)
+                for (int tb = off[b] / T; tb <= (off[b] + shell_nf(b) - 1) / T; ++tb)
                     mark[(size_t)std::max(ta, tb) * tm + std::min(ta, tb)] = 1;
         }
     std::vector<int> tiles;
@@ -382,13 +396,65 @@ int build_pairs(ris_ctx *c)
 
 }  // namespace
 
+// Reverse Cuthill-McKee order of the atoms on the graph that joins two atoms
+// when the Gaussian product of their most diffuse shells, exp(-a b / (a + b)
+// |A - B|^2), is at least 1e-15 (a fixed threshold: the order does not depend
+// on the screen setting).  BFS from an unvisited atom of least degree,
+// neighbours by increasing degree, then reversed: a narrow band for chains and
+// other extended molecules.
+static std::vector<int> atom_band_order(const ris_mol *mol)
+{
+    const int n = mol->natm;
+    std::vector<double> amin(n, 1e300);
+    for (int s = 0; s < mol->nshell; ++s) amin[mol->shell_atom[s]] = std::min(amin[mol->shell_atom[s]], mol->shell_exp[s]);
+    std::vector<std::vector<int>> nb(n);
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            if (amin[i] > 1e299 || amin[j] > 1e299) continue;  // an atom without AO shells
+            double r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double t = mol->xyz[3 * i + d] - mol->xyz[3 * j + d];
+                r2 += t * t;
+            }
+            if (std::exp(-amin[i] * amin[j] / (amin[i] + amin[j]) * r2) >= 1e-15) {
+                nb[i].push_back(j);
+                nb[j].push_back(i);
+            }
+        }
+    std::vector<int> deg(n);
+    for (int i = 0; i < n; ++i) deg[i] = (int)nb[i].size();
+    auto by_degree = [&](int a, int b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; };
+    for (auto &v : nb) std::sort(v.begin(), v.end(), by_degree);
+    std::vector<int> out;
+    out.reserve(n);
+    std::vector<char> seen(n, 0);
+    while ((int)out.size() < n) {
+        int start = -1;
+        for (int i = 0; i < n; ++i)
+            if (!seen[i] && (start < 0 || by_degree(i, start))) start = i;
+        size_t head = out.size();
+        out.push_back(start);
+        seen[start] = 1;
+        while (head < out.size()) {
+            const int u = out[head++];
+            for (int w : nb[u])
+                if (!seen[w]) {
+                    seen[w] = 1;
+                    out.push_back(w);
+                }
+        }
+    }
+    std::reverse(out.begin(), out.end());
+    return out;
+}
+
 // ---- sizes of every device region, shared by the calls and ris_request_bytes
 struct Dims {
     int N, nmo, o, v, nJ, nK, nshAO, nshJ, natm;
 };
 
 struct MoLayout {
-    size_t oC, oE, oA, oOO, oVO, oVV, oROO, total;
+    size_t oC, oCI, oE, oA, oOO, oVO, oVV, oROO, total;
 };
 MoLayout mo_layout(const Dims &d)
 {
@@ -396,6 +462,7 @@ MoLayout mo_layout(const Dims &d)
     MoLayout L;
     const long vo = (long)d.v * d.o;
     L.oC = pv.take((size_t)d.N * d.nmo);
+    L.oCI = pv.take((size_t)d.N * d.nmo);  // C rows in the integral order (forward transforms)
     L.oE = pv.take(d.nmo);
     L.oA = pv.take((size_t)d.nJ * vo);
     L.oOO = pv.take((size_t)d.nK * d.o * d.o);
@@ -547,7 +614,7 @@ ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
 }
 
 struct AuxLayout {
-    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, oPP, oPI, oGT, total;
+    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, oPP, oPI, oGT, oOI, oPJ, total;
 };
 AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
 {
@@ -556,6 +623,8 @@ AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
     L.oAO = cv.take(shell_bytes(nsh) / 8 + 1);
     L.oAX = cv.take(shell_bytes(nshJ) / 8 + 1);
     L.oP = cv.take(nao / 2 + 1);
+    L.oOI = cv.take(nsh / 2 + 1);   // integral-order first functions (ints)
+    L.oPJ = cv.take(nao / 2 + 1);   // integral-order permutation (ints)
     L.oMJ = cv.take((size_t)nJ * nJ);
     L.oLJ = cv.take((size_t)nJ * nJ);
     L.oIJ = cv.take((size_t)nJ * nJ);
@@ -1171,17 +1240,43 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
     std::vector<int> caller_off(nsh + 1, 0);
     for (int s = 0; s < nsh; ++s) caller_off[s + 1] = caller_off[s] + ncart(mol->shell_l[s]);
     const int nao = caller_off[nsh];
-    std::vector<int> order;
-    for (int l = 0; l <= kMaxAOL; ++l) {
-        c->ao.lbeg[l] = (int)order.size();
-        for (int s = 0; s < nsh; ++s)
-            if (mol->shell_l[s] == l) order.push_back(s);
+    // AO function order of every matrix: atoms in reverse Cuthill-McKee order
+    // (each atom's shells in the caller's order), so that the shell pairs the
+    // screen keeps, and the 128 x 128 tiles of Gamma^P that hold them, gather
+    // near the diagonal.  The kernels' shell tables are sorted by l, and within
+    // one l by that atom order, so consecutive shells of a class have
+    // increasing first functions (writes and partner reads stay local).
+    std::vector<int> fofs(nsh, 0), order;
+    {
+        const std::vector<int> ord = atom_band_order(mol);
+        std::vector<std::vector<int>> by_atom(natm);
+        for (int s = 0; s < nsh; ++s) by_atom[mol->shell_atom[s]].push_back(s);
+        int g = 0;
+        for (int a : ord)
+            for (int s : by_atom[a]) {
+                fofs[s] = g;
+                g += ncart(mol->shell_l[s]);
+            }
+        for (int l = 0; l <= kMaxAOL; ++l) {
+            c->ao.lbeg[l] = (int)order.size();
+            for (int a : ord)
+                for (int s : by_atom[a])
+                    if (mol->shell_l[s] == l) order.push_back(s);
+        }
+        c->ao.lbeg[kMaxAOL + 1] = nsh;
     }
-    c->ao.lbeg[kMaxAOL + 1] = nsh;
     std::vector<double> x(nsh), y(nsh), z(nsh), e(nsh), nr(nsh);
     std::vector<int> at(nsh), off(nsh + 1);
     c->h_ao_perm.assign(nao, 0);
-    int f = 0;
+    std::vector<int> off_int(nsh + 1, 0);
+    c->h_ao_perm_int.assign(nao, 0);
+    for (int i = 0, g = 0; i < nsh; ++i) {
+        const int sc = order[i], l = mol->shell_l[sc];
+        off_int[i] = g;
+        for (int k = 0; k < ncart(l); ++k) c->h_ao_perm_int[g + k] = caller_off[sc] + k;
+        g += ncart(l);
+    }
+    off_int[nsh] = nao;
     for (int i = 0; i < nsh; ++i) {
         const int s = order[i], a = mol->shell_atom[s], l = mol->shell_l[s];
         x[i] = mol->xyz[3 * a];
@@ -1190,11 +1285,11 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         e[i] = mol->shell_exp[s];
         nr[i] = radial_norm(e[i], l);
         at[i] = a;
-        off[i] = f;
-        for (int k = 0; k < ncart(l); ++k) c->h_ao_perm[f + k] = caller_off[s] + k;
-        f += ncart(l);
+        off[i] = fofs[s];
+        for (int k = 0; k < ncart(l); ++k) c->h_ao_perm[fofs[s] + k] = caller_off[s] + k;
     }
-    off[nsh] = f;
+    int f = nao;
+    off[nsh] = nao;
     c->h_sh_off = off;
     c->h_sh_xyz.resize(3 * (size_t)nsh);
     for (int i = 0; i < nsh; ++i) {
@@ -1241,6 +1336,11 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         st1 = upload_shells(c, nshJ, ax, ay, az, ae, anr, aat, aoff, base + AL.oAX, &c->aux.sh);
         if (st1) return st1;
         c->d_ao_perm = (int *)(base + AL.oP);
+        c->d_ao_perm_int = (int *)(base + AL.oPJ);
+        HIPCHK(c, hipMemcpyAsync(base + AL.oOI, off_int.data(), 4 * (size_t)(nsh + 1), hipMemcpyHostToDevice,
+                                 c->stream));
+        c->ao_int = c->ao;  // the same shells, first functions in the integral order
+        c->ao_int.sh.off = (const int *)(base + AL.oOI);
         c->MJ = (double *)(base + AL.oMJ);
         c->LinvJ = (double *)(base + AL.oLJ);
         c->MinvJ = (double *)(base + AL.oIJ);
@@ -1265,6 +1365,8 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
     c->nsJ = natm;
 
     HIPCHK(c, hipMemcpyAsync(c->d_ao_perm, c->h_ao_perm.data(), sizeof(int) * nao, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_ao_perm_int, c->h_ao_perm_int.data(), sizeof(int) * nao, hipMemcpyHostToDevice,
+                             c->stream));
     {
         const int sp = build_pairs(c);
         if (sp) return sp;
@@ -1358,11 +1460,14 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
     double *X = (double *)(wsb + IW.oX), *Z = (double *)(wsb + IW.oZ);
     const size_t tmp_el = IW.total / 8;  // the whole region as scratch for the fits
 
-    // C rows into the internal (l-sorted) AO order
+    // C rows into the matrix order of the contraction, and into the integral
+    // order of the forward transforms (the kernels' shell order)
+    double *Cint = (double *)((char *)c->C - ML.oC + ML.oCI);
     HIPCHK(c, gather_rows(mo->C, c->C, c->d_ao_perm, N, nmo, nmo, c->stream));
+    HIPCHK(c, gather_rows(mo->C, Cint, c->d_ao_perm_int, N, nmo, nmo, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->eps, mo->eps, 8 * nmo, hipMemcpyDeviceToDevice, c->stream));
 
-    const double *CO = c->C, *CV = c->C + o;
+    const double *CO = Cint, *CV = Cint + o;
     const long oo = (long)o * o;
     // blocks of whole J shells [cs0, cs1) = functions [f0, f1); the K set is
     // the leading nK (s) functions, so a block holds K functions only below nK
@@ -1374,9 +1479,9 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
         const int f0 = shf[cs0], nb = shf[cs1] - f0, nbk = std::max(0, std::min(f0 + nb, nK) - f0);
         // (mu nu|P) for the block
         hipEvent_t t_int = stage_begin(c);
-        HIPCHK(c, launch_int3c(c->ao, c->aux, c->auxl_beg, c->boys, X, c->stream, cs0, cs1));
+        HIPCHK(c, launch_int3c(c->ao_int, c->aux, c->auxl_beg, c->boys, X, c->stream, cs0, cs1));
         stage_end(c, t_int, RIS_STAGE_INT3C, 0.0, 8.0 * (double)nb * NN);
-        if (dbg) HIPCHK(c, scatter_sq(X, dbg + (size_t)f0 * NN, c->d_ao_perm, N, nb, c->stream));
+        if (dbg) HIPCHK(c, scatter_sq(X, dbg + (size_t)f0 * NN, c->d_ao_perm_int, N, nb, c->stream));
         hipEvent_t t_mo = stage_begin(c);
         // Z^P = X^P C_O  [nb][N][o]
         GemmArgs g = gm(N, o, N, false, false, 1.0, X, N, CO, nmo, 0.0, Z, o);
