@@ -40,10 +40,9 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the Gamma back-transform GEMM (listed lower tiles) from the
 # FETCH_SIZE / WRITE_SIZE counter runs on the 199-atom workload (fetch scaled by
 # 2.0, write by 1.0 after a 1 GiB copy calibration), averaged over the 28
-# launches of a step (19 plain: 21.57 + 3.20 GB, 9 accumulating: 23.97 + 3.70 GB);
-# valid only for the GEMM source it was measured on (sha256 prefix; a later edit
-# that left the FP64 kernels' machine code identical keeps them valid); null otherwise.
-GAMMA_TRAFFIC = {"gemm_src_sha256": "3d476486cedb2d55", "workload": "chain200", "bytes_per_launch": 25.70e9}
+# launches of a step; valid only for the GEMM source it was measured on (sha256
+# prefix), null otherwise.
+GAMMA_TRAFFIC = {"gemm_src_sha256": "d1af00ef506489ee", "workload": "chain200", "bytes_per_launch": 17.80e9}
 
 
 def log(*a):
