@@ -362,12 +362,12 @@ def main():
     ap.add_argument("--serve", type=int, default=128,
                     help="requests of the serving replay (20-120 atoms; 0: skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
-    ap.add_argument("--zrhs", action="store_true",
-                    help="also time the ris Z-vector right-hand-side terms for the step's outputs")
-    ap.add_argument("--davidson", type=int, default=0,
-                    help="also time the TDA-ris Davidson solve for this many roots")
-    ap.add_argument("--zvector", type=int, default=0,
-                    help="also time the ris Z-vector solve for this many right-hand sides")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the timing of the rows beyond the step (Z-vector right-hand side, Davidson, MINRES)")
+    ap.add_argument("--davidson", type=int, default=10,
+                    help="roots of the timed TDA-ris Davidson solve (0: skip)")
+    ap.add_argument("--zvector", type=int, default=10,
+                    help="right-hand sides of the timed ris Z-vector solve (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
@@ -508,12 +508,13 @@ def main():
             log(f"[bench] {mode}: {rate:.2f} grads+NACs/s ({rate / value:.2f}x fp64), max|dgrad| "
                 f"{modes[mode]['max_abs_dgrad_vs_fp64']:.2e} max|dNAC| {modes[mode]['max_abs_dnac_vs_fp64']:.2e}")
         res["precision_modes"] = modes
-    if args.zrhs:
+    if not args.no_next and not big:
+        # the rows beyond the step, timed on the same workload (FP64)
         res["zrhs"] = zrhs_bench(ctx, prob, jp, radii, C, eps, X, Y, outs)
-    if args.davidson > 0:
-        res["davidson"] = davidson_bench(ctx, prob, jp, radii, C, eps, args.davidson)
-    if args.zvector > 0:
-        res["zvector"] = zvector_bench(ctx, prob, jp, radii, C, eps, args.zvector, 1e-8)
+        if args.davidson > 0:
+            res["davidson"] = davidson_bench(ctx, prob, jp, radii, C, eps, args.davidson, maxit=10)
+        if args.zvector > 0:
+            res["zvector"] = zvector_bench(ctx, prob, jp, radii, C, eps, args.zvector, 1e-8)
     ctx.close()
     if args.serve > 0:
         sv = serve_bench(args.serve, args.serve_slots, radii)
