@@ -34,6 +34,20 @@ int ris_test_dgemm(int M, int N, int K, int transA, int transB, double alpha, co
 int ris_test_gemm(int mode, int M, int N, int K, int transA, int transB, double alpha, const double *A, long lda,
                   long sA, const double *B, long ldb, long sB, double beta, double *C, long ldc, long sC, int batch);
 
+/* The split-BF16 product on pre-split operands (the kernel of the exchange
+ * weights' Y^P and Gamma^P products in the split modes): A (M x K) and B
+ * (N x K), FP64 device matrices with leading dimensions lda, ldb, are split
+ * into ns = 2 or 3 bf16 parts per element (of fl32(x)), then
+ * C = alpha A B^T + beta C (FP64, leading dimension ldc), or with
+ * out_planes != 0 (beta 0) the FP32 product is written as ns bf16 parts whose
+ * sum in FP64 is returned in C.  kband = w > 0 (K = 3w, B zero in its
+ * (1st row, 3rd k) and (3rd row, 1st k) w-blocks) skips those zero blocks;
+ * lower != 0 (M == N) computes the 128 x 128 tiles on or below the diagonal
+ * only, leaving C's other tiles untouched.  Allocates its own planes;
+ * synchronous.  1: invalid arguments, 7: device error. */
+int ris_test_pgemm(int ns, int M, int N, int K, double alpha, const double *A, long lda, const double *B, long ldb,
+                   double beta, double *C, long ldc, int kband, int lower, int out_planes);
+
 /* Eigen-decomposition of a small symmetric m x m matrix by the path's
  * one-workgroup Jacobi kernel (used for Davidson subspaces): A (device,
  * row-major, m x m) is replaced by the eigenvectors as rows, w (device, m)

@@ -95,7 +95,8 @@ struct ris_ctx {
     // the 128 x 128 lower tiles of an AO-pair matrix that hold a kept shell
     // pair (mt << 16 | nt): the exchange weights Gamma^P are formed only there
     std::vector<int> h_sh_off;  // first AO function of each internal shell (+ total)
-    int *d_gtiles = nullptr;
+    int *d_gtiles = nullptr;     // lower tiles row by row, then the same tiles column by column
+    int *d_gtiles_cm = nullptr;
     int ngtiles = 0;
     double gtile_lower = 0.0;  // elements on or below the diagonal inside those tiles
 
@@ -239,7 +240,7 @@ void free_aux(ris_ctx *c)
     c->d_ao_perm_int = nullptr;
     c->ao_int = AOGeom{};
     c->d_pair_ptr = c->d_pair_idx = nullptr;
-    c->d_gtiles = nullptr;
+    c->d_gtiles = c->d_gtiles_cm = nullptr;
     c->ngtiles = 0;
     c->MJ = c->LinvJ = c->MinvJ = c->MinvK = nullptr;
     c->ao = AOGeom{};
@@ -385,6 +386,12 @@ int build_pairs(ris_ctx *c)
             }
     c->ngtiles = (int)tiles.size();
     c->gtile_lower = lower;
+    // the same tiles column by column: launches whose per-P operand is B (the
+    // second half of a NAC) then meet each of its row panels in consecutive tiles
+    std::vector<int> tiles_cm(tiles);
+    std::stable_sort(tiles_cm.begin(), tiles_cm.end(), [](int a, int b) { return (a & 0xffff) < (b & 0xffff); });
+    tiles.insert(tiles.end(), tiles_cm.begin(), tiles_cm.end());
+    c->d_gtiles_cm = c->d_gtiles + c->ngtiles;
     HIPCHK(c, hipMemcpyAsync(c->d_pair_ptr, ptr.data(), 4 * ptr.size(), hipMemcpyHostToDevice, c->stream));
     if (!idx.empty())
         HIPCHK(c, hipMemcpyAsync(c->d_pair_idx, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, c->stream));
@@ -527,6 +534,14 @@ int vpq_splits(int nK)
     const int t = (nK + 127) / 128;
     return std::max(1, std::min(256, 1024 / (t * t)));
 }
+// doubles holding a reduced-precision copy of a rows x cols FP64 matrix: float
+// (FP32 mode) or the bf16 planes of the split modes (up to three 2-byte parts
+// per element of the padded width plane_ld(cols))
+size_t xcopy_doubles(size_t rows, long cols)
+{
+    return std::max((rows * cols + 1) / 2, (rows * plane_ld(cols) * 3 + 3) / 4);
+}
+
 struct ContractWs {
     size_t oR, oL, oRLT, oF, oD, otT, ocv, oTall, oHUO, oHOU, oHUU, oW, oHc, oY, oG, oV2, oSK, op3, op2, oshA, oshC,
         oshP, oFf, oWf, total;
@@ -552,10 +567,10 @@ ContractWs contract_ws(const Dims &d, int ns)
     L.oW = cv.take((size_t)d.nK * o3 * o3);
     // gathered H_UO / H_OU blocks ([P][i][j], four of them) and G of the metric weights
     L.oHc = cv.take((size_t)4 * d.nK * oo + (size_t)d.nK * d.nK);
-    L.oY = cv.take((size_t)d.nK * d.N * o3);
-    // FP32 copies of F_s and W^P for the FP32 mode (float elements, two per slot)
-    L.oFf = cv.take(((size_t)ns * d.N * o3 + 1) / 2);
-    L.oWf = cv.take(((size_t)d.nK * o3 * o3 + 1) / 2);
+    L.oY = cv.take(std::max((size_t)d.nK * d.N * o3, xcopy_doubles((size_t)d.nK * d.N, o3)));
+    // reduced-precision copies of F_s and W^P (W^P transposed in the planes)
+    L.oFf = cv.take(xcopy_doubles((size_t)ns * d.N, o3));
+    L.oWf = cv.take(xcopy_doubles((size_t)d.nK * o3, o3));
     L.oG = cv.take((size_t)NO * d.nK * NN);
     L.oV2 = cv.take((size_t)NO * d.nJ * d.nJ);
     L.oSK = cv.take(std::max((size_t)kSplitV * ns * d.nJ, (size_t)vpq_splits(d.nK) * d.nK * d.nK));
@@ -585,7 +600,7 @@ ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
     L.oL = cv.take((size_t)ns * vo);
     L.oRLT = cv.take((size_t)d.v * w2);
     L.oF = cv.take((size_t)ns * d.N * o3);
-    L.oFf = cv.take(((size_t)ns * d.N * o3 + 1) / 2);
+    L.oFf = cv.take(xcopy_doubles((size_t)ns * d.N, o3));
     L.oD = cv.take((size_t)ns * NN);
     L.otT = cv.take((size_t)ns * d.nJ);
     L.ocv = cv.take((size_t)ns * d.nJ);
@@ -606,8 +621,8 @@ ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
     L.oTall = cv.take((size_t)nb * d.v * 2 * d.o);
     L.oHUU = cv.take((size_t)2 * nb * oo);
     L.oW = cv.take((size_t)nb * o3 * o3);
-    L.oWf = cv.take(((size_t)nb * o3 * o3 + 1) / 2);
-    L.oY = cv.take((size_t)nb * d.N * o3);
+    L.oWf = cv.take(xcopy_doubles((size_t)nb * o3, o3));
+    L.oY = cv.take(std::max((size_t)nb * d.N * o3, xcopy_doubles((size_t)nb * d.N, o3)));
     L.oG = cv.take((size_t)nb * NN);
     L.total = cv.off;
     return L;
@@ -634,7 +649,7 @@ AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
     L.oPI = cv.take(((size_t)nsh * nsh + 1) / 2);
     // lower-tile list of the AO-pair matrix (ints, 2 per slot)
     const size_t tm = (size_t)(nao + 127) / 128;
-    L.oGT = cv.take((tm * (tm + 1) / 2 + 1) / 2);
+    L.oGT = cv.take((tm * (tm + 1) + 1) / 2);  // two orders of the list
     L.total = cv.off;
     return L;
 }
@@ -1661,16 +1676,97 @@ int ris_response_matvec_noalloc(ris_ctx *c, int op, int nvec, const double *V, d
     return matvec_run(c, op, nvec, V, out, (char *)c->scratch_dev, chunk, false);
 }
 
+// Parts per element of the split-BF16 modes (0: no planes)
+static int plane_parts(const ris_ctx *c)
+{
+    return c->prec == RIS_BF16X3 ? 2 : c->prec == RIS_BF16X6 ? 3 : 0;
+}
+
+// The reduced-precision copy of the per-state factors F (ns x N x 3o): float
+// in the FP32 mode, bf16 planes (part stride ns N plane_ld(3o)) in the split modes.
+static hipError_t reduced_f(ris_ctx *c, const double *F, int ns, float *Ff)
+{
+    const long o3 = 3L * c->nocc, N = c->nao, ldp = plane_ld(o3);
+    if (c->prec == RIS_FP32) return to_float(F, Ff, (size_t)ns * N * o3, c->stream);
+    if (const int np = plane_parts(c))
+        return split_planes(F, (int)N, (int)o3, o3, N * o3, ns, (uint16_t *)Ff, ns * N * ldp, N * ldp, np, c->stream);
+    return hipSuccess;
+}
+
+// state s of reduced_f's copy
+static const float *f_state(const ris_ctx *c, const float *Ff, int s)
+{
+    const long o3 = 3L * c->nocc, N = c->nao;
+    if (plane_parts(c)) return (const float *)((const uint16_t *)Ff + s * N * plane_ld(o3));
+    return Ff + s * N * o3;
+}
+
+// W^P for nP exchange functions: FP64 (W) in the FP64 mode, float (Wf) in the
+// FP32 mode, planes of W^P transposed (in Wf's region) in the split modes.
+static hipError_t assemble_w(ris_ctx *c, const BlockGrid &gw, double *W, float *Wf, int nP)
+{
+    const int o = c->nocc;
+    if (c->prec == RIS_FP64) return assemble3(gw, W, o, nP, c->stream, nullptr);
+    if (c->prec == RIS_FP32) return assemble3(gw, nullptr, o, nP, c->stream, Wf);
+    const long o3 = 3L * o;
+    return assemble3_planes(gw, (uint16_t *)Wf, o, nP, nP * o3 * plane_ld(o3), plane_parts(c), c->stream);
+}
+
 // Y^P = F_I W^P and the exchange weights Gamma^P for nP auxiliary functions:
-// Gamma^P = -2 c_x Y^P F_I^T (same state) or -c_x (Y^P F_J^T + F_J Y^P^T);
-// only the lower triangle of each symmetric Gamma^P is formed (and read).  In
-// the FP32 mode the products take the float copies FfI / FfJ / Wf and Y is float.
+// Gamma^P = -2 c_x Y^P F_I^T (same state) or -c_x (Y^P F_J^T + F_J Y^P^T).
+// Only the lower tiles of each symmetric Gamma^P are formed (and the lower
+// triangle read).  FI, FJ: the FP64 factors; FfI, FfJ: their
+// reduced copies (reduced_f; in the split modes the planes of state I and J,
+// part stride fps); W / Wf as assemble_w leaves them; Y3 holds Y^P (FP64,
+// float or planes).
 static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, const double *FJ, const float *FfI,
-                          const float *FfJ, const double *W, const float *Wf, double *Y3, double *Gk, bool same)
+                          const float *FfJ, long fps, const double *W, const float *Wf, double *Y3, double *Gk,
+                          bool same)
 {
     const long o3 = 3L * o, NN = (long)N * N;
-    // FP32 and split-BF16 modes: F, W and Y as float (both round them to FP32 first)
-    const bool f32 = c->prec != RIS_FP64;
+    const int np = plane_parts(c);
+    // one timed group per GEMM launch; a lower-tile launch does
+    // nP N (N + 1) 3o flops and moves Y, F_J (reduced in the reduced modes)
+    // and the lower half of Gamma (always double)
+    // only the lower tiles that hold a kept AO shell pair (the derivative
+    // contraction reads Gamma nowhere else); the flops and bytes counted are
+    // those of the lower-triangle elements inside them
+    const double fl_low = 2.0 * nP * c->gtile_lower * o3;
+    const double ein = c->prec == RIS_FP64 ? 8.0 : np ? 2.0 * np : 4.0;
+    const double by_low = ein * ((double)nP * N * o3 + (double)N * o3) + 8.0 * nP * c->gtile_lower;
+    if (np) {
+        // split modes on the planes: A and B k-fast, K the padded width
+        const long ldp = plane_ld(o3), yps = nP * N * ldp;
+        const uint16_t *PI = (const uint16_t *)FfI, *PJ = (const uint16_t *)FfJ, *PW = (const uint16_t *)Wf;
+        uint16_t *PY = (uint16_t *)Y3;
+        PGemmArgs p{};
+        p.M = N; p.N = (int)o3; p.K = (int)ldp; p.ns = np;
+        p.A = PI; p.lda = ldp; p.psA = fps; p.sA = 0;
+        p.B = PW; p.ldb = ldp; p.psB = nP * o3 * ldp; p.sB = o3 * ldp;
+        p.alpha = 1.0;
+        p.Cp = PY; p.ldc = ldp; p.psC = yps; p.sC = N * ldp;
+        p.batch = nP; p.kband = o;
+        hipEvent_t t_y = stage_begin(c);
+        HIPCHK(c, pgemm(p, c->stream));
+        stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nP * N * o3 * o3, 0.0);
+        for (int h = 0; h < (same ? 1 : 2); ++h) {
+            p = PGemmArgs{};
+            p.M = N; p.N = N; p.K = (int)ldp; p.ns = np;
+            // h = 0: Y^P F_J^T; h = 1: + F_J Y^P^T
+            p.A = h ? PJ : PY; p.lda = ldp; p.psA = h ? fps : yps; p.sA = h ? 0 : N * ldp;
+            p.B = h ? PY : PJ; p.ldb = ldp; p.psB = h ? yps : fps; p.sB = h ? N * ldp : 0;
+            p.alpha = (same ? -2.0 : -1.0) * c->cx;
+            p.beta = h ? 1.0 : 0.0;
+            p.C = Gk; p.ldc = N; p.sC = NN;
+            p.batch = nP; p.lower = true; p.tiles = h ? c->d_gtiles_cm : c->d_gtiles; p.ntiles = c->ngtiles;
+            hipEvent_t t_g = stage_begin(c);
+            HIPCHK(c, pgemm(p, c->stream));
+            stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low + (h ? 8.0 * nP * c->gtile_lower : 0.0));
+        }
+        return RIS_OK;
+    }
+    // FP64 and FP32 modes: F, W and Y as double or float (FP32 rounds them first)
+    const bool f32 = c->prec == RIS_FP32;
     float *Y3f = (float *)Y3;
     GemmArgs g = gm(N, (int)o3, (int)o3, false, false, 1.0, FI, o3, W, o3, 0.0, Y3, o3);
     g.batch = nP; g.strideA = 0; g.strideB = o3 * o3; g.strideC = (long)N * o3;
@@ -1687,15 +1783,6 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
     hipEvent_t t_y = stage_begin(c);
     HIPCHK(c, gemm_mp(g, c->prec, c->stream));
     stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nP * N * o3 * o3, 0.0);
-    // one timed group per GEMM launch; a lower-tile launch does
-    // nP N (N + 1) 3o flops and moves Y, F_J (float in the FP32 mode)
-    // and the lower half of Gamma (always double)
-    // only the lower tiles that hold a kept AO shell pair (the derivative
-    // contraction reads Gamma nowhere else); the flops and bytes counted are
-    // those of the lower-triangle elements inside them
-    const double fl_low = 2.0 * nP * c->gtile_lower * o3;
-    const double ein = f32 ? 4.0 : 8.0;
-    const double by_low = ein * ((double)nP * N * o3 + (double)N * o3) + 8.0 * nP * c->gtile_lower;
     if (same) {
         g = gm(N, N, (int)o3, false, true, -2.0 * c->cx, Y3, o3, FJ, o3, 0.0, Gk, N);
         g.batch = nP; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN; g.lower = true;
@@ -1722,7 +1809,7 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
         stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low);
         g = gm(N, N, (int)o3, false, true, -c->cx, FJ, o3, Y3, o3, 1.0, Gk, N);
         g.batch = nP; g.strideA = 0; g.strideB = (long)N * o3; g.strideC = NN; g.lower = true;
-        g.tiles = c->d_gtiles; g.ntiles = c->ngtiles;
+        g.tiles = f32 ? c->d_gtiles_cm : c->d_gtiles; g.ntiles = c->ngtiles;
         if (f32) {
             g.A = (const double *)FfJ;
             g.B = (const double *)Y3f;
@@ -1766,7 +1853,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
            *TR = P_(CW.oTR), *G1 = P_(CW.oG1), *V2 = P_(CW.oV2), *SK = P_(CW.oSK), *p3 = P_(CW.op3),
            *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP), *Tall = P_(CW.oTall),
            *HUU = P_(CW.oHUU), *W = P_(CW.oW), *Y3 = P_(CW.oY), *G = P_(CW.oG);
-    const bool f32 = c->prec != RIS_FP64;
+    // reduced-precision copies of F and W^P (reduced_f, assemble_w)
     float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
     const double *CO = c->C, *CV = c->C + o;
 
@@ -1785,7 +1872,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
         for (int s = 0; s < ns; ++s)
             HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
                                        hipMemcpyDeviceToDevice, c->stream));
-        if (f32) HIPCHK(c, to_float(F, Ff, (size_t)ns * N * o3, c->stream));
+        HIPCHK(c, reduced_f(c, F, ns, Ff));
         g = gm(N, N, o, false, true, 1.0, F, o3, CO, nmo, 0.0, D, N);
         g.batch = ns; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
         HIPCHK(c, dgemm(g, c->stream));
@@ -1888,7 +1975,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                 gw.b[1][0][0] = sc(HRuo, 0.25); gw.b[1][1][0] = sc(HRuu, 0.25);  gw.b[1][2][0] = sc(HLuo, -0.25);
                 gw.b[1][1][1] = sc(HLuu, 0.25);
                 gw.b[2][0][0] = none;           gw.b[2][1][0] = sc(HLou, -0.25); gw.b[2][2][0] = sc(Hoo, 0.25);
-                HIPCHK(c, assemble3(gw, W, o, m, c->stream, f32 ? Wf : nullptr));
+                HIPCHK(c, assemble_w(c, gw, W, Wf, m));
                 stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 9.0 * (double)oo * m);
                 // G rows of the block: <H_RUU^P + H_LUU^P, c_oo^Q>
                 double *G1q = G1 + (size_t)q * nK * nK;
@@ -1901,7 +1988,8 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                                               oo, t ? 1.0 : 0.0, G1q + (size_t)p0 * nK, nK), bsplit, SK, c->stream));
                 stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)m * nK * oo, 0.0);
                 const int rr = gamma_products(c, N, o, m, F + (size_t)I * N * o3, F + (size_t)J * N * o3,
-                                              Ff + (size_t)I * N * o3, Ff + (size_t)J * N * o3, W, Wf, Y3, G, I == J);
+                                              f_state(c, Ff, I), f_state(c, Ff, J), ns * N * plane_ld(o3), W, Wf,
+                                              Y3, G, I == J);
                 if (rr != RIS_OK) return rr;
                 // derivative contraction over the block's (s) shells, Coulomb part
                 // included, into the partial slot q of the group
@@ -2001,7 +2089,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
            *p3 = P_(CW.op3), *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP);
     // FP32 and split-BF16 modes: F, W and Y stored as float for the two products
     // that build Gamma (both kernels round the operands to FP32 first: same results)
-    const bool f32 = c->prec != RIS_FP64;
+    // reduced-precision copies of F and W^P (reduced_f, assemble_w)
     float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
     const double *CO = c->C, *CV = c->C + o;
 
@@ -2022,7 +2110,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         for (int s = 0; s < ns; ++s)
             HIPCHK(c, hipMemcpy2DAsync(F + (size_t)s * N * o3 + o, o3 * 8, CO, (size_t)nmo * 8, (size_t)o * 8, N,
                                        hipMemcpyDeviceToDevice, c->stream));
-        if (f32) HIPCHK(c, to_float(F, Ff, (size_t)ns * N * o3, c->stream));
+        HIPCHK(c, reduced_f(c, F, ns, Ff));
         // D_s = sym(U_Rs C_O^T) = R^S_s
         g = gm(N, N, o, false, true, 1.0, F, o3, CO, nmo, 0.0, D, N);
         g.batch = ns; g.strideA = (long)N * o3; g.strideB = 0; g.strideC = NN;
@@ -2094,7 +2182,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             gw.b[1][0][0] = sc(HRuo, 0.25); gw.b[1][1][0] = sc(HRuu, 0.25);  gw.b[1][2][0] = sc(HLuo, -0.25);
             gw.b[1][1][1] = sc(HLuu, 0.25);
             gw.b[2][0][0] = none;           gw.b[2][1][0] = sc(HLou, -0.25); gw.b[2][2][0] = sc(Hoo, 0.25);
-            HIPCHK(c, assemble3(gw, W, o, nK, c->stream, f32 ? Wf : nullptr));
+            HIPCHK(c, assemble_w(c, gw, W, Wf, nK));
             stage_end(c, t_yw, RIS_STAGE_YW, 0.0, 8.0 * 9.0 * (double)oo * nK);
             hipEvent_t t_v = stage_begin(c);
             // metric weights: W2 = -alpha_J c_I c_J^T + c_x V with V_PQ = sum_kl H^P_kl W^Q_kl
@@ -2121,7 +2209,8 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             double *Gk = G + (size_t)k * nK * NN;
             {
                 const int r = gamma_products(c, N, o, nK, F + (size_t)I * N * o3, F + (size_t)J * N * o3,
-                                             Ff + (size_t)I * N * o3, Ff + (size_t)J * N * o3, W, Wf, Y3, Gk, I == J);
+                                             f_state(c, Ff, I), f_state(c, Ff, J), ns * N * plane_ld(o3), W, Wf,
+                                             Y3, Gk, I == J);
                 if (r != RIS_OK) return r;
             }
         }

@@ -135,6 +135,40 @@ hipError_t bgemm_kc(const GemmArgs &g, int kc, hipStream_t st, int nparts = 2);
 // into ranges of kc indexed by the batch (ris_gemm.hip).
 hipError_t gemm_kc(const GemmArgs &g, int mode, int kc, hipStream_t st);
 
+// Split-BF16 operands kept pre-split ("planes"): the FP32 value x32 of every
+// element as ns bf16 parts (ns = 2: hi, lo; ns = 3: hi, mid, lo; the parts of
+// the split-BF16 GEMM), part p of a rows x cols matrix at base + p * ps, each
+// part rows x plane_ld(cols) with the padding columns zero (the width padded
+// to whole k-slabs of 32).
+constexpr long plane_ld(long cols) { return (cols + 31) & ~31L; }
+// C_b = alpha * A_b B_b^T (+ beta * C_b) for b < batch with both operands
+// k-fast planes: A_b M x K, B_b N x K (K a multiple of 32, the padded width).
+// Output either FP64 (C, ldc, sC) or, with Cp set, planes of the FP32
+// product (Cp, ldc, psC, sC; columns [N, ldc) written zero; beta 0).
+// kband = w > 0: B's rows and K are three blocks of w with B zero in its
+// (1st row, 3rd k) and (3rd row, 1st k) blocks (see GemmArgs).
+struct PGemmArgs {
+    int M, N, K, ns;
+    const uint16_t *A;
+    long lda, psA, sA;
+    const uint16_t *B;
+    long ldb, psB, sB;
+    double alpha, beta;
+    double *C;
+    uint16_t *Cp;
+    long ldc, psC, sC;
+    int batch, kband;
+    bool lower;
+    const int *tiles;
+    int ntiles;
+};
+hipError_t pgemm(const PGemmArgs &g, hipStream_t st);
+// Planes (ns parts, leading dimension plane_ld(cols), parts ps apart) of the
+// batch x rows x cols FP64 matrices x (leading dimension ldx, batch stride sx)
+// into dst (batch stride sdst).
+hipError_t split_planes(const double *x, int rows, int cols, long ldx, long sx, int batch, uint16_t *dst, long ps,
+                        long sdst, int ns, hipStream_t st);
+
 // Dense linear algebra on small matrices (ris_linalg.hip).
 // In-place Cholesky of the n x n SPD matrix (lower triangle written, upper
 // zeroed); *info (device int) = 0 or the 1-based failing column.  A pivot

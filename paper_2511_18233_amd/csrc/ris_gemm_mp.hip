@@ -20,8 +20,10 @@
 // D[4(l/16) + e][l%16] to accumulator element e (rows in blocks of four, unlike
 // the interleaved rows of the FP64 instruction).
 #include <algorithm>
+#include <type_traits>
 
 #include "ris_common.hpp"
+#include "ris_linalg.hpp"
 
 namespace ris {
 namespace {
@@ -39,7 +41,7 @@ constexpr int PAD2 = 8;  // bf16 elements; keeps 16-byte alignment of each LDS r
 // contiguous range; lower: the tiles mt >= nt of a square grid, row by row;
 // otherwise groups of GROUP_M m-tiles with the n-tile as the slower index.
 __device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool lower, const int *tiles, int &z,
-                                        int &mt, int &nt)
+                                        int &mt, int &nt, int group = GROUP_M)
 {
     const int q = total / NXCD, r = total % NXCD;
     const int xcd = b % NXCD, local = b / NXCD;
@@ -65,10 +67,10 @@ __device__ __forceinline__ void tile_of(int b, int total, int tm, int tn, bool l
     const int per = tm * tn;
     z = lin / per;
     const int t = lin % per;
-    const int gsz = GROUP_M * tn;
+    const int gsz = group * tn;
     const int g = t / gsz, tg = t % gsz;
-    const int m0 = g * GROUP_M;
-    const int gm = min(GROUP_M, tm - m0);
+    const int m0 = g * group;
+    const int gm = min(group, tm - m0);
     mt = m0 + tg % gm;
     nt = tg / gm;
 }
@@ -317,7 +319,307 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
 }
 
+// ------------------------------------------------ pre-split operands --
+// The same products on operands already held as bf16 planes (PGemmArgs),
+// both k-fast: 128 x 128 tiles, 4 waves of 64 x 64, k-slabs of 32.  Per slab
+// and operand a thread moves 2 ns chunks of 16 bytes (8 consecutive k of one
+// row of one part; four threads cover a row's 32 k) from global memory
+// through registers into LDS; two register sets keep the loads of slab
+// it + 2 in flight while slab it is multiplied.  K and the band bounds are
+// multiples of 32 (the planes' padded width, zero past the logical one), so
+// every slab is whole and the loop has no tail.  Rows past M or N are read
+// clamped and never stored.  LDS rows are swizzled (swz).  The products and
+// their order per slab are those of k_bgemm3.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// LDS rows of 32 bf16 (64 bytes, unpadded) hold their four 16-byte chunks in
+// the order c ^ swz(r): with it both the fragment reads (lane l: row l % 16,
+// chunk l / 16) and the staging writes (lane l: row l / 4, chunk l % 4) are
+// free of bank conflicts on gfx950 (measured with the LDS conflict counter;
+// plain rows and rows padded to 80 bytes conflict on the reads).
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
+
+template <int NS, bool OUTP, bool BETA>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pgemm(PGemmArgs g, int tm,
+                                                                                          int tn, int total)
+{
+    // [stage][A, B][part][row][k], 16-byte chunk c of row r at chunk c ^ swz(r)
+    __shared__ __attribute__((aligned(16))) uint16_t S[2][2][NS][BM][BK2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int bz, mt, nt;
+    // full grids: groups of 8 m-tiles per sweep of the n-tiles, so a B panel
+    // (W^P of the Y product) is fetched once per 8 row panels of A
+    tile_of(blockIdx.x, total, tm, tn, g.lower, g.tiles, bz, mt, nt, 8);
+    const int m0 = mt * BM, n0 = nt * BN;
+    int kbeg = 0, kend = g.K;
+    if (g.kband > 0) {  // whole slabs: the bounds rounded outward into B's zero blocks
+        const int w = g.kband;
+        if (n0 >= 2 * w) kbeg = w & ~(BK2 - 1);
+        if (n0 + BN <= w) kend = min(g.K, (2 * w + BK2 - 1) & ~(BK2 - 1));
+    }
+    const char *A = reinterpret_cast<const char *>(g.A + (long)bz * g.sA);
+    const char *B = reinterpret_cast<const char *>(g.B + (long)bz * g.sB);
+    const long psA = 2 * g.psA, psB = 2 * g.psB;  // bytes
+
+    // chunk q < 2 of this thread: row 64 q + tid / 4, k-offset kq (stored at
+    // kqs: rows 64 q + tid / 4 share their swizzle)
+    const int kq = 8 * (tid & 3), kqs = 8 * ((tid & 3) ^ swz(tid >> 2));
+    int rq[2];
+    unsigned offA[2], offB[2];  // byte offsets of (row, kq) from the operand base
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        rq[q] = 64 * q + (tid >> 2);
+        offA[q] = (unsigned)(((long)min(m0 + rq[q], g.M - 1) * g.lda + kq) * 2);
+        offB[q] = (unsigned)(((long)min(n0 + rq[q], g.N - 1) * g.ldb + kq) * 2);
+    }
+    // two register sets of staged chunks: slab it + 2 is loaded while slab it
+    // is multiplied and slab it + 1 waits in the other set
+    v4u xa[2][NS][2], xb[2][NS][2];
+    typedef std::integral_constant<int, 0> S0_;
+    typedef std::integral_constant<int, 1> S1_;
+    // slab s into register set SET (every slab is whole: K and the band
+    // bounds are multiples of 32)
+    auto load_slab = [&](auto set, int s) {
+        constexpr int SET = decltype(set)::value;
+        const long k0 = kbeg + (long)s * BK2;
+        const char *a = A + 2 * k0, *b = B + 2 * k0;
+#pragma unroll
+        for (int p = 0; p < NS; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                xa[SET][p][q] = *reinterpret_cast<const v4u *>(a + p * psA + offA[q]);
+                xb[SET][p][q] = *reinterpret_cast<const v4u *>(b + p * psB + offB[q]);
+            }
+    };
+    // set SET into LDS stage SET (slab s sits in set s % 2 and stage s % 2)
+    auto store = [&](auto set) {
+        constexpr int SET = decltype(set)::value;
+#pragma unroll
+        for (int p = 0; p < NS; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                *reinterpret_cast<v4u *>(&S[SET][0][p][rq[q]][kqs]) = xa[SET][p][q];
+                *reinterpret_cast<v4u *>(&S[SET][1][p][rq[q]][kqs]) = xb[SET][p][q];
+            }
+    };
+
+    v4f acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    // fragment rows start at multiples of 16, so their swizzle is that of lane & 15
+    const int kofs = 8 * ((lane >> 4) ^ swz(lane & 15));
+    const int nslab = kend > kbeg ? (kend - kbeg + BK2 - 1) / BK2 : 0;
+    // slab it from LDS stage CUR = it % 2
+    auto slab = [&](int it, auto cur) {
+        constexpr int CUR = decltype(cur)::value;
+        constexpr int NXT = 1 - CUR;
+        typedef std::integral_constant<int, NXT> N_;
+        // slab it + 2 into the set slab it left (stored to LDS one slab ago);
+        // its global loads go out first, ahead of this slab's work (the last
+        // two slabs reload the last one: in bounds, never stored)
+        load_slab(cur, min(it + 2, nslab - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        // fragments in the order the products use them: the parts of product 0
+        // (hi of A, lo of B), then lo of A and hi of B, then mid (NS = 3)
+        v8bf fa_[NS][4], fb_[NS][4];
+        constexpr int pa_[3] = {0, NS - 1, 1}, pb_[3] = {NS - 1, 0, 1};
+#pragma unroll
+        for (int h = 0; h < NS; ++h) {
+            const int p = pa_[h], q = pb_[h];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                fa_[p][i] = *reinterpret_cast<const v8bf *>(&S[CUR][0][p][wm * 64 + i * 16 + (lane & 15)][kofs]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                fb_[q][j] = *reinterpret_cast<const v8bf *>(&S[CUR][1][q][wn * 64 + j * 16 + (lane & 15)][kofs]);
+        }
+        constexpr int NP = NS == 2 ? 3 : 6;
+#pragma unroll
+        for (int u = 0; u < NP; ++u)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_[part_a<NS>(u)][i], fb_[part_b<NS>(u)][j],
+                                                                        acc[i][j], 0, 0, 0);
+        // slab it + 1 into the other stage, last read in slab it - 1 (before
+        // the barrier that ended it), after every MFMA of this slab
+        __builtin_amdgcn_sched_barrier(0);
+        if (it + 1 < nslab) store(N_{});
+        __syncthreads();
+    };
+    if (nslab > 0) {
+        load_slab(S0_{}, 0);
+        store(S0_{});
+        load_slab(S1_{}, min(1, nslab - 1));
+    }
+    __syncthreads();
+    int it = 0;
+    for (; it + 1 < nslab; it += 2) {
+        slab(it, S0_{});
+        slab(it + 1, S1_{});
+    }
+    if (it < nslab) slab(it, S0_{});
+
+    const float falpha = (float)g.alpha;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
+                if constexpr (OUTP) {
+                    if (row < g.M && col < g.ldc) {
+                        __bf16 t[NS];
+                        split_bf16<NS>(acc[i][j][e], col < g.N ? falpha : 0.0f, t);
+                        uint16_t *cp = g.Cp + (long)bz * g.sC + (long)row * g.ldc + col;
+#pragma unroll
+                        for (int p = 0; p < NS; ++p) cp[p * g.psC] = __builtin_bit_cast(uint16_t, t[p]);
+                    }
+                } else {
+                    if (row < g.M && col < g.N) {
+                        double *cp = g.C + (long)bz * g.sC + (long)row * g.ldc + col;
+                        double v = g.alpha * (double)acc[i][j][e];
+                        if constexpr (BETA) v += g.beta * *cp;
+                        *cp = v;
+                    }
+                }
+            }
+        }
+}
+
+// ns bf16 parts of fl32(x) per element (split_bf16), zero in the padding columns
+template <int NS>
+__global__ void k_split_planes(const double *__restrict__ x, int rows, int cols, long ldx, long sx,
+                               uint16_t *__restrict__ dst, long ps, long sdst, long ldp)
+{
+    const long n = (long)rows * ldp;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const int b = blockIdx.y;
+    const int r = (int)(idx / ldp), cidx = (int)(idx - (long)r * ldp);
+    const double v = cidx < cols ? x[(long)b * sx + (long)r * ldx + cidx] : 0.0;
+    __bf16 t[NS];
+    split_bf16<NS>(v, 1.0f, t);
+    uint16_t *d = dst + (long)b * sdst + idx;
+#pragma unroll
+    for (int p = 0; p < NS; ++p) d[p * ps] = __builtin_bit_cast(uint16_t, t[p]);
+}
+
+// Planes of W^T for a 3 x 3 block assembly (k_assemble3's sources): one
+// workgroup per 64 x 64 tile of W and matrix P, read along W's rows into LDS
+// and written along W^T's rows; rows [3o, plane_ld(3o)) of W^T's columns
+// (the padding) are written zero.
+template <int NS>
+__global__ void k_assemble3_planes(BlockGrid g, uint16_t *__restrict__ Wt, int o, long ps)
+{
+    __shared__ float T[64][65];
+    const int n3 = 3 * o;
+    const long ldp = plane_ld(n3);
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64, P = blockIdx.z;
+    const int tid = threadIdx.x;
+#pragma unroll 4
+    for (int k = 0; k < 16; ++k) {
+        const int rr = 4 * k + (tid >> 6), cc = tid & 63;
+        const int r = r0 + rr, cidx = c0 + cc;
+        double v = 0.0;
+        if (r < n3 && cidx < n3) {
+            const int bi = r / o, bj = cidx / o, i = r - bi * o, j = cidx - bj * o;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const BlockSrc b = g.b[bi][bj][t];
+                if (b.base) v += b.scale * b.base[P * b.sP + (long)i * b.si + (long)j * b.sj];
+            }
+        }
+        T[rr][cc] = (float)v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < 16; ++k) {
+        const int cc = 4 * k + (tid >> 6), rr = tid & 63;
+        const int r = r0 + rr, cidx = c0 + cc;
+        if (cidx < n3 && r < ldp) {
+            __bf16 t[NS];
+            split_bf16<NS>(T[rr][cc], 1.0f, t);
+            uint16_t *d = Wt + ((long)P * n3 + cidx) * ldp + r;
+#pragma unroll
+            for (int p = 0; p < NS; ++p) d[p * ps] = __builtin_bit_cast(uint16_t, t[p]);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t assemble3_planes(const BlockGrid &g, uint16_t *Wt, int o, int nP, long ps, int ns, hipStream_t st)
+{
+    if (o <= 0 || nP <= 0) return hipSuccess;
+    if ((ns != 2 && ns != 3) || nP > 65535) return hipErrorInvalidValue;
+    const long n3 = 3L * o, ldp = plane_ld(n3);
+    dim3 grid((unsigned)((n3 + 63) / 64), (unsigned)((ldp + 63) / 64), (unsigned)nP);
+    if (ns == 2) hipLaunchKernelGGL(k_assemble3_planes<2>, grid, dim3(256), 0, st, g, Wt, o, ps);
+    else hipLaunchKernelGGL(k_assemble3_planes<3>, grid, dim3(256), 0, st, g, Wt, o, ps);
+    return hipGetLastError();
+}
+
+hipError_t pgemm(const PGemmArgs &g, hipStream_t st)
+{
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    if ((g.ns != 2 && g.ns != 3) || g.K <= 0 || g.K % BK2 || g.lda % 8 || g.ldb % 8 || g.lda < g.K ||
+        g.ldb < g.K || g.psA % 8 || g.psB % 8 || g.sA % 8 || g.sB % 8 || !g.A || !g.B ||
+        (reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B)) % 16)
+        return hipErrorInvalidValue;
+    if (g.Cp ? (g.beta != 0.0 || g.lower || g.ldc < g.N || g.C) : !g.C) return hipErrorInvalidValue;
+    if (g.kband > 0 && (g.lower || g.K != plane_ld(3L * g.kband))) return hipErrorInvalidValue;
+    // 32-bit byte offsets of the rows from the operand base
+    if (((long)(g.M - 1) * g.lda + g.K) * 2 >= (1L << 32) || ((long)(g.N - 1) * g.ldb + g.K) * 2 >= (1L << 32))
+        return hipErrorInvalidValue;
+    const int tm = (g.M + BM - 1) / BM;
+    int tn = (g.N + BN - 1) / BN;
+    if (g.Cp) tn = (int)((g.ldc + BN - 1) / BN);  // the padding columns are written too
+    if (g.lower && g.M != g.N) return hipErrorInvalidValue;
+    long total = g.lower ? (long)tm * (tm + 1) / 2 * g.batch : (long)tm * tn * g.batch;
+    if (g.tiles) {
+        if (!g.lower || g.ntiles <= 0) return hipErrorInvalidValue;
+        tn = g.ntiles;
+        total = (long)g.ntiles * g.batch;
+    }
+    if (total > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)total);
+#define RIS_PG_LAUNCH(NS_, OUTP_, BETA_) \
+    hipLaunchKernelGGL((k_pgemm<NS_, OUTP_, BETA_>), grid, dim3(256), 0, st, g, tm, tn, (int)total)
+    if (g.ns == 2) {
+        if (g.Cp) RIS_PG_LAUNCH(2, true, false);
+        else if (g.beta != 0.0) RIS_PG_LAUNCH(2, false, true);
+        else RIS_PG_LAUNCH(2, false, false);
+    } else {
+        if (g.Cp) RIS_PG_LAUNCH(3, true, false);
+        else if (g.beta != 0.0) RIS_PG_LAUNCH(3, false, true);
+        else RIS_PG_LAUNCH(3, false, false);
+    }
+#undef RIS_PG_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t split_planes(const double *x, int rows, int cols, long ldx, long sx, int batch, uint16_t *dst, long ps,
+                        long sdst, int ns, hipStream_t st)
+{
+    if (rows <= 0 || cols <= 0 || batch <= 0) return hipSuccess;
+    if ((ns != 2 && ns != 3) || batch > 65535) return hipErrorInvalidValue;
+    const long ldp = plane_ld(cols);
+    const long n = (long)rows * ldp;
+    dim3 grid((unsigned)((n + 255) / 256), (unsigned)batch);
+    if (ns == 2)
+        hipLaunchKernelGGL(k_split_planes<2>, grid, dim3(256), 0, st, x, rows, cols, ldx, sx, dst, ps, sdst, ldp);
+    else
+        hipLaunchKernelGGL(k_split_planes<3>, grid, dim3(256), 0, st, x, rows, cols, ldx, sx, dst, ps, sdst, ldp);
+    return hipGetLastError();
+}
 
 // Split-BF16 product (ns = 2 parts: mode 2, ns = 3: mode 3); kc > 0: split-K
 // ranges (kc a multiple of 32).
@@ -448,4 +750,65 @@ extern "C" int ris_test_gemm(int mode, int M, int N, int K, int transA, int tran
     g.batch = batch; g.nred = 1;
     if (ris::gemm_mp(g, mode, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return 7;
     return 0;
+}
+
+namespace ris {
+namespace {
+// sum of the ns parts of each plane element back into FP64 (test entry only)
+__global__ void k_planes_sum(const uint16_t *__restrict__ P, long ps, int ns, int rows, int cols, long ldp,
+                             double *__restrict__ C, long ldc)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)rows * cols) return;
+    const int r = (int)(idx / cols), cidx = (int)(idx - (long)r * cols);
+    double v = 0.0;
+    for (int p = 0; p < ns; ++p)
+        v += (double)(float)__builtin_bit_cast(__bf16, P[p * ps + (long)r * ldp + cidx]);
+    C[(long)r * ldc + cidx] = v;
+}
+}  // namespace
+}  // namespace ris
+
+extern "C" int ris_test_pgemm(int ns, int M, int N, int K, double alpha, const double *A, long lda, const double *B,
+                              long ldb, double beta, double *C, long ldc, int kband, int lower, int out_planes)
+{
+    using namespace ris;
+    if ((ns != 2 && ns != 3) || M <= 0 || N <= 0 || K <= 0 || !A || !B || !C || lda < K || ldb < K || ldc < N ||
+        (kband > 0 && K != 3 * kband) || (lower && (M != N || out_planes)) || (out_planes && beta != 0.0))
+        return 1;
+    const long ldp = plane_ld(K), psa = (long)M * ldp, psb = (long)N * ldp, ldcp = plane_ld(N);
+    uint16_t *pa = nullptr, *pb = nullptr, *pc = nullptr;
+    int rc = 0;
+    if (hipMalloc((void **)&pa, 2 * psa * ns) != hipSuccess || hipMalloc((void **)&pb, 2 * psb * ns) != hipSuccess ||
+        (out_planes && hipMalloc((void **)&pc, 2 * (long)M * ldcp * ns) != hipSuccess))
+        rc = 7;
+    if (!rc && (split_planes(A, M, K, lda, 0, 1, pa, psa, 0, ns, 0) != hipSuccess ||
+                split_planes(B, N, K, ldb, 0, 1, pb, psb, 0, ns, 0) != hipSuccess))
+        rc = 7;
+    if (!rc) {
+        PGemmArgs g{};
+        g.M = M; g.N = N; g.K = (int)ldp; g.ns = ns;
+        g.A = pa; g.lda = ldp; g.psA = psa;
+        g.B = pb; g.ldb = ldp; g.psB = psb;
+        g.alpha = alpha; g.beta = beta;
+        if (out_planes) {
+            g.Cp = pc; g.ldc = ldcp; g.psC = (long)M * ldcp;
+        } else {
+            g.C = C; g.ldc = ldc;
+        }
+        g.batch = 1; g.kband = kband; g.lower = lower != 0;
+        const hipError_t e = pgemm(g, 0);
+        if (e == hipErrorInvalidValue) rc = 1;
+        else if (e != hipSuccess) rc = 7;
+    }
+    if (!rc && out_planes) {
+        hipLaunchKernelGGL(k_planes_sum, dim3((unsigned)(((long)M * N + 255) / 256)), dim3(256), 0, 0, pc,
+                           (long)M * ldcp, ns, M, N, ldcp, C, ldc);
+        if (hipGetLastError() != hipSuccess) rc = 7;
+    }
+    if (hipDeviceSynchronize() != hipSuccess && !rc) rc = 7;
+    if (pa) (void)hipFree(pa);
+    if (pb) (void)hipFree(pb);
+    if (pc) (void)hipFree(pc);
+    return rc;
 }

@@ -293,7 +293,7 @@ __global__ void k_assemble3(BlockGrid g, double *__restrict__ W, float *__restri
         if (b.base) v += b.scale * b.base[P * b.sP + (long)i * b.si + (long)j * b.sj];
     }
     const long at = ((long)P * n3 + row) * n3 + bj * o + j;
-    W[at] = v;
+    if (W) W[at] = v;
     if (Wf) Wf[at] = (float)v;
 }
 

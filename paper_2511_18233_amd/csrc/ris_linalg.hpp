@@ -34,8 +34,12 @@ struct BlockSrc {
 struct BlockGrid {
     BlockSrc b[3][3][2];  // up to two summed sources per block; base == nullptr means none
 };
-// Wf (may be null) receives a float copy of W in the same pass.
+// W and Wf (either may be null) receive W and a float copy of it.
 hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st, float *Wf = nullptr);
+// Planes (ns bf16 parts of the FP32 values, see plane_ld) of the transposes of
+// the same assembly: part p of W_P^T at Wt + p ps + P 3o plane_ld(3o), its row c
+// holding column c of W_P (ris_gemm_mp.hip).
+hipError_t assemble3_planes(const BlockGrid &g, uint16_t *Wt, int o, int nP, long ps, int ns, hipStream_t st);
 // y = (float)x elementwise
 hipError_t to_float(const double *x, float *y, size_t n, hipStream_t st);
 // out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] + beta * out over n0 x n1 x n2

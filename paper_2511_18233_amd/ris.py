@@ -32,7 +32,7 @@ EXPORTS = ("ris_ctx_create", "ris_ctx_destroy", "ris_last_error", "ris_ctx_bytes
            "ris_ctx_stage_stats",
            # test-only building blocks (include/ris_test.h)
            "ris_test_mfma_probe", "ris_test_dgemm", "ris_test_gemm", "ris_test_sym_eig",
-           "ris_test_transpose", "ris_test_boys")
+           "ris_test_transpose", "ris_test_boys", "ris_test_pgemm")
 
 
 class RisError(RuntimeError):
@@ -115,6 +115,9 @@ def load_library(path: str = LIB_PATH):
     lib.ris_test_sym_eig.argtypes = [ctypes.c_int, vp, vp]
     lib.ris_test_transpose.argtypes = [vp, L, vp, L, ctypes.c_int, ctypes.c_int]
     lib.ris_test_boys.argtypes = [ctypes.c_int, vp, vp]
+    lib.ris_test_pgemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp,
+                                   ctypes.c_long, vp, ctypes.c_long, ctypes.c_double, vp, ctypes.c_long,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int]
     _lib = lib
     return lib
 
