@@ -232,53 +232,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
     };
 
+    // A wave whose 64 x 64 sub-tile holds nothing that is stored skips its
+    // fragment reads, MFMAs and stores (it still stages its share of the
+    // operands): the sub-tile past the last row or column of a ragged tile, and
+    // in the lower-tile mode the strictly upper sub-tile of a diagonal tile.
+    const bool act = m0 + wm * 64 < M && n0 + wn * 64 < N && !(lower && mt == nt && wm < wn);
     if (niter > 0) {
         load(0);
         store(0);
     }
     __syncthreads();
-    for (int it = 0; it < niter; ++it) {
+    // one k-slab; ACT: with the matrix-core work
+    auto slab = [&](int it, auto act_tag) {
+        constexpr bool ACT = decltype(act_tag)::value;
         const int cur = it & 1;
         // next slab (the last iteration reloads its own slab: in bounds, never read)
         load(min(it + 1, niter - 1));
+        if constexpr (ACT) {
 #pragma unroll
-        for (int kk = 0; kk < SK; kk += 4) {
-            T fa[4], fb[4];
+            for (int kk = 0; kk < SK; kk += 4) {
+                T fa[4], fb[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fa[i] = As[cur][kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
+                for (int i = 0; i < 4; ++i) fa[i] = As[cur][kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) fb[j] = Bs[cur][kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
+                for (int j = 0; j < 4; ++j) fb[j] = Bs[cur][kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = Cfg::mfma(fa[i], fb[j], acc[i][j]);
+                    for (int j = 0; j < 4; ++j) acc[i][j] = Cfg::mfma(fa[i], fb[j], acc[i][j]);
+            }
         }
         // the other buffer was last read in iteration it-1, before the barrier that ended it
         store(cur ^ 1);
-        // schedule: fragment reads of the first k-step, then the global loads
-        // one per MFMA, the remaining fragment reads one per MFMA, and the LDS
-        // writes one per MFMA over the last MFMAs of the slab
-        constexpr int NMF = 16 * (SK / 4), NLD = 2 * NQ, NDR = 8 * (SK / 4), NDW = 2 * NQ;
+        if constexpr (ACT) {
+            // schedule: fragment reads of the first k-step, then the global loads
+            // one per MFMA, the remaining fragment reads one per MFMA, and the LDS
+            // writes one per MFMA over the last MFMAs of the slab
+            constexpr int NMF = 16 * (SK / 4), NLD = 2 * NQ, NDR = 8 * (SK / 4), NDW = 2 * NQ;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            for (int u = 0; u < 8; ++u) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
 #pragma unroll
-        for (int u = 0; u < NLD; ++u) {
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        }
+            for (int u = 0; u < NLD; ++u) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
 #pragma unroll
-        for (int u = 0; u < NDR - 8; ++u) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        }
+            for (int u = 0; u < NDR - 8; ++u) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
 #pragma unroll
-        for (int u = 0; u < NMF - NLD - (NDR - 8) - NDW; ++u) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            for (int u = 0; u < NMF - NLD - (NDR - 8) - NDW; ++u) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
 #pragma unroll
-        for (int u = 0; u < NDW; ++u) {
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            for (int u = 0; u < NDW; ++u) {
+                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
         }
         __syncthreads();
+    };
+    if (act) {
+        for (int it = 0; it < niter; ++it) slab(it, std::true_type{});
+    } else {
+        for (int it = 0; it < niter; ++it) slab(it, std::false_type{});
+        return;
     }
 
 #pragma unroll

@@ -413,39 +413,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // fragment rows start at multiples of 16, so their swizzle is that of lane & 15
     const int kofs = 8 * ((lane >> 4) ^ swz(lane & 15));
     const int nslab = kend > kbeg ? (kend - kbeg + BK2 - 1) / BK2 : 0;
-    // slab it from LDS stage CUR = it % 2
-    auto slab = [&](int it, auto cur) {
+    // A wave whose 64 x 64 sub-tile holds nothing that is stored skips its
+    // fragment reads, MFMAs and stores (it still stages its share of the
+    // operands): past the last row or stored column of a ragged tile, and in
+    // the lower-tile mode the strictly upper sub-tile of a diagonal tile.
+    const bool act = m0 + wm * 64 < g.M && n0 + wn * 64 < (OUTP ? (int)g.ldc : g.N) &&
+                     !(g.lower && mt == nt && wm < wn);
+    // slab it from LDS stage CUR = it % 2; ACT: with the matrix-core work
+    auto slab = [&](int it, auto cur, auto act_tag) {
         constexpr int CUR = decltype(cur)::value;
         constexpr int NXT = 1 - CUR;
+        constexpr bool ACT = decltype(act_tag)::value;
         typedef std::integral_constant<int, NXT> N_;
         // slab it + 2 into the set slab it left (stored to LDS one slab ago);
         // its global loads go out first, ahead of this slab's work (the last
         // two slabs reload the last one: in bounds, never stored)
         load_slab(cur, min(it + 2, nslab - 1));
         __builtin_amdgcn_sched_barrier(0);
-        // fragments in the order the products use them: the parts of product 0
-        // (hi of A, lo of B), then lo of A and hi of B, then mid (NS = 3)
-        v8bf fa_[NS][4], fb_[NS][4];
-        constexpr int pa_[3] = {0, NS - 1, 1}, pb_[3] = {NS - 1, 0, 1};
+        if constexpr (ACT) {
+            // fragments in the order the products use them: the parts of product 0
+            // (hi of A, lo of B), then lo of A and hi of B, then mid (NS = 3)
+            v8bf fa_[NS][4], fb_[NS][4];
+            constexpr int pa_[3] = {0, NS - 1, 1}, pb_[3] = {NS - 1, 0, 1};
 #pragma unroll
-        for (int h = 0; h < NS; ++h) {
-            const int p = pa_[h], q = pb_[h];
+            for (int h = 0; h < NS; ++h) {
+                const int p = pa_[h], q = pb_[h];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                fa_[p][i] = *reinterpret_cast<const v8bf *>(&S[CUR][0][p][wm * 64 + i * 16 + (lane & 15)][kofs]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                fb_[q][j] = *reinterpret_cast<const v8bf *>(&S[CUR][1][q][wn * 64 + j * 16 + (lane & 15)][kofs]);
-        }
-        constexpr int NP = NS == 2 ? 3 : 6;
-#pragma unroll
-        for (int u = 0; u < NP; ++u)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
+                    fa_[p][i] = *reinterpret_cast<const v8bf *>(&S[CUR][0][p][wm * 64 + i * 16 + (lane & 15)][kofs]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_[part_a<NS>(u)][i], fb_[part_b<NS>(u)][j],
-                                                                        acc[i][j], 0, 0, 0);
+                    fb_[q][j] = *reinterpret_cast<const v8bf *>(&S[CUR][1][q][wn * 64 + j * 16 + (lane & 15)][kofs]);
+            }
+            constexpr int NP = NS == 2 ? 3 : 6;
+#pragma unroll
+            for (int u = 0; u < NP; ++u)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_[part_a<NS>(u)][i], fb_[part_b<NS>(u)][j],
+                                                                            acc[i][j], 0, 0, 0);
+        }
         // slab it + 1 into the other stage, last read in slab it - 1 (before
         // the barrier that ended it), after every MFMA of this slab
         __builtin_amdgcn_sched_barrier(0);
@@ -459,11 +468,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
     __syncthreads();
     int it = 0;
-    for (; it + 1 < nslab; it += 2) {
-        slab(it, S0_{});
-        slab(it + 1, S1_{});
+    if (act) {
+        for (; it + 1 < nslab; it += 2) {
+            slab(it, S0_{}, std::true_type{});
+            slab(it + 1, S1_{}, std::true_type{});
+        }
+        if (it < nslab) slab(it, S0_{}, std::true_type{});
+    } else {
+        for (; it + 1 < nslab; it += 2) {
+            slab(it, S0_{}, std::false_type{});
+            slab(it + 1, S1_{}, std::false_type{});
+        }
+        if (it < nslab) slab(it, S0_{}, std::false_type{});
+        return;
     }
-    if (it < nslab) slab(it, S0_{});
 
     const float falpha = (float)g.alpha;
 #pragma unroll
