@@ -42,7 +42,7 @@ PEAK_HBM_GBS = 8000.0
 # 2.0, write by 1.0 after a 1 GiB copy calibration), averaged over the 28
 # launches of a step; valid only for the GEMM source it was measured on (sha256
 # prefix), null otherwise.
-GAMMA_TRAFFIC = {"gemm_src_sha256": "d1af00ef506489ee", "workload": "chain200", "bytes_per_launch": 17.80e9}
+GAMMA_TRAFFIC = {"gemm_src_sha256": "b2a0b1edb46ba2ef", "workload": "chain200", "bytes_per_launch": 17.43e9}
 
 
 def log(*a):
@@ -490,7 +490,9 @@ def main():
     # the same step in each reduced-precision mode, against the FP64 step's outputs
     if args.mode_steps > 0 and args.precision == "fp64":
         modes = {}
-        for mode in ("fp32", "bf16x6", "bf16x3"):
+        # the exchange contractions in each reduced precision; "+transforms": the
+        # MO transforms of (mu nu|P) in it as well
+        for mode in ("fp32", "bf16x6", "bf16x3", "fp32+transforms", "bf16x3+transforms"):
             mt, mtot, mst = run_steps(ctx, make_step(mode), args.mode_steps, 1, mode)
             g = g_out.cpu().numpy()
             n = n_out.cpu().numpy()
@@ -501,7 +503,7 @@ def main():
                 "grads_nacs_per_s": round(rate, 4), "ms_per_step": round(1e3 * mtot / args.mode_steps, 2),
                 "ms_per_step_min": round(1e3 * min(mt), 2), "steps": args.mode_steps,
                 "vs_plain_fp64": round(rate / value, 4),
-                "roofline": gamma_roofline(mst, mode, args.workload),
+                "roofline": gamma_roofline(mst, mode.split("+")[0], args.workload),
                 "max_abs_dgrad_vs_fp64": max(per[:len(grads)]) if grads else None,
                 "max_abs_dnac_vs_fp64": max(per[len(grads):]) if pairs else None,
                 "max_abs_grad": float(np.abs(g_ref).max()),
