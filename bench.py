@@ -264,7 +264,7 @@ def stage_table(stats, steps):
     return out
 
 
-def serve_bench(nreq, nslots, radii, mixed=("fp32", "bf16x6")):
+def serve_bench(nreq, nslots, radii, mixed=("fp32", "bf16x6", "bf16x3")):
     """Serving replay (chain molecules 20-120 atoms from seeded trajectories,
     2 gradients + 1 NAC numerator each):
       * sequential FP64: one slot, requests back to back (the reference loop

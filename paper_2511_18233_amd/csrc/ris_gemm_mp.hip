@@ -13,8 +13,10 @@
 //          hi.hi + hi.mid + mid.hi + hi.lo + lo.hi + mid.mid (mid.lo, lo.mid
 //          and lo.lo, 2^-24 and below, are dropped).
 //
-// Same contract as the FP64 dgemm (batch, batch-reduce, transposes, alpha,
-// beta) and the same XCD-aware tile order.  Lane layouts (checked by the probe
+// k_bgemm3 has the same contract as the FP64 dgemm (batch, batch-reduce,
+// transposes, alpha, beta) and the same XCD-aware tile order; k_pgemm runs the
+// split modes' two products of every output (Y^P = F_I W^P, Gamma^P) on
+// operands kept pre-split in HBM (PGemmArgs).  Lane layouts (checked by the probe
 // tests): FP32 16x16x4 as FP64 (A[l%16][l/16], B[l/16][l%16]); BF16 16x16x32
 // lane l holds A[l%16][8(l/16)+s], B[8(l/16)+s][l%16], s = 0..7; both write
 // D[4(l/16) + e][l%16] to accumulator element e (rows in blocks of four, unlike

@@ -2,9 +2,10 @@
 (about 1.8 TB) cannot be held and the calls block over the auxiliary index by
 themselves.  The oracle cannot run at this size; checked instead, on two
 gradients and one NAC numerator: translational invariance of the gradients,
-agreement of the FP32 mode with FP64 within 1e-8 Ha/Bohr (the same outputs
-through a different arithmetic), and that the context stayed far below the
-unblocked footprint."""
+agreement of the FP32 mode with FP64 within 1e-8 Ha/Bohr and of the split-BF16
+mode (three products, operands on bf16 planes) within the 1e-6 it claims (the
+same outputs through a different arithmetic), and that the context stayed far
+below the unblocked footprint."""
 import sys
 
 import numpy as np
@@ -40,7 +41,7 @@ def test_chain500_blocked_precisions_and_invariance(radii):
     res = {}
     ctx = RisContext(0)
     try:
-        for prec in ("fp64", "fp32"):
+        for prec in ("fp64", "fp32", "bf16x3"):
             say(f"[gpu]   {prec}: aux + int3c")
             ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, True)
             ctx.int3c(C, eps, prob.nocc, 2.0, 0.25, precision=prec)
@@ -54,9 +55,13 @@ def test_chain500_blocked_precisions_and_invariance(radii):
         ctx.close()
     g64, n64 = res["fp64"]
     g32, n32 = res["fp32"]
+    gb, nb = res["bf16x3"]
     inv = np.abs(g64.sum(1)).max()
     d = max(np.abs(g32 - g64).max(), np.abs(n32 - n64).max())
-    say(f"[gpu]   max |sum_A grad| {inv:.2e}; fp32 vs fp64 {d:.2e} (max |grad| {np.abs(g64).max():.2e})")
+    db = max(np.abs(gb - g64).max(), np.abs(nb - n64).max())
+    say(f"[gpu]   max |sum_A grad| {inv:.2e}; fp32 vs fp64 {d:.2e}, bf16x3 vs fp64 {db:.2e} "
+        f"(max |grad| {np.abs(g64).max():.2e})")
     assert np.abs(g64).max() > 0
     assert inv <= 1e-12
     assert d <= 1e-8
+    assert db <= 1e-6
