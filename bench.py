@@ -452,7 +452,8 @@ def main():
     # translational invariance of the gradients (sum over atoms vanishes)
     inv = float(np.abs(g_ref.sum(1)).max()) if len(grads) else 0.0
     from paper_2511_18233_amd.ris import request_bytes
-    plan0 = request_bytes(m.Z, m.shell_atom, m.shell_l, radii, m.nao, prob.nocc, ns, ns, len(outs))
+    plan0 = request_bytes(m.Z, m.shell_atom, m.shell_l, radii, m.nao, prob.nocc, ns, ns, len(outs), xyz=m.xyz,
+                          shell_exp=m.shell_exp)
     hbm = {"held_gb": round(ctx.bytes_held / 1e9, 2),
            "unblocked_plan_gb": round(plan0 / 1e9, 2)}
     log(f"[bench] translational invariance max |sum_A grad| {inv:.2e}; HBM held {hbm['held_gb']} GB "

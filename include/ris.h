@@ -138,8 +138,11 @@ int ris_ctx_release(ris_ctx *ctx);
  * nmo orbitals (nocc occupied), nstate amplitude vectors, matvecs of up to
  * nvec vectors and nout gradient/NAC outputs (0 for any of the three if that
  * call is not made).  The sizing is the one the calls themselves use, so a
- * scheduler can admit requests by HBM footprint.  Host-only, no device work;
- * returns 0 for invalid input. */
+ * scheduler can admit requests by HBM footprint.  The geometry and exponents
+ * enter through the AO shell pairs the default screen keeps (the derivative
+ * contraction holds a copy of the exchange weights of those pairs): a
+ * molecule given with all atoms at one point is sized for every pair, an
+ * upper bound.  Host-only, no device work; returns 0 for invalid input. */
 size_t ris_request_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int nocc, int nstate, int nvec,
                          int nout);
 

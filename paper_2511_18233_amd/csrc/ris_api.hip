@@ -99,6 +99,14 @@ struct ris_ctx {
     int *d_gtiles_cm = nullptr;
     int ngtiles = 0;
     double gtile_lower = 0.0;  // elements on or below the diagonal inside those tiles
+    // numbering of the compact copy of the exchange weights read by the
+    // derivative contraction (build_pairs): block start and orientation per
+    // partner-list entry, the lower partners of each shell with their block
+    // starts, and the function pairs of all blocks (0: no copy, the weights
+    // are read in place)
+    int *d_pair_gq = nullptr, *d_pk_ptr = nullptr, *d_pk_sb = nullptr, *d_pk_base = nullptr;
+    int *d_pc_ptr = nullptr, *d_pc_cn = nullptr, *d_pc_qb = nullptr;  // the copy's column lists (PackLists)
+    long nfq = 0;
 
     // ---- int3c state
     bool have_int3c = false;
@@ -242,6 +250,9 @@ void free_aux(ris_ctx *c)
     c->d_pair_ptr = c->d_pair_idx = nullptr;
     c->d_gtiles = c->d_gtiles_cm = nullptr;
     c->ngtiles = 0;
+    c->d_pair_gq = c->d_pk_ptr = c->d_pk_sb = c->d_pk_base = nullptr;
+    c->d_pc_ptr = c->d_pc_cn = c->d_pc_qb = nullptr;
+    c->nfq = 0;
     c->MJ = c->LinvJ = c->MinvJ = c->MinvK = nullptr;
     c->ao = AOGeom{};
     c->aux = AuxGeom{};
@@ -335,6 +346,12 @@ GemmArgs gm(int M, int N, int K, bool tA, bool tB, double alpha, const double *A
     return g;
 }
 
+// The screen's test for an AO shell pair of exponents ea, eb at squared distance r2.
+bool pair_kept(double ea, double eb, double r2, double thr)
+{
+    return thr <= 0.0 || std::exp(-ea * eb / (ea + eb) * r2) >= thr;
+}
+
 // Partner lists of the AO shell-pair screen: pair (a, b) is kept when its
 // Gaussian product prefactor exp(-a b / (a + b) |A - B|^2) is >= c->screen
 // (every pair when the threshold is 0).  Lists are grouped by the partner's
@@ -351,9 +368,7 @@ int build_pairs(ris_ctx *c)
             ptr[(size_t)ncls * a + l] = (int)idx.size();
             for (int b = c->ao.lbeg[l]; b < c->ao.lbeg[l + 1]; ++b) {
                 const double dx = X[3 * a] - X[3 * b], dy = X[3 * a + 1] - X[3 * b + 1], dz = X[3 * a + 2] - X[3 * b + 2];
-                const double ea = E[a], eb = E[b];
-                if (thr <= 0.0 || std::exp(-ea * eb / (ea + eb) * (dx * dx + dy * dy + dz * dz)) >= thr)
-                    idx.push_back(b);
+                if (pair_kept(E[a], E[b], dx * dx + dy * dy + dz * dz, thr)) idx.push_back(b);
             }
         }
     ptr[(size_t)ncls * nsh] = (int)idx.size();
@@ -392,6 +407,74 @@ int build_pairs(ris_ctx *c)
     std::stable_sort(tiles_cm.begin(), tiles_cm.end(), [](int a, int b) { return (a & 0xffff) < (b & 0xffff); });
     tiles.insert(tiles.end(), tiles_cm.begin(), tiles_cm.end());
     c->d_gtiles_cm = c->d_gtiles + c->ngtiles;
+    // Compact copy of the exchange weights (the derivative contraction's
+    // s-shell classes): each unordered kept pair owns one block of
+    // nf(a) nf(b) function pairs, stored in the orientation whose first shell
+    // starts later in the AO order (rows >= columns: the lower triangle the
+    // weights are formed in), blocks ordered by that shell and then by the
+    // partner's first function.  pk: those partners of each shell in that
+    // order; gq[e] of list entry e = (a, b): block start << 1, | 1 when a is
+    // the earlier shell (its functions then run second in the block).
+    std::vector<int> pk_ptr((size_t)nsh + 1, 0), pk_sb, gq(idx.size());
+    std::vector<long> pk_base;
+    long nfq = 0;
+    for (int a = 0; a < nsh; ++a) {
+        pk_ptr[a] = (int)pk_sb.size();
+        const size_t k0 = pk_sb.size();
+        for (size_t q = ptr[(size_t)ncls * a]; q < (size_t)ptr[(size_t)ncls * (a + 1)]; ++q)
+            if (off[idx[q]] <= off[a]) pk_sb.push_back(idx[q]);
+        std::sort(pk_sb.begin() + k0, pk_sb.end(), [&](int x, int y) { return off[x] < off[y]; });
+        for (size_t k = k0; k < pk_sb.size(); ++k) {
+            pk_base.push_back(nfq);
+            nfq += (long)shell_nf(a) * shell_nf(pk_sb[k]);
+        }
+    }
+    pk_ptr[nsh] = (int)pk_sb.size();
+    // block starts are stored as int with the orientation bit
+    c->nfq = nfq < (1L << 30) ? nfq : 0;
+    if (c->nfq > 0) {
+        for (int a = 0; a < nsh; ++a)
+            for (size_t q = ptr[(size_t)ncls * a]; q < (size_t)ptr[(size_t)ncls * (a + 1)]; ++q) {
+                const int b = idx[q];
+                const bool flip = off[a] < off[b];
+                const int x = flip ? b : a, y = flip ? a : b;
+                const auto beg = pk_sb.begin() + pk_ptr[x], end = pk_sb.begin() + pk_ptr[x + 1];
+                const auto it = std::lower_bound(beg, end, y, [&](int s, int t) { return off[s] < off[t]; });
+                if (it == end || *it != y) return fail(c, RIS_E_INVALID, "internal: shell-pair lists not symmetric");
+                gq[q] = (int)(pk_base[it - pk_sb.begin()] << 1) | (flip ? 1 : 0);
+            }
+        std::vector<int> base32(pk_base.begin(), pk_base.end());
+        // the columns of each shell's earlier partners (its own block apart)
+        std::vector<int> pc_ptr((size_t)nsh + 1, 0), pc_cn, pc_qb;
+        for (int a = 0; a < nsh; ++a) {
+            pc_ptr[a] = (int)pc_cn.size();
+            if (pk_ptr[a + 1] == pk_ptr[a] || pk_sb[pk_ptr[a + 1] - 1] != a)
+                return fail(c, RIS_E_INVALID, "internal: shell %d is not its own last partner", a);
+            for (int k = pk_ptr[a]; k < pk_ptr[a + 1] - 1; ++k) {
+                const int b = pk_sb[k], nb = shell_nf(b);
+                for (int kb = 0; kb < nb; ++kb) {
+                    pc_cn.push_back((off[b] + kb) * 8 + nb);
+                    pc_qb.push_back((int)(pk_base[k] + kb));
+                }
+            }
+        }
+        pc_ptr[nsh] = (int)pc_cn.size();
+        HIPCHK(c, hipMemcpyAsync(c->d_pc_ptr, pc_ptr.data(), 4 * pc_ptr.size(), hipMemcpyHostToDevice, c->stream));
+        if (!pc_cn.empty()) {
+            HIPCHK(c, hipMemcpyAsync(c->d_pc_cn, pc_cn.data(), 4 * pc_cn.size(), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->d_pc_qb, pc_qb.data(), 4 * pc_qb.size(), hipMemcpyHostToDevice, c->stream));
+        }
+        if (!gq.empty())
+            HIPCHK(c, hipMemcpyAsync(c->d_pair_gq, gq.data(), 4 * gq.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->d_pk_ptr, pk_ptr.data(), 4 * pk_ptr.size(), hipMemcpyHostToDevice, c->stream));
+        if (!pk_sb.empty()) {
+            HIPCHK(c, hipMemcpyAsync(c->d_pk_sb, pk_sb.data(), 4 * pk_sb.size(), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->d_pk_base, base32.data(), 4 * base32.size(), hipMemcpyHostToDevice,
+                                     c->stream));
+        }
+        // the copies read from host vectors: finish them before those go
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     HIPCHK(c, hipMemcpyAsync(c->d_pair_ptr, ptr.data(), 4 * ptr.size(), hipMemcpyHostToDevice, c->stream));
     if (!idx.empty())
         HIPCHK(c, hipMemcpyAsync(c->d_pair_idx, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, c->stream));
@@ -458,6 +541,7 @@ static std::vector<int> atom_band_order(const ris_mol *mol)
 // ---- sizes of every device region, shared by the calls and ris_request_bytes
 struct Dims {
     int N, nmo, o, v, nJ, nK, nshAO, nshJ, natm;
+    long nfq;  // function pairs of the compact exchange-weight copy (0: none)
 };
 
 struct MoLayout {
@@ -544,7 +628,7 @@ size_t xcopy_doubles(size_t rows, long cols)
 
 struct ContractWs {
     size_t oR, oL, oRLT, oF, oD, otT, ocv, oTall, oHUO, oHOU, oHUU, oW, oHc, oY, oG, oV2, oSK, op3, op2, oshA, oshC,
-        oshP, oFf, oWf, total;
+        oshP, oFf, oWf, oGc, total;
 };
 ContractWs contract_ws(const Dims &d, int ns)
 {
@@ -572,6 +656,8 @@ ContractWs contract_ws(const Dims &d, int ns)
     L.oFf = cv.take(xcopy_doubles((size_t)ns * d.N, o3));
     L.oWf = cv.take(xcopy_doubles((size_t)d.nK * o3, o3));
     L.oG = cv.take((size_t)NO * d.nK * NN);
+    // compact copy of the kept lower blocks of Gamma, K function fastest
+    L.oGc = cv.take((size_t)NO * d.nfq * d.nK);
     L.oV2 = cv.take((size_t)NO * d.nJ * d.nJ);
     L.oSK = cv.take(std::max((size_t)kSplitV * ns * d.nJ, (size_t)vpq_splits(d.nK) * d.nK * d.nK));
     L.op3 = cv.take((size_t)d.nshAO * d.nshJ * 3 * NO * 6);
@@ -629,7 +715,7 @@ ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
 }
 
 struct AuxLayout {
-    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, oPP, oPI, oGT, oOI, oPJ, total;
+    size_t oAO, oAX, oP, oMJ, oLJ, oIJ, oIK, oPP, oPI, oPQ, oGT, oOI, oPJ, total;
 };
 AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
 {
@@ -647,6 +733,11 @@ AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
     // screened pair lists sized for the unscreened worst case (ints, 2 per slot)
     L.oPP = cv.take(((size_t)(kMaxAOL + 1) * nsh + 2) / 2);
     L.oPI = cv.take(((size_t)nsh * nsh + 1) / 2);
+    // numbering of the compact exchange-weight copy (ints): a block start per
+    // list entry, the earlier partners of each shell (pointers, shells, block
+    // starts) and their columns (pointers, two lists of at most nsh * nao:
+    // a shell's earlier partners hold at most nao functions)
+    L.oPQ = cv.take(((size_t)2 * nsh * nsh + 4 * (size_t)nsh + 4 + 2 * (size_t)nsh * nao) / 2 + 1);
     // lower-tile list of the AO-pair matrix (ints, 2 per slot)
     const size_t tm = (size_t)(nao + 127) / 128;
     L.oGT = cv.take((tm * (tm + 1) + 1) / 2);  // two orders of the list
@@ -656,7 +747,7 @@ AuxLayout aux_layout(int nsh, int nshJ, int nao, int nJ, int nK)
 
 Dims ctx_dims(const ris_ctx *c)
 {
-    return Dims{c->nao, c->nmo, c->nocc, c->nvir, c->nJ, c->nK, c->nshAO, c->nshJ, c->natm};
+    return Dims{c->nao, c->nmo, c->nocc, c->nvir, c->nJ, c->nK, c->nshAO, c->nshJ, c->natm, c->nfq};
 }
 
 // ========================================================================
@@ -722,7 +813,17 @@ size_t ris_plan_bytes(const ris_mol *mol, const ris_aux_opts *opts, int nmo, int
     const int natm = mol->natm;
     const int nshJ = natm + (opts->j_p_on_heavy ? nheavy : 0);
     const int nJ = natm + (opts->j_p_on_heavy ? 3 * nheavy : 0);
-    const Dims d{nao, nmo, nocc, nmo - nocc, nJ, natm, mol->shell_l ? mol->nshell : 0, nshJ, natm};
+    // function pairs of the unordered AO shell pairs the default screen keeps
+    long nfq = 0;
+    for (int a = 0; a < mol->nshell; ++a)
+        for (int b = 0; b <= a; ++b) {
+            const double *A = mol->xyz + 3 * mol->shell_atom[a], *B = mol->xyz + 3 * mol->shell_atom[b];
+            const double r2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+            if (pair_kept(mol->shell_exp[a], mol->shell_exp[b], r2, kDefaultScreen))
+                nfq += (long)ncart(mol->shell_l[a]) * ncart(mol->shell_l[b]);
+        }
+    const Dims d{nao, nmo, nocc, nmo - nocc, nJ, natm, mol->shell_l ? mol->nshell : 0, nshJ, natm,
+                 nfq < (1L << 30) ? nfq : 0};
     size_t ws;
     if (aux_block == 0) {
         ws = int3c_ws(d, d.nJ).total;
@@ -1362,6 +1463,13 @@ int ris_aux_build(ris_ctx *c, const ris_mol *mol, const ris_aux_opts *opts, int 
         c->MinvK = (double *)(base + AL.oIK);
         c->d_pair_ptr = (int *)(base + AL.oPP);
         c->d_pair_idx = (int *)(base + AL.oPI);
+        c->d_pair_gq = (int *)(base + AL.oPQ);
+        c->d_pk_ptr = c->d_pair_gq + (size_t)nsh * nsh;
+        c->d_pk_sb = c->d_pk_ptr + nsh + 1;
+        c->d_pk_base = c->d_pk_sb + (size_t)nsh * (nsh + 1) / 2;
+        c->d_pc_ptr = c->d_pk_base + (size_t)nsh * (nsh + 1) / 2;
+        c->d_pc_cn = c->d_pc_ptr + nsh + 1;
+        c->d_pc_qb = c->d_pc_cn + (size_t)nsh * nao;
         c->d_gtiles = (int *)(base + AL.oGT);
     }
     c->aux.nshell = nshJ;
@@ -2086,7 +2194,8 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
     double *R = P_(CW.oR), *L = P_(CW.oL), *RLT = P_(CW.oRLT), *F = P_(CW.oF), *D = P_(CW.oD), *tT = P_(CW.otT),
            *cvec = P_(CW.ocv), *Tall = P_(CW.oTall), *HUO = P_(CW.oHUO), *HOU = P_(CW.oHOU), *HUU = P_(CW.oHUU),
            *W = P_(CW.oW), *Hc = P_(CW.oHc), *Y3 = P_(CW.oY), *G = P_(CW.oG), *V2 = P_(CW.oV2), *SK = P_(CW.oSK),
-           *p3 = P_(CW.op3), *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP);
+           *p3 = P_(CW.op3), *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP),
+           *Gc = P_(CW.oGc);
     // FP32 and split-BF16 modes: F, W and Y stored as float for the two products
     // that build Gamma (both kernels round the operands to FP32 first: same results)
     // reduced-precision copies of F and W^P (reduced_f, assemble_w)
@@ -2148,6 +2257,13 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         job.partial = p3;
         job.pair_ptr = c->screen > 0.0 ? c->d_pair_ptr : nullptr;
         job.pair_idx = c->d_pair_idx;
+        if (c->nfq > 0) {
+            job.gcomp = Gc;
+            job.nfq = c->nfq;
+            job.lst_ptr = c->d_pair_ptr;
+            job.lst_idx = c->d_pair_idx;
+            job.lst_gq = c->d_pair_gq;
+        }
         for (int k = 0; k < NO; ++k) {
             const int kk = k0 + std::min(k, nb - 1);
             job.stI[k] = pI[kk];
@@ -2217,6 +2333,10 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         // three-centre derivative contraction + metric derivative, reduced into atoms
         HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * NO * 6, 0.0, c->stream));
         hipEvent_t t_d = stage_begin(c);
+        if (job.gcomp)
+            HIPCHK(c, launch_pack_gamma(c->ao, G, nb, nK,
+                                        PackLists{c->d_pk_ptr, c->d_pk_base, c->d_pc_ptr, c->d_pc_cn, c->d_pc_qb},
+                                        c->nfq, Gc, c->stream));
         HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream));
         stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)nb * nK * NN);
         HIPCHK(c, fill(p2, (size_t)c->nshJ * 2 * nb * 3, 0.0, c->stream));

@@ -75,8 +75,38 @@ struct DerivJob {
     // in class l are pair_idx[pair_ptr[(kMaxAOL+1) sa + l] .. pair_ptr[(kMaxAOL+1) sa + l + 1])
     const int *pair_ptr;
     const int *pair_idx;
+    // Optional compact copy of gammaK (null: gammaK is read in place).  With
+    // it, the s-shell classes of the K block run on a second kernel (lanes
+    // over the K functions).  Layout Gc[o][q][k], k < nK fastest, q = the
+    // function pair inside the block of its unordered kept shell pair
+    // (nfq pairs in all, see launch_pack_gamma).  lst_ptr / lst_idx are the
+    // partner lists in pair_ptr / pair_idx form (always given, every pair when
+    // nothing is screened) and lst_gq[e] = base << 1 | flip for list entry e:
+    // the pair's block starts at q = base and is stored with the partner's
+    // functions first when flip is set.
+    const double *gcomp;
+    long nfq;
+    const int *lst_ptr;
+    const int *lst_idx;
+    const int *lst_gq;
 };
 constexpr int kMaxOutChunk = 4;
+// Gc[o][base + ka nb + kb][k] = gammaK_o[k][mu0 + ka][nu0 + kb] for o < nout and
+// every unordered kept AO shell pair (a, b) whose b starts at or before a
+// (the diagonal block taken from the lower triangle), base = the pair's block
+// start.  gammaK: [nout][nK][nao][nao], only the lower blocks of kept pairs
+// are read.  The lists (device, built with the pair lists):
+struct PackLists {
+    // pk_ptr[a] .. pk_ptr[a + 1]: a's partners b starting at or before a, by
+    // first function (a itself last); pk_base: their block starts
+    const int *pk_ptr, *pk_base;
+    // pc_ptr[a] .. pc_ptr[a + 1]: the columns of those partners other than a,
+    // in order; pc_cn = column * 8 + the partner's function count, pc_qb =
+    // block start + the column's index in the partner
+    const int *pc_ptr, *pc_cn, *pc_qb;
+};
+hipError_t launch_pack_gamma(const AOGeom &ao, const double *gammaK, int nout, int nK, const PackLists &pl,
+                             long nfq, double *Gc, hipStream_t st);
 // Only the aux shells in [cs0, cs1) (cs1 < 0: to the last shell); partial
 // slots of the other shells are left untouched.
 hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],

@@ -275,6 +275,15 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
     // K functions are the leading (s) J functions; gammaK holds [kbeg, kbeg + nK)
     const bool inK = P0 >= job.kbeg && P0 < job.kbeg + job.nK;
     const size_t nao2 = (size_t)nao * nao;
+    // Every load below is issued on every lane and for every output slot
+    // (slots past nout read the last output's data, C shells outside the K
+    // block a density element scaled by 0): a load under a branch, even a
+    // uniform one, is waited for on its own.
+    const bool kin = LC == 0 && inK && job.gammaK;
+    const double kf = kin ? 1.0 : 0.0;
+    const double *gK = kin ? job.gammaK + (size_t)(P0 - job.kbeg) * nao2 : job.dens;
+    const size_t gKo = kin ? (size_t)job.nK * nao2 : 0;
+    const int olast = max(job.nout - 1, 0);
 
     double acc[NO][6];
 #pragma unroll
@@ -353,8 +362,15 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
                 double dI[NO], dJ[NO];
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
-                    dI[o] = (o < job.nout) ? job.alphaJ * job.dens[(size_t)job.stI[o] * nao2 + mn] : 0.0;
-                    dJ[o] = (o < job.nout) ? job.alphaJ * job.dens[(size_t)job.stJ[o] * nao2 + mn] : 0.0;
+                    if constexpr (LB == 2 && LC == 1) {
+                        // these classes spill: loads and sums held back by the
+                        // output test keep fewer values live and measured faster
+                        dI[o] = (o < job.nout) ? job.alphaJ * job.dens[(size_t)job.stI[o] * nao2 + mn] : 0.0;
+                        dJ[o] = (o < job.nout) ? job.alphaJ * job.dens[(size_t)job.stJ[o] * nao2 + mn] : 0.0;
+                    } else {
+                        dI[o] = job.alphaJ * job.dens[(size_t)job.stI[o] * nao2 + mn];
+                        dJ[o] = job.alphaJ * job.dens[(size_t)job.stJ[o] * nao2 + mn];
+                    }
                 }
                 sfor<ncart(LC)>([&](auto kc) {
                     constexpr int sx = cpow(LC, kc, 0), sy = cpow(LC, kc, 1), sz = cpow(LC, kc, 2);
@@ -368,18 +384,18 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
                     dC[2] = -f * hsum<NX, NY, NZ, sx, sy, sz + 1>(ex, ey, ez, r);
 #pragma unroll
                     for (int o = 0; o < NO; ++o) {
-                        if (o < job.nout) {
-                            double w = dI[o] * cJ[o][kc] + dJ[o] * cI[o][kc];
-                            if (inK && job.gammaK)
-                                w += job.gammaK[((size_t)o * job.nK + (P0 - job.kbeg) + kc) * nao2 + mnl];
-                            const double w2 = 2.0 * w;
-                            acc[o][0] += w2 * dA[0];
-                            acc[o][1] += w2 * dA[1];
-                            acc[o][2] += w2 * dA[2];
-                            acc[o][3] += w * dC[0];
-                            acc[o][4] += w * dC[1];
-                            acc[o][5] += w * dC[2];
-                        }
+                        if constexpr (LB == 2 && LC == 1)
+                            if (o >= job.nout) continue;
+                        double w = dI[o] * cJ[o][kc] + dJ[o] * cI[o][kc];
+                        // K functions are s shells: one component
+                        if constexpr (LC == 0) w += kf * gK[(size_t)min(o, olast) * gKo + mnl];
+                        const double w2 = 2.0 * w;
+                        acc[o][0] += w2 * dA[0];
+                        acc[o][1] += w2 * dA[1];
+                        acc[o][2] += w2 * dA[2];
+                        acc[o][3] += w * dC[0];
+                        acc[o][4] += w * dC[1];
+                        acc[o][5] += w * dC[2];
                     }
                 });
             });
@@ -397,6 +413,222 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
         }
     if (lane < G && cvalid) {
         // only the job's outputs: the partial slots of other outputs are left as they are
+        double *dst = job.partial + (((size_t)sa * nshAux + sc) * (kMaxAOL + 1) + LB) * NO * 6;
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+            if (o < job.nout) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dst[o * 6 + k] = acc[o][k];
+            }
+    }
+}
+
+// ------------------------------------------------------------------------
+// The exchange weights gammaK are the bulk of what the contraction reads, and
+// in place (lanes over B partners) every lane reads its own scattered element,
+// half of them across rows.  Their s-shell classes can instead run on a copy
+// with the K function fastest: k_pack_gamma copies the lower block of every
+// kept shell pair into Gc[o][q][k]; k_int3c_deriv_k then takes one A shell
+// and 16 consecutive K functions per wave, its four quarter-waves walking
+// different B partners, so the 16 lanes of a quarter read 16 consecutive k of
+// one function pair (one 128-byte line) and share its density elements.
+
+// One workgroup per (output, A shell a, 64 consecutive k).  For each row mu
+// of a, the columns of a's kept partners that start before a (the flattened
+// list pc: column * 8 + the partner's function count, and the block start
+// + column index) go through LDS 64 at a time: each wave reads a contiguous
+// row segment of one plane k, then each wave writes one column's 64 values of
+// k as a contiguous run.  The diagonal block (a, a) is copied element by
+// element from the lower triangle afterwards.
+constexpr int kPackCols = 64;
+__global__ __launch_bounds__(256) void k_pack_gamma(const int *__restrict__ off, int lb1, int lb2, int nsh, int nao,
+                                                    int nK, const double *__restrict__ G,
+                                                    const int *__restrict__ pk_ptr, const int *__restrict__ pk_base,
+                                                    const int *__restrict__ pc_ptr, const int *__restrict__ pc_cn,
+                                                    const int *__restrict__ pc_qb, long nfq, double *__restrict__ Gc)
+{
+    __shared__ double tile[64][kPackCols + 1];  // [k][column]; odd row stride: column reads by k are conflict-free
+    const int ngrp = (nK + 63) / 64;
+    const int g = blockIdx.x % ngrp;
+    const int a = (blockIdx.x / ngrp) % nsh;
+    const int o = blockIdx.x / (ngrp * nsh);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int k0 = g * 64, nk = min(64, nK - k0);
+    const size_t nn = (size_t)nao * nao;
+    const double *Gb = G + ((size_t)o * nK + k0) * nn;  // plane k0 + kl at Gb + kl * nn
+    double *Go = Gc + (size_t)o * nfq * nK + k0;
+    const int na = ncart(a >= lb2 ? 2 : (a >= lb1 ? 1 : 0));
+    const int mu0 = off[a], j0 = pc_ptr[a], j1 = pc_ptr[a + 1];
+    for (int ka = 0; ka < na; ++ka) {
+        const size_t row = (size_t)(mu0 + ka) * nao;
+        for (int jc = j0; jc < j1; jc += kPackCols) {
+            const int nc = min(kPackCols, j1 - jc);
+            {
+                // all 16 loads of the wave in flight together: plane and
+                // column clamped into range, the extra rows of the tile unused
+                const int col = pc_cn[jc + min(lane, nc - 1)] >> 3;
+                double v[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) v[i] = Gb[(size_t)min(wv + 4 * i, nk - 1) * nn + row + col];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) tile[wv + 4 * i][lane] = v[i];
+            }
+            __syncthreads();
+            if (lane < nk)
+                for (int c = wv; c < nc; c += 4) {
+                    const long q = (long)pc_qb[jc + c] + (long)ka * (pc_cn[jc + c] & 7);
+                    Go[(size_t)q * nK + lane] = tile[lane][c];
+                }
+            __syncthreads();
+        }
+    }
+    // the diagonal block: the last partner in a's list, its upper elements
+    // taken from the lower triangle
+    const long qd = pk_base[pk_ptr[a + 1] - 1];
+    if (lane < nk)
+        for (int e = wv; e < na * na; e += 4) {
+            const int ka = e / na, kb = e % na;
+            const int r = mu0 + max(ka, kb), c = mu0 + min(ka, kb);
+            Go[(size_t)(qd + e) * nK + lane] = Gb[lane * nn + (size_t)r * nao + c];
+        }
+}
+
+// The s-shell (LC = 0) classes of the K block on the copy: the same triplet
+// terms as k_int3c_deriv, a wave per (A shell, 16 K functions), lane l on
+// K function l % 16 and every fourth partner from l / 16; each lane owns the
+// partial slot of its (A shell, C shell) after the sum over its quarters.
+template <int LA, int LB, int NO>
+__global__ __launch_bounds__(64) void k_int3c_deriv_k(ShellTab ao, int nao, int a0, int na, ShellTab aux, int c0,
+                                                      int nc, int nshAux, const double *__restrict__ boys,
+                                                      DerivJob job)
+{
+    constexpr int QL = 16, NQ = 64 / QL;
+    const int ncg = (nc + QL - 1) / QL;
+    const int total = na * ncg;
+    if ((int)blockIdx.x >= total) return;
+    int lin;
+    {
+        // each XCD walks a contiguous range, the C-shell group fastest
+        const int q = total / 8, r = total % 8, x = blockIdx.x % 8, local = blockIdx.x / 8;
+        lin = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + local;
+    }
+    const int lane = threadIdx.x, slot = lane / QL;
+    const int sa = a0 + lin / ncg;
+    const int ci = (lin % ncg) * QL + lane % QL;
+    const bool cvalid = ci < nc;
+    const int sc = c0 + min(ci, nc - 1);
+
+    constexpr int L = LA + LB + 1;
+    const double Ax = ao.x[sa], Ay = ao.y[sa], Az = ao.z[sa];
+    const double c = aux.exp[sc];
+    const double Cx = aux.x[sc], Cy = aux.y[sc], Cz = aux.z[sc];
+    const int mu0 = ao.off[sa], P0 = aux.off[sc];
+    const int kk = P0 - job.kbeg;  // position in the K block (the launcher checks the range)
+    const size_t nao2 = (size_t)nao * nao;
+
+    double acc[NO][6];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[o][k] = 0.0;
+    double cI[NO], cJ[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        cI[o] = job.cvec[(size_t)job.stI[o] * job.nJ + P0];
+        cJ[o] = job.cvec[(size_t)job.stJ[o] * job.nJ + P0];
+    }
+    const double *gk = job.gcomp + kk;
+    const size_t gstride = (size_t)job.nfq * job.nK;  // one output's copy
+    // loads on every lane and output slot (past nout: the last output's
+    // data), never under a branch (see k_int3c_deriv)
+    const int olast = max(job.nout - 1, 0);
+
+    const int e0 = job.lst_ptr[(kMaxAOL + 1) * sa + LB];
+    const int cnt = cvalid ? job.lst_ptr[(kMaxAOL + 1) * sa + LB + 1] - e0 : 0;
+    for (int ib = slot; ib < cnt; ib += NQ) {
+        const int sb = job.lst_idx[e0 + ib];
+        const int gq = job.lst_gq[e0 + ib];
+        const long gbase = gq >> 1;
+        const bool flip = gq & 1;
+        const double a = ao.exp[sa], b = ao.exp[sb];
+        const double p = a + b, ip = 1.0 / p;
+        const double Bx = ao.x[sb], By = ao.y[sb], Bz = ao.z[sb];
+        const double P[3] = {(a * Ax + b * Bx) * ip, (a * Ay + b * By) * ip, (a * Az + b * Bz) * ip};
+        const double ab2 = (Ax - Bx) * (Ax - Bx) + (Ay - By) * (Ay - By) + (Az - Bz) * (Az - Bz);
+        const double kab = exp(-a * b * ip * ab2);
+        const double alpha = p * c / (p + c);
+        double r[rsize(L)];
+        hermite_r<L>(alpha, P[0] - Cx, P[1] - Cy, P[2] - Cz, boys, r);
+        const double inv2p = 0.5 * ip;
+        Herm<LA + 1, LB> Ex, Ey, Ez;
+        herm_build<LA + 1, LB>(P[0] - Ax, P[0] - Bx, inv2p, Ex);
+        herm_build<LA + 1, LB>(P[1] - Ay, P[1] - By, inv2p, Ey);
+        herm_build<LA + 1, LB>(P[2] - Az, P[2] - Bz, inv2p, Ez);
+        const double pref = kTwoPi52 / (p * c * sqrt(p + c)) * kab * ao.nrm[sa] * ao.nrm[sb] * aux.nrm[sc];
+        const int nu0 = ao.off[sb];
+        const double twoa = 2.0 * a;
+
+        sfor<ncart(LA)>([&](auto ka) {
+            constexpr int ix = cpow(LA, ka, 0), iy = cpow(LA, ka, 1), iz = cpow(LA, ka, 2);
+            sfor<ncart(LB)>([&](auto kb) {
+                constexpr int jx = cpow(LB, kb, 0), jy = cpow(LB, kb, 1), jz = cpow(LB, kb, 2);
+                const double *ex = Ex.e[ix][jx];
+                const double *ey = Ey.e[iy][jy];
+                const double *ez = Ez.e[iz][jz];
+                double dx[ix + jx + 2], dy[iy + jy + 2], dz[iz + jz + 2];
+                sfor<ix + jx + 2>([&](auto t) {
+                    double v = twoa * Ex.e[ix + 1][jx][t];
+                    if constexpr (ix > 0 && t <= ix - 1 + jx) v -= ix * Ex.e[ix - 1][jx][t];
+                    dx[t] = v;
+                });
+                sfor<iy + jy + 2>([&](auto t) {
+                    double v = twoa * Ey.e[iy + 1][jy][t];
+                    if constexpr (iy > 0 && t <= iy - 1 + jy) v -= iy * Ey.e[iy - 1][jy][t];
+                    dy[t] = v;
+                });
+                sfor<iz + jz + 2>([&](auto t) {
+                    double v = twoa * Ez.e[iz + 1][jz][t];
+                    if constexpr (iz > 0 && t <= iz - 1 + jz) v -= iz * Ez.e[iz - 1][jz][t];
+                    dz[t] = v;
+                });
+                constexpr int NX = ix + jx + 1, NY = iy + jy + 1, NZ = iz + jz + 1;
+                const size_t mn = (size_t)(mu0 + ka) * nao + nu0 + kb;
+                const long q = gbase + (flip ? (long)kb * ncart(LA) + ka : (long)ka * ncart(LB) + kb);
+                const double f = pref * cnorm(LA, ka) * cnorm(LB, kb);
+                double dA[3], dC[3];
+                dA[0] = f * hsum<NX + 1, NY, NZ, 0, 0, 0>(dx, ey, ez, r);
+                dA[1] = f * hsum<NX, NY + 1, NZ, 0, 0, 0>(ex, dy, ez, r);
+                dA[2] = f * hsum<NX, NY, NZ + 1, 0, 0, 0>(ex, ey, dz, r);
+                dC[0] = -f * hsum<NX, NY, NZ, 1, 0, 0>(ex, ey, ez, r);
+                dC[1] = -f * hsum<NX, NY, NZ, 0, 1, 0>(ex, ey, ez, r);
+                dC[2] = -f * hsum<NX, NY, NZ, 0, 0, 1>(ex, ey, ez, r);
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    const double dI = job.alphaJ * job.dens[(size_t)job.stI[o] * nao2 + mn];
+                    const double dJ = job.alphaJ * job.dens[(size_t)job.stJ[o] * nao2 + mn];
+                    const double w = dI * cJ[o] + dJ * cI[o] + gk[(size_t)min(o, olast) * gstride + (size_t)q * job.nK];
+                    const double w2 = 2.0 * w;
+                    acc[o][0] += w2 * dA[0];
+                    acc[o][1] += w2 * dA[1];
+                    acc[o][2] += w2 * dA[2];
+                    acc[o][3] += w * dC[0];
+                    acc[o][4] += w * dC[1];
+                    acc[o][5] += w * dC[2];
+                }
+            });
+        });
+    }
+    // the four quarters of a K function, in a fixed order
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            double v = acc[o][k];
+            v += __shfl_xor(v, 32, 64);
+            v += __shfl_xor(v, 16, 64);
+            acc[o][k] = v;
+        }
+    if (slot == 0 && cvalid) {
         double *dst = job.partial + (((size_t)sa * nshAux + sc) * (kMaxAOL + 1) + LB) * NO * 6;
 #pragma unroll
         for (int o = 0; o < NO; ++o)
@@ -571,6 +803,14 @@ void deriv_one(const AOGeom &ao, const AuxGeom &aux, const int *auxl_beg, int cs
     int c0, nc;
     if (!class_range<LC>(auxl_beg, cs0, cs1, &c0, &nc)) return;
     if (na == 0 || nb == 0) return;
+    if constexpr (LC == 0) {
+        if (job.gcomp) {
+            // K block on its copy (launch_int3c_deriv checked the range)
+            hipLaunchKernelGGL((k_int3c_deriv_k<LA, LB, kMaxOutChunk>), dim3(na * ((nc + 15) / 16)), dim3(64), 0, st,
+                               ao.sh, ao.nao, a0, na, aux.sh, c0, nc, aux.nshell, boys, job);
+            return;
+        }
+    }
     // d-shell partner lists are short: four C shells per wave there
     constexpr int G = LB == 2 ? 4 : (LB == 1 ? 2 : 1);
     hipLaunchKernelGGL((k_int3c_deriv<LA, LB, LC, kMaxOutChunk, G>), dim3(na * ((nc + G - 1) / G)), dim3(64), 0, st,
@@ -623,6 +863,15 @@ hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg
 {
     if (cs1 < 0) cs1 = aux.nshell;
     if (cs0 < 0 || cs0 > cs1 || cs1 > aux.nshell) return hipErrorInvalidValue;
+    if (job.gcomp) {
+        // the copy serves the s shells of the range: all of them must be K
+        // functions of the block (s shells hold one function each)
+        int c0, nc;
+        if (!job.gammaK || !job.lst_ptr || !job.lst_idx || !job.lst_gq || job.nfq <= 0) return hipErrorInvalidValue;
+        if (class_range<0>(auxl_beg, cs0, cs1, &c0, &nc) &&
+            (c0 < job.kbeg || c0 + nc > job.kbeg + job.nK || auxl_beg[0] != 0))
+            return hipErrorInvalidValue;
+    }
     deriv_one<0, 0, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
     deriv_one<0, 1, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
     deriv_one<0, 2, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
@@ -641,6 +890,17 @@ hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg
     deriv_one<2, 0, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
     deriv_one<2, 1, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
     deriv_one<2, 2, 1>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_gamma(const AOGeom &ao, const double *gammaK, int nout, int nK, const PackLists &pl,
+                             long nfq, double *Gc, hipStream_t st)
+{
+    if (nout <= 0 || nK <= 0 || ao.nshell <= 0) return hipSuccess;
+    if (nout > kMaxOutChunk || nfq <= 0) return hipErrorInvalidValue;
+    const long blocks = (long)nout * ao.nshell * ((nK + 63) / 64);
+    hipLaunchKernelGGL(k_pack_gamma, dim3((unsigned)blocks), dim3(256), 0, st, ao.sh.off, ao.lbeg[1], ao.lbeg[2],
+                       ao.nshell, ao.nao, nK, gammaK, pl.pk_ptr, pl.pk_base, pl.pc_ptr, pl.pc_cn, pl.pc_qb, nfq, Gc);
     return hipGetLastError();
 }
 

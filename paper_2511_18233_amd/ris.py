@@ -123,15 +123,17 @@ def load_library(path: str = LIB_PATH):
 
 
 def request_bytes(Z, shell_atom, shell_l, radius_bohr, nmo, nocc, nstate, nvec=0, nout=0, theta=0.2,
-                  j_p_on_heavy=True, aux_block=0) -> int:
+                  j_p_on_heavy=True, aux_block=0, xyz=None, shell_exp=None) -> int:
     """Device bytes one request needs (host-only sizing from the library);
-    aux_block > 0: the footprint of the path blocked over the auxiliary index."""
+    aux_block > 0: the footprint of the path blocked over the auxiliary index.
+    xyz (Bohr) and shell_exp size the screened AO shell pairs; without them
+    every pair counts as kept (an upper bound)."""
     lib = load_library()
     Z = np.ascontiguousarray(Z, dtype=np.int32)
     sa = np.ascontiguousarray(shell_atom, dtype=np.int32)
     sl = np.ascontiguousarray(shell_l, dtype=np.int32)
-    se = np.ones(sl.shape[0])
-    xyz = np.zeros((Z.shape[0], 3))
+    se = np.ones(sl.shape[0]) if shell_exp is None else np.ascontiguousarray(shell_exp, dtype=np.float64)
+    xyz = np.zeros((Z.shape[0], 3)) if xyz is None else np.ascontiguousarray(xyz, dtype=np.float64)
     rad = np.ascontiguousarray(radius_bohr, dtype=np.float64)
     ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
     mol = _Mol(Z.shape[0], Z.ctypes.data_as(ip), xyz.ctypes.data_as(dp), sl.shape[0], sa.ctypes.data_as(ip),

@@ -100,7 +100,8 @@ class GpuExecutor:
     def need_bytes(self, r: Request) -> int:
         from .ris import request_bytes
         return request_bytes(r.Z, r.shell_atom, r.shell_l, self.rad, r.C.shape[1], r.nocc, r.X.shape[0], 0,
-                             len(r.sel) + len(r.pairs), self.theta, r.j_p_on_heavy)
+                             len(r.sel) + len(r.pairs), self.theta, r.j_p_on_heavy, xyz=r.xyz,
+                             shell_exp=r.shell_exp)
 
     def run(self, r: Request):
         torch = self.torch

@@ -53,7 +53,7 @@ def _plan(name, block):
     m = molgen.make_molecule(kind, natm, basis, np.random.default_rng(molgen.WORKLOAD_SEED[name]))
     nocc = m.nelec // 2
     return request_bytes(m.Z, m.shell_atom, m.shell_l, molgen.radii_bohr_table(), m.nao, nocc, ns, ns, 2 * ns - 1,
-                         aux_block=block)
+                         aux_block=block, xyz=m.xyz, shell_exp=m.shell_exp)
 
 
 def test_hbm_planner_host_sizing():

@@ -113,9 +113,10 @@ def test_budget_forces_blocks(ctx, radii):
     prob = molgen.make_chain_problem(12, seed=5, nstate=3, tda=False)
     outs = _outs(prob.nstate)
     m = prob.mol
-    full = request_bytes(m.Z, m.shell_atom, m.shell_l, radii, m.nao, prob.nocc, prob.nstate, 2, len(outs))
+    full = request_bytes(m.Z, m.shell_atom, m.shell_l, radii, m.nao, prob.nocc, prob.nstate, 2, len(outs),
+                         xyz=m.xyz, shell_exp=m.shell_exp)
     plan = request_bytes(m.Z, m.shell_atom, m.shell_l, radii, m.nao, prob.nocc, prob.nstate, 2, len(outs),
-                         aux_block=4)
+                         aux_block=4, xyz=m.xyz, shell_exp=m.shell_exp)
     say(f"[gpu] budget-forced blocking: unblocked plan {full} B, 4-function blocks {plan} B")
     assert plan < full
     _, _, ref_gpu, mv0, _ = _run(ctx, prob, radii, 0, outs)

@@ -31,7 +31,8 @@ def test_chain500_blocked_precisions_and_invariance(radii):
     prob = molgen.make_problem("chain500")
     m = prob.mol
     ns = prob.nstate
-    plan0 = request_bytes(m.Z, m.shell_atom, m.shell_l, radii, m.nao, prob.nocc, ns, 0, 3)
+    plan0 = request_bytes(m.Z, m.shell_atom, m.shell_l, radii, m.nao, prob.nocc, ns, 0, 3, xyz=m.xyz,
+                          shell_exp=m.shell_exp)
     say(f"[gpu]   nao={m.nao} nocc={prob.nocc} unblocked plan {plan0 / 1e9:.0f} GB")
     dev = torch.device("cuda", 0)
     C = torch.as_tensor(prob.C, device=dev)
