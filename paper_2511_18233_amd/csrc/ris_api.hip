@@ -674,7 +674,7 @@ ContractWs contract_ws(const Dims &d, int ns)
 // and per block of nb functions Tall, H_UU, W (+ float copy), Y and Gamma.
 struct ContractBlkWs {
     size_t oR, oL, oRLT, oF, oFf, oD, otT, ocv, oHI0, oHI1, oHJ0, oHJ1, oTR, oG1, oV2, oSK, op3, op2, oshA, oshC, oshP,
-        oTall, oHUU, oW, oWf, oY, oG, oOut, total;
+        oTall, oHUU, oW, oWf, oY, oG, oGc, oOut, total;
 };
 ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
 {
@@ -710,6 +710,7 @@ ContractBlkWs contract_blk_ws(const Dims &d, int ns, int nb)
     L.oWf = cv.take(xcopy_doubles((size_t)nb * o3, o3));
     L.oY = cv.take(std::max((size_t)nb * d.N * o3, xcopy_doubles((size_t)nb * d.N, o3)));
     L.oG = cv.take((size_t)nb * NN);
+    L.oGc = cv.take((size_t)d.nfq * nb);  // compact copy of the block's Gamma (one output)
     L.total = cv.off;
     return L;
 }
@@ -1940,6 +1941,25 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
 //   G_PQ = <H_RUU^P + H_LUU^P, c_oo^Q> + <H_RUO^P, H_ROU^Q> - <H_LUO^P, H_LOU^Q>
 // (<.,.> the elementwise inner product over (i, j)), which needs only the
 // H_OU blocks of the two states over all P and the block's H_UU.
+// The derivative contraction reads its exchange weights from the compact
+// copy Gc (when the pair blocks are numbered): set the job up for it, and
+// fill it from Gamma ([nout][nK][nao][nao], lower blocks) before the launch.
+static void set_compact(const ris_ctx *c, DerivJob &job, double *Gc)
+{
+    if (c->nfq <= 0) return;
+    job.gcomp = Gc;
+    job.nfq = c->nfq;
+    job.lst_ptr = c->d_pair_ptr;
+    job.lst_idx = c->d_pair_idx;
+    job.lst_gq = c->d_pair_gq;
+}
+static hipError_t pack_compact(const ris_ctx *c, const double *G, int nout, int nK, double *Gc)
+{
+    return launch_pack_gamma(c->ao, G, nout, nK,
+                             PackLists{c->d_pk_ptr, c->d_pk_base, c->d_pc_ptr, c->d_pc_cn, c->d_pc_qb}, c->nfq, Gc,
+                             c->stream);
+}
+
 static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const double *Y, int npair,
                                   const int *pI, const int *pJ, double *outg, int nb)
 {
@@ -1960,7 +1980,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
            *cvec = P_(CW.ocv), *HI0 = P_(CW.oHI0), *HI1 = P_(CW.oHI1), *HJ0 = P_(CW.oHJ0), *HJ1 = P_(CW.oHJ1),
            *TR = P_(CW.oTR), *G1 = P_(CW.oG1), *V2 = P_(CW.oV2), *SK = P_(CW.oSK), *p3 = P_(CW.op3),
            *p2 = P_(CW.op2), *shA = P_(CW.oshA), *shC = P_(CW.oshC), *shP = P_(CW.oshP), *Tall = P_(CW.oTall),
-           *HUU = P_(CW.oHUU), *W = P_(CW.oW), *Y3 = P_(CW.oY), *G = P_(CW.oG);
+           *HUU = P_(CW.oHUU), *W = P_(CW.oW), *Y3 = P_(CW.oY), *G = P_(CW.oG), *Gc = P_(CW.oGc);
     // reduced-precision copies of F and W^P (reduced_f, assemble_w)
     float *Ff = (float *)(wsb + CW.oFf), *Wf = (float *)(wsb + CW.oWf);
     const double *CO = c->C, *CV = c->C + o;
@@ -2044,6 +2064,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
         job.alphaJ = c->alphaJ;
         job.pair_ptr = c->screen > 0.0 ? c->d_pair_ptr : nullptr;
         job.pair_idx = c->d_pair_idx;
+        set_compact(c, job, Gc);
         for (int p0 = 0; p0 < nK; p0 += nb) {
             const int m = std::min(nb, nK - p0);
             hipEvent_t t_b = stage_begin(c);
@@ -2110,6 +2131,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                     job.stJ[u] = J;
                 }
                 hipEvent_t t_d = stage_begin(c);
+                if (job.gcomp) HIPCHK(c, pack_compact(c, G, 1, m, Gc));
                 HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, p0, p0 + m));
                 stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)m * NN);
             }
@@ -2257,13 +2279,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         job.partial = p3;
         job.pair_ptr = c->screen > 0.0 ? c->d_pair_ptr : nullptr;
         job.pair_idx = c->d_pair_idx;
-        if (c->nfq > 0) {
-            job.gcomp = Gc;
-            job.nfq = c->nfq;
-            job.lst_ptr = c->d_pair_ptr;
-            job.lst_idx = c->d_pair_idx;
-            job.lst_gq = c->d_pair_gq;
-        }
+        set_compact(c, job, Gc);
         for (int k = 0; k < NO; ++k) {
             const int kk = k0 + std::min(k, nb - 1);
             job.stI[k] = pI[kk];
@@ -2333,10 +2349,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         // three-centre derivative contraction + metric derivative, reduced into atoms
         HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * NO * 6, 0.0, c->stream));
         hipEvent_t t_d = stage_begin(c);
-        if (job.gcomp)
-            HIPCHK(c, launch_pack_gamma(c->ao, G, nb, nK,
-                                        PackLists{c->d_pk_ptr, c->d_pk_base, c->d_pc_ptr, c->d_pc_cn, c->d_pc_qb},
-                                        c->nfq, Gc, c->stream));
+        if (job.gcomp) HIPCHK(c, pack_compact(c, G, nb, nK, Gc));
         HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream));
         stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)nb * nK * NN);
         HIPCHK(c, fill(p2, (size_t)c->nshJ * 2 * nb * 3, 0.0, c->stream));
@@ -2361,7 +2374,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
 // block and once per pair for its rows of V (a block already in place is not
 // recomputed, so a single block costs one evaluation).
 struct ExtraWs {
-    size_t oD, ot, oc, ocs, oSK, oV2, oV, oVr, op3, op2, oshA, oshC, oshP, oG, oCb, oUb, oXb, oBq, total;
+    size_t oD, ot, oc, ocs, oSK, oV2, oV, oVr, op3, op2, oshA, oshC, oshP, oG, oCb, oUb, oXb, oBq, oGc, total;
 };
 // K-split of the Gram-type products V = X B^T (m x nq output, K = nao^2): about
 // 1024 workgroups over the output tiles
@@ -2394,6 +2407,7 @@ static ExtraWs extra_ws(const Dims &d, int ne, int nb)
     L.oUb = cv.take((size_t)nb * NN);
     L.oXb = cv.take((size_t)nb * NN);
     L.oBq = cv.take((size_t)nb * NN);
+    L.oGc = cv.take((size_t)d.nfq * nb);  // compact copy of a block's exchange weights (one pair)
     L.total = cv.off;
     return L;
 }
@@ -2419,7 +2433,7 @@ static int contract_extra(ris_ctx *c, int ne, const ris_extra_pair *ex, const in
     double *Dx = P_(EW.oD), *t = P_(EW.ot), *cr = P_(EW.oc), *cs = P_(EW.ocs), *SK = P_(EW.oSK), *V2 = P_(EW.oV2),
            *Vk = P_(EW.oV), *Vr = P_(EW.oVr), *p3 = P_(EW.op3), *p2 = P_(EW.op2), *shA = P_(EW.oshA),
            *shC = P_(EW.oshC), *shP = P_(EW.oshP), *Gt = P_(EW.oG), *Cb = P_(EW.oCb), *Ub = P_(EW.oUb),
-           *Xb = P_(EW.oXb), *Bq = P_(EW.oBq);
+           *Xb = P_(EW.oXb), *Bq = P_(EW.oBq), *Gc = P_(EW.oGc);
     const std::vector<int> &aoff = c->h_aux_off;
 
     // densities in the internal AO order, symmetrised: Dx[2e] = D1 of pair e, Dx[2e+1] = D2
@@ -2465,6 +2479,7 @@ static int contract_extra(ris_ctx *c, int ne, const ris_extra_pair *ex, const in
     job.alphaJ = 1.0;  // cJ is carried by the scaled Coulomb vectors cs
     job.pair_ptr = c->screen > 0.0 ? c->d_pair_ptr : nullptr;
     job.pair_idx = c->d_pair_idx;
+    set_compact(c, job, Gc);
     const auto kblocks = shell_blocks(0, nK);  // the K functions: the leading s shells, one function each
     for (int e0 = 0; e0 < ne; e0 += NO) {
         const int r = std::min(NO, ne - e0);
@@ -2512,6 +2527,7 @@ static int contract_extra(ris_ctx *c, int ne, const ris_extra_pair *ex, const in
                     job.stI[u] = 2 * e;
                     job.stJ[u] = 2 * e + 1;
                 }
+                if (job.gcomp) HIPCHK(c, pack_compact(c, Ub, 1, m, Gc));
                 HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, k0, k1));
             }
         }

@@ -864,12 +864,13 @@ hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg
     if (cs1 < 0) cs1 = aux.nshell;
     if (cs0 < 0 || cs0 > cs1 || cs1 > aux.nshell) return hipErrorInvalidValue;
     if (job.gcomp) {
-        // the copy serves the s shells of the range: all of them must be K
-        // functions of the block (s shells hold one function each)
+        // the copy serves the s shells of the range (a range of p shells
+        // only carries the Coulomb part): all of them must be K functions of
+        // the block (s shells hold one function each)
         int c0, nc;
-        if (!job.gammaK || !job.lst_ptr || !job.lst_idx || !job.lst_gq || job.nfq <= 0) return hipErrorInvalidValue;
         if (class_range<0>(auxl_beg, cs0, cs1, &c0, &nc) &&
-            (c0 < job.kbeg || c0 + nc > job.kbeg + job.nK || auxl_beg[0] != 0))
+            (!job.gammaK || !job.lst_ptr || !job.lst_idx || !job.lst_gq || job.nfq <= 0 || c0 < job.kbeg ||
+             c0 + nc > job.kbeg + job.nK || auxl_beg[0] != 0))
             return hipErrorInvalidValue;
     }
     deriv_one<0, 0, 0>(ao, aux, auxl_beg, cs0, cs1, boys, job, st);
