@@ -800,7 +800,7 @@ void ris_ctx_destroy(ris_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (auto &b : c->bufs) (void)hipFree(b.p);
     release_marks(c);
-    for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -1273,8 +1273,9 @@ int ris_ctx_set_blocking(ris_ctx *c, int aux_block)
 int ris_ctx_set_profiling(ris_ctx *c, int enable)
 {
     if (!c) return RIS_E_INVALID;
-    hipSetDevice(c->device);
-    hipStreamSynchronize(c->stream);
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     release_marks(c);
     c->prof = enable != 0;
     return RIS_OK;
@@ -1941,9 +1942,10 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
 //   G_PQ = <H_RUU^P + H_LUU^P, c_oo^Q> + <H_RUO^P, H_ROU^Q> - <H_LUO^P, H_LOU^Q>
 // (<.,.> the elementwise inner product over (i, j)), which needs only the
 // H_OU blocks of the two states over all P and the block's H_UU.
-// The derivative contraction reads its exchange weights from the compact
-// copy Gc (when the pair blocks are numbered): set the job up for it, and
-// fill it from Gamma ([nout][nK][nao][nao], lower blocks) before the launch.
+// The derivative contraction reads the weights of its s-shell classes from
+// the compact copy Gc (when the pair blocks are numbered): set the job up for
+// it, and fill it from the job's Gamma, densities and Coulomb vectors before
+// the launch.
 static void set_compact(const ris_ctx *c, DerivJob &job, double *Gc)
 {
     if (c->nfq <= 0) return;
@@ -1953,10 +1955,9 @@ static void set_compact(const ris_ctx *c, DerivJob &job, double *Gc)
     job.lst_idx = c->d_pair_idx;
     job.lst_gq = c->d_pair_gq;
 }
-static hipError_t pack_compact(const ris_ctx *c, const double *G, int nout, int nK, double *Gc)
+static hipError_t pack_compact(const ris_ctx *c, const DerivJob &job)
 {
-    return launch_pack_gamma(c->ao, G, nout, nK,
-                             PackLists{c->d_pk_ptr, c->d_pk_base, c->d_pc_ptr, c->d_pc_cn, c->d_pc_qb}, c->nfq, Gc,
+    return launch_pack_gamma(c->ao, job, PackLists{c->d_pk_ptr, c->d_pk_base, c->d_pc_ptr, c->d_pc_cn, c->d_pc_qb},
                              c->stream);
 }
 
@@ -2131,7 +2132,7 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                     job.stJ[u] = J;
                 }
                 hipEvent_t t_d = stage_begin(c);
-                if (job.gcomp) HIPCHK(c, pack_compact(c, G, 1, m, Gc));
+                if (job.gcomp) HIPCHK(c, pack_compact(c, job));
                 HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, p0, p0 + m));
                 stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)m * NN);
             }
@@ -2349,7 +2350,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         // three-centre derivative contraction + metric derivative, reduced into atoms
         HIPCHK(c, fill(p3, (size_t)c->nshAO * c->nshJ * 3 * NO * 6, 0.0, c->stream));
         hipEvent_t t_d = stage_begin(c);
-        if (job.gcomp) HIPCHK(c, pack_compact(c, G, nb, nK, Gc));
+        if (job.gcomp) HIPCHK(c, pack_compact(c, job));
         HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream));
         stage_end(c, t_d, RIS_STAGE_DERIV, 0.0, 8.0 * (double)nb * nK * NN);
         HIPCHK(c, fill(p2, (size_t)c->nshJ * 2 * nb * 3, 0.0, c->stream));
@@ -2527,7 +2528,7 @@ static int contract_extra(ris_ctx *c, int ne, const ris_extra_pair *ex, const in
                     job.stI[u] = 2 * e;
                     job.stJ[u] = 2 * e + 1;
                 }
-                if (job.gcomp) HIPCHK(c, pack_compact(c, Ub, 1, m, Gc));
+                if (job.gcomp) HIPCHK(c, pack_compact(c, job));
                 HIPCHK(c, launch_int3c_deriv(c->ao, c->aux, c->auxl_beg, c->boys, job, c->stream, k0, k1));
             }
         }

@@ -75,9 +75,10 @@ struct DerivJob {
     // in class l are pair_idx[pair_ptr[(kMaxAOL+1) sa + l] .. pair_ptr[(kMaxAOL+1) sa + l + 1])
     const int *pair_ptr;
     const int *pair_idx;
-    // Optional compact copy of gammaK (null: gammaK is read in place).  With
-    // it, the s-shell classes of the K block run on a second kernel (lanes
-    // over the K functions).  Layout Gc[o][q][k], k < nK fastest, q = the
+    // Optional compact copy of the s-shell weights (null: gammaK and the
+    // densities are read in place).  With it, the s-shell classes of the K
+    // block run on a second kernel (lanes over the K functions) that reads
+    // only the copy.  Layout Gc[o][q][k], k < nK fastest, q = the
     // function pair inside the block of its unordered kept shell pair
     // (nfq pairs in all, see launch_pack_gamma).  lst_ptr / lst_idx are the
     // partner lists in pair_ptr / pair_idx form (always given, every pair when
@@ -91,7 +92,7 @@ struct DerivJob {
     const int *lst_gq;
 };
 constexpr int kMaxOutChunk = 4;
-// Gc[o][base + ka nb + kb][k] = gammaK_o[k][mu0 + ka][nu0 + kb] for o < nout and
+// Gc[o][base + ka nb + kb][k] = W_o[k][mu0 + ka][nu0 + kb] for o < nout and
 // every unordered kept AO shell pair (a, b) whose b starts at or before a
 // (the diagonal block taken from the lower triangle), base = the pair's block
 // start.  gammaK: [nout][nK][nao][nao], only the lower blocks of kept pairs
@@ -105,8 +106,11 @@ struct PackLists {
     // block start + the column's index in the partner
     const int *pc_ptr, *pc_cn, *pc_qb;
 };
-hipError_t launch_pack_gamma(const AOGeom &ao, const double *gammaK, int nout, int nK, const PackLists &pl,
-                             long nfq, double *Gc, hipStream_t st);
+// The copy of job.gammaK (job.nout outputs, job.nK K functions from J
+// function job.kbeg) into job.gcomp, holding the whole weight of the s-shell
+// triplets: the Coulomb part alphaJ (D_I c_J + D_J c_I) of the job's states
+// is added to every element.
+hipError_t launch_pack_gamma(const AOGeom &ao, const DerivJob &job, const PackLists &pl, hipStream_t st);
 // Only the aux shells in [cs0, cs1) (cs1 < 0: to the last shell); partial
 // slots of the other shells are left untouched.
 hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg[kMaxAuxL + 2],

@@ -439,13 +439,18 @@ __global__ __launch_bounds__(64) void k_int3c_deriv(ShellTab ao, int nao, int a0
 // + column index) go through LDS 64 at a time: each wave reads a contiguous
 // row segment of one plane k, then each wave writes one column's 64 values of
 // k as a contiguous run.  The diagonal block (a, a) is copied element by
-// element from the lower triangle afterwards.
+// element from the lower triangle afterwards.  What is stored is the whole
+// weight of the s-shell triplets, the Coulomb part added on the way:
+//   Gamma_o^k[mu nu] + alphaJ (D_I[mu nu] c_J[k] + D_J[mu nu] c_I[k])
+// (symmetric in mu nu like Gamma; the density elements are the same for
+// all lanes).
 constexpr int kPackCols = 64;
 __global__ __launch_bounds__(256) void k_pack_gamma(const int *__restrict__ off, int lb1, int lb2, int nsh, int nao,
                                                     int nK, const double *__restrict__ G,
                                                     const int *__restrict__ pk_ptr, const int *__restrict__ pk_base,
                                                     const int *__restrict__ pc_ptr, const int *__restrict__ pc_cn,
-                                                    const int *__restrict__ pc_qb, long nfq, double *__restrict__ Gc)
+                                                    const int *__restrict__ pc_qb, long nfq, double *__restrict__ Gc,
+                                                    DerivJob job)
 {
     __shared__ double tile[64][kPackCols + 1];  // [k][column]; odd row stride: column reads by k are conflict-free
     const int ngrp = (nK + 63) / 64;
@@ -459,6 +464,11 @@ __global__ __launch_bounds__(256) void k_pack_gamma(const int *__restrict__ off,
     double *Go = Gc + (size_t)o * nfq * nK + k0;
     const int na = ncart(a >= lb2 ? 2 : (a >= lb1 ? 1 : 0));
     const int mu0 = off[a], j0 = pc_ptr[a], j1 = pc_ptr[a + 1];
+    // Coulomb factors of this lane's K function (J function kbeg + k)
+    const int kc = job.kbeg + k0 + min(lane, nk - 1);
+    const double cJa = job.alphaJ * job.cvec[(size_t)job.stJ[o] * job.nJ + kc];
+    const double cIa = job.alphaJ * job.cvec[(size_t)job.stI[o] * job.nJ + kc];
+    const double *DI = job.dens + (size_t)job.stI[o] * nn, *DJ = job.dens + (size_t)job.stJ[o] * nn;
     for (int ka = 0; ka < na; ++ka) {
         const size_t row = (size_t)(mu0 + ka) * nao;
         for (int jc = j0; jc < j1; jc += kPackCols) {
@@ -476,8 +486,10 @@ __global__ __launch_bounds__(256) void k_pack_gamma(const int *__restrict__ off,
             __syncthreads();
             if (lane < nk)
                 for (int c = wv; c < nc; c += 4) {
-                    const long q = (long)pc_qb[jc + c] + (long)ka * (pc_cn[jc + c] & 7);
-                    Go[(size_t)q * nK + lane] = tile[lane][c];
+                    const int cn = pc_cn[jc + c];
+                    const long q = (long)pc_qb[jc + c] + (long)ka * (cn & 7);
+                    const size_t mn = row + (cn >> 3);
+                    Go[(size_t)q * nK + lane] = tile[lane][c] + DI[mn] * cJa + DJ[mn] * cIa;
                 }
             __syncthreads();
         }
@@ -488,8 +500,8 @@ __global__ __launch_bounds__(256) void k_pack_gamma(const int *__restrict__ off,
     if (lane < nk)
         for (int e = wv; e < na * na; e += 4) {
             const int ka = e / na, kb = e % na;
-            const int r = mu0 + max(ka, kb), c = mu0 + min(ka, kb);
-            Go[(size_t)(qd + e) * nK + lane] = Gb[lane * nn + (size_t)r * nao + c];
+            const size_t mn = (size_t)(mu0 + max(ka, kb)) * nao + mu0 + min(ka, kb);
+            Go[(size_t)(qd + e) * nK + lane] = Gb[lane * nn + mn] + DI[mn] * cJa + DJ[mn] * cIa;
         }
 }
 
@@ -531,12 +543,6 @@ __global__ __launch_bounds__(64) void k_int3c_deriv_k(ShellTab ao, int nao, int 
     for (int o = 0; o < NO; ++o)
 #pragma unroll
         for (int k = 0; k < 6; ++k) acc[o][k] = 0.0;
-    double cI[NO], cJ[NO];
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-        cI[o] = job.cvec[(size_t)job.stI[o] * job.nJ + P0];
-        cJ[o] = job.cvec[(size_t)job.stJ[o] * job.nJ + P0];
-    }
     const double *gk = job.gcomp + kk;
     const size_t gstride = (size_t)job.nfq * job.nK;  // one output's copy
     // loads on every lane and output slot (past nout: the last output's
@@ -604,9 +610,8 @@ __global__ __launch_bounds__(64) void k_int3c_deriv_k(ShellTab ao, int nao, int 
                 dC[2] = -f * hsum<NX, NY, NZ, 0, 0, 1>(ex, ey, ez, r);
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
-                    const double dI = job.alphaJ * job.dens[(size_t)job.stI[o] * nao2 + mn];
-                    const double dJ = job.alphaJ * job.dens[(size_t)job.stJ[o] * nao2 + mn];
-                    const double w = dI * cJ[o] + dJ * cI[o] + gk[(size_t)min(o, olast) * gstride + (size_t)q * job.nK];
+                    // the whole weight, Coulomb part included (k_pack_gamma)
+                    const double w = gk[(size_t)min(o, olast) * gstride + (size_t)q * job.nK];
                     const double w2 = 2.0 * w;
                     acc[o][0] += w2 * dA[0];
                     acc[o][1] += w2 * dA[1];
@@ -894,14 +899,16 @@ hipError_t launch_int3c_deriv(const AOGeom &ao, const AuxGeom &aux, int auxl_beg
     return hipGetLastError();
 }
 
-hipError_t launch_pack_gamma(const AOGeom &ao, const double *gammaK, int nout, int nK, const PackLists &pl,
-                             long nfq, double *Gc, hipStream_t st)
+hipError_t launch_pack_gamma(const AOGeom &ao, const DerivJob &job, const PackLists &pl, hipStream_t st)
 {
+    const int nout = job.nout, nK = job.nK;
     if (nout <= 0 || nK <= 0 || ao.nshell <= 0) return hipSuccess;
-    if (nout > kMaxOutChunk || nfq <= 0) return hipErrorInvalidValue;
+    if (nout > kMaxOutChunk || job.nfq <= 0 || !job.gammaK || !job.gcomp || !job.dens || !job.cvec)
+        return hipErrorInvalidValue;
     const long blocks = (long)nout * ao.nshell * ((nK + 63) / 64);
     hipLaunchKernelGGL(k_pack_gamma, dim3((unsigned)blocks), dim3(256), 0, st, ao.sh.off, ao.lbeg[1], ao.lbeg[2],
-                       ao.nshell, ao.nao, nK, gammaK, pl.pk_ptr, pl.pk_base, pl.pc_ptr, pl.pc_cn, pl.pc_qb, nfq, Gc);
+                       ao.nshell, ao.nao, nK, job.gammaK, pl.pk_ptr, pl.pk_base, pl.pc_ptr, pl.pc_cn, pl.pc_qb,
+                       job.nfq, const_cast<double *>(job.gcomp), job);
     return hipGetLastError();
 }
 
