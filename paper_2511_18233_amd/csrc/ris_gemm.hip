@@ -173,16 +173,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     typedef typename std::conditional<std::is_same<EA, float>::value, float, double>::type RA;
     typedef typename std::conditional<std::is_same<EB, float>::value, float, double>::type RB;
     int offA[NQ], offB[NQ];
-    unsigned vA = 0, vB = 0;  // bit q: staging row q inside the operand
+    RA mA[NQ];
+    RB mB[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int gm = m0 + rf + RSTEP * q, gn = n0 + rf + RSTEP * q;
-        vA |= (gm < M ? 1u : 0u) << q;
-        vB |= (gn < N ? 1u : 0u) << q;
+        mA[q] = gm < M ? RA(1) : RA(0);
+        mB[q] = gn < N ? RB(1) : RB(0);
         offA[q] = (min(gm, M - 1) - m0) * (int)lda;
         offB[q] = (min(gn, N - 1) - n0) * (int)ldb;
     }
-    const bool vAc = m0 + cf < M, vBc = n0 + cf < N;
+    const RA mAc = m0 + cf < M ? RA(1) : RA(0);
+    const RB mBc = n0 + cf < N ? RB(1) : RB(0);
     const int cA = min(m0 + cf, M - 1) - m0, cB = min(n0 + cf, N - 1) - n0;
     const RA ralpha = (RA)alpha;
 
@@ -202,20 +204,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             if (!TA) {
                 const int gk = k0 + kf;
                 const RA x = (RA)ld_off(pA, offA[q] + min(gk, kend - 1));
-                ra[q] = x * ((gk < kend && (vA >> q & 1u)) ? RA(1) : RA(0));
+                ra[q] = x * (gk < kend ? mA[q] : RA(0));
             } else {
                 const int gk = k0 + kr + 2 * q;
                 const RA x = (RA)ld_off(pA, (min(gk, kend - 1) - k0) * (int)lda + cA);
-                ra[q] = x * ((gk < kend && vAc) ? RA(1) : RA(0));
+                ra[q] = x * (gk < kend ? mAc : RA(0));
             }
             if (!TB) {
                 const int gk = k0 + kr + 2 * q;
                 const RB x = (RB)ld_off(pB, (min(gk, kend - 1) - k0) * (int)ldb + cB);
-                rb[q] = x * ((gk < kend && vBc) ? RB(1) : RB(0));
+                rb[q] = x * (gk < kend ? mBc : RB(0));
             } else {
                 const int gk = k0 + kf;
                 const RB x = (RB)ld_off(pB, offB[q] + min(gk, kend - 1));
-                rb[q] = x * ((gk < kend && (vB >> q & 1u)) ? RB(1) : RB(0));
+                rb[q] = x * (gk < kend ? mB[q] : RB(0));
             }
         }
     };
