@@ -2114,8 +2114,9 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
                 const long tmn = (long)((m + 127) / 128) * ((nK + 127) / 128);
                 const int bsplit = (int)std::max(1L, std::min({256L, 1024L / tmn, (long)(skcap / ((size_t)m * nK))}));
                 for (int t = 0; t < 2; ++t)
-                    HIPCHK(c, dgemm_splitk(gm(m, nK, (int)oo, false, true, 1.0, HUU + (size_t)t * m * oo, oo, c->coo,
-                                              oo, t ? 1.0 : 0.0, G1q + (size_t)p0 * nK, nK), bsplit, SK, c->stream));
+                    HIPCHK(c, gemm_splitk(gm(m, nK, (int)oo, false, true, 1.0, HUU + (size_t)t * m * oo, oo, c->coo,
+                                             oo, t ? 1.0 : 0.0, G1q + (size_t)p0 * nK, nK), c->prec, bsplit, SK,
+                                          c->stream));
                 stage_end(c, t_v, RIS_STAGE_VPQ, 4.0 * (double)m * nK * oo, 0.0);
                 const int rr = gamma_products(c, N, o, m, F + (size_t)I * N * o3, F + (size_t)J * N * o3,
                                               f_state(c, Ff, I), f_state(c, Ff, J), ns * N * plane_ld(o3), W, Wf,
@@ -2160,8 +2161,8 @@ static int contract_pairs_blocked(ris_ctx *c, int nstate, const double *X, const
             // G += <H_RUO^P, H_ROU^Q> - <H_LUO^P, H_LOU^Q>  (H_UO^P[i][j] = H_OU(I)^P[j][i])
             for (int t = 0; t < 2; ++t) {
                 HIPCHK(c, permute3(HIt[t], TR, nK, o, o, oo, 1, o, oo, o, 1, c->stream));
-                HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)oo, false, true, t ? -1.0 : 1.0, TR, oo, HJt[t], oo, 1.0, G1q,
-                                          nK), nsplit, SK, c->stream));
+                HIPCHK(c, gemm_splitk(gm(nK, nK, (int)oo, false, true, t ? -1.0 : 1.0, TR, oo, HJt[t], oo, 1.0, G1q,
+                                         nK), c->prec, nsplit, SK, c->stream));
             }
             HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ,
                                nJ, 0.0, V2q, nJ), c->stream));
@@ -2332,8 +2333,8 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             HIPCHK(c, permute3(HOU + (size_t)(ns + J) * o, Lc, nK, o, o, (long)o * w2, w2, 1, oo, o, 1, c->stream));
             const double *gA[4] = {HUU, HUU + (size_t)nK * oo, Ru, Lu}, *gB[4] = {c->coo, c->coo, Rc, Lc};
             for (int u = 0; u < 4; ++u)
-                HIPCHK(c, dgemm_splitk(gm(nK, nK, (int)oo, false, true, u == 3 ? -1.0 : 1.0, gA[u], oo, gB[u], oo,
-                                          u ? 1.0 : 0.0, Gm, nK), nsplit, SK, c->stream));
+                HIPCHK(c, gemm_splitk(gm(nK, nK, (int)oo, false, true, u == 3 ? -1.0 : 1.0, gA[u], oo, gB[u], oo,
+                                         u ? 1.0 : 0.0, Gm, nK), c->prec, nsplit, SK, c->stream));
             HIPCHK(c, dgemm(gm(nJ, nJ, 1, true, false, -c->alphaJ, cvec + (size_t)I * nJ, nJ, cvec + (size_t)J * nJ,
                                nJ, 0.0, V2k, nJ), c->stream));
             HIPCHK(c, add_sym(Gm, nK, V2k, nJ, 0.25 * c->cx, c->stream));
