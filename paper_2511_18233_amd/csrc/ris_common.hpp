@@ -80,7 +80,7 @@ struct DerivJob {
     // block run on a second kernel (lanes over the K functions) that reads
     // only the copy.  Layout Gc[o][q][k], k < nK fastest, q = the
     // function pair inside the block of its unordered kept shell pair
-    // (nfq pairs in all, see launch_pack_gamma).  lst_ptr / lst_idx are the
+    // (nfq function pairs in all, see launch_pack_gamma).  lst_ptr / lst_idx are the
     // partner lists in pair_ptr / pair_idx form (always given, every pair when
     // nothing is screened) and lst_gq[e] = base << 1 | flip for list entry e:
     // the pair's block starts at q = base and is stored with the partner's
@@ -92,11 +92,13 @@ struct DerivJob {
     const int *lst_gq;
 };
 constexpr int kMaxOutChunk = 4;
-// Gc[o][base + ka nb + kb][k] = W_o[k][mu0 + ka][nu0 + kb] for o < nout and
+// Gc[o][base + ka nb + kb][k] = W_o^k[mu0 + ka][nu0 + kb] for o < nout and
 // every unordered kept AO shell pair (a, b) whose b starts at or before a
 // (the diagonal block taken from the lower triangle), base = the pair's block
-// start.  gammaK: [nout][nK][nao][nao], only the lower blocks of kept pairs
-// are read.  The lists (device, built with the pair lists):
+// start, W_o^k = gammaK_o^k + alphaJ (D_I c_J[k] + D_J c_I[k]) the whole weight
+// of the s-shell triplets (symmetric).  gammaK: [nout][nK][nao][nao], only the
+// lower blocks of kept pairs are read.  The lists (device, built with the pair
+// lists):
 struct PackLists {
     // pk_ptr[a] .. pk_ptr[a + 1]: a's partners b starting at or before a, by
     // first function (a itself last); pk_base: their block starts
@@ -106,10 +108,8 @@ struct PackLists {
     // block start + the column's index in the partner
     const int *pc_ptr, *pc_cn, *pc_qb;
 };
-// The copy of job.gammaK (job.nout outputs, job.nK K functions from J
-// function job.kbeg) into job.gcomp, holding the whole weight of the s-shell
-// triplets: the Coulomb part alphaJ (D_I c_J + D_J c_I) of the job's states
-// is added to every element.
+// Fills job.gcomp from job.gammaK (job.nout outputs, job.nK K functions from
+// J function job.kbeg), the densities and Coulomb vectors of the job's states.
 hipError_t launch_pack_gamma(const AOGeom &ao, const DerivJob &job, const PackLists &pl, hipStream_t st);
 // Only the aux shells in [cs0, cs1) (cs1 < 0: to the last shell); partial
 // slots of the other shells are left untouched.

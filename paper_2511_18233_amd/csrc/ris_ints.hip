@@ -534,9 +534,8 @@ __global__ __launch_bounds__(64) void k_int3c_deriv_k(ShellTab ao, int nao, int 
     const double Ax = ao.x[sa], Ay = ao.y[sa], Az = ao.z[sa];
     const double c = aux.exp[sc];
     const double Cx = aux.x[sc], Cy = aux.y[sc], Cz = aux.z[sc];
-    const int mu0 = ao.off[sa], P0 = aux.off[sc];
+    const int P0 = aux.off[sc];
     const int kk = P0 - job.kbeg;  // position in the K block (the launcher checks the range)
-    const size_t nao2 = (size_t)nao * nao;
 
     double acc[NO][6];
 #pragma unroll
@@ -571,7 +570,6 @@ __global__ __launch_bounds__(64) void k_int3c_deriv_k(ShellTab ao, int nao, int 
         herm_build<LA + 1, LB>(P[1] - Ay, P[1] - By, inv2p, Ey);
         herm_build<LA + 1, LB>(P[2] - Az, P[2] - Bz, inv2p, Ez);
         const double pref = kTwoPi52 / (p * c * sqrt(p + c)) * kab * ao.nrm[sa] * ao.nrm[sb] * aux.nrm[sc];
-        const int nu0 = ao.off[sb];
         const double twoa = 2.0 * a;
 
         sfor<ncart(LA)>([&](auto ka) {
@@ -598,7 +596,6 @@ __global__ __launch_bounds__(64) void k_int3c_deriv_k(ShellTab ao, int nao, int 
                     dz[t] = v;
                 });
                 constexpr int NX = ix + jx + 1, NY = iy + jy + 1, NZ = iz + jz + 1;
-                const size_t mn = (size_t)(mu0 + ka) * nao + nu0 + kb;
                 const long q = gbase + (flip ? (long)kb * ncart(LA) + ka : (long)ka * ncart(LB) + kb);
                 const double f = pref * cnorm(LA, ka) * cnorm(LB, kb);
                 double dA[3], dC[3];
