@@ -278,23 +278,38 @@ __global__ void k_axpby(const double *__restrict__ src, double *__restrict__ dst
 //   src[P][i][j] = base[P * sP + i * si + j * sj] * scale   (base null = 0).
 // grid: (3 column blocks x chunks of 256 columns, 3o rows, nP); the column
 // block, hence the source descriptors, is uniform per workgroup
-__global__ void k_assemble3(BlockGrid g, double *__restrict__ W, float *__restrict__ Wf, int o, int nP, int nchunk)
+__global__ __launch_bounds__(256) void k_assemble3(BlockGrid g, double *__restrict__ W, float *__restrict__ Wf, int o)
 {
+    // one workgroup per (row, P): the row's three column blocks in turn, so a
+    // block's sources are the same for every thread; a missing source is read
+    // from a present one with factor 0 (or the block is zero), so the loads
+    // need no branch
     const int n3 = 3 * o;
-    const int bj = blockIdx.x / nchunk;
-    const int j = (blockIdx.x - bj * nchunk) * blockDim.x + threadIdx.x;
-    if (j >= o) return;
-    const int row = blockIdx.y, P = blockIdx.z;
+    const int row = blockIdx.x, P = blockIdx.y;
     const int bi = row / o, i = row - bi * o;
-    double v = 0.0;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const BlockSrc b = g.b[bi][bj][t];
-        if (b.base) v += b.scale * b.base[P * b.sP + (long)i * b.si + (long)j * b.sj];
+    const long rbase = ((long)P * n3 + row) * n3;
+    for (int bj = 0; bj < 3; ++bj) {
+        const BlockSrc s0 = g.b[bi][bj][0], s1 = g.b[bi][bj][1];
+        const long at0 = rbase + (long)bj * o;
+        if (!s0.base && !s1.base) {
+            for (int j = threadIdx.x; j < o; j += blockDim.x) {
+                if (W) W[at0 + j] = 0.0;
+                if (Wf) Wf[at0 + j] = 0.0f;
+            }
+            continue;
+        }
+        const BlockSrc a = s0.base ? s0 : s1;
+        const BlockSrc b = s1.base ? s1 : a;
+        const double ca = s0.base ? s0.scale : 0.0;
+        const double cb = s1.base ? s1.scale : 0.0;
+        const double *pa = a.base + P * a.sP + (long)i * a.si;
+        const double *pb = b.base + P * b.sP + (long)i * b.si;
+        for (int j = threadIdx.x; j < o; j += blockDim.x) {
+            const double v = ca * pa[(long)j * a.sj] + cb * pb[(long)j * b.sj];
+            if (W) W[at0 + j] = v;
+            if (Wf) Wf[at0 + j] = (float)v;
+        }
     }
-    const long at = ((long)P * n3 + row) * n3 + bj * o + j;
-    if (W) W[at] = v;
-    if (Wf) Wf[at] = (float)v;
 }
 
 __global__ void k_to_float(const double *__restrict__ x, float *__restrict__ y, size_t n)
@@ -515,8 +530,7 @@ hipError_t to_float(const double *x, float *y, size_t n, hipStream_t st)
 hipError_t assemble3(const BlockGrid &g, double *W, int o, int nP, hipStream_t st, float *Wf)
 {
     if (o <= 0 || nP <= 0) return hipSuccess;
-    const int nchunk = (int)nblk((size_t)o, 256);
-    hipLaunchKernelGGL(k_assemble3, dim3(3 * nchunk, 3 * o, nP), dim3(256), 0, st, g, W, Wf, o, nP, nchunk);
+    hipLaunchKernelGGL(k_assemble3, dim3(3 * o, nP), dim3(256), 0, st, g, W, Wf, o);
     return hipGetLastError();
 }
 
