@@ -42,7 +42,7 @@ PEAK_HBM_GBS = 8000.0
 # 2.0, write by 1.0 after a 1 GiB copy calibration), averaged over the 28
 # launches of a step; valid only for the GEMM source it was measured on (sha256
 # prefix), null otherwise.
-GAMMA_TRAFFIC = {"gemm_src_sha256": "b2a0b1edb46ba2ef", "workload": "chain200", "bytes_per_launch": 17.43e9}
+GAMMA_TRAFFIC = {"gemm_src_sha256": "38c892350b37dabc", "workload": "chain200", "bytes_per_launch": 17.41e9}
 
 
 def log(*a):

@@ -493,16 +493,29 @@ extern "C" int ris_test_dgemm(int M, int N, int K, int transA, int transB, doubl
 // long K: K is cut into nsplit ranges, each range writes its partial product
 // to ws[z][M][N]; a second kernel sums the partials in a fixed order.
 namespace {
-__global__ void k_splitk_reduce(const double *__restrict__ ws, int nsplit, int M, int N, double beta,
-                                double *__restrict__ C, long ldc)
+// A workgroup of 256 takes 32 consecutive elements: thread (g, e) sums the
+// partials z = g, g + 8, ... of element e (a wave reads 32 consecutive
+// elements of two partials), then the 8 group sums are added in order.
+__global__ __launch_bounds__(256) void k_splitk_reduce(const double *__restrict__ ws, int nsplit, int M, int N,
+                                                       double beta, double *__restrict__ C, long ldc)
 {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)M * N) return;
-    const int m = (int)(idx / N), n = (int)(idx % N);
+    __shared__ double part[8][32];
+    const long tot = (long)M * N;
+    const int e = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const long idx = (long)blockIdx.x * 32 + e;
     double s = 0.0;
-    for (int z = 0; z < nsplit; ++z) s += ws[(size_t)z * M * N + idx];
-    double *cp = C + (long)m * ldc + n;
-    *cp = (beta == 0.0) ? s : s + beta * *cp;
+    if (idx < tot)
+        for (int z = grp; z < nsplit; z += 8) s += ws[(size_t)z * tot + idx];
+    part[grp][e] = s;
+    __syncthreads();
+    if (grp == 0 && idx < tot) {
+        double v = part[0][e];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) v += part[k][e];
+        const int m = (int)(idx / N), n = (int)(idx % N);
+        double *cp = C + (long)m * ldc + n;
+        *cp = (beta == 0.0) ? v : v + beta * *cp;
+    }
 }
 }  // namespace
 
@@ -525,7 +538,8 @@ hipError_t gemm_splitk(const GemmArgs &g, int mode, int nsplit, double *ws, hipS
     hipError_t e = mode >= 2 ? bgemm_kc(p, kc, st, mode == 2 ? 2 : 3) : gemm_kc(p, mode, kc, st);
     if (e != hipSuccess) return e;
     const long tot = (long)g.M * g.N;
-    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ws, used, g.M, g.N,
+    if ((tot + 31) / 32 > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((tot + 31) / 32)), dim3(256), 0, st, ws, used, g.M, g.N,
                        g.beta, g.C, g.ldc);
     return hipGetLastError();
 }

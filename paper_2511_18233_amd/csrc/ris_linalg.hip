@@ -318,16 +318,19 @@ __global__ void k_to_float(const double *__restrict__ x, float *__restrict__ y, 
     if (i < n) y[i] = (float)x[i];
 }
 
-// out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] (+ beta * out) over n0 x n1 x n2
+// out[i0*o0 + i1*o1 + i2*o2] = alpha * in[i0*s0 + i1*s1 + i2*s2] (+ beta * out) over n0 x n1 x n2;
+// the element index is split with divisions of type I (32-bit when the
+// element count fits)
+template <typename I>
 __global__ void k_permute3(const double *__restrict__ in, double *__restrict__ out, int n0, int n1, int n2,
                            long s0, long s1, long s2, long o0, long o1, long o2, double alpha, double beta)
 {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)n0 * n1 * n2) return;
-    const long i2 = idx % n2, r = idx / n2;
-    const long i1 = r % n1, i0 = r / n1;
-    double *d = out + i0 * o0 + i1 * o1 + i2 * o2;
-    const double v = alpha * in[i0 * s0 + i1 * s1 + i2 * s2];
+    const I idx = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+    if ((long)idx >= (long)n0 * n1 * n2) return;
+    const I i2 = idx % (I)n2, r = idx / (I)n2;
+    const I i1 = r % (I)n1, i0 = r / (I)n1;
+    double *d = out + (long)i0 * o0 + (long)i1 * o1 + (long)i2 * o2;
+    const double v = alpha * in[(long)i0 * s0 + (long)i1 * s1 + (long)i2 * s2];
     *d = (beta == 0.0) ? v : v + beta * *d;
 }
 
@@ -539,8 +542,12 @@ hipError_t permute3(const double *in, double *out, int n0, int n1, int n2, long 
 {
     const size_t n = (size_t)n0 * n1 * n2;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_permute3, dim3(nblk(n, 256)), dim3(256), 0, st, in, out, n0, n1, n2, s0, s1, s2, o0, o1, o2,
-                       alpha, beta);
+    if (n + 256 < (size_t)0x7fffffff)
+        hipLaunchKernelGGL(k_permute3<unsigned>, dim3(nblk(n, 256)), dim3(256), 0, st, in, out, n0, n1, n2, s0, s1,
+                           s2, o0, o1, o2, alpha, beta);
+    else
+        hipLaunchKernelGGL(k_permute3<long>, dim3(nblk(n, 256)), dim3(256), 0, st, in, out, n0, n1, n2, s0, s1, s2,
+                           o0, o1, o2, alpha, beta);
     return hipGetLastError();
 }
 
