@@ -71,3 +71,33 @@ def test_hbm_planner_host_sizing():
     assert _plan("chain500", 0) > 288e9
     assert _plan("chain500", 100) < 0.9 * 288e9
     assert _plan("chain500", -1) == 0
+
+
+def test_plan_counts_the_screened_pairs():
+    """ris_plan_bytes holds, per chunk of 4 outputs, the compact copy of the
+    s-shell weights over the AO shell pairs the default screen keeps
+    (prefactor exp(-ab/(a+b)|A-B|^2) >= 1e-15; diagonal blocks whole): with the
+    geometry given, the 199-atom plan is smaller than the all-pairs bound by
+    4 x (function pairs the screen drops) x nK x 8 bytes, counted here in numpy."""
+    import numpy as np
+    import molgen
+    from paper_2511_18233_amd import ris
+    if not os.path.exists(ris.LIB_PATH):
+        pytest.skip("libris_hip.so not built (run __graft_entry__.build())")
+    kind, natm, basis, ns, _ = molgen.WORKLOADS["chain200"]
+    m = molgen.make_molecule(kind, natm, basis, np.random.default_rng(molgen.WORKLOAD_SEED["chain200"]))
+    nocc = m.nelec // 2
+    args = (m.Z, m.shell_atom, m.shell_l, molgen.radii_bohr_table(), m.nao, nocc, ns, ns, 2 * ns - 1)
+    bound = ris.request_bytes(*args)
+    plan = ris.request_bytes(*args, xyz=m.xyz, shell_exp=m.shell_exp)
+    sl = np.asarray(m.shell_l)
+    c = np.asarray(m.xyz)[np.asarray(m.shell_atom)]
+    e = np.asarray(m.shell_exp)
+    d2 = ((c[:, None, :] - c[None, :, :]) ** 2).sum(-1)
+    keep = np.exp(-e[:, None] * e[None, :] / (e[:, None] + e[None, :]) * d2) >= 1e-15
+    nf = np.array([1, 3, 6])[sl]
+    pairs = np.tril(np.ones_like(keep)) * nf[:, None] * nf[None, :]
+    dropped = int((pairs * ~keep).sum())
+    assert dropped > 0
+    expect = 4 * dropped * len(m.Z) * 8  # nK = one s function per atom
+    assert abs((bound - plan) - expect) <= 4096, (bound - plan, expect)
