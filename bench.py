@@ -229,9 +229,9 @@ KERNELS = {
     "fp32": ("k_gemm<1,false,true,*,float,float,double> listed lower tiles, f32 inputs "
              "(Gamma^P = (F_I W^P) F_J^T, batched over P)", PEAK_FP32_TFLOPS, 1.0),
     "bf16x3": ("k_pgemm<2,...> listed lower tiles, three bf16 products on pre-split bf16 planes (Gamma^P = "
-               "(F_I W^P) F_J^T, batched over P)", PEAK_BF16_TFLOPS, 3.0),
+               "(F_I W^P) F_J^T, batched over P; for two states Y^P F_J^T + F_J Y^P^T in one launch)", PEAK_BF16_TFLOPS, 3.0),
     "bf16x6": ("k_pgemm<3,...> listed lower tiles, six bf16 products on pre-split bf16 planes (Gamma^P = "
-               "(F_I W^P) F_J^T, batched over P)", PEAK_BF16_TFLOPS, 6.0),
+               "(F_I W^P) F_J^T, batched over P; for two states Y^P F_J^T + F_J Y^P^T in one launch)", PEAK_BF16_TFLOPS, 6.0),
 }
 
 

@@ -43,10 +43,13 @@ int ris_test_gemm(int mode, int M, int N, int K, int transA, int transB, double 
  * sum in FP64 is returned in C.  kband = w > 0 (K = 3w, B zero in its
  * (1st row, 3rd k) and (3rd row, 1st k) w-blocks) skips those zero blocks;
  * lower != 0 (M == N) computes the 128 x 128 tiles on or below the diagonal
- * only, leaving C's other tiles untouched.  Allocates its own planes;
- * synchronous.  1: invalid arguments, 7: device error. */
+ * only, leaving C's other tiles untouched.  sym2 != 0 (M == N, beta 0, FP64
+ * output, no band) computes C = alpha (A B^T + B A^T) in one launch, the
+ * form of the exchange weights of a transition between two states.
+ * Allocates its own planes; synchronous.  1: invalid arguments, 7: device
+ * error. */
 int ris_test_pgemm(int ns, int M, int N, int K, double alpha, const double *A, long lda, const double *B, long ldb,
-                   double beta, double *C, long ldc, int kband, int lower, int out_planes);
+                   double beta, double *C, long ldc, int kband, int lower, int out_planes, int sym2);
 
 /* Eigen-decomposition of a small symmetric m x m matrix by the path's
  * one-workgroup Jacobi kernel (used for Davidson subspaces): A (device,

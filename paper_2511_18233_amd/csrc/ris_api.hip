@@ -1859,20 +1859,20 @@ static int gamma_products(ris_ctx *c, int N, int o, int nP, const double *FI, co
         hipEvent_t t_y = stage_begin(c);
         HIPCHK(c, pgemm(p, c->stream));
         stage_end(c, t_y, RIS_STAGE_YW, 2.0 * (double)nP * N * o3 * o3, 0.0);
-        for (int h = 0; h < (same ? 1 : 2); ++h) {
-            p = PGemmArgs{};
-            p.M = N; p.N = N; p.K = (int)ldp; p.ns = np;
-            // h = 0: Y^P F_J^T; h = 1: + F_J Y^P^T
-            p.A = h ? PJ : PY; p.lda = ldp; p.psA = h ? fps : yps; p.sA = h ? 0 : N * ldp;
-            p.B = h ? PY : PJ; p.ldb = ldp; p.psB = h ? yps : fps; p.sB = h ? N * ldp : 0;
-            p.alpha = (same ? -2.0 : -1.0) * c->cx;
-            p.beta = h ? 1.0 : 0.0;
-            p.C = Gk; p.ldc = N; p.sC = NN;
-            p.batch = nP; p.lower = true; p.tiles = h ? c->d_gtiles_cm : c->d_gtiles; p.ntiles = c->ngtiles;
-            hipEvent_t t_g = stage_begin(c);
-            HIPCHK(c, pgemm(p, c->stream));
-            stage_end(c, t_g, RIS_STAGE_GAMMA, fl_low, by_low + (h ? 8.0 * nP * c->gtile_lower : 0.0));
-        }
+        // Y^P F_J^T, and for two states + F_J Y^P^T in the same launch (sym2)
+        p = PGemmArgs{};
+        p.M = N; p.N = N; p.K = (int)ldp; p.ns = np;
+        p.A = PY; p.lda = ldp; p.psA = yps; p.sA = N * ldp;
+        p.B = PJ; p.ldb = ldp; p.psB = fps; p.sB = 0;
+        p.alpha = (same ? -2.0 : -1.0) * c->cx;
+        p.sym2 = !same;
+        p.C = Gk; p.ldc = N; p.sC = NN;
+        p.batch = nP; p.lower = true; p.tiles = c->d_gtiles; p.ntiles = c->ngtiles;
+        hipEvent_t t_g = stage_begin(c);
+        HIPCHK(c, pgemm(p, c->stream));
+        // the two-product launch reads each operand twice
+        stage_end(c, t_g, RIS_STAGE_GAMMA, (same ? 1.0 : 2.0) * fl_low,
+                  by_low + (same ? 0.0 : ein * ((double)nP * N * o3 + (double)N * o3)));
         return RIS_OK;
     }
     // FP64 and FP32 modes: F, W and Y as double or float (FP32 rounds them first)

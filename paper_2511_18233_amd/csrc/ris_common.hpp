@@ -195,6 +195,8 @@ struct PGemmArgs {
     bool lower;
     const int *tiles;
     int ntiles;
+    // C = alpha (A B^T + B A^T) (FP64 C, beta 0, M == N, lda == ldb, no band)
+    bool sym2;
 };
 hipError_t pgemm(const PGemmArgs &g, hipStream_t st);
 // Planes (ns parts, leading dimension plane_ld(cols), parts ps apart) of the

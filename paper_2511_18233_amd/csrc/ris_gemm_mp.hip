@@ -331,7 +331,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // multiples of 32 (the planes' padded width, zero past the logical one), so
 // every slab is whole and the loop has no tail.  Rows past M or N are read
 // clamped and never stored.  LDS rows are swizzled (swz).  The products and
-// their order per slab are those of k_bgemm3.
+// their order per slab are those of k_bgemm3.  SYM2 (M == N, lda == ldb):
+// C = alpha (A B^T + B A^T) in one pass, the k-slabs of A B^T followed by
+// those of B A^T (operand bases and part strides swapped) into the same
+// accumulators.
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 // LDS rows of 32 bf16 (64 bytes, unpadded) hold their four 16-byte chunks in
@@ -341,7 +344,7 @@ typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 // plain rows and rows padded to 80 bytes conflict on the reads).
 __device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
 
-template <int NS, bool OUTP, bool BETA>
+template <int NS, bool OUTP, bool BETA, bool SYM2 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pgemm(PGemmArgs g, int tm,
                                                                                           int tn, int total)
 {
@@ -380,18 +383,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     v4u xa[2][NS][2], xb[2][NS][2];
     typedef std::integral_constant<int, 0> S0_;
     typedef std::integral_constant<int, 1> S1_;
+    // k-slabs per product (SYM2: two products, nh slabs each)
+    const int nh = kend > kbeg ? (kend - kbeg + BK2 - 1) / BK2 : 0;
     // slab s into register set SET (every slab is whole: K and the band
-    // bounds are multiples of 32)
+    // bounds are multiples of 32); with SYM2, slabs from nh on are those of
+    // B A^T: B's rows at the tile's row offsets (offA, as lda == ldb and
+    // M == N) and A's at its column offsets
     auto load_slab = [&](auto set, int s) {
         constexpr int SET = decltype(set)::value;
-        const long k0 = kbeg + (long)s * BK2;
-        const char *a = A + 2 * k0, *b = B + 2 * k0;
+        const bool sw = SYM2 && s >= nh;
+        const long k0 = kbeg + (long)(sw ? s - nh : s) * BK2;
+        const char *a = (sw ? B : A) + 2 * k0, *b = (sw ? A : B) + 2 * k0;
+        const long pa = sw ? psB : psA, pb = sw ? psA : psB;
 #pragma unroll
         for (int p = 0; p < NS; ++p)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                xa[SET][p][q] = *reinterpret_cast<const v4u *>(a + p * psA + offA[q]);
-                xb[SET][p][q] = *reinterpret_cast<const v4u *>(b + p * psB + offB[q]);
+                xa[SET][p][q] = *reinterpret_cast<const v4u *>(a + p * pa + offA[q]);
+                xb[SET][p][q] = *reinterpret_cast<const v4u *>(b + p * pb + offB[q]);
             }
     };
     // set SET into LDS stage SET (slab s sits in set s % 2 and stage s % 2)
@@ -414,7 +423,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
     // fragment rows start at multiples of 16, so their swizzle is that of lane & 15
     const int kofs = 8 * ((lane >> 4) ^ swz(lane & 15));
-    const int nslab = kend > kbeg ? (kend - kbeg + BK2 - 1) / BK2 : 0;
+    const int nslab = SYM2 ? 2 * nh : nh;
     // A wave whose 64 x 64 sub-tile holds nothing that is stored skips its
     // fragment reads, MFMAs and stores (it still stages its share of the
     // operands): past the last row or stored column of a ragged tile, and in
@@ -595,6 +604,8 @@ hipError_t pgemm(const PGemmArgs &g, hipStream_t st)
         (reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B)) % 16)
         return hipErrorInvalidValue;
     if (g.Cp ? (g.beta != 0.0 || g.lower || g.ldc < g.N || g.C) : !g.C) return hipErrorInvalidValue;
+    if (g.sym2 && (g.Cp || g.beta != 0.0 || g.kband > 0 || g.M != g.N || g.lda != g.ldb))
+        return hipErrorInvalidValue;
     if (g.kband > 0 && (g.lower || g.K != plane_ld(3L * g.kband))) return hipErrorInvalidValue;
     // 32-bit byte offsets of the rows from the operand base
     if (((long)(g.M - 1) * g.lda + g.K) * 2 >= (1L << 32) || ((long)(g.N - 1) * g.ldb + g.K) * 2 >= (1L << 32))
@@ -611,16 +622,18 @@ hipError_t pgemm(const PGemmArgs &g, hipStream_t st)
     }
     if (total > 0x7fffffffL) return hipErrorInvalidValue;
     dim3 grid((unsigned)total);
-#define RIS_PG_LAUNCH(NS_, OUTP_, BETA_) \
-    hipLaunchKernelGGL((k_pgemm<NS_, OUTP_, BETA_>), grid, dim3(256), 0, st, g, tm, tn, (int)total)
+#define RIS_PG_LAUNCH(NS_, OUTP_, BETA_, SYM2_) \
+    hipLaunchKernelGGL((k_pgemm<NS_, OUTP_, BETA_, SYM2_>), grid, dim3(256), 0, st, g, tm, tn, (int)total)
     if (g.ns == 2) {
-        if (g.Cp) RIS_PG_LAUNCH(2, true, false);
-        else if (g.beta != 0.0) RIS_PG_LAUNCH(2, false, true);
-        else RIS_PG_LAUNCH(2, false, false);
+        if (g.Cp) RIS_PG_LAUNCH(2, true, false, false);
+        else if (g.sym2) RIS_PG_LAUNCH(2, false, false, true);
+        else if (g.beta != 0.0) RIS_PG_LAUNCH(2, false, true, false);
+        else RIS_PG_LAUNCH(2, false, false, false);
     } else {
-        if (g.Cp) RIS_PG_LAUNCH(3, true, false);
-        else if (g.beta != 0.0) RIS_PG_LAUNCH(3, false, true);
-        else RIS_PG_LAUNCH(3, false, false);
+        if (g.Cp) RIS_PG_LAUNCH(3, true, false, false);
+        else if (g.sym2) RIS_PG_LAUNCH(3, false, false, true);
+        else if (g.beta != 0.0) RIS_PG_LAUNCH(3, false, true, false);
+        else RIS_PG_LAUNCH(3, false, false, false);
     }
 #undef RIS_PG_LAUNCH
     return hipGetLastError();
@@ -790,11 +803,13 @@ __global__ void k_planes_sum(const uint16_t *__restrict__ P, long ps, int ns, in
 }  // namespace ris
 
 extern "C" int ris_test_pgemm(int ns, int M, int N, int K, double alpha, const double *A, long lda, const double *B,
-                              long ldb, double beta, double *C, long ldc, int kband, int lower, int out_planes)
+                              long ldb, double beta, double *C, long ldc, int kband, int lower, int out_planes,
+                              int sym2)
 {
     using namespace ris;
     if ((ns != 2 && ns != 3) || M <= 0 || N <= 0 || K <= 0 || !A || !B || !C || lda < K || ldb < K || ldc < N ||
-        (kband > 0 && K != 3 * kband) || (lower && (M != N || out_planes)) || (out_planes && beta != 0.0))
+        (kband > 0 && K != 3 * kband) || (lower && (M != N || out_planes)) || (out_planes && beta != 0.0) ||
+        (sym2 && (M != N || out_planes || beta != 0.0 || kband > 0)))
         return 1;
     const long ldp = plane_ld(K), psa = (long)M * ldp, psb = (long)N * ldp, ldcp = plane_ld(N);
     uint16_t *pa = nullptr, *pb = nullptr, *pc = nullptr;
@@ -816,7 +831,7 @@ extern "C" int ris_test_pgemm(int ns, int M, int N, int K, double alpha, const d
         } else {
             g.C = C; g.ldc = ldc;
         }
-        g.batch = 1; g.kband = kband; g.lower = lower != 0;
+        g.batch = 1; g.kband = kband; g.lower = lower != 0; g.sym2 = sym2 != 0;
         const hipError_t e = pgemm(g, 0);
         if (e == hipErrorInvalidValue) rc = 1;
         else if (e != hipSuccess) rc = 7;

@@ -117,7 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.ris_test_boys.argtypes = [ctypes.c_int, vp, vp]
     lib.ris_test_pgemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp,
                                    ctypes.c_long, vp, ctypes.c_long, ctypes.c_double, vp, ctypes.c_long,
-                                   ctypes.c_int, ctypes.c_int, ctypes.c_int]
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     _lib = lib
     return lib
 

@@ -1,7 +1,7 @@
 """The split-BF16 product on pre-split operands (bf16 planes), through the
 ris_test_pgemm entry: FP64 output with alpha / beta, plane output, the banded
-K of the exchange weights, lower tiles, ragged M, N and K (K padded to a
-multiple of 32 with zero columns).  Reference: the same parts of fl32(x)
+K of the exchange weights, lower tiles, the two-product form A B^T + B A^T,
+ragged M, N and K (K padded to a multiple of 32 with zero columns).  Reference: the same parts of fl32(x)
 formed in numpy (round-to-nearest-even to bf16) and the same products summed
 in FP64; the kernel sums in FP32, so the bar is 2e-5 of sum |A||B|^T (a wrong
 index or part moves an element by O(1) of it)."""
@@ -53,15 +53,16 @@ def _p(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def run(lib, ns, A, B, alpha, beta, C0, kband=0, lower=0, out_planes=0):
+def run(lib, ns, A, B, alpha, beta, C0, kband=0, lower=0, out_planes=0, sym2=0):
     import torch
     dA = torch.as_tensor(A, device="cuda")
     dB = torch.as_tensor(B, device="cuda")
     dC = torch.as_tensor(C0, device="cuda").clone()
     M, K = A.shape
     N = B.shape[0]
-    say(f"[gpu] pgemm ns={ns} M={M} N={N} K={K} kband={kband} lower={lower} planes={out_planes}")
-    st = lib.ris_test_pgemm(ns, M, N, K, alpha, _p(dA), K, _p(dB), K, beta, _p(dC), N, kband, lower, out_planes)
+    say(f"[gpu] pgemm ns={ns} M={M} N={N} K={K} kband={kband} lower={lower} planes={out_planes} sym2={sym2}")
+    st = lib.ris_test_pgemm(ns, M, N, K, alpha, _p(dA), K, _p(dB), K, beta, _p(dC), N, kband, lower, out_planes,
+                            sym2)
     assert st == 0
     return dC.cpu().numpy()
 
@@ -144,11 +145,46 @@ def test_pgemm_plane_output(lib, ns):
     assert np.all(np.abs(got - ref) <= 2e-5 * (np.abs(A) @ np.abs(B).T) + keep * np.abs(ref))
 
 
+@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("lower", [0, 1])
+def test_pgemm_sym2(lib, ns, lower):
+    """C = alpha (A B^T + B A^T) in one launch (the exchange weights of a
+    transition between two states): both products of the parts, summed in one
+    set of FP32 accumulators; ragged n and K; with lower tiles the elements on
+    or below the diagonal (the upper quarter of a diagonal tile may be
+    written too, the rest is untouched)"""
+    rng = np.random.default_rng(31 + ns + 2 * lower)
+    n, K = 301, 117
+    A = rng.standard_normal((n, K))
+    B = rng.standard_normal((n, K)) * 3e-3
+    sentinel = 12345.0
+    got = run(lib, ns, A, B, -0.7, 0.0, np.full((n, n), sentinel), lower=lower, sym2=1)
+    ref = emulate(A, B, ns, -0.7) + emulate(B, A, ns, -0.7)
+    bound = 2e-5 * 0.7 * (np.abs(A) @ np.abs(B).T + np.abs(B) @ np.abs(A).T)
+    # the two halves are not interchangeable: dropping either moves elements
+    # by far more than the bar
+    assert np.max(np.abs(emulate(A, B, ns, -0.7) - ref) - bound) > 0
+    r, c = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    if not lower:
+        assert np.all(np.abs(got - ref) <= bound)
+        return
+    tr, tc = r // 128, c // 128
+    low = r >= c
+    assert np.all(np.abs(got - ref)[low] <= bound[low])
+    assert np.all(got[tr < tc] == sentinel)
+    diag_up = (tr == tc) & (r < c)
+    assert np.all((got[diag_up] == sentinel) | (np.abs(got - ref)[diag_up] <= bound[diag_up]))
+
+
 def test_pgemm_refuses_bad_arguments(lib):
     import torch
     d = torch.zeros(64, dtype=torch.float64, device="cuda")
     # ns outside {2, 3}; lower with M != N; plane output with beta; kband with K != 3w
-    assert lib.ris_test_pgemm(4, 4, 4, 4, 1.0, _p(d), 4, _p(d), 4, 0.0, _p(d), 4, 0, 0, 0) == 1
-    assert lib.ris_test_pgemm(2, 4, 5, 4, 1.0, _p(d), 4, _p(d), 4, 0.0, _p(d), 5, 0, 1, 0) == 1
-    assert lib.ris_test_pgemm(2, 4, 4, 4, 1.0, _p(d), 4, _p(d), 4, 1.0, _p(d), 4, 0, 0, 1) == 1
-    assert lib.ris_test_pgemm(2, 4, 4, 6, 1.0, _p(d), 6, _p(d), 6, 0.0, _p(d), 4, 3, 0, 0) == 1
+    assert lib.ris_test_pgemm(4, 4, 4, 4, 1.0, _p(d), 4, _p(d), 4, 0.0, _p(d), 4, 0, 0, 0, 0) == 1
+    assert lib.ris_test_pgemm(2, 4, 5, 4, 1.0, _p(d), 4, _p(d), 4, 0.0, _p(d), 5, 0, 1, 0, 0) == 1
+    assert lib.ris_test_pgemm(2, 4, 4, 4, 1.0, _p(d), 4, _p(d), 4, 1.0, _p(d), 4, 0, 0, 1, 0) == 1
+    assert lib.ris_test_pgemm(2, 4, 4, 6, 1.0, _p(d), 6, _p(d), 6, 0.0, _p(d), 4, 3, 0, 0, 0) == 1
+    # the two-product form: M != N, beta, plane output
+    assert lib.ris_test_pgemm(2, 4, 5, 4, 1.0, _p(d), 4, _p(d), 4, 0.0, _p(d), 5, 0, 0, 0, 1) == 1
+    assert lib.ris_test_pgemm(2, 4, 4, 4, 1.0, _p(d), 4, _p(d), 4, 1.0, _p(d), 4, 0, 0, 0, 1) == 1
+    assert lib.ris_test_pgemm(2, 4, 4, 4, 1.0, _p(d), 4, _p(d), 4, 0.0, _p(d), 4, 0, 0, 1, 1) == 1
