@@ -542,41 +542,61 @@ __global__ void k_split_planes(const double *__restrict__ x, int rows, int cols,
 }
 
 // Planes of W^T for a 3 x 3 block assembly (k_assemble3's sources): one
-// workgroup per 64 x 64 tile of W and matrix P, read along W's rows into LDS
-// and written along W^T's rows; rows [3o, plane_ld(3o)) of W^T's columns
-// (the padding) are written zero.
+// workgroup per 64 x 64 piece (i0, j0) of one block (bi, bj) and matrix P, so
+// the block's source descriptors are uniform; the piece is read into LDS along
+// whichever index is contiguous in its first source (rows of a row-major
+// block, columns of a transposed one), with clamped indices so the loads need
+// no branch, and written along W^T's rows.  A last row of workgroups
+// (blockIdx.y == 3 nto) writes the padding columns [3o, plane_ld(3o)) of W^T's
+// rows zero.
 template <int NS>
-__global__ void k_assemble3_planes(BlockGrid g, uint16_t *__restrict__ Wt, int o, long ps)
+__global__ __launch_bounds__(256) void k_assemble3_planes(BlockGrid g, uint16_t *__restrict__ Wt, int o, long ps)
 {
     __shared__ float T[64][65];
-    const int n3 = 3 * o;
+    const int n3 = 3 * o, nto = (o + 63) >> 6;
     const long ldp = plane_ld(n3);
-    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64, P = blockIdx.z;
-    const int tid = threadIdx.x;
-#pragma unroll 4
-    for (int k = 0; k < 16; ++k) {
-        const int rr = 4 * k + (tid >> 6), cc = tid & 63;
-        const int r = r0 + rr, cidx = c0 + cc;
-        double v = 0.0;
-        if (r < n3 && cidx < n3) {
-            const int bi = r / o, bj = cidx / o, i = r - bi * o, j = cidx - bj * o;
+    const int bj = blockIdx.x / nto, j0 = (blockIdx.x - bj * nto) * 64;
+    const int P = blockIdx.z, tid = threadIdx.x;
+    uint16_t *const Wp = Wt + (long)P * n3 * ldp;
+    if ((int)blockIdx.y == 3 * nto) {
+        for (int e = tid; e < 64 * 32; e += 256) {
+            const int cc = e >> 5, r = n3 + (e & 31);
+            if (j0 + cc < o && r < ldp) {
+                uint16_t *d = Wp + (long)(bj * o + j0 + cc) * ldp + r;
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const BlockSrc b = g.b[bi][bj][t];
-                if (b.base) v += b.scale * b.base[P * b.sP + (long)i * b.si + (long)j * b.sj];
+                for (int p = 0; p < NS; ++p) d[p * ps] = 0;
             }
         }
-        T[rr][cc] = (float)v;
+        return;
+    }
+    const int bi = blockIdx.y / nto, i0 = (blockIdx.y - bi * nto) * 64;
+    const BlockSrc s0 = g.b[bi][bj][0], s1 = g.b[bi][bj][1];
+    if (s0.base || s1.base) {
+        // a missing source is read from the present one with factor 0
+        const BlockSrc a = s0.base ? s0 : s1;
+        const BlockSrc b = s1.base ? s1 : a;
+        const double ca = s0.base ? s0.scale : 0.0, cb = s1.base ? s1.scale : 0.0;
+        const double *pa = a.base + P * a.sP, *pb = b.base + P * b.sP;
+        const bool rows = a.sj == 1;
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) {
+            const int u = 4 * k + (tid >> 6), w = tid & 63;
+            const int ii = rows ? u : w, jj = rows ? w : u;
+            const long i = min(i0 + ii, o - 1), j = min(j0 + jj, o - 1);
+            T[ii][jj] = (float)(ca * pa[i * a.si + j * a.sj] + cb * pb[i * b.si + j * b.sj]);
+        }
+    } else {
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) T[4 * k + (tid >> 6)][tid & 63] = 0.0f;
     }
     __syncthreads();
 #pragma unroll 4
     for (int k = 0; k < 16; ++k) {
         const int cc = 4 * k + (tid >> 6), rr = tid & 63;
-        const int r = r0 + rr, cidx = c0 + cc;
-        if (cidx < n3 && r < ldp) {
+        if (j0 + cc < o && i0 + rr < o) {
             __bf16 t[NS];
             split_bf16<NS>(T[rr][cc], 1.0f, t);
-            uint16_t *d = Wt + ((long)P * n3 + cidx) * ldp + r;
+            uint16_t *d = Wp + (long)(bj * o + j0 + cc) * ldp + bi * o + i0 + rr;
 #pragma unroll
             for (int p = 0; p < NS; ++p) d[p * ps] = __builtin_bit_cast(uint16_t, t[p]);
         }
@@ -589,8 +609,8 @@ hipError_t assemble3_planes(const BlockGrid &g, uint16_t *Wt, int o, int nP, lon
 {
     if (o <= 0 || nP <= 0) return hipSuccess;
     if ((ns != 2 && ns != 3) || nP > 65535) return hipErrorInvalidValue;
-    const long n3 = 3L * o, ldp = plane_ld(n3);
-    dim3 grid((unsigned)((n3 + 63) / 64), (unsigned)((ldp + 63) / 64), (unsigned)nP);
+    const long nto = (o + 63) / 64;
+    dim3 grid((unsigned)(3 * nto), (unsigned)(3 * nto + 1), (unsigned)nP);
     if (ns == 2) hipLaunchKernelGGL(k_assemble3_planes<2>, grid, dim3(256), 0, st, g, Wt, o, ps);
     else hipLaunchKernelGGL(k_assemble3_planes<3>, grid, dim3(256), 0, st, g, Wt, o, ps);
     return hipGetLastError();
