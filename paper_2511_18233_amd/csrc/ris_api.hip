@@ -1822,35 +1822,43 @@ static hipError_t assemble_w(ris_ctx *c, const BlockGrid &gw, double *W, float *
     return assemble3_planes(gw, (uint16_t *)Wf, o, nP, nP * o3 * plane_ld(o3), plane_parts(c), c->stream);
 }
 
-// Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j] in the split modes on
-// bf16 planes: c_vv (rows (a,P), k = b) and (R,L)^T are split once into the
-// scratch (room bytes, free at this point) and multiplied by the plane kernel,
-// whose staging schedule runs this K = v product at a higher rate than
-// splitting the FP64 operands inside the loop.  Returns false, having done
-// nothing, when the mode keeps FP64 or FP32 operands or the planes do not fit
-// (the caller then takes gemm_mp).
-static bool tall_on_planes(ris_ctx *c, int v, int nK, long w2, const double *RLT, double *Tall, char *scratch,
-                           size_t room, hipError_t *err)
+// The per-state products of the split modes on bf16 planes:
+//   Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j],
+//   HOU[(P,i)][(t,s,j)]  = sum_b c_vo^P[b][i] (R,L)_s[b][j].
+// c_vv (rows (a,P), k = b), c_vo^T and (R,L)^T are split once into the scratch
+// (room bytes, free at this point) and multiplied by the plane kernel, whose
+// staging schedule runs these K = v products at a higher rate than splitting
+// the FP64 operands inside the loop.  Returns false, having done nothing, when
+// the mode keeps FP64 or FP32 operands or the planes do not fit (the caller
+// then takes gemm_mp).
+static bool state_products_on_planes(ris_ctx *c, int v, int o, int nK, long w2, const double *RLT, double *Tall,
+                                     double *HOU, char *scratch, size_t room, hipError_t *err)
 {
     *err = hipSuccess;
     const int np = plane_parts(c);
-    if (!np || v <= 0 || nK <= 0 || w2 <= 0) return false;
-    const long ldp = plane_ld(v), rows = (long)v * nK;
-    const size_t bA = (size_t)rows * ldp * 2 * np, bB = (size_t)w2 * ldp * 2 * np, bT = (size_t)w2 * v * 8;
+    if (!np || v <= 0 || o <= 0 || nK <= 0 || w2 <= 0) return false;
+    const long ldp = plane_ld(v), rows = (long)v * nK, rows2 = (long)nK * o;
+    const size_t bA = (size_t)rows * ldp * 2 * np, bA2 = (size_t)rows2 * ldp * 2 * np, bB = (size_t)w2 * ldp * 2 * np;
+    const size_t bT = (size_t)std::max(rows2, w2) * v * 8;  // FP64 staging of c_vo^T, then of (R,L)^T
     // the plane kernel's 32-bit row offsets and int sizes
-    if (bA + bB + bT > room || rows * ldp * 2 >= (1L << 32) || rows >= (1L << 31) || w2 >= (1L << 31)) return false;
-    uint16_t *PA = (uint16_t *)scratch, *PB = PA + (size_t)rows * ldp * np;
-    double *RT = (double *)(PB + (size_t)w2 * ldp * np);
+    if (bA + bA2 + bB + bT > room || rows * ldp * 2 >= (1L << 32) || rows2 * ldp * 2 >= (1L << 32) ||
+        rows >= (1L << 31) || w2 >= (1L << 31))
+        return false;
+    uint16_t *PA = (uint16_t *)scratch, *PA2 = PA + (size_t)rows * ldp * np, *PB = PA2 + (size_t)rows2 * ldp * np;
+    double *XT = (double *)(PB + (size_t)w2 * ldp * np);
+    // stream order keeps the two uses of XT apart
     hipError_t e = split_planes(c->cvv, (int)rows, v, v, 0, 1, PA, rows * ldp, 0, np, c->stream);
-    if (e == hipSuccess) e = transpose(RLT, w2, RT, v, v, (int)w2, c->stream);
-    if (e == hipSuccess) e = split_planes(RT, (int)w2, v, v, 0, 1, PB, w2 * ldp, 0, np, c->stream);
-    if (e == hipSuccess) {
+    if (e == hipSuccess) e = transpose(c->cvo, rows2, XT, v, v, (int)rows2, c->stream);
+    if (e == hipSuccess) e = split_planes(XT, (int)rows2, v, v, 0, 1, PA2, rows2 * ldp, 0, np, c->stream);
+    if (e == hipSuccess) e = transpose(RLT, w2, XT, v, v, (int)w2, c->stream);
+    if (e == hipSuccess) e = split_planes(XT, (int)w2, v, v, 0, 1, PB, w2 * ldp, 0, np, c->stream);
+    for (int h = 0; h < 2 && e == hipSuccess; ++h) {
         PGemmArgs p{};
-        p.M = (int)rows; p.N = (int)w2; p.K = (int)ldp; p.ns = np;
-        p.A = PA; p.lda = ldp; p.psA = rows * ldp;
+        p.M = (int)(h ? rows2 : rows); p.N = (int)w2; p.K = (int)ldp; p.ns = np;
+        p.A = h ? PA2 : PA; p.lda = ldp; p.psA = (h ? rows2 : rows) * ldp;
         p.B = PB; p.ldb = ldp; p.psB = w2 * ldp;
         p.alpha = 1.0;
-        p.C = Tall; p.ldc = w2;
+        p.C = h ? HOU : Tall; p.ldc = w2;
         p.batch = 1;
         e = pgemm(p, c->stream);
     }
@@ -2289,16 +2297,18 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         HIPCHK(c, dgemm_splitk(gm(ns, nJ, (int)vo, false, true, 1.0, R, vo, c->aiJ, vo, 0.0, tT, nJ), kSplitV, SK,
                                c->stream));
         HIPCHK(c, dgemm(gm(ns, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
-        // Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j]  (split modes: on planes in
-        // Gamma's region, which is not in use until the exchange weights)
+        // Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j]
+        // HOU[(P,i)][(t,s,j)] = sum_b c_vo^P[b][i] (R,L)_s[b][j]  (= H_OU blocks)
+        // (split modes: on planes in Gamma's region, not in use until the exchange weights)
         hipError_t te;
-        if (tall_on_planes(c, v, nK, w2, RLT, Tall, (char *)G, (size_t)NO * nK * NN * 8, &te)) HIPCHK(c, te);
-        else
+        if (state_products_on_planes(c, v, o, nK, w2, RLT, Tall, HOU, (char *)G, (size_t)NO * nK * NN * 8, &te)) {
+            HIPCHK(c, te);
+        } else {
             HIPCHK(c, gemm_mp(gm(v * nK, (int)w2, v, false, false, 1.0, c->cvv, v, RLT, w2, 0.0, Tall, w2), c->prec,
                               c->stream));
-        // HOU[(P,i)][(t,s,j)] = sum_b c_vo^P[b][i] (R,L)_s[b][j]  (= H_OU blocks)
-        HIPCHK(c, gemm_mp(gm(nK * o, (int)w2, v, true, false, 1.0, c->cvo, (long)nK * o, RLT, w2, 0.0, HOU, w2),
-                          c->prec, c->stream));
+            HIPCHK(c, gemm_mp(gm(nK * o, (int)w2, v, true, false, 1.0, c->cvo, (long)nK * o, RLT, w2, 0.0, HOU, w2),
+                              c->prec, c->stream));
+        }
         // HUO[(t,s,i)][(P,j)] = HOU[(P,j)][(t,s,i)]  (H_UO^P of a state is the transpose of its H_OU^P)
         HIPCHK(c, transpose(HOU, w2, HUO, (long)nK * o, nK * o, (int)w2, c->stream));
     }
