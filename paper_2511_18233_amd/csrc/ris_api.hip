@@ -1822,46 +1822,72 @@ static hipError_t assemble_w(ris_ctx *c, const BlockGrid &gw, double *W, float *
     return assemble3_planes(gw, (uint16_t *)Wf, o, nP, nP * o3 * plane_ld(o3), plane_parts(c), c->stream);
 }
 
+// Planes the split modes keep from the per-state stage for the H_UU products:
+// (R,L)^T (w2 rows (t,s,i), k = a) and, per P, Tall^P^T (w2 rows (t,s,j),
+// k = a, P stride w2 ld), both of leading dimension ld with parts prl / ptall
+// apart.  tall == nullptr: the stage ran on FP64 or float operands.
+struct StatePlanes {
+    const uint16_t *rl = nullptr, *tall = nullptr;
+    long ld = 0, prl = 0, ptall = 0;
+};
+
 // The per-state products of the split modes on bf16 planes:
-//   Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j],
-//   HOU[(P,i)][(t,s,j)]  = sum_b c_vo^P[b][i] (R,L)_s[b][j].
-// c_vv (rows (a,P), k = b), c_vo^T and (R,L)^T are split once into the scratch
-// (room bytes, free at this point) and multiplied by the plane kernel, whose
-// staging schedule runs these K = v products at a higher rate than splitting
-// the FP64 operands inside the loop.  Returns false, having done nothing, when
-// the mode keeps FP64 or FP32 operands or the planes do not fit (the caller
-// then takes gemm_mp).
-static bool state_products_on_planes(ris_ctx *c, int v, int o, int nK, long w2, const double *RLT, double *Tall,
-                                     double *HOU, char *scratch, size_t room, hipError_t *err)
+//   Tall^P[(t,s,j)][a] = sum_b (R,L)_s[b][j] c_vv^P[a][b]   (as planes, for H_UU),
+//   HOU[(P,i)][(t,s,j)] = sum_b c_vo^P[b][i] (R,L)_s[b][j]   (FP64).
+// c_vv (rows (a,P), k = b), c_vo^T and (R,L)^T are split into the scratch
+// (room bytes, free during this stage), except (R,L)^T, which goes with the
+// Tall planes into Tall's region (tallroom bytes; H_UU reads both later), and
+// multiplied by the plane kernel, whose staging schedule runs these K = v
+// products at a higher rate than splitting the FP64 operands inside the loop.
+// Returns false, having done nothing, when the mode keeps FP64 or FP32
+// operands or the planes do not fit (the caller then takes gemm_mp).
+static bool state_products_on_planes(ris_ctx *c, int v, int o, int nK, long w2, const double *RLT, char *tallreg,
+                                     size_t tallroom, double *HOU, char *scratch, size_t room, StatePlanes *sp,
+                                     hipError_t *err)
 {
     *err = hipSuccess;
     const int np = plane_parts(c);
     if (!np || v <= 0 || o <= 0 || nK <= 0 || w2 <= 0) return false;
     const long ldp = plane_ld(v), rows = (long)v * nK, rows2 = (long)nK * o;
     const size_t bA = (size_t)rows * ldp * 2 * np, bA2 = (size_t)rows2 * ldp * 2 * np, bB = (size_t)w2 * ldp * 2 * np;
+    const size_t bTP = (size_t)nK * w2 * ldp * 2 * np;
     const size_t bT = (size_t)std::max(rows2, w2) * v * 8;  // FP64 staging of c_vo^T, then of (R,L)^T
-    // the plane kernel's 32-bit row offsets and int sizes
-    if (bA + bA2 + bB + bT > room || rows * ldp * 2 >= (1L << 32) || rows2 * ldp * 2 >= (1L << 32) ||
-        rows >= (1L << 31) || w2 >= (1L << 31))
+    // the plane kernel's 32-bit row offsets (c_vv's rows of one P lie nK rows apart) and int sizes
+    if (bA + bA2 + bT > room || bTP + bB > tallroom || rows * ldp * 2 >= (1L << 32) ||
+        rows2 * ldp * 2 >= (1L << 32) || rows >= (1L << 31) || w2 >= (1L << 31))
         return false;
-    uint16_t *PA = (uint16_t *)scratch, *PA2 = PA + (size_t)rows * ldp * np, *PB = PA2 + (size_t)rows2 * ldp * np;
-    double *XT = (double *)(PB + (size_t)w2 * ldp * np);
+    uint16_t *PA = (uint16_t *)scratch, *PA2 = PA + (size_t)rows * ldp * np;
+    double *XT = (double *)(PA2 + (size_t)rows2 * ldp * np);
+    uint16_t *TP = (uint16_t *)tallreg, *PB = TP + (size_t)nK * w2 * ldp * np;
     // stream order keeps the two uses of XT apart
     hipError_t e = split_planes(c->cvv, (int)rows, v, v, 0, 1, PA, rows * ldp, 0, np, c->stream);
     if (e == hipSuccess) e = transpose(c->cvo, rows2, XT, v, v, (int)rows2, c->stream);
     if (e == hipSuccess) e = split_planes(XT, (int)rows2, v, v, 0, 1, PA2, rows2 * ldp, 0, np, c->stream);
     if (e == hipSuccess) e = transpose(RLT, w2, XT, v, v, (int)w2, c->stream);
     if (e == hipSuccess) e = split_planes(XT, (int)w2, v, v, 0, 1, PB, w2 * ldp, 0, np, c->stream);
-    for (int h = 0; h < 2 && e == hipSuccess; ++h) {
+    if (e == hipSuccess) {
+        // batch P: (R,L)^T against c_vv's rows (a, P), written as planes with
+        // the padding columns [v, ldp) zero
         PGemmArgs p{};
-        p.M = (int)(h ? rows2 : rows); p.N = (int)w2; p.K = (int)ldp; p.ns = np;
-        p.A = h ? PA2 : PA; p.lda = ldp; p.psA = (h ? rows2 : rows) * ldp;
+        p.M = (int)w2; p.N = v; p.K = (int)ldp; p.ns = np;
+        p.A = PB; p.lda = ldp; p.psA = w2 * ldp; p.sA = 0;
+        p.B = PA; p.ldb = (long)nK * ldp; p.psB = rows * ldp; p.sB = ldp;
+        p.alpha = 1.0;
+        p.Cp = TP; p.ldc = ldp; p.psC = (long)nK * w2 * ldp; p.sC = w2 * ldp;
+        p.batch = nK;
+        e = pgemm(p, c->stream);
+    }
+    if (e == hipSuccess) {
+        PGemmArgs p{};
+        p.M = (int)rows2; p.N = (int)w2; p.K = (int)ldp; p.ns = np;
+        p.A = PA2; p.lda = ldp; p.psA = rows2 * ldp;
         p.B = PB; p.ldb = ldp; p.psB = w2 * ldp;
         p.alpha = 1.0;
-        p.C = h ? HOU : Tall; p.ldc = w2;
+        p.C = HOU; p.ldc = w2;
         p.batch = 1;
         e = pgemm(p, c->stream);
     }
+    sp->rl = PB; sp->tall = TP; sp->ld = ldp; sp->prl = w2 * ldp; sp->ptall = (long)nK * w2 * ldp;
     *err = e;
     return true;
 }
@@ -2271,6 +2297,7 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
     const double *CO = c->C, *CV = c->C + o;
 
     // ---- per-state intermediates
+    StatePlanes sp;  // split modes: the planes H_UU reads (none: FP64 or float operands)
     hipEvent_t t_h = stage_begin(c);
     HIPCHK(c, make_rl(X, Y, R, L, (size_t)ns * vo, c->stream));
     // RLT[a][t][s][i] = (R, L)_s[a][i]
@@ -2299,9 +2326,11 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
         HIPCHK(c, dgemm(gm(ns, nJ, nJ, false, false, 1.0, tT, nJ, c->MinvJ, nJ, 0.0, cvec, nJ), c->stream));
         // Tall[(a,P)][(t,s,j)] = sum_b c_vv^P[a][b] (R,L)_s[b][j]
         // HOU[(P,i)][(t,s,j)] = sum_b c_vo^P[b][i] (R,L)_s[b][j]  (= H_OU blocks)
-        // (split modes: on planes in Gamma's region, not in use until the exchange weights)
+        // (split modes: on planes, Tall transposed per P as planes in its own region, the
+        // other operands in Gamma's region, not in use until the exchange weights)
         hipError_t te;
-        if (state_products_on_planes(c, v, o, nK, w2, RLT, Tall, HOU, (char *)G, (size_t)NO * nK * NN * 8, &te)) {
+        if (state_products_on_planes(c, v, o, nK, w2, RLT, (char *)Tall, (size_t)v * nK * w2 * 8, HOU, (char *)G,
+                                     (size_t)NO * nK * NN * 8, &sp, &te)) {
             HIPCHK(c, te);
         } else {
             HIPCHK(c, gemm_mp(gm(v * nK, (int)w2, v, false, false, 1.0, c->cvv, v, RLT, w2, 0.0, Tall, w2), c->prec,
@@ -2342,11 +2371,23 @@ static int contract_pairs(ris_ctx *c, int nstate, const double *X, const double 
             hipEvent_t t_u = stage_begin(c);
             // H_UU^P = (R,L)_I^T Tall^P_{(R,L) J}  (symmetric for a gradient: lower tiles + mirror)
             for (int t = 0; t < 2; ++t) {
-                GemmArgs g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2,
-                                Tall + (size_t)(t * ns + J) * o, (long)nK * w2, 0.0, HUU + (size_t)t * nK * oo, o);
-                g.batch = nK; g.strideA = 0; g.strideB = w2; g.strideC = oo;
-                g.lower = I == J;
-                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                if (sp.tall) {
+                    PGemmArgs p{};
+                    p.M = o; p.N = o; p.K = (int)sp.ld; p.ns = plane_parts(c);
+                    p.A = sp.rl + (size_t)(t * ns + I) * o * sp.ld; p.lda = sp.ld; p.psA = sp.prl; p.sA = 0;
+                    p.B = sp.tall + (size_t)(t * ns + J) * o * sp.ld; p.ldb = sp.ld; p.psB = sp.ptall;
+                    p.sB = w2 * sp.ld;
+                    p.alpha = 1.0;
+                    p.C = HUU + (size_t)t * nK * oo; p.ldc = o; p.sC = oo;
+                    p.batch = nK; p.lower = I == J;
+                    HIPCHK(c, pgemm(p, c->stream));
+                } else {
+                    GemmArgs g = gm(o, o, v, true, false, 1.0, RLT + (size_t)(t * ns + I) * o, w2,
+                                    Tall + (size_t)(t * ns + J) * o, (long)nK * w2, 0.0, HUU + (size_t)t * nK * oo, o);
+                    g.batch = nK; g.strideA = 0; g.strideB = w2; g.strideC = oo;
+                    g.lower = I == J;
+                    HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                }
                 if (I == J) HIPCHK(c, mirror_lower(HUU + (size_t)t * nK * oo, o, o, oo, nK, c->stream));
             }
             stage_end(c, t_u, RIS_STAGE_HBLK, 4.0 * (double)nK * oo * v, 0.0);
