@@ -402,7 +402,8 @@ int build_pairs(ris_ctx *c)
     c->ngtiles = (int)tiles.size();
     c->gtile_lower = lower;
     // the same tiles column by column: launches whose per-P operand is B (the
-    // second half of a NAC) then meet each of its row panels in consecutive tiles
+    // second half of a NAC in the FP32 mode) then meet each of its row panels in
+    // consecutive tiles
     std::vector<int> tiles_cm(tiles);
     std::stable_sort(tiles_cm.begin(), tiles_cm.end(), [](int a, int b) { return (a & 0xffff) < (b & 0xffff); });
     tiles.insert(tiles.end(), tiles_cm.begin(), tiles_cm.end());
@@ -1671,6 +1672,12 @@ int ris_int3c(ris_ctx *c, const ris_mo *mo, double *dbg)
 }
 
 // ------------------------------------------------------------------------
+// Parts per element of the split-BF16 modes (0: no planes)
+static int plane_parts(const ris_ctx *c)
+{
+    return c->prec == RIS_BF16X3 ? 2 : c->prec == RIS_BF16X6 ? 3 : 0;
+}
+
 // Argument checks shared by both matvec entry points.
 static int matvec_check(ris_ctx *c, int op, int nvec, const double *V, double *out)
 {
@@ -1715,11 +1722,32 @@ static int matvec_run(ris_ctx *c, int op, int nvec, const double *V, double *out
         // the exchange terms pair the fitted c^P of one index pair with the raw
         // (pq|P) of the other: sum_PQ (pq|P) (M_K^-1)_PQ (rs|Q) = sum_P c^P_pq (rs|P)
         if (cKA[op] != 0.0) {
-            // T[P][b][k][i] = sum_j V_k[b][j] (ij|P)
-            for (int k = 0; k < nv; ++k) {
-                GemmArgs g = gm(v, o, o, false, true, 1.0, Vk + k * vo, o, c->roo, o, 0.0, T + (size_t)k * o, nvo);
-                g.batch = nK; g.strideA = 0; g.strideB = oo; g.strideC = (long)v * nvo;
-                HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+            // T[P][b][k][i] = sum_j V_k[b][j] (ij|P); in the split modes on bf16
+            // planes of V's chunk and of (ij|P) (both k-fast), formed in the
+            // split-K region, which the U product below only fills afterwards
+            const int np = plane_parts(c);
+            const long ldo = plane_ld(o);
+            const size_t pr = (size_t)nK * o * ldo, pv = (size_t)nv * v * ldo;
+            if (np && (pr + pv) * 2 * np <= skcap * 8 && (long)pr * 2 < (1L << 32) && (long)pv * 2 < (1L << 32)) {
+                uint16_t *PR = (uint16_t *)SKm, *PV = PR + pr * np;
+                HIPCHK(c, split_planes(c->roo, nK * o, o, o, 0, 1, PR, (long)pr, 0, np, c->stream));
+                HIPCHK(c, split_planes(Vk, nv * v, o, o, 0, 1, PV, (long)pv, 0, np, c->stream));
+                for (int k = 0; k < nv; ++k) {
+                    PGemmArgs p{};
+                    p.M = v; p.N = o; p.K = (int)ldo; p.ns = np;
+                    p.A = PV + (size_t)k * v * ldo; p.lda = ldo; p.psA = (long)pv; p.sA = 0;
+                    p.B = PR; p.ldb = ldo; p.psB = (long)pr; p.sB = (long)o * ldo;
+                    p.alpha = 1.0;
+                    p.C = T + (size_t)k * o; p.ldc = nvo; p.sC = (long)v * nvo;
+                    p.batch = nK;
+                    HIPCHK(c, pgemm(p, c->stream));
+                }
+            } else {
+                for (int k = 0; k < nv; ++k) {
+                    GemmArgs g = gm(v, o, o, false, true, 1.0, Vk + k * vo, o, c->roo, o, 0.0, T + (size_t)k * o, nvo);
+                    g.batch = nK; g.strideA = 0; g.strideB = oo; g.strideC = (long)v * nvo;
+                    HIPCHK(c, gemm_mp(g, c->prec, c->stream));
+                }
             }
             // U[a][(k,i)] = sum_{(P,b)} c^P_ab T[(P,b)][(k,i)];  out_k[a][i] -= c_x U[a][k][i]
             HIPCHK(c, gemm_splitk(gm(v, (int)nvo, nK * v, false, false, 1.0, c->cvv, (long)nK * v, T, nvo, 0.0, U, nvo),
@@ -1784,12 +1812,6 @@ int ris_response_matvec_noalloc(ris_ctx *c, int op, int nvec, const double *V, d
                     nvec, need, kNoAllocScratchBytes);
     // every buffer of the matvec is written before it is read: nothing to clear
     return matvec_run(c, op, nvec, V, out, (char *)c->scratch_dev, chunk, false);
-}
-
-// Parts per element of the split-BF16 modes (0: no planes)
-static int plane_parts(const ris_ctx *c)
-{
-    return c->prec == RIS_BF16X3 ? 2 : c->prec == RIS_BF16X6 ? 3 : 0;
 }
 
 // The reduced-precision copy of the per-state factors F (ns x N x 3o): float
