@@ -184,6 +184,41 @@ def test_mixed_precision_error(ctx, radii, case, precision):
     torch.cuda.synchronize()
 
 
+# Matvecs in the reduced modes (exchange products in the mode, the rest FP64):
+# relative to the largest element, about ten times the operand rounding of the
+# mode (2^-24 for FP32 and the six-product split, 2^-17 for the three-product
+# split) to allow for FP32 accumulation over o or v terms; measured on these
+# cases: at most 8e-8 (FP32, six products) and 1.9e-6 (three products)
+MATVEC_REL_BAR = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 2e-5}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6", "bf16x3"])
+@pytest.mark.parametrize("case", ["ring12", "chain12_tddft"])
+def test_matvec_reduced_precision(ctx, radii, case, precision):
+    """A, B, A+B and A-B matvecs with the exchange contractions in each
+    reduced mode against the FP64 oracle, the error of each printed (in the
+    split modes the per-vector products run on bf16 planes)."""
+    import torch
+    make, jp = CASES[case]
+    prob = make()
+    m = prob.mol
+    ctx.aux_build(m.Z, m.xyz, m.shell_atom, m.shell_l, m.shell_exp, radii, 0.2, jp)
+    say(f"[gpu] int3c {case} precision={precision}")
+    ctx.int3c(_to(prob.C, ctx.device), _to(prob.eps, ctx.device), prob.nocc, 2.0, 0.25, precision=precision)
+    S = O.setup(prob.mol, radii, j_p_on_heavy=jp)
+    rng = np.random.default_rng(4)
+    V = rng.standard_normal((3,) + prob.X.shape[1:])
+    Vd = _to(V, ctx.device)
+    for op in ("A", "B", "A+B", "A-B"):
+        say(f"[gpu] matvec {case} {precision} {op}")
+        got = ctx.response_matvec(op, Vd).cpu().numpy()
+        ref = O.response_matvec(S, prob.C, prob.eps, prob.nocc, V, op)
+        err = np.abs(got - ref).max()
+        say(f"[gpu]   err {err:.3e} (max {np.abs(ref).max():.3e}, rel {err / np.abs(ref).max():.2e})")
+        assert err <= MATVEC_REL_BAR[precision] * np.abs(ref).max(), op
+    torch.cuda.synchronize()
+
+
 def test_combined_call_matches_separate_calls(ctx, radii):
     prob = molgen.make_chain_problem(12, seed=5, nstate=3, tda=False)
     _setup(ctx, prob, radii, True)
